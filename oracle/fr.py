@@ -1,0 +1,126 @@
+"""FR/CPR spatial residual with the preconditioned common flux (Sec. 2.3) and the
+ESDIRK stage residual (Sec. 2.4, eq. (26)).
+
+R = -div f is evaluated in the differential FR form of eq. (20): the divergence of
+the Lagrange interpolant of the transformed flux plus the correction field built
+from 1-D correction polynomials along each tensor line,
+
+  R_ij = -(1/|J_ij|) [ sum_k D_ik F~_kj + g_L'(xi_i)(F^_L,j - F~_L,j) + g_R'(xi_i)(F^_R,j - F~_R,j)
+                       + sum_k D_jk G~_ik + g_L'(eta_j)(G^_B,i - G~_B,i) + g_R'(eta_j)(G^_T,i - G~_T,i) ],
+
+where F~_L,j = sum_k l_k(-1) F~_kj is the interpolated local flux at the face and
+F^ = |S| f_com is the common flux of eq. (21) in the +xi direction.
+
+Boundary states (the paper does not state them): periodic faces are identified;
+a slip wall uses the ghost (p, u - 2(u.n)n, T); a far-field face uses the free
+stream q_inf; both pass through the same common flux.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gas as G
+from .basis import Ops1D
+from .geometry import QuadGeometry
+
+BC_SLIP_WALL = -1
+BC_FAR_FIELD = -2
+
+
+class FRLevel:
+    """One P-level of a 2-D quad mesh."""
+
+    def __init__(self, mesh, P: int, gas: G.Gas, q_inf=None):
+        assert mesh.dim == 2
+        self.mesh = mesh
+        self.P = P
+        self.gas = gas
+        self.ops = Ops1D(P)
+        self.geo = QuadGeometry(mesh, P)
+        self.n1 = P + 1
+        self.nv = 4
+        self.npts = self.n1 * self.n1
+        self.n = self.nv * self.npts
+        self.ne = mesh.n_elements
+        self.q_inf = None if q_inf is None else np.asarray(q_inf, float)
+
+    # ---- face traces -------------------------------------------------------------
+    def traces(self, q):
+        """Own-side states at the flux points, [Ne, 4, P+1, Nv] (extrapolation along lines)."""
+        o = self.ops
+        q4 = q.reshape(self.ne, self.n1, self.n1, self.nv)  # [e, j, i, v]
+        tl = np.einsum("k,ejkv->ejv", o.lm, q4)
+        tr = np.einsum("k,ejkv->ejv", o.lp, q4)
+        tb = np.einsum("k,ekiv->eiv", o.lm, q4)
+        tt = np.einsum("k,ekiv->eiv", o.lp, q4)
+        return np.stack([tl, tr, tb, tt], axis=1)
+
+    def outside_states(self, own, nbr_tr):
+        """State across each face: the neighbour's trace, or a boundary ghost."""
+        m = self.mesh
+        out = np.empty_like(own)
+        for f in range(4):
+            nb = m.face_nbr[:, f]
+            inner = nb >= 0
+            idx = np.where(inner, nb, 0)
+            tr = nbr_tr[idx, m.face_nbr_face[:, f]]           # [Ne, P+1, Nv]
+            flip = m.face_orient[:, f] == 1
+            tr = np.where(flip[:, None, None], tr[:, ::-1], tr)
+            out[:, f] = np.where(inner[:, None, None], tr, 0.0)
+            wall = nb == BC_SLIP_WALL
+            if np.any(wall):
+                nvec = self.geo.fvec[:, f]
+                nunit = nvec / np.sqrt(np.sum(nvec * nvec, axis=-1))[..., None]
+                u = own[:, f, :, 1:3]
+                un = np.sum(u * nunit, axis=-1)
+                ghost = own[:, f].copy()
+                ghost[..., 1:3] = u - 2.0 * un[..., None] * nunit
+                out[:, f] = np.where(wall[:, None, None], ghost, out[:, f])
+            far = nb == BC_FAR_FIELD
+            if np.any(far):
+                out[:, f] = np.where(far[:, None, None], self.q_inf, out[:, f])
+        return out
+
+    # ---- residual ----------------------------------------------------------------
+    def residual(self, q, q_nbr=None):
+        """R(q) = -div f at the solution points, [Ne, Np, Nv].
+
+        ``q_nbr`` (default q) is the state the neighbours' face traces are taken from;
+        the Jacobian module passes the unperturbed state there so that only the
+        element's own unknowns move.
+        """
+        o, g = self.ops, self.geo
+        ne, n1, nv = self.ne, self.n1, self.nv
+        own = self.traces(q)
+        nbr_tr = own if q_nbr is None else self.traces(q_nbr)
+        out = self.outside_states(own, nbr_tr)
+        fv = g.fvec
+        fh = [G.common_flux(out[:, 0], own[:, 0], fv[:, 0], self.gas),
+              G.common_flux(own[:, 1], out[:, 1], fv[:, 1], self.gas),
+              G.common_flux(out[:, 2], own[:, 2], fv[:, 2], self.gas),
+              G.common_flux(own[:, 3], out[:, 3], fv[:, 3], self.gas)]
+        ft = G.normal_flux(q, g.S_sp, self.gas).reshape(ne, n1, n1, nv)  # [e, j, i, v]
+        gt = G.normal_flux(q, g.T_sp, self.gas).reshape(ne, n1, n1, nv)
+        fl = np.einsum("k,ejkv->ejv", o.lm, ft)
+        fr = np.einsum("k,ejkv->ejv", o.lp, ft)
+        gb = np.einsum("k,ekiv->eiv", o.lm, gt)
+        gtt = np.einsum("k,ekiv->eiv", o.lp, gt)
+        div = np.einsum("ik,ejkv->ejiv", o.D, ft)
+        div = div + o.gL[None, None, :, None] * (fh[0] - fl)[:, :, None, :]
+        div = div + o.gR[None, None, :, None] * (fh[1] - fr)[:, :, None, :]
+        div = div + np.einsum("jk,ekiv->ejiv", o.D, gt)
+        div = div + o.gL[None, :, None, None] * (fh[2] - gb)[:, None, :, :]
+        div = div + o.gR[None, :, None, None] * (fh[3] - gtt)[:, None, :, :]
+        return -div.reshape(ne, self.npts, nv) / g.jac[..., None]
+
+    def stage_residual(self, q, c_mass=0.0, src=None, S=None, q_nbr=None):
+        """F(q) - S with F = R(q) - c_mass q_c(q) + src (eq. (26); c_mass = 1/(omega dt),
+        0 for a steady problem, where F = R)."""
+        F = self.residual(q, q_nbr)
+        if c_mass != 0.0:
+            F = F - c_mass * G.conservative(q, self.gas)
+        if src is not None:
+            F = F + src
+        if S is not None:
+            F = F - S
+        return F

@@ -1,0 +1,204 @@
+"""Element-Jacobi smoother, P-level transfers, the FAS V-cycle, pseudo-transient
+continuation and the ESDIRK driver (Secs. 2.4 and 3).
+
+Readings, where the paper is silent:
+* ||F|| is the Euclidean norm over every solution point and variable of the fine level.
+* Pseudo time: dtau_0 = dtau_init at the start of every stage solve; afterwards the SER
+  law of eq. (31), dtau_m = min(dtau_{m-1} (r_{m-1}/r_m)^1.5, dtau_max), with one global
+  dtau shared by all levels. (The CFL form of eqs. (31)-(33) scales the same law by the
+  mesh's dtau_min.)
+* The smoother D is rebuilt on every level at V-cycles m = 0, k, 2k, ... (k = 10, Sec. 4.1);
+  once a rebuild has used dtau = dtau_max no further rebuilds happen (Sec. 4.3). The
+  fine-level D is built from q^m, a coarse-level D from that level's restricted state
+  q^b inside the same V-cycle.
+* A stage solve stops when r_m / r_0 <= tol, r_m = ||F(q^m)|| at the start of V-cycle m.
+* q-independent source terms cancel in F_l(q) - S_l on coarse levels (eqs. (40), (43)),
+  so only the finest level carries the ESDIRK source.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+from . import gas as G
+from .basis import interpolation_1d, projection_1d
+from .fr import FRLevel
+from .jacobian import element_blocks
+
+
+# ---- ESDIRK tableaux (eq. (24)); stiffly accurate, first stage explicit -----------
+def esdirk_tableau(name: str) -> np.ndarray:
+    """Butcher matrix A (s x s); b is the last row and omega = A[1, 1].
+
+    ESDIRK2: the three-stage, L-stable, stiffly accurate scheme with
+    gamma = 1 - sqrt(2)/2, c = (0, 2 gamma, 1) (Kennedy & Carpenter, as cited in Sec. 2.4).
+    ESDIRK3: the four-stage ESDIRK3(2)4L[2]SA scheme of Kennedy & Carpenter (the
+    implicit part of ARK3(2)4L[2]SA), the third-order scheme the paper cites.
+    """
+    if name == "esdirk2":
+        g = 1.0 - math.sqrt(2.0) / 2.0
+        b1 = math.sqrt(2.0) / 4.0
+        return np.array([[0.0, 0.0, 0.0], [g, g, 0.0], [b1, b1, g]])
+    if name == "esdirk3":
+        g = 1767732205903.0 / 4055673282236.0
+        a31 = 2746238789719.0 / 10658868560708.0
+        a32 = -640167445237.0 / 6845629431997.0
+        b = [1471266399579.0 / 7840856788654.0, -4482444167858.0 / 7529755066697.0,
+             11266239266428.0 / 11593286722821.0, g]
+        return np.array([[0.0, 0.0, 0.0, 0.0], [g, g, 0.0, 0.0],
+                         [a31, a32, g, 0.0], b])
+    raise ValueError(name)
+
+
+# ---- transfers (Sec. 3, eqs. (39), (42) restriction; (44), (45) prolongation) --------
+def restrict(x, Pf: int, Pc: int):
+    """Tensor-product L2 projection of a [Ne, (Pf+1)^2, Nv] field onto degree Pc."""
+    R1 = projection_1d(Pf, Pc)
+    ne, _, nv = x.shape
+    x4 = x.reshape(ne, Pf + 1, Pf + 1, nv)                  # [e, j, i, v]
+    y4 = np.einsum("bj,ai,ejiv->ebav", R1, R1, x4)
+    return y4.reshape(ne, (Pc + 1) ** 2, nv)
+
+
+def prolong(x, Pc: int, Pf: int):
+    """Tensor-product interpolation of a degree-Pc field at the degree-Pf points."""
+    I1 = interpolation_1d(Pc, Pf)
+    ne, _, nv = x.shape
+    x4 = x.reshape(ne, Pc + 1, Pc + 1, nv)
+    y4 = np.einsum("bj,ai,ejiv->ebav", I1, I1, x4)
+    return y4.reshape(ne, (Pf + 1) ** 2, nv)
+
+
+@dataclass
+class PMGOptions:
+    p_levels: tuple = (2, 1, 0)          # P{P0-P1-...}
+    n_smooth: tuple = (5, 10, 20)        # I{n0-n1-...}; pre = post, coarsest once
+    dtau_init: float = 0.01
+    dtau_max: float = 10.0
+    ser_exp: float = 1.5
+    refresh_every: int = 10
+    freeze_at_max: bool = True
+    tol: float = 1e-8
+    max_vcycles: int = 200
+    alpha_r: float = 1.0
+
+
+@dataclass
+class StageStats:
+    n_vcycles: int = 0
+    r0: float = 0.0
+    r_final: float = 0.0
+    history: list = field(default_factory=list)
+    dtau_history: list = field(default_factory=list)
+    refreshes: list = field(default_factory=list)
+    converged: bool = False
+
+
+class PMGSolver:
+    """The P-multigrid stage solver on one mesh."""
+
+    def __init__(self, mesh, gas: G.Gas, opts: PMGOptions, q_inf=None):
+        self.opts = opts
+        self.gas = gas
+        self.levels = [FRLevel(mesh, P, gas, q_inf) for P in opts.p_levels]
+        self.D = [None] * len(self.levels)
+        self.c_mass = 0.0
+        self.src = None
+        self.dtau = opts.dtau_init
+        self.refresh_now = False
+        self.dtau_last_refresh = None
+
+    # ---- level operators ---------------------------------------------------------
+    def F(self, l, q, S=None):
+        """F_l(q) - S_l on level l (only level 0 carries the ESDIRK source)."""
+        return self.levels[l].stage_residual(q, self.c_mass, self.src if l == 0 else None, S)
+
+    def build_D(self, l, q):
+        self.D[l] = element_blocks(self.levels[l], q, self.dtau, self.c_mass)
+
+    def smooth(self, l, q, S, nsweep):
+        """Element Jacobi, eq. (30): q <- q + alpha_r D^{-1} (F_l(q) - S_l), all elements at once."""
+        lev = self.levels[l]
+        for _ in range(nsweep):
+            Fq = self.F(l, q, S).reshape(lev.ne, lev.n, 1)
+            dq = np.linalg.solve(self.D[l], Fq)
+            q = q + self.opts.alpha_r * dq.reshape(q.shape)
+        return q
+
+    # ---- V-cycle (Sec. 3) --------------------------------------------------------
+    def vcycle(self, l, q, S):
+        o = self.opts
+        last = len(self.levels) - 1
+        if self.refresh_now and l > 0:
+            self.build_D(l, q)
+        q = self.smooth(l, q, S, o.n_smooth[l])           # q^a_l
+        if l == last:
+            return q
+        Pf, Pc = o.p_levels[l], o.p_levels[l + 1]
+        d = -self.F(l, q, S)                                # d_l = S_l - F_l(q^a), eqs. (38), (41)
+        qb = restrict(q, Pf, Pc)                            # q^b_{l+1}, eqs. (39), (42)
+        S1 = self.F(l + 1, qb) + restrict(d, Pf, Pc)        # S_{l+1}, eqs. (40), (43)
+        qa1 = self.vcycle(l + 1, qb, S1)
+        q = q + prolong(qa1 - qb, Pc, Pf)                   # q^{c,b}_l, eqs. (44), (45)
+        return self.smooth(l, q, S, o.n_smooth[l])          # q^{c,a}_l
+
+    def residual_norm(self, q):
+        return float(np.sqrt(np.sum(self.F(0, q) ** 2)))
+
+    # ---- pseudo-transient stage solve (Sec. 2.4, eqs. (27)-(31)) -----------------------
+    def stage_solve(self, q, c_mass=0.0, src=None, max_vcycles=None):
+        o = self.opts
+        self.c_mass = c_mass
+        self.src = src
+        st = StageStats()
+        nmax = o.max_vcycles if max_vcycles is None else max_vcycles
+        self.dtau_last_refresh = None
+        r_prev = None
+        for m in range(nmax + 1):
+            r = self.residual_norm(q)
+            st.history.append(r)
+            if m == 0:
+                st.r0 = r
+                self.dtau = o.dtau_init
+            else:
+                self.dtau = min(self.dtau * (r_prev / r) ** o.ser_exp, o.dtau_max)
+            st.r_final = r
+            if r == 0.0 or r / st.r0 <= o.tol:
+                st.converged = True
+                break
+            if m == nmax:
+                break
+            st.dtau_history.append(self.dtau)
+            frozen = (o.freeze_at_max and self.dtau_last_refresh is not None
+                      and self.dtau_last_refresh >= o.dtau_max)
+            self.refresh_now = m == 0 or (m % o.refresh_every == 0 and not frozen)
+            if self.refresh_now:
+                self.build_D(0, q)
+                self.dtau_last_refresh = self.dtau
+                st.refreshes.append(m)
+            q = self.vcycle(0, q, None)
+            st.n_vcycles = m + 1
+            r_prev = r
+        return q, st
+
+    # ---- ESDIRK step (eqs. (24)-(26)) -----------------------------------------------
+    def esdirk_step(self, q_n, dt, tableau: np.ndarray):
+        lev0 = self.levels[0]
+        A = tableau
+        s = A.shape[0]
+        omega = A[1, 1]
+        qc_n = G.conservative(q_n, self.gas)
+        Rs = [lev0.residual(q_n)]
+        q = q_n
+        stats = []
+        for i in range(1, s):
+            acc = qc_n.copy()
+            for j in range(i):
+                acc = acc + dt * A[i, j] * Rs[j]
+            src = acc / (omega * dt)
+            q, st = self.stage_solve(q, c_mass=1.0 / (omega * dt), src=src)
+            stats.append(st)
+            Rs.append(lev0.residual(q))
+        return q, stats

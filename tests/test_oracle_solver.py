@@ -1,0 +1,157 @@
+"""Pins of the oracle's smoother, transfers, FAS V-cycle, pseudo-time control and ESDIRK driver."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gas as G
+from oracle import solver as S
+from oracle.fr import FRLevel
+from oracle.jacobian import pseudo_time_blocks
+
+GAS = G.Gas(eps_mode="local")
+
+
+def _vortex(n=3, P=2, length=10.0, jitter=0.1):
+    mesh = W.periodic_quad_mesh(n, length, jitter=jitter, seed=5)
+    return mesh, W.VortexSpec(length=length)
+
+
+@pytest.mark.parametrize("Pf,Pc", [(2, 1), (3, 2), (3, 1), (4, 2), (1, 0)])
+def test_transfers_exact_on_tensor_polynomials(Pf, Pc):
+    mesh, _ = _vortex(2)
+    lf, lc = FRLevel(mesh, Pf, GAS), FRLevel(mesh, Pc, GAS)
+    xf = np.stack([lf.ops.x[np.arange(lf.npts) % lf.n1], lf.ops.x[np.arange(lf.npts) // lf.n1]], -1)
+    xc = np.stack([lc.ops.x[np.arange(lc.npts) % lc.n1], lc.ops.x[np.arange(lc.npts) // lc.n1]], -1)
+    for a in range(Pc + 1):
+        for b in range(Pc + 1):
+            uf = np.broadcast_to((xf[:, 0] ** a * xf[:, 1] ** b)[None, :, None], (lf.ne, lf.npts, 4))
+            uc = np.broadcast_to((xc[:, 0] ** a * xc[:, 1] ** b)[None, :, None], (lc.ne, lc.npts, 4))
+            assert np.max(np.abs(S.restrict(uf, Pf, Pc) - uc)) < 1e-13
+            assert np.max(np.abs(S.prolong(uc, Pc, Pf) - uf)) < 1e-13
+    rng = np.random.default_rng(0)
+    uc = rng.standard_normal((lc.ne, lc.npts, 4))
+    assert np.max(np.abs(S.restrict(S.prolong(uc, Pc, Pf), Pf, Pc) - uc)) < 1e-13
+
+
+def test_one_sweep_matches_dense_solve_of_fd_blocks():
+    """One element-Jacobi sweep (eq. (30)) against numpy.linalg.solve with the diagonal
+    blocks of a central-difference global Jacobian plus Gamma/dtau."""
+    mesh, vs = _vortex(3, 1)
+    opts = S.PMGOptions(p_levels=(1,), n_smooth=(1,), dtau_init=0.5)
+    sol = S.PMGSolver(mesh, GAS, opts)
+    lev = sol.levels[0]
+    q = vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1])
+    c_mass = 1.0 / (0.29 * 0.05)
+    sol.c_mass, sol.src, sol.dtau = c_mass, None, 0.5
+    sol.build_D(0, q)
+    q1 = sol.smooth(0, q, None, 1)
+    F = lev.stage_residual(q, c_mass)
+    Dfd = pseudo_time_blocks(lev, q, 0.5)
+    for e in range(lev.ne):
+        for c in range(lev.n):
+            p, v = divmod(c, 4)
+            h = 1e-4 * abs(q[e, p, v])
+            qp, qm = q.copy(), q.copy()
+            qp[e, p, v] += h
+            qm[e, p, v] -= h
+            Dfd[e, :, c] -= (lev.stage_residual(qp, c_mass)[e] - lev.stage_residual(qm, c_mass)[e]).ravel() / (2 * h)
+    dq = np.linalg.solve(Dfd, F.reshape(lev.ne, lev.n, 1)).reshape(q.shape)
+    err = np.linalg.norm((q1 - q) - dq, axis=(0, 1)) / np.linalg.norm(dq, axis=(0, 1))
+    assert np.all(err < 1e-5), err
+
+
+def test_fas_fixed_point():
+    """If q solves F_0(q) = S_0 exactly, a V-cycle leaves it unchanged (eqs. (38)-(45))."""
+    mesh, vs = _vortex(3)
+    opts = S.PMGOptions(p_levels=(2, 1, 0), n_smooth=(2, 2, 3), dtau_init=0.3)
+    sol = S.PMGSolver(mesh, GAS, opts)
+    lev = sol.levels[0]
+    q = vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1])
+    sol.c_mass, sol.src, sol.dtau = 20.0, None, 0.3
+    S0 = lev.stage_residual(q, 20.0)          # manufactured forcing: F_0(q) - S_0 = 0
+    sol.refresh_now = True
+    sol.build_D(0, q)
+    q1 = sol.vcycle(0, q, S0)
+    dist = q - vs.freestream()
+    assert np.all(np.linalg.norm(q1 - q, axis=(0, 1)) <= 1e-12 * np.linalg.norm(dist, axis=(0, 1)))
+
+
+def test_vcycle_reduces_stage_residual():
+    mesh, vs = W.vortex_config1()
+    opts = S.PMGOptions(p_levels=(2, 1, 0), n_smooth=(5, 10, 20), max_vcycles=8)
+    sol = S.PMGSolver(mesh, GAS, opts)
+    lev = sol.levels[0]
+    q = vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1])
+    A = S.esdirk_tableau("esdirk2")
+    dt = 0.05
+    src = (G.conservative(q, GAS) + dt * A[1, 0] * lev.residual(q)) / (A[1, 1] * dt)
+    _, st = sol.stage_solve(q, 1.0 / (A[1, 1] * dt), src, max_vcycles=8)
+    h = np.array(st.history)
+    assert h[-1] / h[0] < 0.05
+    assert st.dtau_history[1] > st.dtau_history[0]      # SER grows dtau while r falls
+    assert st.refreshes == [0]
+
+
+@pytest.mark.parametrize("name,order", [("esdirk2", 2), ("esdirk3", 3)])
+def test_esdirk_tableau_order_and_l_stability(name, order):
+    A = S.esdirk_tableau(name)
+    b, c = A[-1], A.sum(axis=1)
+    assert A[0, 0] == 0.0 and np.all(np.diag(A)[1:] == A[1, 1])
+    assert abs(b.sum() - 1) < 1e-15 and abs(b @ c - 0.5) < 1e-15
+    if order >= 3:
+        assert abs(b @ c ** 2 - 1 / 3) < 1e-14 and abs(b @ (A @ c) - 1 / 6) < 1e-14
+    else:
+        assert abs(b @ c ** 2 - 1 / 3) > 1e-3
+    # stability function R(z) = 1 + z b^T (I - zA)^{-1} 1 -> 0 as z -> -inf (L-stable, stiffly accurate)
+    z = -1e8
+    Rz = 1 + z * b @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b)))
+    assert abs(Rz) < 1e-6
+
+
+def _newton_stage(lev, q, c_mass, src, tol=1e-12):
+    """Exact stage solve by Newton's method with the dense complex-step global Jacobian."""
+    n = q.size
+    for _ in range(20):
+        F = lev.stage_residual(q, c_mass, src)
+        if np.linalg.norm(F) < tol * 1e3:
+            break
+        J = np.zeros((n, n))
+        for k in range(n):
+            qc = q.astype(complex).ravel()
+            qc[k] += 1e-30j
+            J[:, k] = lev.stage_residual(qc.reshape(q.shape), c_mass, src).imag.ravel() / 1e-30
+        q = q - np.linalg.solve(J, F.ravel()).reshape(q.shape)
+    return q
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,order", [("esdirk2", 2), ("esdirk3", 3)])
+def test_esdirk_driver_temporal_order(name, order):
+    """Self-convergence in dt of the ESDIRK source construction (eq. (26)) with exact stage solves."""
+    mesh = W.periodic_quad_mesh(2, 10.0)
+    vs = W.VortexSpec(length=10.0, ma_inf=0.3)
+    lev = FRLevel(mesh, 1, GAS)
+    A = S.esdirk_tableau(name)
+    om = A[1, 1]
+    q0 = vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1])
+    T_end = 0.4
+    sols = []
+    for nsteps in (4, 8, 16):
+        dt = T_end / nsteps
+        q = q0.copy()
+        for _ in range(nsteps):
+            qc_n = G.conservative(q, GAS)
+            Rs = [lev.residual(q)]
+            qi = q
+            for i in range(1, A.shape[0]):
+                src = (qc_n + dt * sum(A[i, j] * Rs[j] for j in range(i))) / (om * dt)
+                qi = _newton_stage(lev, qi, 1 / (om * dt), src)
+                Rs.append(lev.residual(qi))
+            q = qi
+        sols.append(q)
+    e1 = np.linalg.norm(sols[0] - sols[1])
+    e2 = np.linalg.norm(sols[1] - sols[2])
+    rate = math.log2(e1 / e2)
+    assert abs(rate - order) < 0.2, rate

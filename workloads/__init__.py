@@ -1,0 +1,162 @@
+"""Seeded synthetic workloads shared by the CPU oracle, the tests and the benchmark.
+
+This module holds no arithmetic of the solver. It produces
+
+* meshes: element geometry nodes, face connectivity and boundary tags;
+* the closed-form isentropic vortex of the accuracy study (Sec. 4.1, eq. (46)),
+  as a pointwise function of physical coordinates and time.
+
+Both the oracle and the GPU path evaluate the vortex at their own solution
+points, which each side computes itself.
+
+Conventions
+-----------
+* Geometry nodes of an element are in tensor order, xi fastest:
+  node ``a + (g+1)*b`` sits at reference coordinates
+  ``(-1 + 2a/g, -1 + 2b/g)`` for geometry order ``g`` (1 = bilinear, 2 = 9-node).
+* Faces of a quad: 0 = (xi=-1), 1 = (xi=+1), 2 = (eta=-1), 3 = (eta=+1).
+* ``face_nbr[e, f] >= 0`` is the neighbour element; a negative value is a boundary
+  tag (``BC_SLIP_WALL``, ``BC_FAR_FIELD``).
+* ``face_nbr_face[e, f]`` is the neighbour's face index and ``face_orient[e, f]``
+  is 0 when flux point k meets the neighbour's flux point k, 1 when it meets
+  point ``P-k`` (reversed edge direction).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+BC_SLIP_WALL = -1
+BC_FAR_FIELD = -2
+
+JITTER_SEED = 20190811
+
+
+@dataclass
+class Mesh:
+    dim: int
+    geom_order: int
+    nodes: np.ndarray          # [Ne, (g+1)^d, d] float64
+    face_nbr: np.ndarray       # [Ne, 2d] int32
+    face_nbr_face: np.ndarray  # [Ne, 2d] int32
+    face_orient: np.ndarray    # [Ne, 2d] int32
+    name: str = ""
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n_elements(self) -> int:
+        return int(self.nodes.shape[0])
+
+
+def periodic_quad_mesh(n: int, length: float = 10.0, jitter: float = 0.0,
+                       seed: int = JITTER_SEED, origin: float | None = None) -> Mesh:
+    """Bilinear quads on the periodic square ``[origin, origin+length]^2``, n x n cells.
+
+    With ``jitter > 0`` every vertex is moved by independent ``U(-jitter*h, jitter*h)``
+    offsets in x and in y (``h = length/n``), drawn from ``numpy.random.default_rng(seed)``:
+    first the n x n array of x offsets, then the n x n array of y offsets, indexed
+    ``[i, j]`` with i the x index. Offsets belong to a periodic vertex class
+    (index mod n), so opposite sides of the box stay matched.
+    Elements are numbered ``e = i + n*j`` (x index fastest).
+    """
+    if origin is None:
+        origin = -0.5 * length
+    h = length / n
+    dx = np.zeros((n, n))
+    dy = np.zeros((n, n))
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        dx = rng.uniform(-jitter * h, jitter * h, size=(n, n))
+        dy = rng.uniform(-jitter * h, jitter * h, size=(n, n))
+    ne = n * n
+    nodes = np.zeros((ne, 4, 2))
+    nbr = np.zeros((ne, 4), np.int32)
+    nbf = np.zeros((ne, 4), np.int32)
+    ori = np.zeros((ne, 4), np.int32)
+    for j in range(n):
+        for i in range(n):
+            e = i + n * j
+            for b in range(2):
+                for a in range(2):
+                    vi, vj = i + a, j + b
+                    nodes[e, a + 2 * b, 0] = origin + vi * h + dx[vi % n, vj % n]
+                    nodes[e, a + 2 * b, 1] = origin + vj * h + dy[vi % n, vj % n]
+            nbr[e, 0] = (i - 1) % n + n * j
+            nbr[e, 1] = (i + 1) % n + n * j
+            nbr[e, 2] = i + n * ((j - 1) % n)
+            nbr[e, 3] = i + n * ((j + 1) % n)
+            nbf[e] = (1, 0, 3, 2)
+    return Mesh(2, 1, nodes, nbr, nbf, ori, name=f"periodic{n}x{n}",
+                info={"length": length, "origin": origin, "jitter": jitter,
+                      "seed": seed if jitter > 0 else None, "periodic": True})
+
+
+@dataclass
+class VortexSpec:
+    """Isentropic vortex of Sec. 4.1 (eq. (46)).
+
+    ``ma_ref`` names the speed the free-stream Mach number is referred to, which the
+    paper does not fix: ``"speed"`` uses |V_inf| (= sqrt(2) for u=v=1), ``"u"`` uses u_inf.
+    Gas constant R = 1 (so T = p/rho); this is the value for which the printed
+    temperature perturbation is the exact isentropic balance.
+    """
+    gamma: float = 1.4
+    rgas: float = 1.0
+    rho_inf: float = 1.0
+    u_inf: tuple = (1.0, 1.0)
+    ma_inf: float = 0.005
+    ma_ref: str = "speed"
+    alpha: float = 5.0
+    phi: float = 0.5
+    center: tuple = (0.0, 0.0)
+    length: float = 10.0       # periodic box length, used to pick the nearest image
+
+    @property
+    def c_inf(self) -> float:
+        ref = math.hypot(*self.u_inf) if self.ma_ref == "speed" else self.u_inf[0]
+        return ref / self.ma_inf
+
+    @property
+    def t_inf(self) -> float:
+        return self.c_inf ** 2 / (self.gamma * self.rgas)
+
+    @property
+    def p_inf(self) -> float:
+        return self.rho_inf * self.rgas * self.t_inf
+
+    def freestream(self) -> np.ndarray:
+        """Primitive free-stream state (p, u, v, T)."""
+        return np.array([self.p_inf, self.u_inf[0], self.u_inf[1], self.t_inf])
+
+    def state(self, x: np.ndarray, y: np.ndarray, t: float = 0.0) -> np.ndarray:
+        """Primitive state (p, u, v, T) of the vortex advected to time t, shape x.shape + (4,)."""
+        x = np.asarray(x, float)
+        y = np.asarray(y, float)
+        L = self.length
+        xr = x - self.center[0] - self.u_inf[0] * t
+        yr = y - self.center[1] - self.u_inf[1] * t
+        xr = xr - L * np.round(xr / L)
+        yr = yr - L * np.round(yr / L)
+        r2 = xr * xr + yr * yr
+        g = self.gamma
+        amp = self.alpha / (2.0 * math.pi)
+        ex = np.exp(self.phi * (1.0 - r2))
+        du = -amp * yr * ex
+        dv = amp * xr * ex
+        dT = -(self.alpha ** 2) * (g - 1.0) / (16.0 * self.phi * g * math.pi ** 2) * ex * ex
+        T = self.t_inf + dT
+        rho = self.rho_inf * (T / self.t_inf) ** (1.0 / (g - 1.0))
+        p = rho * self.rgas * T
+        return np.stack([p, self.u_inf[0] + du, self.u_inf[1] + dv, T], axis=-1)
+
+
+def vortex_config1() -> tuple[Mesh, VortexSpec]:
+    """8x8 uniform periodic quads on [-5,5]^2 (the small parity case)."""
+    return periodic_quad_mesh(8, 10.0), VortexSpec(length=10.0)
+
+
+def vortex_config2() -> tuple[Mesh, VortexSpec]:
+    """64x64 periodic quads on [-5,5]^2, vertices jittered by +-10% of the cell size."""
+    return periodic_quad_mesh(64, 10.0, jitter=0.1, seed=JITTER_SEED), VortexSpec(length=10.0)
