@@ -1,0 +1,222 @@
+/*
+ * pmgfr — P-multigrid FR/CPR stage solver for locally preconditioned low-Mach flow on MI355X.
+ *
+ * C ABI of the hot path of Wang & Yu, "An implicit P-multigrid flux reconstruction method for
+ * simulation of locally preconditioned unsteady Navier-Stokes equations at low Mach numbers"
+ * (arXiv 1908.03972): one pseudo-transient ESDIRK stage solve by FAS V-cycles whose smoother is
+ * element Jacobi with dense element blocks.
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ * - Every function returns a pmg_status. PMG_OK is 0; on failure a message is available from
+ *   pmg_last_error() (thread-local, valid until the next failing call on the same thread).
+ *   Argument checks are synchronous and leave all outputs untouched.
+ * - "device" pointers are HIP device allocations on the level's device; "host" pointers are
+ *   ordinary CPU memory. The library never frees caller memory.
+ * - A state field on a level is double[Nv][Np][Ne] (element index fastest, for coalesced access),
+ *   with Nv = 4 primitive variables (p, u, v, T), Np = (P+1)^2 solution points numbered
+ *   p = i + (P+1) j (i along xi), Ne elements. Sizes below are in elements of that layout.
+ * - `stream` is a hipStream_t (passed as void*). Work is enqueued on it asynchronously unless a
+ *   function says it synchronises. Entry points are not re-entrant on the same handle: calls that
+ *   share a level or factor handle must be ordered on one stream.
+ * - Device-side faults (a zero pivot, a non-finite value) raise a per-level flag that
+ *   pmg_level_status() reads and clears; esdirk_stage_solve() checks it itself.
+ * - Hot calls allocate nothing: every workspace is created with its level.
+ */
+#ifndef PMGFR_H
+#define PMGFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pmg_status;
+#define PMG_OK 0
+#define PMG_E_ARG (-1)          /* invalid argument (null handle, bad enum, bad size)        */
+#define PMG_E_SHAPE (-2)        /* levels or sizes that do not fit together                   */
+#define PMG_E_HIP (-3)          /* a HIP runtime call failed                                  */
+#define PMG_E_SINGULAR (-4)     /* a zero pivot in an element block                           */
+#define PMG_E_NONFINITE (-5)    /* a NaN or Inf in a residual norm                            */
+#define PMG_E_NOT_CONVERGED (-6)/* the stage solve hit max_vcycles                            */
+#define PMG_E_NOMEM (-7)        /* device allocation failed at level or factor creation       */
+
+#define PMG_BC_SLIP_WALL (-1)   /* face_nbr tag: slip wall, ghost (p, u - 2(u.n)n, T)         */
+#define PMG_BC_FAR_FIELD (-2)   /* face_nbr tag: far field, ghost = q_inf                     */
+
+typedef struct pmg_level_s* pmg_level;
+typedef struct pmg_factors_s* pmg_factors;
+
+/* Thread-local text of the last error, or "" if none. The pointer stays owned by the library. */
+const char* pmg_last_error(void);
+
+/* Version of this ABI (major * 100 + minor). */
+int32_t pmg_abi_version(void);
+
+/*
+ * One P-level of a mesh (Sec. 2.3: FR/CPR on quadrilaterals with tensor-product corrections).
+ * All arrays are host memory and are deep-copied; the descriptor may be freed after the call.
+ *   dim          2 (quadrilaterals). 3 is reserved and rejected with PMG_E_ARG.
+ *   P            solution degree, 0..6 (element blocks need P <= 4).
+ *   geom_order   1 (bilinear, 4 nodes) or 2 (biquadratic, 9 nodes).
+ *   nodes        [Ne][(g+1)^2][2] geometry nodes in tensor order, xi fastest, at reference
+ *                coordinates (-1 + 2a/g, -1 + 2b/g).
+ *   face_nbr     [Ne][4] neighbour element across faces (xi=-1, xi=+1, eta=-1, eta=+1), or a
+ *                negative PMG_BC_* tag.
+ *   face_nbr_face[Ne][4] the neighbour's face index (ignored for boundary faces).
+ *   face_orient  [Ne][4] 0 if flux point k meets the neighbour's point k, 1 if point P-k.
+ *   gamma, rgas  ratio of specific heats and gas constant (eqs. (1)-(6), ideal gas).
+ *   eps_mode     reference velocity U_r = eps c of eq. (11): 0 = eps = min(1, Ma) (cut-off
+ *                off), 1 = eps = min(1, max(kappa Ma_inf, Ma)).
+ *   q_inf        free-stream primitive state used by far-field faces.
+ *   device       HIP device ordinal on which the level lives.
+ */
+typedef struct {
+  int32_t dim;
+  int32_t P;
+  int32_t geom_order;
+  int32_t n_elements;
+  const double* nodes;
+  const int32_t* face_nbr;
+  const int32_t* face_nbr_face;
+  const int32_t* face_orient;
+  double gamma;
+  double rgas;
+  int32_t eps_mode;
+  double ma_inf;
+  double kappa;
+  double q_inf[5];
+  int32_t device;
+} pmg_level_desc;
+
+/* Create a level: computes the Gauss solution/flux points, the 1-D operators, the metrics from
+ * the exact element mapping, uploads them and allocates the level's workspace.
+ * Errors: PMG_E_ARG (bad descriptor), PMG_E_NOMEM, PMG_E_HIP. */
+pmg_status pmg_level_create(const pmg_level_desc* desc, pmg_level* out);
+pmg_status pmg_level_destroy(pmg_level L);
+
+/* info[0..7] = dim, P, Np, Nv, n (= Nv Np, the element block size), Ne, device, geom_order. */
+pmg_status pmg_level_info(pmg_level L, int32_t* info);
+
+/* Physical solution-point coordinates, host output double[2][Np][Ne] (x then y). */
+pmg_status pmg_level_points(pmg_level L, double* xy_host);
+
+/* Read and clear the level's device fault flags (synchronises the device).
+ * *flags bit 0: a zero/non-finite pivot was met; returns PMG_E_SINGULAR if set, else PMG_OK. */
+pmg_status pmg_level_status(pmg_level L, int32_t* flags);
+
+/* Storage for the element-Jacobi blocks of one level (Sec. 2.4, eq. (30)): the inverse of every
+ * element block D_e, kept as n x n per element in `precision` 64 (FP64) or 32 (FP32).
+ * Footprint: n * n * Ne * precision/8 bytes. */
+pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out);
+pmg_status pmg_factors_destroy(pmg_factors F);
+
+/*
+ * fr_residual — stage residual of eq. (26) with the FAS forcing of eqs. (34)-(36):
+ *   F = R(q) - c_mass * q_c(q) + src - S,
+ * R = -div f the FR/CPR residual of eq. (20) with the common flux of eq. (21), q_c the
+ * conservative variables, c_mass = 1/(omega dt) (0 for a steady problem, where F = R).
+ *   q    device, state layout, read.      src, S   device state layout or NULL (= 0).
+ *   F    device, state layout, written. May alias S (each entry is read before it is written);
+ *        must not alias q.
+ *   norms device double[Nv+1] or NULL: per-variable Euclidean norms of F and the norm over all
+ *        variables (deterministic two-pass reduction).
+ */
+pmg_status fr_residual(pmg_level L, const double* q, const double* src, const double* S, double c_mass,
+                       double* F, double* norms, void* stream);
+
+/* q_c = (rho, rho u, rho v, rho E) of a primitive state (Sec. 2.1). q, qc: device state layout. */
+pmg_status fr_conservative(pmg_level L, const double* q, double* qc, void* stream);
+
+/*
+ * fr_element_jacobian — element blocks of the pseudo-transient linearisation, eqs. (28)-(30):
+ *   D_e = Gamma(q)/dtau + c_mass M(q) - dR_e/dq_e,
+ * with the neighbours' states held fixed and the common flux differentiated exactly (its mean
+ * state, eigenvalues and preconditioner included). Each block is row-equilibrated by powers of 2
+ * and inverted by Gauss-Jordan elimination with partial pivoting in FP64; the inverse is stored
+ * in `fac` at the factor precision.
+ *   q      device state, read.   dtau > 0 (pass +inf for no pseudo-time term).
+ *   D_out  device double[Ne][n][n] row-major (row index p*Nv + v) or NULL: the unfactored blocks.
+ * A zero pivot sets the level's fault flag (see pmg_level_status).
+ */
+pmg_status fr_element_jacobian(pmg_level L, const double* q, double dtau, double c_mass, double* D_out,
+                               pmg_factors fac, void* stream);
+
+/*
+ * ejacobi_sweep — n_sweeps synchronous element-Jacobi sweeps, eq. (30):
+ *   q <- q + alpha_r D^{-1} (F(q) - S),   F as in fr_residual,
+ * every element using its neighbours' state from the previous sweep.
+ *   q        device state, read and written in place (the library ping-pongs internally).
+ *   fac      blocks built by fr_element_jacobian on the same level.
+ *   F_after  device state or NULL: F(q) - S at the final state (the negative FAS defect).
+ *   norms    device double[Nv+1] or NULL: norms of F(q) - S at the state the first sweep starts
+ *            from (of F_after when n_sweeps is 0).
+ */
+pmg_status ejacobi_sweep(pmg_level L, pmg_factors fac, double* q, const double* src, const double* S,
+                         double c_mass, int32_t n_sweeps, double alpha_r, double* F_after, double* norms,
+                         void* stream);
+
+/*
+ * pmg_restrict — x_c = P x_f: the L2 projection (in the reference element) of each element's
+ * degree-P_f polynomial onto degree P_c, applied per variable (Sec. 3, eqs. (39), (40)).
+ * pmg_prolong — x_f += I dx_c: interpolation of the degree-P_c polynomial at the degree-P_f
+ * points (eqs. (44), (45)).
+ * Both levels must be on the same mesh with P_c < P_f, else PMG_E_SHAPE. nvar in 1..Nv gives the
+ * leading variables of the state layout that are transferred.
+ */
+pmg_status pmg_restrict(pmg_level fine, pmg_level coarse, const double* x_f, double* x_c, int32_t nvar,
+                        void* stream);
+pmg_status pmg_prolong(pmg_level coarse, pmg_level fine, const double* dx_c, double* x_f, int32_t nvar,
+                       void* stream);
+
+/* Options of a stage solve (Secs. 2.4 and 3). */
+typedef struct {
+  int32_t n_levels;               /* 1..8: levels[0] is the finest, degrees strictly decreasing */
+  pmg_level* levels;              /* host array of level handles on one mesh                    */
+  pmg_factors* factors;           /* host array, one per level                                  */
+  const int32_t* n_smooth;        /* host array: I{n0-n1-...}; pre = post, coarsest once         */
+  double dtau_init;               /* pseudo time step at V-cycle 0                               */
+  double dtau_max;                /* SER cap                                                     */
+  double ser_exponent;            /* 1.5 in eq. (31)                                             */
+  int32_t refresh_every;          /* rebuild the blocks every k V-cycles (10 in Sec. 4.1)        */
+  int32_t freeze_at_max;          /* 1: no rebuild after one made with dtau = dtau_max          */
+  double tol_rel;                 /* stop when ||F(q^m)|| / ||F(q^0)|| <= tol_rel                */
+  int32_t max_vcycles;
+  double alpha_r;                 /* relaxation of eq. (30), 1 in the paper                      */
+} pmg_solve_opts;
+
+typedef struct {
+  int32_t n_vcycles;
+  int32_t n_refresh;
+  double r0;
+  double r_final;
+  double* history;                /* host array or NULL: r_m for m = 0..n_vcycles              */
+  int32_t history_capacity;
+  pmg_status status;
+} pmg_solve_stats;
+
+/*
+ * esdirk_stage_solve — solve the ESDIRK stage equation F(q) = 0 of eq. (26) by
+ * pseudo-transient continuation (eq. (27)) with one FAS V-cycle per pseudo step:
+ *   src = (q_c^n + dt sum_j a_row[j] R_prev[j]) / (omega dt),  c_mass = 1/(omega dt);
+ *   dt <= 0 selects a steady solve (F = R, no source).
+ * Per V-cycle m: r_m = ||F(q^m)||; dtau_m by the SER law of eq. (31); blocks rebuilt on every
+ * level when m % refresh_every == 0 (fine level from q^m, coarse levels from their restricted
+ * state); V-cycle of Sec. 3. Stops when r_m / r_0 <= tol_rel.
+ *   qc_n     device state: conservative variables of q^n (unused when steady).
+ *   R_prev   host array of n_prev device states R(q^j); a_row host double[n_prev].
+ *   q        device state, in: initial guess, out: stage solution.
+ *   R_out    device state or NULL: R(q_stage), for later stages.
+ * Synchronises the stream (it reads one norm per V-cycle). Returns PMG_E_NOT_CONVERGED when
+ * max_vcycles is reached, PMG_E_NONFINITE on a NaN norm, PMG_E_SINGULAR on a zero pivot.
+ */
+pmg_status esdirk_stage_solve(const pmg_solve_opts* opts, double omega, double dt, const double* qc_n,
+                              const double* const* R_prev, const double* a_row, int32_t n_prev, double* q,
+                              double* R_out, pmg_solve_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMGFR_H */

@@ -1,0 +1,193 @@
+"""Thin Python binding of the pmgfr C ABI: the same entry points, taking torch tensors for device
+memory and the current torch stream. It only marshals arguments; every computation runs in the
+HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Level:
+    """One P-level of a quadrilateral mesh (a ``pmg_level`` handle)."""
+
+    def __init__(self, mesh, P: int, *, gamma: float = 1.4, rgas: float = 1.0, eps_mode: int = 0,
+                 ma_inf: float = 0.0, kappa: float = 1.0, q_inf=None, device: int = 0):
+        lib = A.lib()
+        nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64)
+        nbr = np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)
+        nbf = np.ascontiguousarray(mesh.face_nbr_face, dtype=np.int32)
+        ori = np.ascontiguousarray(mesh.face_orient, dtype=np.int32)
+        d = A.LevelDesc()
+        d.dim, d.P, d.geom_order, d.n_elements = mesh.dim, P, mesh.geom_order, mesh.n_elements
+        d.nodes = nodes.ctypes.data_as(C.POINTER(C.c_double))
+        d.face_nbr = nbr.ctypes.data_as(C.POINTER(C.c_int32))
+        d.face_nbr_face = nbf.ctypes.data_as(C.POINTER(C.c_int32))
+        d.face_orient = ori.ctypes.data_as(C.POINTER(C.c_int32))
+        d.gamma, d.rgas, d.eps_mode, d.ma_inf, d.kappa = gamma, rgas, eps_mode, ma_inf, kappa
+        qi = np.zeros(5)
+        if q_inf is not None:
+            qi[:len(q_inf)] = q_inf
+        d.q_inf = (C.c_double * 5)(*qi)
+        d.device = device
+        h = A.pmg_level()
+        A.check(lib.pmg_level_create(C.byref(d), C.byref(h)), "pmg_level_create")
+        self.handle = h
+        info = (C.c_int32 * 8)()
+        A.check(lib.pmg_level_info(h, info), "pmg_level_info")
+        self.dim, self.P, self.np, self.nv, self.n, self.ne, self.device, self.geom_order = list(info)
+        self.shape = (self.nv, self.np, self.ne)
+        self.torch_device = torch.device("cuda", self.device)
+
+    def points(self) -> np.ndarray:
+        """Solution-point coordinates [2, Np, Ne]."""
+        out = np.empty((2, self.np, self.ne))
+        A.check(A.lib().pmg_level_points(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))),
+                "pmg_level_points")
+        return out
+
+    def new_state(self) -> torch.Tensor:
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.torch_device)
+
+    def status(self) -> int:
+        flags = C.c_int32(0)
+        A.check(A.lib().pmg_level_status(self.handle, C.byref(flags)), "pmg_level_status")
+        return flags.value
+
+    def check_state(self, t: torch.Tensor | None, name: str, allow_none: bool = True):
+        if t is None:
+            if allow_none:
+                return None
+            raise ValueError(f"{name} is required")
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.torch_device \
+                or tuple(t.shape) != self.shape:
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {self.shape} on "
+                             f"{self.torch_device}")
+        return C.c_void_p(t.data_ptr())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            A.lib().pmg_level_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Factors:
+    """Inverse element blocks of one level (a ``pmg_factors`` handle)."""
+
+    def __init__(self, level: Level, precision: int = 64):
+        h = A.pmg_factors()
+        A.check(A.lib().pmg_factors_create(level.handle, precision, C.byref(h)), "pmg_factors_create")
+        self.handle = h
+        self.level = level
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "handle", None):
+            A.lib().pmg_factors_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _norms_ptr(level: Level, norms):
+    if norms is None:
+        return None
+    if norms.dtype != torch.float64 or norms.numel() < level.nv + 1 or norms.device != level.torch_device:
+        raise ValueError("norms must be a float64 device tensor with Nv+1 entries")
+    return C.c_void_p(norms.data_ptr())
+
+
+def fr_residual(level: Level, q, F, src=None, S=None, c_mass: float = 0.0, norms=None, stream=None):
+    A.check(A.lib().fr_residual(level.handle, level.check_state(q, "q", False), level.check_state(src, "src"),
+                                level.check_state(S, "S"), c_mass, level.check_state(F, "F", False),
+                                _norms_ptr(level, norms), _stream(stream)), "fr_residual")
+
+
+def fr_conservative(level: Level, q, qc, stream=None):
+    A.check(A.lib().fr_conservative(level.handle, level.check_state(q, "q", False),
+                                    level.check_state(qc, "qc", False), _stream(stream)), "fr_conservative")
+
+
+def fr_element_jacobian(level: Level, q, dtau: float, c_mass: float, factors: Factors, D_out=None, stream=None):
+    dptr = None
+    if D_out is not None:
+        if D_out.dtype != torch.float64 or not D_out.is_contiguous() or D_out.numel() != level.ne * level.n ** 2:
+            raise ValueError("D_out must be a contiguous float64 tensor with Ne*n*n entries")
+        dptr = C.c_void_p(D_out.data_ptr())
+    A.check(A.lib().fr_element_jacobian(level.handle, level.check_state(q, "q", False), dtau, c_mass, dptr,
+                                        factors.handle, _stream(stream)), "fr_element_jacobian")
+
+
+def ejacobi_sweep(level: Level, factors: Factors, q, n_sweeps: int, src=None, S=None, c_mass: float = 0.0,
+                  alpha_r: float = 1.0, F_after=None, norms=None, stream=None):
+    A.check(A.lib().ejacobi_sweep(level.handle, factors.handle, level.check_state(q, "q", False),
+                                  level.check_state(src, "src"), level.check_state(S, "S"), c_mass, n_sweeps,
+                                  alpha_r, level.check_state(F_after, "F_after"), _norms_ptr(level, norms),
+                                  _stream(stream)), "ejacobi_sweep")
+
+
+def pmg_restrict(fine: Level, coarse: Level, x_f, x_c, nvar: int = 4, stream=None):
+    A.check(A.lib().pmg_restrict(fine.handle, coarse.handle, fine.check_state(x_f, "x_f", False),
+                                 coarse.check_state(x_c, "x_c", False), nvar, _stream(stream)), "pmg_restrict")
+
+
+def pmg_prolong(coarse: Level, fine: Level, dx_c, x_f, nvar: int = 4, stream=None):
+    A.check(A.lib().pmg_prolong(coarse.handle, fine.handle, coarse.check_state(dx_c, "dx_c", False),
+                                fine.check_state(x_f, "x_f", False), nvar, _stream(stream)), "pmg_prolong")
+
+
+class StageSolver:
+    """Holds the levels, factors and options of ``esdirk_stage_solve``."""
+
+    def __init__(self, levels, factors, n_smooth, *, dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5,
+                 refresh_every=10, freeze_at_max=True, tol_rel=1e-8, max_vcycles=200, alpha_r=1.0):
+        self.levels = list(levels)
+        self.factors = list(factors)
+        nl = len(self.levels)
+        self._lh = (A.pmg_level * nl)(*[lv.handle for lv in self.levels])
+        self._fh = (A.pmg_factors * nl)(*[f.handle for f in self.factors])
+        self._ns = (C.c_int32 * nl)(*n_smooth)
+        o = A.SolveOpts()
+        o.n_levels, o.levels, o.factors, o.n_smooth = nl, self._lh, self._fh, self._ns
+        o.dtau_init, o.dtau_max, o.ser_exponent = dtau_init, dtau_max, ser_exponent
+        o.refresh_every, o.freeze_at_max, o.tol_rel = refresh_every, int(freeze_at_max), tol_rel
+        o.max_vcycles, o.alpha_r = max_vcycles, alpha_r
+        self.opts = o
+
+    def solve(self, q, *, omega=0.0, dt=0.0, qc_n=None, R_prev=(), a_row=(), R_out=None, stream=None,
+              raise_on_error=True):
+        L0 = self.levels[0]
+        nprev = len(R_prev)
+        rp = (C.c_void_p * max(nprev, 1))(*[L0.check_state(r, "R_prev", False) for r in R_prev])
+        ar = (C.c_double * max(nprev, 1))(*a_row)
+        cap = self.opts.max_vcycles + 1
+        hist = (C.c_double * cap)()
+        st = A.SolveStats()
+        st.history = C.cast(hist, C.POINTER(C.c_double))
+        st.history_capacity = cap
+        status = A.lib().esdirk_stage_solve(C.byref(self.opts), omega, dt, L0.check_state(qc_n, "qc_n"), rp, ar,
+                                            nprev, L0.check_state(q, "q", False), L0.check_state(R_out, "R_out"),
+                                            C.byref(st), _stream(stream))
+        out = {"status": status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh, "r0": st.r0,
+               "r_final": st.r_final, "history": list(hist[:min(st.n_vcycles + 1, cap)])}
+        if raise_on_error:
+            A.check(status, "esdirk_stage_solve")
+        return out

@@ -1,0 +1,687 @@
+// Host side of the pmgfr C ABI: level setup (points, 1-D operators, metrics), argument checks,
+// kernel sequencing for the smoother and transfers, and the pseudo-transient stage solve with
+// FAS V-cycles (Secs. 2.4 and 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/pmgfr.h"
+#include "internal.hpp"
+
+using pmg::Ops1D;
+
+namespace {
+
+thread_local std::string g_error;
+
+pmg_status fail(pmg_status code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+pmg_status hip_fail(hipError_t err, const char* what) {
+  return fail(PMG_E_HIP, std::string(what) + ": " + hipGetErrorString(err));
+}
+
+#define PMG_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// ---- 1-D polynomial machinery --------------------------------------------------------------
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence and P'_{k+1} = P'_{k-1} + (2k+1) P_k.
+void legendre(int n, double x, double& pn, double& dpn) {
+  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+  if (n == 0) {
+    pn = 1.0;
+    dpn = 0.0;
+    return;
+  }
+  for (int k = 1; k < n; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+    const double d2 = d0 + (2.0 * k + 1.0) * p1;
+    p0 = p1;
+    p1 = p2;
+    d0 = d1;
+    d1 = d2;
+  }
+  pn = p1;
+  dpn = d1;
+}
+
+// Gauss-Legendre points (ascending) and weights by Newton's method on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double xi = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+    double pn = 0.0, dpn = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, xi, pn, dpn);
+      const double dx = pn / dpn;
+      xi -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    legendre(n, xi, pn, dpn);
+    x[n - 1 - k] = xi;
+    w[n - 1 - k] = 2.0 / ((1.0 - xi * xi) * dpn * dpn);
+  }
+}
+
+double lagrange(const std::vector<double>& nodes, int k, double x) {
+  double r = 1.0;
+  for (size_t m = 0; m < nodes.size(); ++m)
+    if ((int)m != k) r *= (x - nodes[m]) / (nodes[k] - nodes[m]);
+  return r;
+}
+
+double lagrange_deriv(const std::vector<double>& nodes, int k, double x) {
+  double s = 0.0;
+  for (size_t a = 0; a < nodes.size(); ++a) {
+    if ((int)a == k) continue;
+    double t = 1.0 / (nodes[k] - nodes[a]);
+    for (size_t m = 0; m < nodes.size(); ++m)
+      if ((int)m != k && m != a) t *= (x - nodes[m]) / (nodes[k] - nodes[m]);
+    s += t;
+  }
+  return s;
+}
+
+// Barycentric differentiation matrix D[i][k] = l_k'(x_i) on distinct nodes.
+void diff_matrix(const std::vector<double>& x, double* D) {
+  const int n = (int)x.size();
+  std::vector<double> c(n, 1.0);
+  for (int i = 0; i < n; ++i)
+    for (int m = 0; m < n; ++m)
+      if (m != i) c[i] *= (x[i] - x[m]);
+  for (int i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int k = 0; k < n; ++k) {
+      if (k == i) continue;
+      D[i * n + k] = (c[i] / c[k]) / (x[i] - x[k]);
+      diag += 1.0 / (x[i] - x[k]);
+    }
+    D[i * n + i] = diag;
+  }
+}
+
+// FR correction derivatives with g_R = (L_{P+1} + L_P)/2 (g_DG) and g_L(x) = g_R(-x).
+double radau_right_deriv(int P, double x) {
+  double a, da, b, db;
+  legendre(P + 1, x, a, da);
+  legendre(P, x, b, db);
+  return 0.5 * (da + db);
+}
+
+void build_ops(int P, Ops1D& o, std::vector<double>& x, std::vector<double>& w) {
+  const int n1 = P + 1;
+  gauss_legendre(n1, x, w);
+  std::memset(&o, 0, sizeof(o));
+  o.n1 = n1;
+  diff_matrix(x, o.D);
+  for (int k = 0; k < n1; ++k) {
+    o.lm[k] = lagrange(x, k, -1.0);
+    o.lp[k] = lagrange(x, k, 1.0);
+    o.gR[k] = radau_right_deriv(P, x[k]);
+    o.gL[k] = -radau_right_deriv(P, -x[k]);
+  }
+}
+
+// Restriction (L2 projection onto degree Pc) and prolongation (interpolation) 1-D matrices.
+void projection_matrix(const pmg_level_s& f, const pmg_level_s& c, std::vector<double>& R) {
+  const int nf = f.n1, nc = c.n1;
+  R.assign((size_t)nc * nf, 0.0);
+  for (int a = 0; a < nc; ++a)
+    for (int i = 0; i < nf; ++i) {
+      double s = 0.0;
+      for (int k = 0; k <= c.P; ++k) {
+        double la, dla, li, dli;
+        legendre(k, c.x1[a], la, dla);
+        legendre(k, f.x1[i], li, dli);
+        s += la * (2.0 * k + 1.0) * 0.5 * f.w1[i] * li;
+      }
+      R[a * nf + i] = s;
+    }
+}
+
+void interpolation_matrix(const pmg_level_s& c, const pmg_level_s& f, std::vector<double>& I) {
+  const int nf = f.n1, nc = c.n1;
+  I.assign((size_t)nf * nc, 0.0);
+  for (int i = 0; i < nf; ++i)
+    for (int a = 0; a < nc; ++a) I[i * nc + a] = lagrange(c.x1, a, f.x1[i]);
+}
+
+// ---- geometry --------------------------------------------------------------------------------
+struct MapEval {
+  double x, y, x_xi, x_eta, y_xi, y_eta;
+};
+
+MapEval map_at(const double* nodes, int g, double xi, double eta) {
+  std::vector<double> gn(g + 1);
+  for (int a = 0; a <= g; ++a) gn[a] = -1.0 + 2.0 * a / g;
+  MapEval m{0, 0, 0, 0, 0, 0};
+  for (int b = 0; b <= g; ++b)
+    for (int a = 0; a <= g; ++a) {
+      const double na = lagrange(gn, a, xi), nb = lagrange(gn, b, eta);
+      const double dna = lagrange_deriv(gn, a, xi), dnb = lagrange_deriv(gn, b, eta);
+      const double X = nodes[2 * (a + (g + 1) * b)], Y = nodes[2 * (a + (g + 1) * b) + 1];
+      m.x += na * nb * X;
+      m.y += na * nb * Y;
+      m.x_xi += dna * nb * X;
+      m.y_xi += dna * nb * Y;
+      m.x_eta += na * dnb * X;
+      m.y_eta += na * dnb * Y;
+    }
+  return m;
+}
+
+template <class T>
+pmg_status upload(T** dst, const std::vector<T>& src) {
+  hipError_t e = hipMalloc(dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return fail(PMG_E_NOMEM, "hipMalloc failed for level data");
+  e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy level data");
+  return PMG_OK;
+}
+
+pmg_status alloc_zero(double** dst, size_t n) {
+  hipError_t e = hipMalloc(dst, std::max<size_t>(n, 1) * sizeof(double));
+  if (e != hipSuccess) return fail(PMG_E_NOMEM, "hipMalloc failed for level workspace");
+  e = hipMemset(*dst, 0, std::max<size_t>(n, 1) * sizeof(double));
+  if (e != hipSuccess) return hip_fail(e, "hipMemset workspace");
+  return PMG_OK;
+}
+
+void free_level(pmg_level_s* L) {
+  if (!L) return;
+  void* ptrs[] = {L->met, L->fvec, L->nbr, L->nbf, L->ori, L->wq,    L->wF,
+                  L->wS,  L->wqb,  L->wql, L->wsrc, L->part, L->norms, L->flag};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete L;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+pmg_status check_level(pmg_level L) {
+  if (!L) return fail(PMG_E_ARG, "null level handle");
+  return PMG_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+const char* pmg_last_error(void) { return g_error.c_str(); }
+
+int32_t pmg_abi_version(void) { return 100; }
+
+pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
+  if (!d || !out) return fail(PMG_E_ARG, "null descriptor or output");
+  *out = nullptr;
+  if (d->dim != 2) return fail(PMG_E_ARG, "only dim = 2 (quadrilaterals) is supported");
+  if (d->P < 0 || d->P > 6) return fail(PMG_E_ARG, "P must be in 0..6");
+  if (d->geom_order != 1 && d->geom_order != 2) return fail(PMG_E_ARG, "geom_order must be 1 or 2");
+  if (d->n_elements <= 0) return fail(PMG_E_ARG, "n_elements must be positive");
+  if (!d->nodes || !d->face_nbr || !d->face_nbr_face || !d->face_orient)
+    return fail(PMG_E_ARG, "null mesh array");
+  if (!(d->gamma > 1.0) || !(d->rgas > 0.0)) return fail(PMG_E_ARG, "gamma must exceed 1 and rgas be positive");
+  if (d->eps_mode != 0 && d->eps_mode != 1) return fail(PMG_E_ARG, "eps_mode must be 0 or 1");
+  const int ne = d->n_elements;
+  for (int k = 0; k < 4 * ne; ++k) {
+    const int nb = d->face_nbr[k];
+    if (nb >= ne || nb < PMG_BC_FAR_FIELD) return fail(PMG_E_ARG, "face_nbr entry out of range");
+    if (nb >= 0 && (d->face_nbr_face[k] < 0 || d->face_nbr_face[k] > 3))
+      return fail(PMG_E_ARG, "face_nbr_face entry out of range");
+    if (d->face_orient[k] != 0 && d->face_orient[k] != 1) return fail(PMG_E_ARG, "face_orient must be 0 or 1");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || d->device < 0 || d->device >= ndev)
+    return fail(PMG_E_ARG, "invalid HIP device ordinal");
+  DeviceGuard guard(d->device);
+  if (!guard.ok) return fail(PMG_E_HIP, "hipSetDevice failed");
+
+  pmg_level_s* L = new pmg_level_s();
+  L->dim = 2;
+  L->P = d->P;
+  L->n1 = d->P + 1;
+  L->np = L->n1 * L->n1;
+  L->nv = 4;
+  L->n = L->nv * L->np;
+  L->ne = ne;
+  L->geom_order = d->geom_order;
+  L->device = d->device;
+  L->gas.gamma = d->gamma;
+  L->gas.rgas = d->rgas;
+  L->gas.cp = d->gamma * d->rgas / (d->gamma - 1.0);
+  L->gas.ma_inf = d->ma_inf;
+  L->gas.kappa = d->kappa;
+  L->gas.eps_mode = d->eps_mode;
+  for (int k = 0; k < 5; ++k) L->q_inf[k] = d->q_inf[k];
+  build_ops(d->P, L->ops, L->x1, L->w1);
+
+  // metrics from the exact mapping at solution and flux points
+  const int n1 = L->n1, np = L->np, g = d->geom_order, nn = (g + 1) * (g + 1);
+  std::vector<double> met((size_t)5 * np * ne), fvec((size_t)4 * n1 * 2 * ne);
+  L->xy_host.assign((size_t)2 * np * ne, 0.0);
+  for (int e = 0; e < ne; ++e) {
+    const double* nodes = d->nodes + (size_t)e * nn * 2;
+    for (int jj = 0; jj < n1; ++jj)
+      for (int ii = 0; ii < n1; ++ii) {
+        const int p = ii + n1 * jj;
+        const MapEval m = map_at(nodes, g, L->x1[ii], L->x1[jj]);
+        const double jac = m.x_xi * m.y_eta - m.x_eta * m.y_xi;
+        if (!(jac > 0.0)) {
+          free_level(L);
+          return fail(PMG_E_ARG, "non-positive mapping Jacobian in element " + std::to_string(e));
+        }
+        const size_t o = (size_t)p * ne + e, st = (size_t)np * ne;
+        met[o] = m.y_eta;
+        met[st + o] = -m.x_eta;
+        met[2 * st + o] = -m.y_xi;
+        met[3 * st + o] = m.x_xi;
+        met[4 * st + o] = 1.0 / jac;
+        L->xy_host[o] = m.x;
+        L->xy_host[st + o] = m.y;
+      }
+    for (int f = 0; f < 4; ++f)
+      for (int k = 0; k < n1; ++k) {
+        double xi, eta;
+        if (f < 2) {
+          xi = (f == 0) ? -1.0 : 1.0;
+          eta = L->x1[k];
+        } else {
+          xi = L->x1[k];
+          eta = (f == 2) ? -1.0 : 1.0;
+        }
+        const MapEval m = map_at(nodes, g, xi, eta);
+        const double vx = (f < 2) ? m.y_eta : -m.y_xi;
+        const double vy = (f < 2) ? -m.x_eta : m.x_xi;
+        const size_t o = ((size_t)(f * n1 + k) * 2) * ne + e;
+        fvec[o] = vx;
+        fvec[o + ne] = vy;
+      }
+  }
+  std::vector<int> nbr((size_t)4 * ne), nbf((size_t)4 * ne), ori((size_t)4 * ne);
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < 4; ++f) {
+      nbr[(size_t)f * ne + e] = d->face_nbr[4 * e + f];
+      nbf[(size_t)f * ne + e] = d->face_nbr_face[4 * e + f];
+      ori[(size_t)f * ne + e] = d->face_orient[4 * e + f];
+    }
+  pmg_status s = PMG_OK;
+  if ((s = upload(&L->met, met)) || (s = upload(&L->fvec, fvec)) || (s = upload(&L->nbr, nbr)) ||
+      (s = upload(&L->nbf, nbf)) || (s = upload(&L->ori, ori))) {
+    free_level(L);
+    return s;
+  }
+  const size_t ns = L->state_elems();
+  L->part_blocks = pmg::residual_blocks(*L);
+  if ((s = alloc_zero(&L->wq, ns)) || (s = alloc_zero(&L->wF, ns)) || (s = alloc_zero(&L->wS, ns)) ||
+      (s = alloc_zero(&L->wqb, ns)) || (s = alloc_zero(&L->wql, ns)) || (s = alloc_zero(&L->wsrc, ns)) ||
+      (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1))) {
+    free_level(L);
+    return s;
+  }
+  if (hipMalloc(&L->flag, sizeof(int)) != hipSuccess) {
+    free_level(L);
+    return fail(PMG_E_NOMEM, "hipMalloc failed for the fault flag");
+  }
+  if (hipMemset(L->flag, 0, sizeof(int)) != hipSuccess) {
+    free_level(L);
+    return fail(PMG_E_HIP, "hipMemset fault flag");
+  }
+  *out = L;
+  return PMG_OK;
+}
+
+pmg_status pmg_level_destroy(pmg_level L) {
+  if (!L) return PMG_OK;
+  DeviceGuard guard(L->device);
+  free_level(L);
+  return PMG_OK;
+}
+
+pmg_status pmg_level_info(pmg_level L, int32_t* info) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!info) return fail(PMG_E_ARG, "null info");
+  info[0] = L->dim;
+  info[1] = L->P;
+  info[2] = L->np;
+  info[3] = L->nv;
+  info[4] = L->n;
+  info[5] = L->ne;
+  info[6] = L->device;
+  info[7] = L->geom_order;
+  return PMG_OK;
+}
+
+pmg_status pmg_level_points(pmg_level L, double* xy_host) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!xy_host) return fail(PMG_E_ARG, "null output");
+  std::memcpy(xy_host, L->xy_host.data(), L->xy_host.size() * sizeof(double));
+  return PMG_OK;
+}
+
+pmg_status pmg_level_status(pmg_level L, int32_t* flags) {
+  if (pmg_status s = check_level(L)) return s;
+  DeviceGuard guard(L->device);
+  int h = 0;
+  PMG_HIP(hipDeviceSynchronize());
+  PMG_HIP(hipMemcpy(&h, L->flag, sizeof(int), hipMemcpyDeviceToHost));
+  PMG_HIP(hipMemset(L->flag, 0, sizeof(int)));
+  if (flags) *flags = h;
+  if (h & 1) return fail(PMG_E_SINGULAR, "zero or non-finite pivot in an element block");
+  return PMG_OK;
+}
+
+pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!out) return fail(PMG_E_ARG, "null output");
+  if (precision != 32 && precision != 64) return fail(PMG_E_ARG, "precision must be 32 or 64");
+  if (L->P > 4) return fail(PMG_E_ARG, "element blocks are supported for P <= 4");
+  DeviceGuard guard(L->device);
+  pmg_factors_s* F = new pmg_factors_s();
+  F->L = L;
+  F->precision = precision;
+  F->bytes = (size_t)L->n * L->n * L->ne * (precision / 8);
+  if (hipMalloc(&F->W, F->bytes) != hipSuccess) {
+    delete F;
+    return fail(PMG_E_NOMEM, "hipMalloc failed for element blocks");
+  }
+  if (hipMemset(F->W, 0, F->bytes) != hipSuccess) {
+    (void)hipFree(F->W);
+    delete F;
+    return fail(PMG_E_HIP, "hipMemset element blocks");
+  }
+  *out = F;
+  return PMG_OK;
+}
+
+pmg_status pmg_factors_destroy(pmg_factors F) {
+  if (!F) return PMG_OK;
+  DeviceGuard guard(F->L->device);
+  if (F->W) (void)hipFree(F->W);
+  delete F;
+  return PMG_OK;
+}
+
+pmg_status fr_residual(pmg_level L, const double* q, const double* src, const double* S, double c_mass, double* F,
+                       double* norms, void* stream) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!q || !F) return fail(PMG_E_ARG, "null q or F");
+  if (F == q) return fail(PMG_E_ARG, "F must not alias q");
+  DeviceGuard guard(L->device);
+  hipStream_t st = as_stream(stream);
+  PMG_HIP(pmg::launch_residual(*L, q, src, S, c_mass, F, norms != nullptr, st));
+  if (norms) {
+    PMG_HIP(pmg::launch_norm_finalize(*L, st));
+    if (norms != L->norms)
+      PMG_HIP(hipMemcpyAsync(norms, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  return PMG_OK;
+}
+
+pmg_status fr_conservative(pmg_level L, const double* q, double* qc, void* stream) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!q || !qc) return fail(PMG_E_ARG, "null pointer");
+  DeviceGuard guard(L->device);
+  PMG_HIP(pmg::launch_conservative(*L, q, qc, as_stream(stream)));
+  return PMG_OK;
+}
+
+pmg_status fr_element_jacobian(pmg_level L, const double* q, double dtau, double c_mass, double* D_out,
+                               pmg_factors fac, void* stream) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!q || !fac) return fail(PMG_E_ARG, "null q or factors");
+  if (fac->L != L) return fail(PMG_E_SHAPE, "factors belong to another level");
+  if (!(dtau > 0.0)) return fail(PMG_E_ARG, "dtau must be positive");
+  DeviceGuard guard(L->device);
+  PMG_HIP(pmg::launch_jacobian(*L, q, dtau, c_mass, D_out, *fac, as_stream(stream)));
+  return PMG_OK;
+}
+
+pmg_status ejacobi_sweep(pmg_level L, pmg_factors fac, double* q, const double* src, const double* S,
+                         double c_mass, int32_t n_sweeps, double alpha_r, double* F_after, double* norms,
+                         void* stream) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!q || !fac) return fail(PMG_E_ARG, "null q or factors");
+  if (fac->L != L) return fail(PMG_E_SHAPE, "factors belong to another level");
+  if (n_sweeps < 0) return fail(PMG_E_ARG, "n_sweeps must be >= 0");
+  if (F_after == q) return fail(PMG_E_ARG, "F_after must not alias q");
+  DeviceGuard guard(L->device);
+  hipStream_t st = as_stream(stream);
+  double* in = q;
+  double* out = L->wq;
+  for (int s = 0; s < n_sweeps; ++s) {
+    const bool nrm = (s == 0) && norms;
+    PMG_HIP(pmg::launch_sweep(*L, *fac, in, out, src, S, c_mass, alpha_r, nrm, st));
+    if (nrm) {
+      PMG_HIP(pmg::launch_norm_finalize(*L, st));
+      if (norms != L->norms)
+        PMG_HIP(hipMemcpyAsync(norms, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    std::swap(in, out);
+  }
+  if (in != q) PMG_HIP(hipMemcpyAsync(q, in, L->state_elems() * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (F_after) {
+    const bool nrm = (n_sweeps == 0) && norms;
+    PMG_HIP(pmg::launch_residual(*L, q, src, S, c_mass, F_after, nrm, st));
+    if (nrm) {
+      PMG_HIP(pmg::launch_norm_finalize(*L, st));
+      if (norms != L->norms)
+        PMG_HIP(hipMemcpyAsync(norms, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+  }
+  return PMG_OK;
+}
+
+static pmg_status check_pair(pmg_level fine, pmg_level coarse, int32_t nvar) {
+  if (!fine || !coarse) return fail(PMG_E_ARG, "null level");
+  if (fine->ne != coarse->ne || fine->dim != coarse->dim || fine->device != coarse->device)
+    return fail(PMG_E_SHAPE, "levels are not on the same mesh and device");
+  if (!(coarse->P < fine->P)) return fail(PMG_E_SHAPE, "coarse degree must be below the fine degree");
+  if (nvar < 1 || nvar > fine->nv) return fail(PMG_E_ARG, "nvar out of range");
+  return PMG_OK;
+}
+
+pmg_status pmg_restrict(pmg_level fine, pmg_level coarse, const double* x_f, double* x_c, int32_t nvar,
+                        void* stream) {
+  if (pmg_status s = check_pair(fine, coarse, nvar)) return s;
+  if (!x_f || !x_c) return fail(PMG_E_ARG, "null pointer");
+  DeviceGuard guard(fine->device);
+  std::vector<double> R;
+  projection_matrix(*fine, *coarse, R);
+  PMG_HIP(pmg::launch_restrict(*fine, *coarse, R.data(), x_f, x_c, nvar, as_stream(stream)));
+  return PMG_OK;
+}
+
+pmg_status pmg_prolong(pmg_level coarse, pmg_level fine, const double* dx_c, double* x_f, int32_t nvar,
+                       void* stream) {
+  if (pmg_status s = check_pair(fine, coarse, nvar)) return s;
+  if (!dx_c || !x_f) return fail(PMG_E_ARG, "null pointer");
+  DeviceGuard guard(fine->device);
+  std::vector<double> I;
+  interpolation_matrix(*coarse, *fine, I);
+  PMG_HIP(pmg::launch_prolong(*coarse, *fine, I.data(), dx_c, nullptr, x_f, nvar, as_stream(stream)));
+  return PMG_OK;
+}
+
+}  // extern "C"
+
+// ---- stage solve -------------------------------------------------------------------------------
+namespace {
+
+struct Solve {
+  const pmg_solve_opts* o;
+  hipStream_t st;
+  double c_mass;
+  const double* src;       // finest-level source, or null
+  double dtau;
+  bool refresh;
+  int n_refresh;
+  std::vector<std::vector<double>> R1, I1;   // per level l: matrices between l and l+1
+};
+
+pmg_status vcycle(Solve& s, int l, double* q, const double* S) {
+  const pmg_solve_opts* o = s.o;
+  pmg_level L = o->levels[l];
+  pmg_factors fac = o->factors[l];
+  const bool last = (l == o->n_levels - 1);
+  const double* src = (l == 0) ? s.src : nullptr;
+  if (s.refresh && l > 0) {
+    PMG_HIP(pmg::launch_jacobian(*L, q, s.dtau, s.c_mass, nullptr, *fac, s.st));
+    ++s.n_refresh;
+  }
+  // pre-smoothing; F_after = F_l(q^a) - S_l = -d_l
+  if (pmg_status r = ejacobi_sweep(L, fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r,
+                                   last ? nullptr : L->wF, nullptr, s.st))
+    return r;
+  if (last) return PMG_OK;
+  pmg_level Lc = o->levels[l + 1];
+  // q^b_{l+1} = P q^a_l (eqs. (39), (42)); the coarse working state starts there
+  PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), q, Lc->wqb, Lc->nv, s.st));
+  PMG_HIP(hipMemcpyAsync(Lc->wql, Lc->wqb, Lc->state_elems() * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+  // S_{l+1} = F_{l+1}(q^b) + P d_l = F_{l+1}(q^b) - P (F_l(q^a) - S_l)  (eqs. (40), (43))
+  PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), L->wF, Lc->wS, Lc->nv, s.st));
+  PMG_HIP(pmg::launch_residual(*Lc, Lc->wqb, nullptr, Lc->wS, s.c_mass, Lc->wS, false, s.st));
+  if (pmg_status r = vcycle(s, l + 1, Lc->wql, Lc->wS)) return r;
+  // q^{c,b}_l = q^a_l + I (q^{(c,)a}_{l+1} - q^b_{l+1}) (eqs. (44), (45)), then post-smoothing
+  PMG_HIP(pmg::launch_prolong(*Lc, *L, s.I1[l].data(), Lc->wql, Lc->wqb, q, L->nv, s.st));
+  return ejacobi_sweep(L, fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r, nullptr, nullptr, s.st);
+}
+
+pmg_status read_norm(pmg_level L, hipStream_t st, double& r) {
+  double h[8];
+  PMG_HIP(hipMemcpyAsync(h, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+  PMG_HIP(hipStreamSynchronize(st));
+  r = h[L->nv];
+  return PMG_OK;
+}
+
+}  // namespace
+
+extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, double dt, const double* qc_n,
+                                         const double* const* R_prev, const double* a_row, int32_t n_prev,
+                                         double* q, double* R_out, pmg_solve_stats* stats, void* stream) {
+  if (!o || !q) return fail(PMG_E_ARG, "null options or q");
+  if (o->n_levels < 1 || o->n_levels > 8 || !o->levels || !o->factors || !o->n_smooth)
+    return fail(PMG_E_ARG, "bad level list");
+  for (int l = 0; l < o->n_levels; ++l) {
+    if (!o->levels[l] || !o->factors[l]) return fail(PMG_E_ARG, "null level or factors");
+    if (o->factors[l]->L != o->levels[l]) return fail(PMG_E_SHAPE, "factors do not match their level");
+    if (o->n_smooth[l] < 0) return fail(PMG_E_ARG, "negative smoothing count");
+    if (l > 0 && (o->levels[l]->P >= o->levels[l - 1]->P || o->levels[l]->ne != o->levels[0]->ne ||
+                  o->levels[l]->device != o->levels[0]->device))
+      return fail(PMG_E_SHAPE, "levels must share the mesh with strictly decreasing P");
+  }
+  if (!(o->dtau_init > 0.0) || !(o->dtau_max >= o->dtau_init)) return fail(PMG_E_ARG, "bad dtau range");
+  if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
+  const bool steady = !(dt > 0.0);
+  if (!steady) {
+    if (!(omega > 0.0)) return fail(PMG_E_ARG, "omega must be positive");
+    if (!qc_n || n_prev < 1 || n_prev > 8 || !R_prev || !a_row) return fail(PMG_E_ARG, "bad ESDIRK history");
+  }
+  pmg_level L0 = o->levels[0];
+  DeviceGuard guard(L0->device);
+  Solve s;
+  s.o = o;
+  s.st = as_stream(stream);
+  s.c_mass = steady ? 0.0 : 1.0 / (omega * dt);
+  s.src = nullptr;
+  s.refresh = false;
+  s.n_refresh = 0;
+  s.R1.resize(o->n_levels);
+  s.I1.resize(o->n_levels);
+  for (int l = 0; l + 1 < o->n_levels; ++l) {
+    projection_matrix(*o->levels[l], *o->levels[l + 1], s.R1[l]);
+    interpolation_matrix(*o->levels[l + 1], *o->levels[l], s.I1[l]);
+  }
+  if (!steady) {
+    PMG_HIP(pmg::launch_stage_source(*L0, qc_n, R_prev, a_row, n_prev, dt, s.c_mass, L0->wsrc, s.st));
+    s.src = L0->wsrc;
+  }
+  for (int l = 0; l < o->n_levels; ++l) PMG_HIP(hipMemsetAsync(o->levels[l]->flag, 0, sizeof(int), s.st));
+
+  double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
+  int m = 0;
+  pmg_status result = PMG_E_NOT_CONVERGED;
+  s.dtau = o->dtau_init;
+  if (stats) stats->n_refresh = 0;
+  for (m = 0;; ++m) {
+    // r_m = ||F(q^m)|| on the finest level
+    PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, s.st));
+    PMG_HIP(pmg::launch_norm_finalize(*L0, s.st));
+    if (pmg_status e = read_norm(L0, s.st, r)) return e;
+    if (stats && stats->history && m < stats->history_capacity) stats->history[m] = r;
+    if (!std::isfinite(r)) {
+      result = fail(PMG_E_NONFINITE, "non-finite residual norm");
+      break;
+    }
+    if (m == 0) {
+      r0 = r;
+    } else {
+      s.dtau = std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), o->dtau_max);   // eq. (31)
+    }
+    if (r == 0.0 || r / r0 <= o->tol_rel) {
+      result = PMG_OK;
+      break;
+    }
+    if (m >= o->max_vcycles) {
+      result = fail(PMG_E_NOT_CONVERGED, "stage solve reached max_vcycles");
+      break;
+    }
+    const bool frozen = o->freeze_at_max && dtau_last_refresh >= o->dtau_max;
+    s.refresh = (m == 0) || (m % o->refresh_every == 0 && !frozen);
+    if (s.refresh) {
+      PMG_HIP(pmg::launch_jacobian(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
+      ++s.n_refresh;
+      dtau_last_refresh = s.dtau;
+    }
+    if (pmg_status e = vcycle(s, 0, q, nullptr)) return e;
+    r_prev = r;
+  }
+  if (result != PMG_E_NONFINITE) {
+    int h = 0;
+    PMG_HIP(hipMemcpyAsync(&h, L0->flag, sizeof(int), hipMemcpyDeviceToHost, s.st));
+    for (int l = 1; l < o->n_levels; ++l) {
+      int hl = 0;
+      PMG_HIP(hipMemcpyAsync(&hl, o->levels[l]->flag, sizeof(int), hipMemcpyDeviceToHost, s.st));
+      PMG_HIP(hipStreamSynchronize(s.st));
+      h |= hl;
+    }
+    PMG_HIP(hipStreamSynchronize(s.st));
+    if (h & 1) result = fail(PMG_E_SINGULAR, "zero or non-finite pivot in an element block");
+  }
+  if (R_out && result == PMG_OK)
+    PMG_HIP(pmg::launch_residual(*L0, q, nullptr, nullptr, 0.0, R_out, false, s.st));
+  if (stats) {
+    stats->n_vcycles = m;
+    stats->n_refresh = s.n_refresh;
+    stats->r0 = r0;
+    stats->r_final = r;
+    stats->status = result;
+  }
+  PMG_HIP(hipStreamSynchronize(s.st));
+  return result;
+}

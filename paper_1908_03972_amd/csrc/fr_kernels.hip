@@ -1,0 +1,345 @@
+// FR/CPR residual and fused element-Jacobi sweep kernels (2-D quadrilaterals).
+//
+// One workgroup owns EPW elements; thread (p, el) owns solution point p of element el, so that
+// loads of the [Nv][Np][Ne] state are coalesced over consecutive elements. Per workgroup:
+//   1. point states and transformed fluxes F~ = f.S, G~ = f.T go to LDS;
+//   2. each element's 4(P+1) flux points: own trace (extrapolated along the tensor line), the
+//      neighbour's trace (extrapolated from the neighbour's state) or a boundary ghost, the
+//      common flux of eq. (21) and its jump against the interpolated local flux;
+//   3. R = -(1/|J|)[line derivatives + g_L'/g_R' corrections] (eq. (20)), F = R - c q_c + src - S.
+// The sweep variant then multiplies F by the element's stored inverse block (eq. (30)), with the
+// workgroup re-mapped element-major so that the n x n block stream is read fully coalesced, and
+// writes q + alpha D^{-1} F to a second buffer (synchronous Jacobi: neighbours are read from the
+// input buffer only).
+#include "internal.hpp"
+
+namespace pmg {
+
+template <int P>
+struct Cfg {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = N1 * N1;
+  static constexpr int NV = 4;
+  static constexpr int N = NV * NP;
+  static constexpr int EPW = (256 / NP) > 0 ? (256 / NP) : 1;
+  static constexpr int NACT = EPW * NP;
+  static constexpr int NT = ((NACT + 63) / 64) * 64;
+  static constexpr int NW = NT / 64;
+};
+
+struct ResArgs {
+  LevelView lv;
+  Ops1D ops;
+  GasParams gas;
+  const double* q;
+  const double* src;
+  const double* S;
+  double c_mass;
+  double* F;
+  double* part;
+  const void* W;
+  double alpha;
+  double* q_out;
+};
+
+// MODE 0: residual only; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
+template <int P, int MODE>
+__global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
+  using C = Cfg<P>;
+  constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, EPW = C::EPW;
+  __shared__ double s_q[NV * NP * EPW];
+  __shared__ double s_f[NV * NP * EPW];
+  __shared__ double s_g[NV * NP * EPW];
+  __shared__ double s_j[4 * N1 * NV * EPW];
+  __shared__ double s_red[C::NW * NV];
+
+  const int ne = a.lv.ne;
+  const int tid = threadIdx.x;
+  const bool act = tid < C::NACT;
+  const int el = tid % EPW;
+  const int p = act ? tid / EPW : 0;
+  const int e = blockIdx.x * EPW + el;
+  const bool valid = act && e < ne;
+  const int i = p % N1, j = p / N1;
+  const Ops1D& o = a.ops;
+  const size_t sstride = (size_t)NP * ne;   // stride between variables in the state layout
+
+#define SQ(v, pp, ee) s_q[((v) * NP + (pp)) * EPW + (ee)]
+#define SF(v, pp, ee) s_f[((v) * NP + (pp)) * EPW + (ee)]
+#define SG(v, pp, ee) s_g[((v) * NP + (pp)) * EPW + (ee)]
+#define SJ(f, k, v, ee) s_j[(((f) * N1 + (k)) * NV + (v)) * EPW + (ee)]
+
+  const size_t gp = (size_t)p * ne + e;     // offset of (v=0, p, e)
+  double qv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qv[v] = valid ? a.q[v * sstride + gp] : a.lv.q_inf[v];
+
+  double ij = 0.0;
+  {
+    double sx = 1.0, sy = 0.0, tx = 0.0, ty = 1.0;
+    if (valid) {
+      const double* m = a.lv.met;
+      sx = m[gp];
+      sy = m[sstride + gp];
+      tx = m[2 * sstride + gp];
+      ty = m[3 * sstride + gp];
+      ij = m[4 * sstride + gp];
+    }
+    double fs[NV], ft[NV];
+    normal_flux2(qv, sx, sy, a.gas, fs);
+    normal_flux2(qv, tx, ty, a.gas, ft);
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        SQ(v, p, el) = qv[v];
+        SF(v, p, el) = fs[v];
+        SG(v, p, el) = ft[v];
+      }
+    }
+  }
+  __syncthreads();
+
+  if (act) {
+    for (int t = p; t < 4 * N1; t += NP) {
+      const int f = t / N1, k = t % N1;
+      const double* w = (f == 0 || f == 2) ? o.lm : o.lp;
+      double own[NV], floc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        own[v] = 0.0;
+        floc[v] = 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+        const int pp = (f < 2) ? (m + N1 * k) : (k + N1 * m);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          own[v] += w[m] * SQ(v, pp, el);
+          floc[v] += w[m] * ((f < 2) ? SF(v, pp, el) : SG(v, pp, el));
+        }
+      }
+      double fx = (f < 2) ? 1.0 : 0.0, fy = (f < 2) ? 0.0 : 1.0;
+      int nb = -3;
+      if (e < ne) {
+        const size_t fo = ((size_t)(f * N1 + k) * 2) * ne + e;
+        fx = a.lv.fvec[fo];
+        fy = a.lv.fvec[fo + ne];
+        nb = a.lv.nbr[f * ne + e];
+      }
+      double out[NV];
+      if (nb >= 0) {
+        const int nf = a.lv.nbf[f * ne + e];
+        const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
+        const double* wn = (nf == 0 || nf == 2) ? o.lm : o.lp;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          const int pp = (nf < 2) ? (m + N1 * kk) : (kk + N1 * m);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) out[v] += wn[m] * a.q[v * sstride + (size_t)pp * ne + nb];
+        }
+      } else if (nb == -1) {             // slip wall: reflect the normal velocity
+        const double inv = 1.0 / sqrt(fx * fx + fy * fy);
+        const double nx = fx * inv, ny = fy * inv;
+        const double un = own[1] * nx + own[2] * ny;
+        out[0] = own[0];
+        out[1] = own[1] - 2.0 * un * nx;
+        out[2] = own[2] - 2.0 * un * ny;
+        out[3] = own[3];
+      } else if (nb == -2) {             // far field
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = a.lv.q_inf[v];
+      } else {                           // padding element of the last workgroup
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = own[v];
+      }
+      double fh[NV];
+      if (f == 0 || f == 2)
+        common_flux2(out, own, fx, fy, a.gas, fh);
+      else
+        common_flux2(own, out, fx, fy, a.gas, fh);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) SJ(f, k, v, el) = fh[v] - floc[v];
+    }
+  }
+  __syncthreads();
+
+  double Fv[NV];
+  {
+    double qc[NV];
+    conservative2(qv, a.gas, qc);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double d = 0.0;
+      if (act) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k) d += o.D[i * N1 + k] * SF(v, k + N1 * j, el);
+        d += o.gL[i] * SJ(0, j, v, el) + o.gR[i] * SJ(1, j, v, el);
+#pragma unroll
+        for (int k = 0; k < N1; ++k) d += o.D[j * N1 + k] * SG(v, i + N1 * k, el);
+        d += o.gL[j] * SJ(2, i, v, el) + o.gR[j] * SJ(3, i, v, el);
+      }
+      double fv = -d * ij - a.c_mass * qc[v];
+      if (valid) {
+        if (a.src) fv += a.src[v * sstride + gp];
+        if (a.S) fv -= a.S[v * sstride + gp];
+      }
+      Fv[v] = valid ? fv : 0.0;
+    }
+  }
+
+  if (a.part) {   // per-workgroup sums of F^2 per variable (fixed order, no atomics)
+    double s2[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s2[v] = Fv[v] * Fv[v];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s2[v] += __shfl_xor(s2[v], off, 64);
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_red[wave * NV + v] = s2[v];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double t = 0.0;
+        for (int w = 0; w < C::NW; ++w) t += s_red[w * NV + v];
+        a.part[(size_t)blockIdx.x * NV + v] = t;
+      }
+    }
+  }
+
+  if constexpr (MODE == 0) {
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.F[v * sstride + gp] = Fv[v];
+    }
+  } else {
+    __syncthreads();                      // all reads of s_f / s_g are done
+    double* s_fe = s_g;                   // [EPW][N], index p*Nv + v
+    double* s_dq = s_f;                   // [EPW][N]
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_fe[el * N + p * NV + v] = Fv[v];
+    }
+    __syncthreads();
+    if (act) {
+      const int el2 = tid / NP, p2 = tid % NP;
+      const int e2 = blockIdx.x * EPW + el2;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (e2 < ne) {
+        const double* fe = s_fe + el2 * N;
+        const size_t cs = (size_t)ne * N;            // stride between block columns
+        if constexpr (MODE == 2) {
+          const float* w0 = static_cast<const float*>(a.W) + (size_t)e2 * N + 4 * p2;
+          float accf[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+          for (int c = 0; c < N; ++c) {
+            const float4 w = *reinterpret_cast<const float4*>(w0 + c * cs);
+            const float fc = (float)fe[c];
+            accf[0] = fmaf(w.x, fc, accf[0]);
+            accf[1] = fmaf(w.y, fc, accf[1]);
+            accf[2] = fmaf(w.z, fc, accf[2]);
+            accf[3] = fmaf(w.w, fc, accf[3]);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = (double)accf[v];
+        } else {
+          const double* w0 = static_cast<const double*>(a.W) + (size_t)e2 * N + 4 * p2;
+#pragma unroll 4
+          for (int c = 0; c < N; ++c) {
+            const double2 wa = *reinterpret_cast<const double2*>(w0 + c * cs);
+            const double2 wb = *reinterpret_cast<const double2*>(w0 + c * cs + 2);
+            const double fc = fe[c];
+            acc[0] = fma(wa.x, fc, acc[0]);
+            acc[1] = fma(wa.y, fc, acc[1]);
+            acc[2] = fma(wb.x, fc, acc[2]);
+            acc[3] = fma(wb.y, fc, acc[3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) s_dq[el2 * N + p2 * NV + v] = acc[v];
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.q_out[v * sstride + gp] = qv[v] + a.alpha * s_dq[el * N + p * NV + v];
+    }
+  }
+#undef SQ
+#undef SF
+#undef SG
+#undef SJ
+}
+
+template <int P, int MODE>
+static hipError_t launch_fr_p(const ResArgs& a, int ne, hipStream_t st) {
+  using C = Cfg<P>;
+  const int blocks = (ne + C::EPW - 1) / C::EPW;
+  hipLaunchKernelGGL((k_fr<P, MODE>), dim3(blocks), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_fr(int P, const ResArgs& a, int ne, hipStream_t st) {
+  switch (P) {
+    case 0: return launch_fr_p<0, MODE>(a, ne, st);
+    case 1: return launch_fr_p<1, MODE>(a, ne, st);
+    case 2: return launch_fr_p<2, MODE>(a, ne, st);
+    case 3: return launch_fr_p<3, MODE>(a, ne, st);
+    case 4: return launch_fr_p<4, MODE>(a, ne, st);
+    case 5: return launch_fr_p<5, MODE>(a, ne, st);
+    case 6: return launch_fr_p<6, MODE>(a, ne, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int residual_blocks(const pmg_level_s& L) {
+  const int np = (L.P + 1) * (L.P + 1);
+  const int epw = (256 / np) > 0 ? (256 / np) : 1;
+  return (L.ne + epw - 1) / epw;
+}
+
+static ResArgs base_args(const pmg_level_s& L) {
+  ResArgs a{};
+  a.lv = L.view();
+  a.ops = L.ops;
+  a.gas = L.gas;
+  return a;
+}
+
+hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* src, const double* S,
+                           double c_mass, double* F, bool want_norms, hipStream_t st) {
+  ResArgs a = base_args(L);
+  a.q = q;
+  a.src = src;
+  a.S = S;
+  a.c_mass = c_mass;
+  a.F = F;
+  a.part = want_norms ? L.part : nullptr;
+  return launch_fr<0>(L.P, a, L.ne, st);
+}
+
+hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                        const double* src, const double* S, double c_mass, double alpha, bool want_norms,
+                        hipStream_t st) {
+  ResArgs a = base_args(L);
+  a.q = q_in;
+  a.src = src;
+  a.S = S;
+  a.c_mass = c_mass;
+  a.part = want_norms ? L.part : nullptr;
+  a.W = fac.W;
+  a.alpha = alpha;
+  a.q_out = q_out;
+  if (fac.precision == 32) return launch_fr<2>(L.P, a, L.ne, st);
+  return launch_fr<1>(L.P, a, L.ne, st);
+}
+
+}  // namespace pmg

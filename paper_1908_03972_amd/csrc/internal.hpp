@@ -1,0 +1,109 @@
+// Library-internal types shared by the host orchestration and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "physics.hpp"
+
+namespace pmg {
+
+constexpr int kMaxN1 = 7;   // P <= 6
+constexpr int kNv2 = 4;     // 2-D primitive variables (p, u, v, T)
+
+// 1-D operators of one polynomial degree on Gauss points, passed to kernels by value.
+struct Ops1D {
+  int n1;
+  double D[kMaxN1 * kMaxN1];   // D[i*n1 + k] = l_k'(x_i)
+  double lm[kMaxN1];           // l_k(-1)
+  double lp[kMaxN1];           // l_k(+1)
+  double gL[kMaxN1];           // g_L'(x_i)
+  double gR[kMaxN1];           // g_R'(x_i)
+};
+
+// Device view of one level's geometry and connectivity.
+struct LevelView {
+  int ne;
+  const double* met;    // [5][Np][Ne]: Sx, Sy (= y_eta, -x_eta), Tx, Ty (= -y_xi, x_xi), 1/|J|
+  const double* fvec;   // [4][n1][2][Ne]: +xi (faces 0,1) or +eta (faces 2,3) vector at flux points
+  const int* nbr;       // [4][Ne]
+  const int* nbf;       // [4][Ne]
+  const int* ori;       // [4][Ne]
+  double q_inf[4];
+};
+
+struct KernelStatus {
+  int* flag;            // device int: bit 0 singular pivot, bit 1 non-finite value
+};
+
+}  // namespace pmg
+
+struct pmg_level_s {
+  int dim = 2, P = 0, n1 = 1, np = 1, nv = 4, n = 4, ne = 0, geom_order = 1, device = 0;
+  pmg::GasParams gas{};
+  double q_inf[5] = {0, 0, 0, 0, 0};
+  pmg::Ops1D ops{};
+  std::vector<double> x1, w1;       // 1-D Gauss points/weights
+  std::vector<double> xy_host;      // [2][Np][Ne] solution-point coordinates
+  // device geometry
+  double* met = nullptr;
+  double* fvec = nullptr;
+  int* nbr = nullptr;
+  int* nbf = nullptr;
+  int* ori = nullptr;
+  // device workspace (allocated once at creation)
+  double* wq = nullptr;      // sweep ping-pong state
+  double* wF = nullptr;      // residual / defect
+  double* wS = nullptr;      // FAS forcing S_l
+  double* wqb = nullptr;     // restricted state q^b_l
+  double* wql = nullptr;     // working state q_l of a coarse level
+  double* wsrc = nullptr;    // ESDIRK source (finest level)
+  double* part = nullptr;    // per-workgroup norm partials
+  double* norms = nullptr;   // [Nv + 1]
+  int* flag = nullptr;       // device error flags
+  int part_blocks = 0;
+  size_t state_elems() const { return (size_t)nv * np * ne; }
+  pmg::LevelView view() const {
+    pmg::LevelView v;
+    v.ne = ne;
+    v.met = met;
+    v.fvec = fvec;
+    v.nbr = nbr;
+    v.nbf = nbf;
+    v.ori = ori;
+    for (int k = 0; k < 4; ++k) v.q_inf[k] = q_inf[k];
+    return v;
+  }
+};
+
+struct pmg_factors_s {
+  pmg_level_s* L = nullptr;
+  int precision = 64;     // 64: FP64 inverse blocks; 32: FP32 inverse blocks
+  void* W = nullptr;      // [n][Ne][n] element inverse blocks, column-major per element
+  size_t bytes = 0;
+};
+
+namespace pmg {
+
+// kernel launchers (fr_kernels.hip, jac_kernels.hip, transfer_kernels.hip)
+hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* src, const double* S,
+                           double c_mass, double* F, bool want_norms, hipStream_t st);
+hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                        const double* src, const double* S, double c_mass, double alpha, bool want_norms,
+                        hipStream_t st);
+hipError_t launch_norm_finalize(const pmg_level_s& L, hipStream_t st);
+hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
+                           pmg_factors_s& fac, hipStream_t st);
+hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
+                           double* xc, int nvar, hipStream_t st);
+hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
+                          const double* xb, double* xf, int nvar, hipStream_t st);
+hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc, hipStream_t st);
+hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
+                               int n_prev, double dt, double c_mass, double* src, hipStream_t st);
+int residual_blocks(const pmg_level_s& L);
+
+}  // namespace pmg

@@ -1,0 +1,296 @@
+// Device-side gas physics for the preconditioned FR/CPR residual and its Jacobian.
+//
+// Working variables are the primitive q_p = (p, u, v, T) (Sec. 2.2). Every routine is a
+// template on the scalar type so that the same code gives values (double) and exact
+// forward-mode derivatives (Dual<N>) for the element Jacobian.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pmg {
+
+struct GasParams {
+  double gamma;
+  double rgas;
+  double cp;        // gamma R / (gamma - 1)
+  double ma_inf;
+  double kappa;
+  int eps_mode;     // 0: eps = min(1, Ma) (cut-off off); 1: eps = min(1, max(kappa Ma_inf, Ma)), eq. (11)
+};
+
+// ---- forward-mode dual numbers ------------------------------------------------------
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+};
+
+template <int N>
+__device__ __forceinline__ Dual<N> dconst(double x) {
+  Dual<N> r;
+  r.v = x;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = 0.0;
+  return r;
+}
+
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r;
+  r.v = -a.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  const double inv = 1.0 / b.v;
+  r.v = a.v * inv;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * inv;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, double b) {
+  Dual<N> r = a;
+  r.v += b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(double b, const Dual<N>& a) { return a + b; }
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, double b) {
+  Dual<N> r = a;
+  r.v -= b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(double b, const Dual<N>& a) {
+  Dual<N> r;
+  r.v = b - a.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, double b) {
+  Dual<N> r;
+  r.v = a.v * b;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(double b, const Dual<N>& a) { return a * b; }
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(double b, const Dual<N>& a) {
+  Dual<N> r;
+  const double inv = 1.0 / a.v;
+  r.v = b * inv;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -r.v * a.d[k] * inv;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> dsqrt(const Dual<N>& a) {
+  Dual<N> r;
+  r.v = sqrt(a.v);
+  const double h = 0.5 / r.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * h;
+  return r;
+}
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+
+__device__ __forceinline__ double val(double x) { return x; }
+template <int N>
+__device__ __forceinline__ double val(const Dual<N>& x) { return x.v; }
+
+// |x|, min and max continued from the branch the value selects
+template <class T>
+__device__ __forceinline__ T rabs(const T& x) { return val(x) < 0.0 ? -x : x; }
+template <class T>
+__device__ __forceinline__ T rmin(const T& a, const T& b) { return val(a) <= val(b) ? a : b; }
+template <class T>
+__device__ __forceinline__ T rmax(const T& a, const T& b) { return val(a) >= val(b) ? a : b; }
+
+template <class T>
+__device__ __forceinline__ T lift(double x) { return T(x); }
+template <>
+__device__ __forceinline__ Dual<1> lift<Dual<1>>(double x) { return dconst<1>(x); }
+template <>
+__device__ __forceinline__ Dual<4> lift<Dual<4>>(double x) { return dconst<4>(x); }
+
+// ---- thermodynamic state at one point ----------------------------------------------
+// Quantities of the preconditioned system at a primitive state (2-D).
+template <class T>
+struct State2 {
+  T p, u, v, t;      // primitive variables
+  T rho, rho_p, rho_t, q2, h, c2;
+  T ur2, theta;      // U_r^2 and Theta of eq. (10)
+};
+
+template <class T>
+__device__ __forceinline__ T epsilon_from(const T& q2, const T& c2, const GasParams& g) {
+  // eq. (11): eps = min(1, max(kappa Ma_inf, Ma)); the "local" mode drops the cut-off
+  T ma = dsqrt(q2 / c2);
+  T one = lift<T>(1.0);
+  if (g.eps_mode == 0) return rmin(one, ma);
+  return rmin(one, rmax(lift<T>(g.kappa * g.ma_inf), ma));
+}
+
+template <class T>
+__device__ __forceinline__ State2<T> make_state(const T q[4], const GasParams& g) {
+  State2<T> s;
+  s.p = q[0];
+  s.u = q[1];
+  s.v = q[2];
+  s.t = q[3];
+  s.rho_p = 1.0 / (g.rgas * s.t);
+  s.rho = s.p * s.rho_p;
+  s.rho_t = -s.rho / s.t;
+  s.q2 = s.u * s.u + s.v * s.v;
+  s.h = g.cp * s.t + 0.5 * s.q2;          // H = E + p/rho for an ideal gas
+  s.c2 = g.gamma * g.rgas * s.t;
+  T eps = epsilon_from(s.q2, s.c2, g);
+  s.ur2 = eps * eps * s.c2;
+  s.theta = 1.0 / s.ur2 + 1.0 / (g.cp * s.t);   // 1/U_r^2 - rho_T/(rho C_p), eq. (10)
+  return s;
+}
+
+// conservative variables (rho, rho u, rho v, rho E)
+template <class T>
+__device__ __forceinline__ void conservative2(const T q[4], const GasParams& g, T out[4]) {
+  T rho = q[0] / (g.rgas * q[3]);
+  out[0] = rho;
+  out[1] = rho * q[1];
+  out[2] = rho * q[2];
+  out[3] = q[0] * (1.0 / (g.gamma - 1.0)) + 0.5 * rho * (q[1] * q[1] + q[2] * q[2]);
+}
+
+// inviscid flux along a (not necessarily unit) vector (sx, sy)
+template <class T>
+__device__ __forceinline__ void normal_flux2(const T q[4], double sx, double sy, const GasParams& g,
+                                             T out[4]) {
+  T rho = q[0] / (g.rgas * q[3]);
+  T un = q[1] * sx + q[2] * sy;
+  T mflux = rho * un;
+  T h = g.cp * q[3] + 0.5 * (q[1] * q[1] + q[2] * q[2]);
+  out[0] = mflux;
+  out[1] = mflux * q[1] + q[0] * sx;
+  out[2] = mflux * q[2] + q[0] * sy;
+  out[3] = mflux * h;
+}
+
+// y = Gamma x, eq. (9) in 2-D
+template <class T, class X>
+__device__ __forceinline__ void gamma_mul(const State2<T>& s, const GasParams& g, const X x[4], T y[4]) {
+  T y0 = s.theta * x[0] + s.rho_t * x[3];
+  y[0] = y0;
+  y[1] = s.u * y0 + s.rho * x[1];
+  y[2] = s.v * y0 + s.rho * x[2];
+  y[3] = s.h * y0 - x[0] + s.rho * (s.u * x[1] + s.v * x[2]) + s.rho * g.cp * x[3];
+}
+
+// x = Gamma^{-1} y, from the block structure of Gamma: the momentum rows give the
+// velocity components, the remaining 2x2 system has determinant rho C_p / U_r^2
+template <class T>
+__device__ __forceinline__ void gamma_solve(const State2<T>& s, const GasParams& g, const T y[4], T x[4]) {
+  T z = y[3] - (s.h - s.q2) * y[0] - s.u * y[1] - s.v * y[2];
+  T rcp = s.rho * g.cp;
+  T b = s.ur2 * (y[0] + s.theta * z) / rcp;
+  x[0] = rcp * b - z;
+  x[1] = (y[1] - s.u * y[0]) / s.rho;
+  x[2] = (y[2] - s.v * y[0]) / s.rho;
+  x[3] = b;
+}
+
+// y = A_n x with A_n = d(f.n)/dq_p for a unit normal (nx, ny)
+template <class T>
+__device__ __forceinline__ void flux_jac_mul(const State2<T>& s, const GasParams& g, double nx, double ny,
+                                             const T& un, const T x[4], T y[4]) {
+  T m = s.rho_p * x[0] + s.rho_t * x[3];
+  T dun = nx * x[1] + ny * x[2];
+  T r0 = un * m + s.rho * dun;
+  T rhoun = s.rho * un;
+  y[0] = r0;
+  y[1] = s.u * r0 + rhoun * x[1] + nx * x[0];
+  y[2] = s.v * r0 + rhoun * x[2] + ny * x[0];
+  y[3] = s.h * r0 + rhoun * (s.u * x[1] + s.v * x[2]) + rhoun * g.cp * x[3];
+}
+
+// Common inviscid flux of eq. (21), multiplied by |S|:
+//   |S| [ (f_n(q-) + f_n(q+))/2 - Gamma |Gamma^{-1} A_n| (q+ - q-)/2 ]
+// at the arithmetic mean of the primitive states. The matrix function is applied as the
+// quadratic that interpolates |lambda| at the three distinct eigenvalues of eq. (13)
+// (Newton divided differences), so that
+//   Gamma |X| dq = |l1| G dq + f12 (A - l1 G) dq + f123 (A - l1 G) G^{-1} (A - l2 G) dq.
+template <class T>
+__device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], double sx, double sy,
+                                             const GasParams& g, T out[4]) {
+  const double smag = sqrt(sx * sx + sy * sy);
+  const double nx = sx / smag, ny = sy / smag;
+  T qa[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) qa[k] = 0.5 * (qm[k] + qp[k]);
+  const State2<T> s = make_state(qa, g);
+  T un = s.u * nx + s.v * ny;
+  T alpha = 0.5 * (1.0 - s.ur2 / s.c2);          // beta = 1/c^2 for an ideal gas
+  T cpr = dsqrt(alpha * alpha * un * un + s.ur2);
+  T l1 = un;
+  T l2 = un * (1.0 - alpha) + cpr;
+  T l3 = un * (1.0 - alpha) - cpr;
+  T a1 = rabs(l1), a2 = rabs(l2), a3 = rabs(l3);
+  T f12 = (a2 - a1) / (l2 - l1);
+  T f13 = (a3 - a1) / (l3 - l1);
+  T f123 = (f13 - f12) / (l3 - l2);
+
+  T dq[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dq[k] = qp[k] - qm[k];
+  T gd[4], ad[4], w[4], y[4], ay[4];
+  gamma_mul(s, g, dq, gd);
+  flux_jac_mul(s, g, nx, ny, un, dq, ad);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = ad[k] - l2 * gd[k];
+  gamma_solve(s, g, w, y);
+  flux_jac_mul(s, g, nx, ny, un, y, ay);
+
+  T fm[4], fp[4];
+  normal_flux2(qm, nx, ny, g, fm);
+  normal_flux2(qp, nx, ny, g, fp);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T diss = a1 * gd[k] + f12 * (ad[k] - l1 * gd[k]) + f123 * (ay[k] - l1 * w[k]);
+    out[k] = smag * (0.5 * (fm[k] + fp[k]) - 0.5 * diss);
+  }
+}
+
+}  // namespace pmg

@@ -1,0 +1,166 @@
+// Level transfers (Sec. 3), pointwise helpers and the deterministic norm reduction.
+//
+// Restriction and prolongation apply a 1-D (P_c+1) x (P_f+1) matrix along xi and along eta
+// (sum factorisation), one thread per output value, element index fastest so that every
+// load and store is coalesced. They are bandwidth-bound: one read of the input level and one
+// write of the output level per call.
+#include "internal.hpp"
+
+namespace pmg {
+
+struct Mat1D {
+  double m[kMaxN1 * kMaxN1];   // row-major [rows][cols]
+};
+
+// x_c[v][a + nc b][e] = sum_{j,i} R[b][j] R[a][i] x_f[v][i + nf j][e]
+__global__ void __launch_bounds__(256) k_restrict(int ne, int nvar, int nf1, int nc1, Mat1D R,
+                                                  const double* __restrict__ xf, double* __restrict__ xc) {
+  const size_t npc = (size_t)nc1 * nc1, npf = (size_t)nf1 * nf1;
+  const size_t total = (size_t)nvar * npc * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int pc = (int)(rest % npc);
+  const int v = (int)(rest / npc);
+  const int a = pc % nc1, b = pc / nc1;
+  const double* base = xf + (size_t)v * npf * ne + e;
+  double acc = 0.0;
+  for (int j = 0; j < nf1; ++j) {
+    double row = 0.0;
+    for (int i = 0; i < nf1; ++i) row += R.m[a * nf1 + i] * base[(size_t)(i + nf1 * j) * ne];
+    acc += R.m[b * nf1 + j] * row;
+  }
+  xc[idx] = acc;
+}
+
+// x_f[v][i + nf j][e] += sum_{b,a} I[j][b] I[i][a] (xa - xb)[v][a + nc b][e]
+__global__ void __launch_bounds__(256) k_prolong(int ne, int nvar, int nc1, int nf1, Mat1D I,
+                                                 const double* __restrict__ xa, const double* __restrict__ xb,
+                                                 double* __restrict__ xf) {
+  const size_t npc = (size_t)nc1 * nc1, npf = (size_t)nf1 * nf1;
+  const size_t total = (size_t)nvar * npf * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int pf = (int)(rest % npf);
+  const int v = (int)(rest / npf);
+  const int i = pf % nf1, j = pf / nf1;
+  const size_t off = (size_t)v * npc * ne + e;
+  double acc = 0.0;
+  for (int b = 0; b < nc1; ++b) {
+    double row = 0.0;
+    for (int a = 0; a < nc1; ++a) {
+      const size_t o = off + (size_t)(a + nc1 * b) * ne;
+      const double d = xb ? (xa[o] - xb[o]) : xa[o];
+      row += I.m[i * nc1 + a] * d;
+    }
+    acc += I.m[j * nc1 + b] * row;
+  }
+  xf[idx] += acc;
+}
+
+__global__ void __launch_bounds__(256) k_conservative(int n_points, GasParams g, const double* __restrict__ q,
+                                                      double* __restrict__ qc) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n_points) return;
+  double qv[4], out[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) qv[v] = q[(size_t)v * n_points + idx];
+  conservative2(qv, g, out);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) qc[(size_t)v * n_points + idx] = out[v];
+}
+
+constexpr int kMaxStages = 8;
+struct StageSrc {
+  const double* R[kMaxStages];
+  double a[kMaxStages];
+  int n;
+};
+
+// src = c_mass (q_c^n + dt sum_j a_j R_j), the source of eq. (26)
+__global__ void __launch_bounds__(256) k_stage_source(size_t n, StageSrc s, double dt, double c_mass,
+                                                      const double* __restrict__ qc_n, double* __restrict__ src) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  double acc = 0.0;
+  for (int k = 0; k < s.n; ++k) acc += s.a[k] * s.R[k][idx];
+  src[idx] = c_mass * (qc_n[idx] + dt * acc);
+}
+
+// norms[v] = sqrt(sum_b part[b][v]); norms[Nv] = sqrt(sum_v sum_b part[b][v]). One workgroup,
+// fixed summation order (strided per thread, then a tree), so the result is bitwise repeatable.
+__global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ part, int nblk, int nv,
+                                                       double* __restrict__ norms) {
+  __shared__ double red[256];
+  double total = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * nv + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      norms[v] = sqrt(red[0]);
+      total += red[0];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[nv] = sqrt(total);
+}
+
+static unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
+                           double* xc, int nvar, hipStream_t st) {
+  Mat1D R{};
+  for (int k = 0; k < Lc.n1 * Lf.n1; ++k) R.m[k] = R1[k];
+  const size_t total = (size_t)nvar * Lc.np * Lc.ne;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restrict, dim3(blocks_for(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf, xc);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
+                          const double* xb, double* xf, int nvar, hipStream_t st) {
+  Mat1D I{};
+  for (int k = 0; k < Lc.n1 * Lf.n1; ++k) I.m[k] = I1[k];
+  const size_t total = (size_t)nvar * Lf.np * Lf.ne;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(total)), dim3(256), 0, st, Lf.ne, nvar, Lc.n1, Lf.n1, I, xa, xb,
+                     xf);
+  return hipGetLastError();
+}
+
+hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc, hipStream_t st) {
+  const int npts = L.np * L.ne;
+  if (npts == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conservative, dim3(blocks_for(npts)), dim3(256), 0, st, npts, L.gas, q, qc);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
+                               int n_prev, double dt, double c_mass, double* src, hipStream_t st) {
+  if (n_prev > kMaxStages) return hipErrorInvalidValue;
+  StageSrc s{};
+  s.n = n_prev;
+  for (int k = 0; k < n_prev; ++k) {
+    s.R[k] = R[k];
+    s.a[k] = a[k];
+  }
+  const size_t n = L.state_elems();
+  hipLaunchKernelGGL(k_stage_source, dim3(blocks_for(n)), dim3(256), 0, st, n, s, dt, c_mass, qc_n, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize(const pmg_level_s& L, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, L.part, residual_blocks(L), L.nv, L.norms);
+  return hipGetLastError();
+}
+
+}  // namespace pmg

@@ -1,0 +1,51 @@
+"""The C-ABI library loads on a CPU-only host and exports every function include/pmgfr.h declares
+(no compute calls: those need a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmgfr.h")
+LIB = os.path.join(ROOT, "paper_1908_03972_amd", "libpmgfr.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:pmg_status|int32_t|char\s*\*|const char\s*\*)\s*\**\s*(\w+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for required in ("fr_residual", "fr_element_jacobian", "ejacobi_sweep", "pmg_restrict", "pmg_prolong",
+                     "esdirk_stage_solve"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpmgfr.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    lib.pmg_abi_version.restype = ctypes.c_int32
+    assert lib.pmg_abi_version() == 100
+    lib.pmg_last_error.restype = ctypes.c_char_p
+    assert lib.pmg_last_error() == b""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpmgfr.so not built")
+def test_argument_errors_are_reported_without_a_gpu():
+    from paper_1908_03972_amd import _abi as A
+    lib = A.lib()
+    h = A.pmg_level()
+    assert lib.pmg_level_create(None, ctypes.byref(h)) == A.PMG_E_ARG
+    assert b"null" in lib.pmg_last_error()
+    d = A.LevelDesc()
+    d.dim = 3
+    assert lib.pmg_level_create(ctypes.byref(d), ctypes.byref(h)) == A.PMG_E_ARG
+    assert lib.fr_residual(None, None, None, None, 0.0, None, None, None) == A.PMG_E_ARG
+    assert lib.esdirk_stage_solve(None, 0.0, 0.0, None, None, None, 0, None, None, None, None) == A.PMG_E_ARG

@@ -1,0 +1,230 @@
+"""GPU (HIP through the C ABI) against the CPU oracle, element by element on seeded inputs."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gas as OG
+from oracle import solver as OS
+from oracle.jacobian import element_blocks
+
+from gpu_helpers import (from_dev, make_levels, rel_err_per_var, rounding_floor, to_dev, tolerance,
+                         vortex_on)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_03972_amd import api  # noqa: E402
+
+MESHES = {
+    "cfg1_8x8": lambda: W.periodic_quad_mesh(8, 10.0),
+    "ragged_13x11": lambda: W.periodic_rect_mesh(13, 11, 10.0, 10.0, jitter=0.1, seed=3),
+    "cfg2_64x64": lambda: W.periodic_quad_mesh(64, 10.0, jitter=0.1, seed=W.JITTER_SEED),
+}
+
+
+VS = W.VortexSpec(length=10.0)
+
+
+def scaled_block_error(got, ref, q):
+    """max |got - ref| |q_col| / max_row(|ref| |q_col|): the blocks compared as responses to
+    relative perturbations of each unknown. Plain column scaling would be dominated by the
+    (energy, T) entries, which are a cancellation rho_T H + rho C_p ~ 0 whose rounding differs
+    between any two FP64 implementations."""
+    scale = np.maximum(np.abs(q), np.array([VS.p_inf, 1.0, 1.0, VS.t_inf]) * 1e-3)
+    sc = scale.reshape(q.shape[0], 1, -1)                       # [Ne, 1, n], index p*Nv + v
+    rowmax = np.max(np.abs(ref) * sc, axis=2, keepdims=True)
+    return float(np.max(np.abs(got - ref) * sc / rowmax))
+
+
+@pytest.mark.parametrize("mesh_name,P", [("cfg1_8x8", 2), ("ragged_13x11", 3), ("cfg2_64x64", 3)])
+def test_solution_points_match(mesh_name, P):
+    mesh = MESHES[mesh_name]()
+    olev, glev = make_levels(mesh, P, VS)
+    xy = glev.points()                              # [2, Np, Ne]
+    ref = np.transpose(olev.geo.xy, (2, 1, 0))
+    assert np.max(np.abs(xy - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("mesh_name,P", [("cfg1_8x8", 2), ("cfg1_8x8", 1), ("cfg1_8x8", 0),
+                                         ("ragged_13x11", 0), ("ragged_13x11", 1), ("ragged_13x11", 2),
+                                         ("ragged_13x11", 3), ("ragged_13x11", 4), ("cfg2_64x64", 3)])
+def test_residual_parity(mesh_name, P):
+    mesh = MESHES[mesh_name]()
+    olev, glev = make_levels(mesh, P, VS)
+    q = vortex_on(olev, VS)
+    rng = np.random.default_rng(P)
+    c_mass = 1.0 / (0.2928932 * 0.05)
+    src = OG.conservative(q, olev.gas) * c_mass * (1 + 1e-3 * rng.standard_normal(q.shape))
+    S = 1e-2 * rng.standard_normal(q.shape) * np.abs(src).max(axis=(0, 1))
+
+    def oracle_F(x):
+        return olev.stage_residual(x, c_mass, src, S)
+
+    ref = oracle_F(q)
+    F = glev.new_state()
+    norms = torch.zeros(5, dtype=torch.float64, device="cuda")
+    api.fr_residual(glev, to_dev(q), F, src=to_dev(src), S=to_dev(S), c_mass=c_mass, norms=norms)
+    torch.cuda.synchronize()
+    got = from_dev(F)
+    err = rel_err_per_var(got, ref)
+    tol = tolerance(rounding_floor(oracle_F, q))
+    print(mesh_name, P, "err", err, "tol", tol)
+    assert np.all(err <= tol), (err, tol)
+    nref = np.linalg.norm(ref.reshape(-1, 4), axis=0)
+    nn = norms.cpu().numpy()
+    assert np.allclose(nn[:4], nref, rtol=1e-10)
+    assert abs(nn[4] - np.linalg.norm(ref)) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_residual_freestream_on_gpu():
+    mesh = MESHES["cfg2_64x64"]()
+    olev, glev = make_levels(mesh, 3, VS)
+    q = np.broadcast_to(VS.freestream(), (olev.ne, olev.npts, 4)).copy()
+    F = glev.new_state()
+    api.fr_residual(glev, to_dev(q), F)
+    got = from_dev(F)
+    # each term of R is a flux over the element size: scale by p_inf |V_inf| max(|S|/|J|)
+    speed = np.hypot(*VS.u_inf)
+    inv_h = np.max(np.linalg.norm(olev.geo.S_sp, axis=-1) / olev.geo.jac)
+    assert np.max(np.abs(got[..., :3])) / (VS.p_inf * speed * inv_h) < 1e-13
+    h_inf = 3.5 * VS.t_inf + 0.5 * speed ** 2
+    assert np.max(np.abs(got[..., 3])) / (h_inf * speed * inv_h) < 1e-13 / VS.ma_inf ** 2
+
+
+@pytest.mark.parametrize("Pf,Pc", [(2, 1), (1, 0), (3, 2), (3, 1), (4, 2)])
+def test_transfer_parity(Pf, Pc):
+    mesh = MESHES["ragged_13x11"]()
+    of, gf = make_levels(mesh, Pf, VS)
+    oc, gc = make_levels(mesh, Pc, VS)
+    rng = np.random.default_rng(Pf * 10 + Pc)
+    xf = rng.standard_normal((of.ne, of.npts, 4))
+    xc = rng.standard_normal((oc.ne, oc.npts, 4))
+    out_c = gc.new_state()
+    api.pmg_restrict(gf, gc, to_dev(xf), out_c)
+    ref_c = OS.restrict(xf, Pf, Pc)
+    assert np.max(np.abs(from_dev(out_c) - ref_c)) < 1e-13 * np.max(np.abs(ref_c))
+    base = to_dev(xf)
+    api.pmg_prolong(gc, gf, to_dev(xc), base)
+    ref_f = xf + OS.prolong(xc, Pc, Pf)
+    assert np.max(np.abs(from_dev(base) - ref_f)) < 1e-13 * np.max(np.abs(ref_f))
+
+
+@pytest.mark.parametrize("mesh_name,P", [("cfg1_8x8", 2), ("ragged_13x11", 1), ("ragged_13x11", 3),
+                                         ("cfg1_8x8", 4)])
+def test_element_blocks_parity(mesh_name, P):
+    mesh = MESHES[mesh_name]()
+    olev, glev = make_levels(mesh, P, VS)
+    q = vortex_on(olev, VS)
+    dtau, c_mass = 0.37, 1.0 / (0.2928932 * 0.05)
+    ref = element_blocks(olev, q, dtau, c_mass)                      # [Ne, n, n]
+    fac = api.Factors(glev, 64)
+    D = torch.zeros(glev.ne * glev.n * glev.n, dtype=torch.float64, device="cuda")
+    api.fr_element_jacobian(glev, to_dev(q), dtau, c_mass, fac, D_out=D)
+    torch.cuda.synchronize()
+    assert glev.status() == 0
+    got = D.cpu().numpy().reshape(glev.ne, glev.n, glev.n)
+    err = scaled_block_error(got, ref, q)
+    print(mesh_name, P, "scaled block err", err)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("mesh_name,P,prec", [("cfg1_8x8", 2, 64), ("ragged_13x11", 3, 64),
+                                              ("ragged_13x11", 1, 64), ("cfg1_8x8", 2, 32)])
+def test_sweep_parity(mesh_name, P, prec):
+    mesh = MESHES[mesh_name]()
+    olev, glev = make_levels(mesh, P, VS)
+    q = vortex_on(olev, VS)
+    dtau, c_mass = 0.5, 1.0 / (0.2928932 * 0.05)
+    src = OG.conservative(q, olev.gas) * c_mass + olev.residual(q) * (0.2928932 * 0.05 * c_mass)
+    def oracle_sweeps(q0):
+        sol = OS.PMGSolver(mesh, olev.gas, OS.PMGOptions(p_levels=(P,), n_smooth=(3,)), q_inf=VS.freestream())
+        sol.c_mass, sol.src, sol.dtau = c_mass, src, dtau
+        sol.build_D(0, q0)
+        return sol.smooth(0, q0, None, 3)
+
+    ref = oracle_sweeps(q)
+    rng = np.random.default_rng(11)
+    q_pert = q * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q.shape))
+    floor = rel_err_per_var(oracle_sweeps(q_pert) - VS.freestream(), ref - VS.freestream())
+    fac = api.Factors(glev, prec)
+    qd = to_dev(q)
+    api.fr_element_jacobian(glev, qd, dtau, c_mass, fac)
+    Fa = glev.new_state()
+    api.ejacobi_sweep(glev, fac, qd, 3, src=to_dev(src), c_mass=c_mass, F_after=Fa)
+    torch.cuda.synchronize()
+    got = from_dev(qd)
+    err = rel_err_per_var(got - VS.freestream(), ref - VS.freestream())
+    print(mesh_name, P, prec, "sweep err", err, "floor", floor)
+    if prec == 64:
+        assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
+    else:
+        # FP32 blocks: each sweep's update carries ~u_32 cond(S_r D) relative error
+        assert np.all(err < 1e-4), err
+    Fref = olev.stage_residual(ref, c_mass, src)
+    ferr = rel_err_per_var(from_dev(Fa), Fref)
+    print("F_after err", ferr)
+    assert np.all(ferr < (1e-8 if prec == 64 else 1e-2)), ferr
+
+
+def _stage_case(case):
+    if case == "cfg1_P210":
+        return MESHES["cfg1_8x8"](), (2, 1, 0), (5, 10, 20), 64
+    if case == "ragged_P31":
+        return MESHES["ragged_13x11"](), (3, 1), (3, 6), 64
+    if case == "cfg1_P210_fp32":
+        return MESHES["cfg1_8x8"](), (2, 1, 0), (5, 10, 20), 32
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["cfg1_P210", "ragged_P31", "cfg1_P210_fp32"])
+def test_stage_solve_parity(case):
+    """V-cycles of the ESDIRK2 second-stage solve (eqs. (26)-(31), Sec. 3): the state after each
+    V-cycle count and the residual history against the oracle."""
+    from gpu_helpers import gas_for
+    mesh, plev, nsm, prec = _stage_case(case)
+    nvc = 3
+    gas = gas_for(VS)
+    A = OS.esdirk_tableau("esdirk2")
+    dt, om = 0.05, A[1, 1]
+
+    def run_oracle(q0):
+        opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, max_vcycles=nvc, tol=1e-30)
+        osol = OS.PMGSolver(mesh, gas, opts, q_inf=VS.freestream())
+        lev = osol.levels[0]
+        src = (OG.conservative(q0, gas) + dt * A[1, 0] * lev.residual(q0)) / (om * dt)
+        return osol.stage_solve(q0, 1.0 / (om * dt), src, max_vcycles=nvc)
+
+    olev = OS.PMGSolver(mesh, gas, OS.PMGOptions(p_levels=plev, n_smooth=nsm)).levels[0]
+    q0 = vortex_on(olev, VS)
+    q_ref, st = run_oracle(q0)
+    qinf = VS.freestream()
+    # rounding floor of the oracle's own V-cycles: perturb q^0 by one unit in the last place
+    rng = np.random.default_rng(7)
+    q_pert, _ = run_oracle(q0 * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q0.shape)))
+    floor = rel_err_per_var(q_pert - qinf, q_ref - qinf)
+
+    glevels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf)
+               for P in plev]
+    facs = [api.Factors(lv, prec) for lv in glevels]
+    solver = api.StageSolver(glevels, facs, nsm, max_vcycles=nvc, tol_rel=1e-30)
+    q = to_dev(q0)
+    qc = OG.conservative(q0, gas)
+    out = solver.solve(q, omega=om, dt=dt, qc_n=to_dev(qc), R_prev=[to_dev(olev.residual(q0))],
+                       a_row=[A[1, 0]], raise_on_error=False)
+    torch.cuda.synchronize()
+    assert out["status"] == -6 and out["n_vcycles"] == nvc      # PMG_E_NOT_CONVERGED at max_vcycles
+    err = rel_err_per_var(from_dev(q) - qinf, q_ref - qinf)
+    h_ref = np.array(st.history)
+    h_err = np.abs(np.array(out["history"]) - h_ref) / h_ref
+    print(case, "state err", err, "floor", floor, "history err", h_err)
+    if prec == 64:
+        tol = np.maximum(1e-11, 10.0 * floor)
+        assert np.all(err <= tol), (err, tol)
+        assert np.all(h_err <= max(1e-11, 10.0 * floor.max()))
+    else:
+        # FP32 blocks: the smoother's update carries u_32 * cond(S_r D) relative error per sweep
+        assert np.all(err < 1e-4), err
+        assert np.all(h_err < 1e-3)

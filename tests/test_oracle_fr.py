@@ -18,13 +18,15 @@ def test_freestream_preserved_on_jittered_mesh(P):
     q = np.broadcast_to(vs.freestream(), (lev.ne, lev.npts, 4)).copy()
     R = lev.residual(q)
     speed = np.hypot(*vs.u_inf)
-    scale = vs.p_inf * speed                      # p_inf |V_inf|: mass/momentum flux scale
+    # every term of R is a flux divided by an element size: p_inf |V_inf| max(|S|/|J|)
+    inv_h = np.max(np.linalg.norm(lev.geo.S_sp, axis=-1) / lev.geo.jac)
+    scale = vs.p_inf * speed * inv_h
     assert np.max(np.abs(R[..., :3])) / scale < 1e-13
     # Energy: the preconditioned dissipation multiplies the rounding of the pressure traces
     # by Gamma's (Theta H - 1) ~ H/U_r^2 = H/(eps c)^2, i.e. by 1/eps^2 relative to the
     # energy flux rho H |V| (eqs. (9), (10), (21)); eps = Ma here.
     h_inf = GAS.cp * vs.t_inf + 0.5 * speed ** 2
-    escale = vs.rho_inf * h_inf * speed
+    escale = vs.rho_inf * h_inf * speed * inv_h
     assert np.max(np.abs(R[..., 3])) / escale < 1e-13 / vs.ma_inf ** 2
 
 

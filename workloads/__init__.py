@@ -61,35 +61,42 @@ def periodic_quad_mesh(n: int, length: float = 10.0, jitter: float = 0.0,
     (index mod n), so opposite sides of the box stay matched.
     Elements are numbered ``e = i + n*j`` (x index fastest).
     """
-    if origin is None:
-        origin = -0.5 * length
-    h = length / n
-    dx = np.zeros((n, n))
-    dy = np.zeros((n, n))
+    return periodic_rect_mesh(n, n, length, length, jitter, seed, origin, origin)
+
+
+def periodic_rect_mesh(nx: int, ny: int, lx: float = 10.0, ly: float = 10.0, jitter: float = 0.0,
+                       seed: int = JITTER_SEED, ox: float | None = None, oy: float | None = None) -> Mesh:
+    """Bilinear quads on a periodic nx x ny box (see ``periodic_quad_mesh`` for the jitter recipe,
+    here with offsets of shape (nx, ny) scaled by each direction's cell size)."""
+    ox = -0.5 * lx if ox is None else ox
+    oy = -0.5 * ly if oy is None else oy
+    hx, hy = lx / nx, ly / ny
+    dx = np.zeros((nx, ny))
+    dy = np.zeros((nx, ny))
     if jitter > 0.0:
         rng = np.random.default_rng(seed)
-        dx = rng.uniform(-jitter * h, jitter * h, size=(n, n))
-        dy = rng.uniform(-jitter * h, jitter * h, size=(n, n))
-    ne = n * n
+        dx = rng.uniform(-jitter * hx, jitter * hx, size=(nx, ny))
+        dy = rng.uniform(-jitter * hy, jitter * hy, size=(nx, ny))
+    ne = nx * ny
     nodes = np.zeros((ne, 4, 2))
     nbr = np.zeros((ne, 4), np.int32)
     nbf = np.zeros((ne, 4), np.int32)
     ori = np.zeros((ne, 4), np.int32)
-    for j in range(n):
-        for i in range(n):
-            e = i + n * j
+    for j in range(ny):
+        for i in range(nx):
+            e = i + nx * j
             for b in range(2):
                 for a in range(2):
                     vi, vj = i + a, j + b
-                    nodes[e, a + 2 * b, 0] = origin + vi * h + dx[vi % n, vj % n]
-                    nodes[e, a + 2 * b, 1] = origin + vj * h + dy[vi % n, vj % n]
-            nbr[e, 0] = (i - 1) % n + n * j
-            nbr[e, 1] = (i + 1) % n + n * j
-            nbr[e, 2] = i + n * ((j - 1) % n)
-            nbr[e, 3] = i + n * ((j + 1) % n)
+                    nodes[e, a + 2 * b, 0] = ox + vi * hx + dx[vi % nx, vj % ny]
+                    nodes[e, a + 2 * b, 1] = oy + vj * hy + dy[vi % nx, vj % ny]
+            nbr[e, 0] = (i - 1) % nx + nx * j
+            nbr[e, 1] = (i + 1) % nx + nx * j
+            nbr[e, 2] = i + nx * ((j - 1) % ny)
+            nbr[e, 3] = i + nx * ((j + 1) % ny)
             nbf[e] = (1, 0, 3, 2)
-    return Mesh(2, 1, nodes, nbr, nbf, ori, name=f"periodic{n}x{n}",
-                info={"length": length, "origin": origin, "jitter": jitter,
+    return Mesh(2, 1, nodes, nbr, nbf, ori, name=f"periodic{nx}x{ny}",
+                info={"length": (lx, ly), "origin": (ox, oy), "jitter": jitter,
                       "seed": seed if jitter > 0 else None, "periodic": True})
 
 
