@@ -16,6 +16,12 @@
  * - A state field on a level is double[Nv][Np][Ne] (element index fastest, for coalesced access),
  *   with Nv = 4 primitive variables (p, u, v, T), Np = (P+1)^2 solution points numbered
  *   p = i + (P+1) j (i along xi), Ne elements. Sizes below are in elements of that layout.
+ *   States (q, q_c^n excepted) are stored as offsets from the level's reference state q_ref:
+ *   the unknown held for variable v is q_v - q_ref_v ("gauge" pressure and temperature when
+ *   q_ref = q_inf). At low Mach number the residual's sensitivity to the pressure grows like
+ *   1/Ma^2 (eqs. (9), (10), (21)); storing offsets keeps the unknowns' quantisation at the size
+ *   of the disturbance rather than of the absolute pressure. q_ref = 0 gives plain storage.
+ *   Residuals F and R are not offset.
  * - `stream` is a hipStream_t (passed as void*). Work is enqueued on it asynchronously unless a
  *   function says it synchronises. Entry points are not re-entrant on the same handle: calls that
  *   share a level or factor handle must be ordered on one stream.
@@ -70,6 +76,8 @@ int32_t pmg_abi_version(void);
  *   eps_mode     reference velocity U_r = eps c of eq. (11): 0 = eps = min(1, Ma) (cut-off
  *                off), 1 = eps = min(1, max(kappa Ma_inf, Ma)).
  *   q_inf        free-stream primitive state used by far-field faces.
+ *   q_ref        reference state subtracted from every stored state (see the conventions above);
+ *                all levels of one solve must share it.
  *   device       HIP device ordinal on which the level lives.
  */
 typedef struct {
@@ -87,6 +95,7 @@ typedef struct {
   double ma_inf;
   double kappa;
   double q_inf[5];
+  double q_ref[5];
   int32_t device;
 } pmg_level_desc;
 
@@ -126,7 +135,8 @@ pmg_status pmg_factors_destroy(pmg_factors F);
 pmg_status fr_residual(pmg_level L, const double* q, const double* src, const double* S, double c_mass,
                        double* F, double* norms, void* stream);
 
-/* q_c = (rho, rho u, rho v, rho E) of a primitive state (Sec. 2.1). q, qc: device state layout. */
+/* q_c = (rho, rho u, rho v, rho E) of a stored primitive state (Sec. 2.1); q_c is absolute (not
+ * offset). q, qc: device state layout. */
 pmg_status fr_conservative(pmg_level L, const double* q, double* qc, void* stream);
 
 /*
@@ -162,7 +172,8 @@ pmg_status ejacobi_sweep(pmg_level L, pmg_factors fac, double* q, const double* 
  * degree-P_f polynomial onto degree P_c, applied per variable (Sec. 3, eqs. (39), (40)).
  * pmg_prolong — x_f += I dx_c: interpolation of the degree-P_c polynomial at the degree-P_f
  * points (eqs. (44), (45)).
- * Both levels must be on the same mesh with P_c < P_f, else PMG_E_SHAPE. nvar in 1..Nv gives the
+ * Both levels must be on the same mesh with P_c < P_f and share q_ref, else PMG_E_SHAPE (the
+ * projection preserves constants, so offsets transfer like states). nvar in 1..Nv gives the
  * leading variables of the state layout that are transferred.
  */
 pmg_status pmg_restrict(pmg_level fine, pmg_level coarse, const double* x_f, double* x_c, int32_t nvar,
@@ -194,6 +205,7 @@ typedef struct {
   double* history;                /* host array or NULL: r_m for m = 0..n_vcycles              */
   int32_t history_capacity;
   pmg_status status;
+  double seconds;                 /* host wall time of the stage solve                         */
 } pmg_solve_stats;
 
 /*
@@ -214,6 +226,24 @@ typedef struct {
 pmg_status esdirk_stage_solve(const pmg_solve_opts* opts, double omega, double dt, const double* qc_n,
                               const double* const* R_prev, const double* a_row, int32_t n_prev, double* q,
                               double* R_out, pmg_solve_stats* stats, void* stream);
+
+/*
+ * esdirk_step — one physical time step q^n -> q^{n+1} of eq. (24) with the first stage explicit
+ * and the implicit stages solved by esdirk_stage_solve (the schemes are stiffly accurate, so
+ * q^{n+1} is the last stage value).
+ *   scheme  2: ESDIRK2, three stages (Kennedy & Carpenter), 3: ESDIRK3, four stages
+ *           (ESDIRK3(2)4L[2]SA), the schemes cited in Sec. 2.4.
+ *   q       device state, in q^n, out q^{n+1}.
+ *   work    device, (number of stages) consecutive state arrays: q_c^n and the stage residuals.
+ *   stats   host array of n_stats entries or NULL: one per implicit stage.
+ * Returns the first failing stage's status (its stats say which); q then holds that stage's
+ * last iterate.
+ */
+pmg_status esdirk_step(const pmg_solve_opts* opts, int32_t scheme, double dt, double* q, double* work,
+                       pmg_solve_stats* stats, int32_t n_stats, void* stream);
+
+/* Number of stages of an ESDIRK scheme id (3 or 4), or 0 for an unknown id. */
+int32_t esdirk_stages(int32_t scheme);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,8 @@ class LevelDesc(C.Structure):
         ("nodes", C.POINTER(C.c_double)), ("face_nbr", C.POINTER(C.c_int32)),
         ("face_nbr_face", C.POINTER(C.c_int32)), ("face_orient", C.POINTER(C.c_int32)),
         ("gamma", C.c_double), ("rgas", C.c_double), ("eps_mode", C.c_int32),
-        ("ma_inf", C.c_double), ("kappa", C.c_double), ("q_inf", C.c_double * 5), ("device", C.c_int32),
+        ("ma_inf", C.c_double), ("kappa", C.c_double), ("q_inf", C.c_double * 5), ("q_ref", C.c_double * 5),
+        ("device", C.c_int32),
     ]
 
 
@@ -50,6 +51,7 @@ class SolveStats(C.Structure):
     _fields_ = [
         ("n_vcycles", C.c_int32), ("n_refresh", C.c_int32), ("r0", C.c_double), ("r_final", C.c_double),
         ("history", C.POINTER(C.c_double)), ("history_capacity", C.c_int32), ("status", C.c_int32),
+        ("seconds", C.c_double),
     ]
 
 
@@ -75,6 +77,9 @@ SIGNATURES = {
     "esdirk_stage_solve": (pmg_status, [C.POINTER(SolveOpts), C.c_double, C.c_double, DP, C.POINTER(DP),
                                         C.POINTER(C.c_double), C.c_int32, DP, DP, C.POINTER(SolveStats),
                                         C.c_void_p]),
+    "esdirk_step": (pmg_status, [C.POINTER(SolveOpts), C.c_int32, C.c_double, DP, DP, C.POINTER(SolveStats),
+                                 C.c_int32, C.c_void_p]),
+    "esdirk_stages": (C.c_int32, [C.c_int32]),
 }
 
 _lib = None

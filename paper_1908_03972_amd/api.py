@@ -20,7 +20,7 @@ class Level:
     """One P-level of a quadrilateral mesh (a ``pmg_level`` handle)."""
 
     def __init__(self, mesh, P: int, *, gamma: float = 1.4, rgas: float = 1.0, eps_mode: int = 0,
-                 ma_inf: float = 0.0, kappa: float = 1.0, q_inf=None, device: int = 0):
+                 ma_inf: float = 0.0, kappa: float = 1.0, q_inf=None, q_ref=None, device: int = 0):
         lib = A.lib()
         nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64)
         nbr = np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)
@@ -37,6 +37,11 @@ class Level:
         if q_inf is not None:
             qi[:len(q_inf)] = q_inf
         d.q_inf = (C.c_double * 5)(*qi)
+        qr = np.zeros(5)
+        if q_ref is not None:
+            qr[:len(q_ref)] = q_ref
+        d.q_ref = (C.c_double * 5)(*qr)
+        self.q_ref = qr[:4].copy()
         d.device = device
         h = A.pmg_level()
         A.check(lib.pmg_level_create(C.byref(d), C.byref(h)), "pmg_level_create")
@@ -191,3 +196,27 @@ class StageSolver:
         if raise_on_error:
             A.check(status, "esdirk_stage_solve")
         return out
+
+
+def esdirk_stages(scheme: int) -> int:
+    return int(A.lib().esdirk_stages(scheme))
+
+
+def esdirk_step(solver: StageSolver, scheme: int, dt: float, q, work, stream=None, raise_on_error=True):
+    """One time step of ``esdirk_step``; ``work`` is a float64 device tensor of shape
+    (stages, Nv, Np, Ne). Returns one stats dict per implicit stage."""
+    L0 = solver.levels[0]
+    s = esdirk_stages(scheme)
+    if s == 0:
+        raise ValueError(f"unknown ESDIRK scheme {scheme}")
+    if work.dtype != torch.float64 or not work.is_contiguous() or tuple(work.shape) != (s,) + L0.shape \
+            or work.device != L0.torch_device:
+        raise ValueError(f"work must be a contiguous float64 tensor of shape {(s,) + L0.shape}")
+    stats = (A.SolveStats * (s - 1))()
+    status = A.lib().esdirk_step(C.byref(solver.opts), scheme, dt, L0.check_state(q, "q", False),
+                                 C.c_void_p(work.data_ptr()), stats, s - 1, _stream(stream))
+    out = [{"status": st.status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh, "r0": st.r0,
+            "r_final": st.r_final, "seconds": st.seconds} for st in stats]
+    if raise_on_error:
+        A.check(status, "esdirk_step")
+    return out

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -277,7 +278,10 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   L->gas.ma_inf = d->ma_inf;
   L->gas.kappa = d->kappa;
   L->gas.eps_mode = d->eps_mode;
-  for (int k = 0; k < 5; ++k) L->q_inf[k] = d->q_inf[k];
+  for (int k = 0; k < 5; ++k) {
+    L->q_inf[k] = d->q_inf[k];
+    L->q_ref[k] = d->q_ref[k];
+  }
   build_ops(d->P, L->ops, L->x1, L->w1);
 
   // metrics from the exact mapping at solution and flux points
@@ -501,6 +505,8 @@ static pmg_status check_pair(pmg_level fine, pmg_level coarse, int32_t nvar) {
   if (fine->ne != coarse->ne || fine->dim != coarse->dim || fine->device != coarse->device)
     return fail(PMG_E_SHAPE, "levels are not on the same mesh and device");
   if (!(coarse->P < fine->P)) return fail(PMG_E_SHAPE, "coarse degree must be below the fine degree");
+  for (int k = 0; k < 5; ++k)
+    if (fine->q_ref[k] != coarse->q_ref[k]) return fail(PMG_E_SHAPE, "levels have different q_ref");
   if (nvar < 1 || nvar > fine->nv) return fail(PMG_E_ARG, "nvar out of range");
   return PMG_OK;
 }
@@ -594,6 +600,8 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
     if (l > 0 && (o->levels[l]->P >= o->levels[l - 1]->P || o->levels[l]->ne != o->levels[0]->ne ||
                   o->levels[l]->device != o->levels[0]->device))
       return fail(PMG_E_SHAPE, "levels must share the mesh with strictly decreasing P");
+    for (int k = 0; k < 5; ++k)
+      if (o->levels[l]->q_ref[k] != o->levels[0]->q_ref[k]) return fail(PMG_E_SHAPE, "levels have different q_ref");
   }
   if (!(o->dtau_init > 0.0) || !(o->dtau_max >= o->dtau_init)) return fail(PMG_E_ARG, "bad dtau range");
   if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
@@ -604,6 +612,7 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
   }
   pmg_level L0 = o->levels[0];
   DeviceGuard guard(L0->device);
+  const auto t_start = std::chrono::steady_clock::now();
   Solve s;
   s.o = o;
   s.st = as_stream(stream);
@@ -683,5 +692,67 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
     stats->status = result;
   }
   PMG_HIP(hipStreamSynchronize(s.st));
+  if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return result;
+}
+
+// ---- ESDIRK time step ----------------------------------------------------------------------------
+namespace {
+
+// Butcher matrices (row-major s x s) of the stiffly accurate ESDIRK schemes named in Sec. 2.4.
+int esdirk_tableau(int scheme, double* A) {
+  if (scheme == 2) {            // three stages, gamma = 1 - sqrt(2)/2, c = (0, 2 gamma, 1)
+    const double g = 1.0 - std::sqrt(2.0) / 2.0, b = std::sqrt(2.0) / 4.0;
+    const double t[9] = {0, 0, 0, g, g, 0, b, b, g};
+    std::memcpy(A, t, sizeof(t));
+    return 3;
+  }
+  if (scheme == 3) {            // ESDIRK3(2)4L[2]SA, c = (0, 2 gamma, 3/5, 1)
+    const double g = 1767732205903.0 / 4055673282236.0;
+    const double t[16] = {0, 0, 0, 0,
+                          g, g, 0, 0,
+                          2746238789719.0 / 10658868560708.0, -640167445237.0 / 6845629431997.0, g, 0,
+                          1471266399579.0 / 7840856788654.0, -4482444167858.0 / 7529755066697.0,
+                          11266239266428.0 / 11593286722821.0, g};
+    std::memcpy(A, t, sizeof(t));
+    return 4;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int32_t esdirk_stages(int32_t scheme) {
+  double A[64];
+  return esdirk_tableau(scheme, A);
+}
+
+extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, double dt, double* q, double* work,
+                                  pmg_solve_stats* stats, int32_t n_stats, void* stream) {
+  double A[64];
+  const int s = esdirk_tableau(scheme, A);
+  if (s == 0) return fail(PMG_E_ARG, "unknown ESDIRK scheme");
+  if (!o || !q || !work || o->n_levels < 1 || !o->levels || !o->levels[0]) return fail(PMG_E_ARG, "null argument");
+  if (!(dt > 0.0)) return fail(PMG_E_ARG, "dt must be positive");
+  pmg_level L0 = o->levels[0];
+  const size_t ns = L0->state_elems();
+  double* qc_n = work;
+  std::vector<const double*> R(s);
+  for (int k = 0; k < s - 1; ++k) R[k] = work + (size_t)(k + 1) * ns;
+  {
+    DeviceGuard guard(L0->device);
+    hipStream_t st = as_stream(stream);
+    PMG_HIP(pmg::launch_conservative(*L0, q, qc_n, st));
+    PMG_HIP(pmg::launch_residual(*L0, q, nullptr, nullptr, 0.0, const_cast<double*>(R[0]), false, st));
+  }
+  const double omega = A[1 * s + 1];
+  for (int i = 1; i < s; ++i) {
+    double a_row[8];
+    for (int j = 0; j < i; ++j) a_row[j] = A[i * s + j];
+    pmg_solve_stats* sti = (stats && i - 1 < n_stats) ? &stats[i - 1] : nullptr;
+    double* R_out = (i < s - 1) ? const_cast<double*>(R[i]) : nullptr;
+    const pmg_status r = esdirk_stage_solve(o, omega, dt, qc_n, R.data(), a_row, i, q, R_out, sti, stream);
+    if (r != PMG_OK) return r;
+  }
+  return PMG_OK;
 }

@@ -72,7 +72,10 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   const size_t gp = (size_t)p * ne + e;     // offset of (v=0, p, e)
   double qv[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) qv[v] = valid ? a.q[v * sstride + gp] : a.lv.q_inf[v];
+  for (int v = 0; v < NV; ++v) qv[v] = valid ? a.q[v * sstride + gp] : a.lv.qinf_g[v];
+  double qa[NV];                            // absolute primitive state q_ref + stored offset
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qa[v] = a.lv.q_ref[v] + qv[v];
 
   double ij = 0.0;
   {
@@ -86,8 +89,8 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       ij = m[4 * sstride + gp];
     }
     double fs[NV], ft[NV];
-    normal_flux2(qv, sx, sy, a.gas, fs);
-    normal_flux2(qv, tx, ty, a.gas, ft);
+    normal_flux2(qa, sx, sy, a.gas, fs);
+    normal_flux2(qa, tx, ty, a.gas, ft);
     if (act) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -142,23 +145,34 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       } else if (nb == -1) {             // slip wall: reflect the normal velocity
         const double inv = 1.0 / sqrt(fx * fx + fy * fy);
         const double nx = fx * inv, ny = fy * inv;
-        const double un = own[1] * nx + own[2] * ny;
+        const double ua = a.lv.q_ref[1] + own[1], va = a.lv.q_ref[2] + own[2];
+        const double un = ua * nx + va * ny;
         out[0] = own[0];
-        out[1] = own[1] - 2.0 * un * nx;
-        out[2] = own[2] - 2.0 * un * ny;
+        out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+        out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
         out[3] = own[3];
       } else if (nb == -2) {             // far field
 #pragma unroll
-        for (int v = 0; v < NV; ++v) out[v] = a.lv.q_inf[v];
+        for (int v = 0; v < NV; ++v) out[v] = a.lv.qinf_g[v];
       } else {                           // padding element of the last workgroup
 #pragma unroll
         for (int v = 0; v < NV; ++v) out[v] = own[v];
       }
-      double fh[NV];
-      if (f == 0 || f == 2)
-        common_flux2(out, own, fx, fy, a.gas, fh);
-      else
-        common_flux2(own, out, fx, fy, a.gas, fh);
+      double own_a[NV], out_a[NV], dq[NV], fh[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        own_a[v] = a.lv.q_ref[v] + own[v];
+        out_a[v] = a.lv.q_ref[v] + out[v];
+      }
+      if (f == 0 || f == 2) {            // the neighbour is the '-' side
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
+        common_flux2(out_a, own_a, dq, fx, fy, a.gas, fh);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
+        common_flux2(own_a, out_a, dq, fx, fy, a.gas, fh);
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) SJ(f, k, v, el) = fh[v] - floc[v];
     }
@@ -168,7 +182,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   double Fv[NV];
   {
     double qc[NV];
-    conservative2(qv, a.gas, qc);
+    conservative2(qa, a.gas, qc);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double d = 0.0;

@@ -32,7 +32,8 @@ struct LevelView {
   const int* nbr;       // [4][Ne]
   const int* nbf;       // [4][Ne]
   const int* ori;       // [4][Ne]
-  double q_inf[4];
+  double q_ref[4];      // stored states are q - q_ref
+  double qinf_g[4];     // far-field state in stored form, q_inf - q_ref
 };
 
 struct KernelStatus {
@@ -45,6 +46,7 @@ struct pmg_level_s {
   int dim = 2, P = 0, n1 = 1, np = 1, nv = 4, n = 4, ne = 0, geom_order = 1, device = 0;
   pmg::GasParams gas{};
   double q_inf[5] = {0, 0, 0, 0, 0};
+  double q_ref[5] = {0, 0, 0, 0, 0};
   pmg::Ops1D ops{};
   std::vector<double> x1, w1;       // 1-D Gauss points/weights
   std::vector<double> xy_host;      // [2][Np][Ne] solution-point coordinates
@@ -74,7 +76,10 @@ struct pmg_level_s {
     v.nbr = nbr;
     v.nbf = nbf;
     v.ori = ori;
-    for (int k = 0; k < 4; ++k) v.q_inf[k] = q_inf[k];
+    for (int k = 0; k < 4; ++k) {
+      v.q_ref[k] = q_ref[k];
+      v.qinf_g[k] = q_inf[k] - q_ref[k];
+    }
     return v;
   }
 };

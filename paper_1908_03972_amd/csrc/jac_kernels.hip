@@ -74,10 +74,10 @@ __global__ void __launch_bounds__(256) k_jac(JacArgs a) {
   for (int t = tid; t < NP * NV; t += blockDim.x) {
     const int pp = t / NV, w = t % NV;
     Dual<1> qd[NV];
-    double qv[NV];
+    double qv[NV];                       // absolute state: q_ref + stored offset
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      qv[v] = sq[v * NP + pp];
+      qv[v] = a.lv.q_ref[v] + sq[v * NP + pp];
       qd[v] = dconst<1>(qv[v]);
     }
     qd[w].d[0] = 1.0;
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_jac(JacArgs a) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) ownv[v] += wt[mm] * sq[v * NP + pp];
     }
-    Dual<1> own[NV], out[NV];
+    Dual<1> own[NV], out[NV];            // stored offsets; own seeded in component w
 #pragma unroll
     for (int v = 0; v < NV; ++v) own[v] = dconst<1>(ownv[v]);
     own[w].d[0] = 1.0;
@@ -132,20 +132,31 @@ __global__ void __launch_bounds__(256) k_jac(JacArgs a) {
     } else if (nb == -1) {
       const double inv = 1.0 / sqrt(fx * fx + fy * fy);
       const double nx = fx * inv, ny = fy * inv;
-      Dual<1> un = own[1] * nx + own[2] * ny;
+      Dual<1> ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2];
+      Dual<1> un = ua * nx + va * ny;
       out[0] = own[0];
-      out[1] = own[1] - 2.0 * un * nx;
-      out[2] = own[2] - 2.0 * un * ny;
+      out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+      out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
       out[3] = own[3];
     } else {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.q_inf[v]);
+      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.qinf_g[v]);
     }
-    Dual<1> fh[NV];
-    if (f == 0 || f == 2)
-      common_flux2(out, own, fx, fy, a.gas, fh);
-    else
-      common_flux2(own, out, fx, fy, a.gas, fh);
+    Dual<1> own_a[NV], out_a[NV], dq[NV], fh[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      own_a[v] = own[v] + a.lv.q_ref[v];
+      out_a[v] = out[v] + a.lv.q_ref[v];
+    }
+    if (f == 0 || f == 2) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
+      common_flux2(out_a, own_a, dq, fx, fy, a.gas, fh);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
+      common_flux2(own_a, out_a, dq, fx, fy, a.gas, fh);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) sB[((f * N1 + k) * NV + v) * NV + w] = fh[v].d[0];
   }

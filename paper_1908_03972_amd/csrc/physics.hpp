@@ -248,12 +248,14 @@ __device__ __forceinline__ void flux_jac_mul(const State2<T>& s, const GasParams
 
 // Common inviscid flux of eq. (21), multiplied by |S|:
 //   |S| [ (f_n(q-) + f_n(q+))/2 - Gamma |Gamma^{-1} A_n| (q+ - q-)/2 ]
+// The jump dq = q+ - q- is passed in: callers form it from the stored offsets q - q_ref, which
+// keeps it exact to the size of the disturbance where q+ and q- are large and nearly equal.
 // at the arithmetic mean of the primitive states. The matrix function is applied as the
 // quadratic that interpolates |lambda| at the three distinct eigenvalues of eq. (13)
 // (Newton divided differences), so that
 //   Gamma |X| dq = |l1| G dq + f12 (A - l1 G) dq + f123 (A - l1 G) G^{-1} (A - l2 G) dq.
 template <class T>
-__device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], double sx, double sy,
+__device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], const T dq[4], double sx, double sy,
                                              const GasParams& g, T out[4]) {
   const double smag = sqrt(sx * sx + sy * sy);
   const double nx = sx / smag, ny = sy / smag;
@@ -272,9 +274,6 @@ __device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], doubl
   T f13 = (a3 - a1) / (l3 - l1);
   T f123 = (f13 - f12) / (l3 - l2);
 
-  T dq[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) dq[k] = qp[k] - qm[k];
   T gd[4], ad[4], w[4], y[4], ay[4];
   gamma_mul(s, g, dq, gd);
   flux_jac_mul(s, g, nx, ny, un, dq, ad);

@@ -61,13 +61,17 @@ __global__ void __launch_bounds__(256) k_prolong(int ne, int nvar, int nc1, int 
   xf[idx] += acc;
 }
 
-__global__ void __launch_bounds__(256) k_conservative(int n_points, GasParams g, const double* __restrict__ q,
-                                                      double* __restrict__ qc) {
+struct Ref4 {
+  double v[4];
+};
+
+__global__ void __launch_bounds__(256) k_conservative(int n_points, GasParams g, Ref4 ref,
+                                                      const double* __restrict__ q, double* __restrict__ qc) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n_points) return;
   double qv[4], out[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) qv[v] = q[(size_t)v * n_points + idx];
+  for (int v = 0; v < 4; ++v) qv[v] = ref.v[v] + q[(size_t)v * n_points + idx];
   conservative2(qv, g, out);
 #pragma unroll
   for (int v = 0; v < 4; ++v) qc[(size_t)v * n_points + idx] = out[v];
@@ -140,7 +144,9 @@ hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const do
 hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc, hipStream_t st) {
   const int npts = L.np * L.ne;
   if (npts == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_conservative, dim3(blocks_for(npts)), dim3(256), 0, st, npts, L.gas, q, qc);
+  Ref4 ref{};
+  for (int k = 0; k < 4; ++k) ref.v[k] = L.q_ref[k];
+  hipLaunchKernelGGL(k_conservative, dim3(blocks_for(npts)), dim3(256), 0, st, npts, L.gas, ref, q, qc);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def make_levels(mesh, P, vs: W.VortexSpec, device=0):
     gas = gas_for(vs)
     olev = FRLevel(mesh, P, gas, q_inf=vs.freestream())
     glev = api.Level(mesh, P, gamma=vs.gamma, rgas=vs.rgas, eps_mode=0, ma_inf=vs.ma_inf,
-                     q_inf=vs.freestream(), device=device)
+                     q_inf=vs.freestream(), q_ref=vs.freestream(), device=device)
     return olev, glev
 
 

@@ -26,6 +26,7 @@ MESHES = {
 
 
 VS = W.VortexSpec(length=10.0)
+REF = VS.freestream()          # the HIP levels store states as offsets q - REF
 
 
 def scaled_block_error(got, ref, q):
@@ -66,7 +67,7 @@ def test_residual_parity(mesh_name, P):
     ref = oracle_F(q)
     F = glev.new_state()
     norms = torch.zeros(5, dtype=torch.float64, device="cuda")
-    api.fr_residual(glev, to_dev(q), F, src=to_dev(src), S=to_dev(S), c_mass=c_mass, norms=norms)
+    api.fr_residual(glev, to_dev(q - REF), F, src=to_dev(src), S=to_dev(S), c_mass=c_mass, norms=norms)
     torch.cuda.synchronize()
     got = from_dev(F)
     err = rel_err_per_var(got, ref)
@@ -82,9 +83,8 @@ def test_residual_parity(mesh_name, P):
 def test_residual_freestream_on_gpu():
     mesh = MESHES["cfg2_64x64"]()
     olev, glev = make_levels(mesh, 3, VS)
-    q = np.broadcast_to(VS.freestream(), (olev.ne, olev.npts, 4)).copy()
     F = glev.new_state()
-    api.fr_residual(glev, to_dev(q), F)
+    api.fr_residual(glev, glev.new_state(), F)           # the free stream is the zero offset
     got = from_dev(F)
     # each term of R is a flux over the element size: scale by p_inf |V_inf| max(|S|/|J|)
     speed = np.hypot(*VS.u_inf)
@@ -122,7 +122,7 @@ def test_element_blocks_parity(mesh_name, P):
     ref = element_blocks(olev, q, dtau, c_mass)                      # [Ne, n, n]
     fac = api.Factors(glev, 64)
     D = torch.zeros(glev.ne * glev.n * glev.n, dtype=torch.float64, device="cuda")
-    api.fr_element_jacobian(glev, to_dev(q), dtau, c_mass, fac, D_out=D)
+    api.fr_element_jacobian(glev, to_dev(q - REF), dtau, c_mass, fac, D_out=D)
     torch.cuda.synchronize()
     assert glev.status() == 0
     got = D.cpu().numpy().reshape(glev.ne, glev.n, glev.n)
@@ -148,15 +148,16 @@ def test_sweep_parity(mesh_name, P, prec):
     ref = oracle_sweeps(q)
     rng = np.random.default_rng(11)
     q_pert = q * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q.shape))
-    floor = rel_err_per_var(oracle_sweeps(q_pert) - VS.freestream(), ref - VS.freestream())
+    ref_pert = oracle_sweeps(q_pert)
+    floor = rel_err_per_var(ref_pert - VS.freestream(), ref - VS.freestream())
     fac = api.Factors(glev, prec)
-    qd = to_dev(q)
+    qd = to_dev(q - REF)
     api.fr_element_jacobian(glev, qd, dtau, c_mass, fac)
     Fa = glev.new_state()
     api.ejacobi_sweep(glev, fac, qd, 3, src=to_dev(src), c_mass=c_mass, F_after=Fa)
     torch.cuda.synchronize()
-    got = from_dev(qd)
-    err = rel_err_per_var(got - VS.freestream(), ref - VS.freestream())
+    got = from_dev(qd)                                   # offsets from REF = q_inf
+    err = rel_err_per_var(got, ref - VS.freestream())
     print(mesh_name, P, prec, "sweep err", err, "floor", floor)
     if prec == 64:
         assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
@@ -164,9 +165,13 @@ def test_sweep_parity(mesh_name, P, prec):
         # FP32 blocks: each sweep's update carries ~u_32 cond(S_r D) relative error
         assert np.all(err < 1e-4), err
     Fref = olev.stage_residual(ref, c_mass, src)
+    ffloor = rel_err_per_var(olev.stage_residual(ref_pert, c_mass, src), Fref)
     ferr = rel_err_per_var(from_dev(Fa), Fref)
-    print("F_after err", ferr)
-    assert np.all(ferr < (1e-8 if prec == 64 else 1e-2)), ferr
+    print("F_after err", ferr, "floor", ffloor)
+    if prec == 64:
+        assert np.all(ferr <= np.maximum(1e-11, 10.0 * ffloor)), (ferr, ffloor)
+    else:
+        assert np.all(ferr < 1e-2), ferr
 
 
 def _stage_case(case):
@@ -206,17 +211,17 @@ def test_stage_solve_parity(case):
     q_pert, _ = run_oracle(q0 * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q0.shape)))
     floor = rel_err_per_var(q_pert - qinf, q_ref - qinf)
 
-    glevels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf)
-               for P in plev]
+    glevels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf,
+                         q_ref=REF) for P in plev]
     facs = [api.Factors(lv, prec) for lv in glevels]
     solver = api.StageSolver(glevels, facs, nsm, max_vcycles=nvc, tol_rel=1e-30)
-    q = to_dev(q0)
+    q = to_dev(q0 - REF)
     qc = OG.conservative(q0, gas)
     out = solver.solve(q, omega=om, dt=dt, qc_n=to_dev(qc), R_prev=[to_dev(olev.residual(q0))],
                        a_row=[A[1, 0]], raise_on_error=False)
     torch.cuda.synchronize()
     assert out["status"] == -6 and out["n_vcycles"] == nvc      # PMG_E_NOT_CONVERGED at max_vcycles
-    err = rel_err_per_var(from_dev(q) - qinf, q_ref - qinf)
+    err = rel_err_per_var(from_dev(q), q_ref - qinf)
     h_ref = np.array(st.history)
     h_err = np.abs(np.array(out["history"]) - h_ref) / h_ref
     print(case, "state err", err, "floor", floor, "history err", h_err)
@@ -228,3 +233,43 @@ def test_stage_solve_parity(case):
         # FP32 blocks: the smoother's update carries u_32 * cond(S_r D) relative error per sweep
         assert np.all(err < 1e-4), err
         assert np.all(h_err < 1e-3)
+
+
+def test_esdirk_step_parity():
+    """One ESDIRK2 time step (eq. (24)) through the C ABI against the oracle's driver, stages
+    converged to a 1e-4 relative drop."""
+    from gpu_helpers import gas_for
+    mesh = MESHES["cfg1_8x8"]()
+    plev, nsm = (2, 1, 0), (5, 10, 20)
+    gas = gas_for(VS)
+    opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, tol=1e-4, max_vcycles=60)
+    osol = OS.PMGSolver(mesh, gas, opts, q_inf=VS.freestream())
+    q0 = vortex_on(osol.levels[0], VS)
+    q_ref, st_ref = osol.esdirk_step(q0, 0.05, OS.esdirk_tableau("esdirk2"))
+    qinf = VS.freestream()
+    glevels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf,
+                         q_ref=REF) for P in plev]
+    facs = [api.Factors(lv, 64) for lv in glevels]
+    solver = api.StageSolver(glevels, facs, nsm, tol_rel=1e-4, max_vcycles=60)
+    q = to_dev(q0 - REF)
+    work = torch.zeros((3,) + glevels[0].shape, dtype=torch.float64, device="cuda")
+    stats = api.esdirk_step(solver, 2, 0.05, q, work)
+    torch.cuda.synchronize()
+    assert [s["n_vcycles"] for s in stats] == [s.n_vcycles for s in st_ref]
+    err = rel_err_per_var(from_dev(q), q_ref - qinf)
+    print("esdirk step err", err, [s["n_vcycles"] for s in stats])
+    assert np.all(err < 1e-8), err
+
+
+def test_residual_parity_plain_storage():
+    """q_ref = 0: the level stores absolute primitive states."""
+    mesh = MESHES["cfg1_8x8"]()
+    olev, _ = make_levels(mesh, 2, VS)
+    glev = api.Level(mesh, 2, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=REF)
+    q = vortex_on(olev, VS)
+    ref = olev.residual(q)
+    F = glev.new_state()
+    api.fr_residual(glev, to_dev(q), F)
+    err = rel_err_per_var(from_dev(F), ref)
+    tol = tolerance(rounding_floor(olev.residual, q))
+    assert np.all(err <= tol), (err, tol)
