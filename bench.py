@@ -89,14 +89,79 @@ def cpu_baseline(n_side=32):
             "cpu": platform.processor() or platform.machine()}
 
 
+FORMS = {"mixed": (32, True), "fp64": (64, False)}   # (block precision, graph replay)
+TOLS = (1e-4, 1e-6, 1e-8)
+
+
+def time_to_tolerances(stage_stats):
+    """Per stage: wall time until r_m / r_0 first fell to each tolerance (None if never), from
+    the residual history and the stage's mean V-cycle time."""
+    out = {f"{t:.0e}": [] for t in TOLS}
+    floors = []
+    for st in stage_stats:
+        h = np.asarray(st["history"])
+        floors.append(float(h.min() / h[0]))
+        per_vc = st["seconds"] / max(st["n_vcycles"], 1)
+        for t in TOLS:
+            hit = np.nonzero(h / h[0] <= t)[0]
+            out[f"{t:.0e}"].append(float(hit[0] * per_vc) if hit.size else None)
+    return out, floors
+
+
+def run_form(api, torch, levels, q0, form, scheme, dt, steps, warmup, max_vcycles, work):
+    prec, graph = FORMS[form]
+    facs = [api.Factors(lv, prec) for lv in levels]
+    solver = api.StageSolver(levels, facs, N_SMOOTH if len(levels) == 3 else (5, 10, 20)[:len(levels)],
+                             dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5, refresh_every=10, freeze_at_max=True,
+                             tol_rel=1e-8, max_vcycles=max_vcycles, use_graph=graph)
+    q = q0.clone()
+    for _ in range(warmup):
+        api.esdirk_step(solver, scheme, dt, q, work, raise_on_error=False)
+    q.copy_(q0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stage_stats = []
+    for _ in range(steps):
+        stage_stats += api.esdirk_step(solver, scheme, dt, q, work, raise_on_error=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return facs, solver, q, stage_stats, elapsed
+
+
+PROFILE_PMC = os.path.join(ROOT, "profiles", "k_fr_sweep_vortex64_P321_pmc.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fr_kernels.hip", "physics.hpp", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1908_03972_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused P=3 sweep from the committed counter summary, or None
+    when the kernel sources have changed since the counters were taken."""
+    try:
+        vals = dict(line.split(": ", 1) for line in open(PROFILE_PMC).read().splitlines()
+                    if line.startswith(("traffic_bytes_per_launch:", "kernel_source_hash:")))
+    except (OSError, ValueError):
+        return None
+    if vals.get("kernel_source_hash", "").strip() != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--max-vcycles", type=int, default=2000)
+    ap.add_argument("--max-vcycles", type=int, default=400)
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the 8x8 time-to-1e-8 measurement")
     ap.add_argument("--kernel-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -108,38 +173,29 @@ def main():
     from paper_1908_03972_amd import api
 
     dev = torch.device("cuda", 0)
+
+    def setup(mesh, vs, plev):
+        qinf = vs.freestream()
+        levels = [api.Level(mesh, P, gamma=vs.gamma, rgas=vs.rgas, eps_mode=0, ma_inf=vs.ma_inf,
+                            q_inf=qinf, q_ref=qinf) for P in plev]
+        xy = levels[0].points()
+        # states are stored as offsets from the free stream (gauge pressure and temperature)
+        q0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(vs.state(xy[0], xy[1]) - qinf, -1, 0))).to(dev)
+        return levels, q0
+
     mesh, vs = W.vortex_config2()
-    qinf = vs.freestream()
-    levels = [api.Level(mesh, P, gamma=vs.gamma, rgas=vs.rgas, eps_mode=0, ma_inf=vs.ma_inf,
-                        q_inf=qinf, q_ref=qinf) for P in P_LEVELS]
+    levels, q0 = setup(mesh, vs, P_LEVELS)
     L0 = levels[0]
-    xy = L0.points()
-    # states are stored as offsets from the free stream (gauge pressure and temperature)
-    q0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(vs.state(xy[0], xy[1]) - qinf, -1, 0))).to(dev)
-    s = api.esdirk_stages(SCHEME)
-    work = torch.zeros((s,) + L0.shape, dtype=torch.float64, device=dev)
+    work = torch.zeros((api.esdirk_stages(SCHEME),) + L0.shape, dtype=torch.float64, device=dev)
     per_vc = dof_updates_per_vcycle(L0.ne, P_LEVELS, N_SMOOTH)
 
     results = {}
     finals = {}
     for form in args.forms.split(","):
-        prec = 32 if form == "mixed" else 64
-        facs = [api.Factors(lv, prec) for lv in levels]
-        solver = api.StageSolver(levels, facs, N_SMOOTH, dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5,
-                                 refresh_every=10, freeze_at_max=True, tol_rel=1e-8, max_vcycles=args.max_vcycles)
-        q = q0.clone()
-        for _ in range(args.warmup):
-            api.esdirk_step(solver, SCHEME, DT, q, work, raise_on_error=False)
-        q.copy_(q0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stage_stats = []
-        for _ in range(args.steps):
-            stage_stats += api.esdirk_step(solver, SCHEME, DT, q, work, raise_on_error=False)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
+        facs, solver, q, stage_stats, elapsed = run_form(api, torch, levels, q0, form, SCHEME, DT, args.steps,
+                                                         args.warmup, args.max_vcycles, work)
         nvc = sum(st["n_vcycles"] for st in stage_stats)
-        converged = all(st["status"] == 0 for st in stage_stats)
+        ttt, floors = time_to_tolerances(stage_stats)
         # live per-launch duration of the dominant kernel: the fused residual + sweep on the
         # finest level, timed with HIP events on the stream the library launches on
         # (alpha_r = 0 keeps the state fixed; the kernel does the same work)
@@ -153,17 +209,21 @@ def main():
         torch.cuda.synchronize()
         k_ms = ev0.elapsed_time(ev1) / args.kernel_reps
         n = L0.n
+        prec = FORMS[form][0]
         bytes_per_dof = (4 if prec == 32 else 8) * n + 24
         launch_bytes = L0.ne * n * bytes_per_dof
         results[form] = {
+            "block_precision": prec, "graph_replay": FORMS[form][1],
             "dof_updates_per_s": nvc * per_vc / elapsed,
             "elapsed_s": elapsed,
             "ms_per_step": 1e3 * elapsed / args.steps,
+            "ms_per_vcycle": 1e3 * elapsed / max(nvc, 1),
             "vcycles": nvc,
             "vcycles_per_stage": [st["n_vcycles"] for st in stage_stats],
-            "time_to_1e-8_s_mean": float(np.mean([st["seconds"] for st in stage_stats])),
-            "time_to_1e-8_s_total": float(np.sum([st["seconds"] for st in stage_stats])),
-            "converged": converged,
+            "stages_converged_to_1e-8": sum(st["status"] == 0 for st in stage_stats),
+            "stages": len(stage_stats),
+            "time_to_tol_s_per_stage": ttt,
+            "min_rel_residual_per_stage": floors,
             "sweep_kernel_ms": k_ms,
             "sweep_bytes_per_launch": launch_bytes,
             "sweep_bytes_per_dof_update": bytes_per_dof,
@@ -174,6 +234,11 @@ def main():
     head = "mixed" if "mixed" in results else next(iter(results))
     r = results[head]
     achieved = r["sweep_bytes_per_launch"] / (r["sweep_kernel_ms"] * 1e-3) / 1e9
+
+    def mean_time(res, tol):
+        v = [x for x in res["time_to_tol_s_per_stage"][tol] if x is not None]
+        return float(np.mean(v)) if len(v) == len(res["time_to_tol_s_per_stage"][tol]) else None
+
     line = {
         "metric": METRIC,
         "value": r["dof_updates_per_s"],
@@ -188,22 +253,42 @@ def main():
         "dtype": "f64+f32" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "isentropic vortex Ma 0.005, periodic 64x64 jittered quads, P{3-2-1} I{5-10-20}, "
-                               "ESDIRK3 dt 0.05, stages to 1e-8",
+                               f"ESDIRK3 dt 0.05, stages to 1e-8 or {args.max_vcycles} V-cycles",
                    "elements": L0.ne, "dof_fine": L0.ne * L0.n, "dof_updates_per_vcycle": per_vc,
                    "form": head},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_fr<3,{2 if head == 'mixed' else 1}> (fused residual + element-Jacobi sweep, P=3)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if FORMS[head][0] == 32 else None,
+                     "kernel": f"k_fr<3,{2 if FORMS[head][0] == 32 else 1}> (fused residual + element-Jacobi sweep, P=3)",
                      "kernel_ms": r["sweep_kernel_ms"], "bytes_per_launch": r["sweep_bytes_per_launch"]},
-        "time_to_1e-8_s": r["time_to_1e-8_s_mean"],
+        "time_to_1e-4_s": mean_time(r, "1e-04"),
+        "time_to_1e-8_s": mean_time(r, "1e-08"),
         "forms": results,
     }
     if "mixed" in finals and "fp64" in finals:
         d = finals["fp64"]                     # offsets from the free stream
         line["mixed_vs_fp64_rel_err"] = (np.linalg.norm((finals["mixed"] - finals["fp64"]).reshape(4, -1), axis=1)
                                          / np.linalg.norm(d.reshape(4, -1), axis=1)).tolist()
-        line["speedup_time_to_1e-8_mixed_over_fp64"] = (results["fp64"]["time_to_1e-8_s_total"]
-                                                        / results["mixed"]["time_to_1e-8_s_total"])
+        t_m, t_f = mean_time(results["mixed"], "1e-04"), mean_time(results["fp64"], "1e-04")
+        line["speedup_time_to_1e-4_mixed_over_fp64"] = (t_f / t_m) if (t_m and t_f) else None
+    if not args.no_small:
+        # time to the 1e-8 drop where it is reachable: the 8x8 P{2-1-0} ESDIRK2 vortex
+        m1, v1 = W.vortex_config1()
+        lv1, q1 = setup(m1, v1, (2, 1, 0))
+        w1 = torch.zeros((api.esdirk_stages(2),) + lv1[0].shape, dtype=torch.float64, device=dev)
+        small = {}
+        for form in args.forms.split(","):
+            _, _, _, sst, el = run_form(api, torch, lv1, q1, form, 2, DT, 5, 1, 2000, w1)
+            ttt, floors = time_to_tolerances(sst)
+            small[form] = {"elapsed_s": el, "stages": len(sst),
+                           "stages_converged_to_1e-8": sum(s["status"] == 0 for s in sst),
+                           "vcycles_per_stage": [s["n_vcycles"] for s in sst],
+                           "time_to_1e-8_s_mean": mean_time({"time_to_tol_s_per_stage": ttt}, "1e-08"),
+                           "time_to_1e-8_s_total": float(sum(s["seconds"] for s in sst))}
+        if "mixed" in small and "fp64" in small and small["mixed"]["time_to_1e-8_s_total"] > 0:
+            small["speedup_time_to_1e-8_mixed_over_fp64"] = (small["fp64"]["time_to_1e-8_s_total"]
+                                                             / small["mixed"]["time_to_1e-8_s_total"])
+        line["time_to_1e-8_8x8_P210_esdirk2"] = small
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

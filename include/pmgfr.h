@@ -195,6 +195,8 @@ typedef struct {
   double tol_rel;                 /* stop when ||F(q^m)|| / ||F(q^0)|| <= tol_rel                */
   int32_t max_vcycles;
   double alpha_r;                 /* relaxation of eq. (30), 1 in the paper                      */
+  int32_t use_graph;              /* 1: replay V-cycles without a block rebuild from a HIP graph
+                                     captured once per argument set (same results, fewer launches) */
 } pmg_solve_opts;
 
 typedef struct {
@@ -236,8 +238,9 @@ pmg_status esdirk_stage_solve(const pmg_solve_opts* opts, double omega, double d
  *   q       device state, in q^n, out q^{n+1}.
  *   work    device, (number of stages) consecutive state arrays: q_c^n and the stage residuals.
  *   stats   host array of n_stats entries or NULL: one per implicit stage.
- * Returns the first failing stage's status (its stats say which); q then holds that stage's
- * last iterate.
+ * A stage that reaches max_vcycles leaves its last iterate as the stage value and the later
+ * stages still run; the step then returns PMG_E_NOT_CONVERGED. Any other failure stops the step
+ * with that status (recorded in the stats of the stages not run); q holds the last iterate.
  */
 pmg_status esdirk_step(const pmg_solve_opts* opts, int32_t scheme, double dt, double* q, double* work,
                        pmg_solve_stats* stats, int32_t n_stats, void* stream);

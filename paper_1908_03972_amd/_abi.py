@@ -44,6 +44,7 @@ class SolveOpts(C.Structure):
         ("n_smooth", C.POINTER(C.c_int32)), ("dtau_init", C.c_double), ("dtau_max", C.c_double),
         ("ser_exponent", C.c_double), ("refresh_every", C.c_int32), ("freeze_at_max", C.c_int32),
         ("tol_rel", C.c_double), ("max_vcycles", C.c_int32), ("alpha_r", C.c_double),
+        ("use_graph", C.c_int32),
     ]
 
 

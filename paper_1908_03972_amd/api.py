@@ -163,7 +163,8 @@ class StageSolver:
     """Holds the levels, factors and options of ``esdirk_stage_solve``."""
 
     def __init__(self, levels, factors, n_smooth, *, dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5,
-                 refresh_every=10, freeze_at_max=True, tol_rel=1e-8, max_vcycles=200, alpha_r=1.0):
+                 refresh_every=10, freeze_at_max=True, tol_rel=1e-8, max_vcycles=200, alpha_r=1.0,
+                 use_graph=False):
         self.levels = list(levels)
         self.factors = list(factors)
         nl = len(self.levels)
@@ -175,6 +176,7 @@ class StageSolver:
         o.dtau_init, o.dtau_max, o.ser_exponent = dtau_init, dtau_max, ser_exponent
         o.refresh_every, o.freeze_at_max, o.tol_rel = refresh_every, int(freeze_at_max), tol_rel
         o.max_vcycles, o.alpha_r = max_vcycles, alpha_r
+        o.use_graph = int(use_graph)
         self.opts = o
 
     def solve(self, q, *, omega=0.0, dt=0.0, qc_n=None, R_prev=(), a_row=(), R_out=None, stream=None,
@@ -204,7 +206,7 @@ def esdirk_stages(scheme: int) -> int:
 
 def esdirk_step(solver: StageSolver, scheme: int, dt: float, q, work, stream=None, raise_on_error=True):
     """One time step of ``esdirk_step``; ``work`` is a float64 device tensor of shape
-    (stages, Nv, Np, Ne). Returns one stats dict per implicit stage."""
+    (stages, Nv, Np, Ne). Returns one stats dict per implicit stage (with its residual history)."""
     L0 = solver.levels[0]
     s = esdirk_stages(scheme)
     if s == 0:
@@ -213,10 +215,16 @@ def esdirk_step(solver: StageSolver, scheme: int, dt: float, q, work, stream=Non
             or work.device != L0.torch_device:
         raise ValueError(f"work must be a contiguous float64 tensor of shape {(s,) + L0.shape}")
     stats = (A.SolveStats * (s - 1))()
+    cap = solver.opts.max_vcycles + 1
+    hists = [(C.c_double * cap)() for _ in range(s - 1)]
+    for st, h in zip(stats, hists):
+        st.history = C.cast(h, C.POINTER(C.c_double))
+        st.history_capacity = cap
     status = A.lib().esdirk_step(C.byref(solver.opts), scheme, dt, L0.check_state(q, "q", False),
                                  C.c_void_p(work.data_ptr()), stats, s - 1, _stream(stream))
     out = [{"status": st.status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh, "r0": st.r0,
-            "r_final": st.r_final, "seconds": st.seconds} for st in stats]
+            "r_final": st.r_final, "seconds": st.seconds,
+            "history": list(h[:min(st.n_vcycles + 1, cap)])} for st, h in zip(stats, hists)]
     if raise_on_error:
         A.check(status, "esdirk_step")
     return out

@@ -214,6 +214,8 @@ pmg_status alloc_zero(double** dst, size_t n) {
 
 void free_level(pmg_level_s* L) {
   if (!L) return;
+  if (L->vc_exec) (void)hipGraphExecDestroy(L->vc_exec);
+  if (L->capture_stream) (void)hipStreamDestroy(L->capture_stream);
   void* ptrs[] = {L->met, L->fvec, L->nbr, L->nbf, L->ori, L->wq,    L->wF,
                   L->wS,  L->wqb,  L->wql, L->wsrc, L->part, L->norms, L->flag};
   for (void* p : ptrs)
@@ -222,6 +224,28 @@ void free_level(pmg_level_s* L) {
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// n synchronous element-Jacobi sweeps ping-ponging between q and the level's workspace (kernels
+// only, so the sequence can be captured in a graph); optional norms of the first sweep's F and
+// F_after = F(q) - S at the final state.
+pmg_status run_sweeps(pmg_level_s& L, const pmg_factors_s& fac, double* q, const double* src, const double* S,
+                      double c_mass, int n, double alpha, double* F_after, bool norms, hipStream_t st) {
+  double* in = q;
+  double* out = L.wq;
+  for (int k = 0; k < n; ++k) {
+    const bool nrm = norms && k == 0;
+    PMG_HIP(pmg::launch_sweep(L, fac, in, out, src, S, c_mass, alpha, nrm, st));
+    if (nrm) PMG_HIP(pmg::launch_norm_finalize(L, st));
+    std::swap(in, out);
+  }
+  if (in != q) PMG_HIP(pmg::launch_copy(L.state_elems(), in, q, st));
+  if (F_after) {
+    const bool nrm = norms && n == 0;
+    PMG_HIP(pmg::launch_residual(L, q, src, S, c_mass, F_after, nrm, st));
+    if (nrm) PMG_HIP(pmg::launch_norm_finalize(L, st));
+  }
+  return PMG_OK;
+}
 
 pmg_status check_level(pmg_level L) {
   if (!L) return fail(PMG_E_ARG, "null level handle");
@@ -286,7 +310,7 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
 
   // metrics from the exact mapping at solution and flux points
   const int n1 = L->n1, np = L->np, g = d->geom_order, nn = (g + 1) * (g + 1);
-  std::vector<double> met((size_t)5 * np * ne), fvec((size_t)4 * n1 * 2 * ne);
+  std::vector<double> met((size_t)5 * np * ne), fvec((size_t)4 * n1 * 3 * ne);
   L->xy_host.assign((size_t)2 * np * ne, 0.0);
   for (int e = 0; e < ne; ++e) {
     const double* nodes = d->nodes + (size_t)e * nn * 2;
@@ -321,9 +345,11 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
         const MapEval m = map_at(nodes, g, xi, eta);
         const double vx = (f < 2) ? m.y_eta : -m.y_xi;
         const double vy = (f < 2) ? -m.x_eta : m.x_xi;
-        const size_t o = ((size_t)(f * n1 + k) * 2) * ne + e;
-        fvec[o] = vx;
-        fvec[o + ne] = vy;
+        const double len = std::sqrt(vx * vx + vy * vy);
+        const size_t o = ((size_t)(f * n1 + k) * 3) * ne + e;
+        fvec[o] = vx / len;
+        fvec[o + ne] = vy / len;
+        fvec[o + 2 * ne] = len;
       }
   }
   std::vector<int> nbr((size_t)4 * ne), nbf((size_t)4 * ne), ori((size_t)4 * ne);
@@ -475,28 +501,9 @@ pmg_status ejacobi_sweep(pmg_level L, pmg_factors fac, double* q, const double* 
   if (F_after == q) return fail(PMG_E_ARG, "F_after must not alias q");
   DeviceGuard guard(L->device);
   hipStream_t st = as_stream(stream);
-  double* in = q;
-  double* out = L->wq;
-  for (int s = 0; s < n_sweeps; ++s) {
-    const bool nrm = (s == 0) && norms;
-    PMG_HIP(pmg::launch_sweep(*L, *fac, in, out, src, S, c_mass, alpha_r, nrm, st));
-    if (nrm) {
-      PMG_HIP(pmg::launch_norm_finalize(*L, st));
-      if (norms != L->norms)
-        PMG_HIP(hipMemcpyAsync(norms, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    }
-    std::swap(in, out);
-  }
-  if (in != q) PMG_HIP(hipMemcpyAsync(q, in, L->state_elems() * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (F_after) {
-    const bool nrm = (n_sweeps == 0) && norms;
-    PMG_HIP(pmg::launch_residual(*L, q, src, S, c_mass, F_after, nrm, st));
-    if (nrm) {
-      PMG_HIP(pmg::launch_norm_finalize(*L, st));
-      if (norms != L->norms)
-        PMG_HIP(hipMemcpyAsync(norms, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    }
-  }
+  if (pmg_status r = run_sweeps(*L, *fac, q, src, S, c_mass, n_sweeps, alpha_r, F_after, norms != nullptr, st))
+    return r;
+  if (norms && norms != L->norms) PMG_HIP(pmg::launch_copy(L->nv + 1, L->norms, norms, st));
   return PMG_OK;
 }
 
@@ -560,21 +567,81 @@ pmg_status vcycle(Solve& s, int l, double* q, const double* S) {
     ++s.n_refresh;
   }
   // pre-smoothing; F_after = F_l(q^a) - S_l = -d_l
-  if (pmg_status r = ejacobi_sweep(L, fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r,
-                                   last ? nullptr : L->wF, nullptr, s.st))
+  if (pmg_status r = run_sweeps(*L, *fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r, last ? nullptr : L->wF,
+                                false, s.st))
     return r;
   if (last) return PMG_OK;
   pmg_level Lc = o->levels[l + 1];
-  // q^b_{l+1} = P q^a_l (eqs. (39), (42)); the coarse working state starts there
-  PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), q, Lc->wqb, Lc->nv, s.st));
-  PMG_HIP(hipMemcpyAsync(Lc->wql, Lc->wqb, Lc->state_elems() * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+  // q^b_{l+1} = P q^a_l (eqs. (39), (42)), written also to the coarse working state
+  PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), q, Lc->wqb, Lc->nv, s.st, Lc->wql));
   // S_{l+1} = F_{l+1}(q^b) + P d_l = F_{l+1}(q^b) - P (F_l(q^a) - S_l)  (eqs. (40), (43))
   PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), L->wF, Lc->wS, Lc->nv, s.st));
   PMG_HIP(pmg::launch_residual(*Lc, Lc->wqb, nullptr, Lc->wS, s.c_mass, Lc->wS, false, s.st));
   if (pmg_status r = vcycle(s, l + 1, Lc->wql, Lc->wS)) return r;
   // q^{c,b}_l = q^a_l + I (q^{(c,)a}_{l+1} - q^b_{l+1}) (eqs. (44), (45)), then post-smoothing
   PMG_HIP(pmg::launch_prolong(*Lc, *L, s.I1[l].data(), Lc->wql, Lc->wqb, q, L->nv, s.st));
-  return ejacobi_sweep(L, fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r, nullptr, nullptr, s.st);
+  return run_sweeps(*L, *fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r, nullptr, false, s.st);
+}
+
+// One V-cycle followed by the finest-level residual norm of its result.
+pmg_status vcycle_and_norm(Solve& s, double* q) {
+  if (pmg_status e = vcycle(s, 0, q, nullptr)) return e;
+  pmg_level L0 = s.o->levels[0];
+  PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, s.st));
+  PMG_HIP(pmg::launch_norm_finalize(*L0, s.st));
+  return PMG_OK;
+}
+
+// Everything a captured V-cycle depends on: replaying it is valid while this key is unchanged.
+std::vector<uintptr_t> graph_key(const Solve& s, const double* q) {
+  const pmg_solve_opts* o = s.o;
+  std::vector<uintptr_t> k;
+  k.push_back((uintptr_t)q);
+  k.push_back((uintptr_t)s.src);
+  uint64_t cm, ar;
+  std::memcpy(&cm, &s.c_mass, 8);
+  std::memcpy(&ar, &o->alpha_r, 8);
+  k.push_back((uintptr_t)cm);
+  k.push_back((uintptr_t)ar);
+  k.push_back((uintptr_t)o->n_levels);
+  for (int l = 0; l < o->n_levels; ++l) {
+    k.push_back((uintptr_t)o->levels[l]);
+    k.push_back((uintptr_t)o->factors[l]);
+    k.push_back((uintptr_t)o->factors[l]->precision);
+    k.push_back((uintptr_t)o->n_smooth[l]);
+  }
+  return k;
+}
+
+// Capture (or reuse) the graph of vcycle_and_norm for this solve and launch it on s.st.
+pmg_status vcycle_graph(Solve& s, double* q) {
+  pmg_level L0 = s.o->levels[0];
+  const std::vector<uintptr_t> key = graph_key(s, q);
+  if (!L0->vc_exec || L0->vc_key != key) {
+    if (L0->vc_exec) {
+      PMG_HIP(hipGraphExecDestroy(L0->vc_exec));
+      L0->vc_exec = nullptr;
+    }
+    if (!L0->capture_stream) PMG_HIP(hipStreamCreateWithFlags(&L0->capture_stream, hipStreamNonBlocking));
+    Solve sc = s;
+    sc.st = L0->capture_stream;
+    sc.refresh = false;
+    PMG_HIP(hipStreamBeginCapture(sc.st, hipStreamCaptureModeRelaxed));
+    const pmg_status e = vcycle_and_norm(sc, q);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(sc.st, &g);
+    if (e != PMG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&L0->vc_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+    L0->vc_key = key;
+  }
+  PMG_HIP(hipGraphLaunch(L0->vc_exec, s.st));
+  return PMG_OK;
 }
 
 pmg_status read_norm(pmg_level L, hipStream_t st, double& r) {
@@ -637,11 +704,11 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
   pmg_status result = PMG_E_NOT_CONVERGED;
   s.dtau = o->dtau_init;
   if (stats) stats->n_refresh = 0;
+  // r_0 = ||F(q^0)||; every V-cycle ends with the norm of its result, r_{m+1}
+  PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, s.st));
+  PMG_HIP(pmg::launch_norm_finalize(*L0, s.st));
+  if (pmg_status e = read_norm(L0, s.st, r)) return e;
   for (m = 0;; ++m) {
-    // r_m = ||F(q^m)|| on the finest level
-    PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, s.st));
-    PMG_HIP(pmg::launch_norm_finalize(*L0, s.st));
-    if (pmg_status e = read_norm(L0, s.st, r)) return e;
     if (stats && stats->history && m < stats->history_capacity) stats->history[m] = r;
     if (!std::isfinite(r)) {
       result = fail(PMG_E_NONFINITE, "non-finite residual norm");
@@ -666,9 +733,14 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
       PMG_HIP(pmg::launch_jacobian(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
       ++s.n_refresh;
       dtau_last_refresh = s.dtau;
+      if (pmg_status e = vcycle_and_norm(s, q)) return e;
+    } else if (o->use_graph) {
+      if (pmg_status e = vcycle_graph(s, q)) return e;
+    } else {
+      if (pmg_status e = vcycle_and_norm(s, q)) return e;
     }
-    if (pmg_status e = vcycle(s, 0, q, nullptr)) return e;
     r_prev = r;
+    if (pmg_status e = read_norm(L0, s.st, r)) return e;
   }
   if (result != PMG_E_NONFINITE) {
     int h = 0;
@@ -746,13 +818,25 @@ extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, doubl
     PMG_HIP(pmg::launch_residual(*L0, q, nullptr, nullptr, 0.0, const_cast<double*>(R[0]), false, st));
   }
   const double omega = A[1 * s + 1];
+  pmg_status worst = PMG_OK;
   for (int i = 1; i < s; ++i) {
     double a_row[8];
     for (int j = 0; j < i; ++j) a_row[j] = A[i * s + j];
     pmg_solve_stats* sti = (stats && i - 1 < n_stats) ? &stats[i - 1] : nullptr;
     double* R_out = (i < s - 1) ? const_cast<double*>(R[i]) : nullptr;
     const pmg_status r = esdirk_stage_solve(o, omega, dt, qc_n, R.data(), a_row, i, q, R_out, sti, stream);
-    if (r != PMG_OK) return r;
+    if (r == PMG_E_NOT_CONVERGED) {
+      // the last iterate stands in for the stage value; later stages still run
+      worst = r;
+      if (R_out) {
+        DeviceGuard guard(L0->device);
+        PMG_HIP(pmg::launch_residual(*L0, q, nullptr, nullptr, 0.0, R_out, false, as_stream(stream)));
+      }
+    } else if (r != PMG_OK) {
+      for (int k = i; k < s - 1 && stats && k < n_stats; ++k) stats[k].status = r;
+      return r;
+    }
   }
+  if (worst != PMG_OK) return fail(worst, "a stage solve reached max_vcycles");
   return PMG_OK;
 }

@@ -15,13 +15,20 @@
 
 namespace pmg {
 
+// Elements per workgroup: small workgroups (64-128 lanes) so that even the coarsest level of a
+// few thousand elements spreads over all 256 CUs; each W column a workgroup streams is then
+// EPW * n * 4 B ~ 1 KB contiguous.
+constexpr int epw_for(int P) {
+  return P == 0 ? 64 : P == 1 ? 16 : P == 2 ? 7 : P == 3 ? 4 : P == 4 ? 5 : P == 5 ? 3 : 5;
+}
+
 template <int P>
 struct Cfg {
   static constexpr int N1 = P + 1;
   static constexpr int NP = N1 * N1;
   static constexpr int NV = 4;
   static constexpr int N = NV * NP;
-  static constexpr int EPW = (256 / NP) > 0 ? (256 / NP) : 1;
+  static constexpr int EPW = epw_for(P);
   static constexpr int NACT = EPW * NP;
   static constexpr int NT = ((NACT + 63) / 64) * 64;
   static constexpr int NW = NT / 64;
@@ -77,20 +84,35 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) qa[v] = a.lv.q_ref[v] + qv[v];
 
-  double ij = 0.0;
-  {
-    double sx = 1.0, sy = 0.0, tx = 0.0, ty = 1.0;
-    if (valid) {
-      const double* m = a.lv.met;
-      sx = m[gp];
-      sy = m[sstride + gp];
-      tx = m[2 * sstride + gp];
-      ty = m[3 * sstride + gp];
-      ij = m[4 * sstride + gp];
+  // every operand of this point is requested up front, before the first barrier
+  double ij = 0.0, sx = 1.0, sy = 0.0, tx = 0.0, ty = 1.0;
+  double srcv[NV], sv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    srcv[v] = 0.0;
+    sv[v] = 0.0;
+  }
+  if (valid) {
+    const double* m = a.lv.met;
+    sx = m[gp];
+    sy = m[sstride + gp];
+    tx = m[2 * sstride + gp];
+    ty = m[3 * sstride + gp];
+    ij = m[4 * sstride + gp];
+    if (a.src) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) srcv[v] = a.src[v * sstride + gp];
     }
+    if (a.S) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sv[v] = a.S[v * sstride + gp];
+    }
+  }
+  const double rho = qa[0] / (a.gas.rgas * qa[3]);
+  {
     double fs[NV], ft[NV];
-    normal_flux2(qa, sx, sy, a.gas, fs);
-    normal_flux2(qa, tx, ty, a.gas, ft);
+    normal_flux2_rho(qa, rho, sx, sy, a.gas, fs);
+    normal_flux2_rho(qa, rho, tx, ty, a.gas, ft);
     if (act) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -121,12 +143,13 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
           floc[v] += w[m] * ((f < 2) ? SF(v, pp, el) : SG(v, pp, el));
         }
       }
-      double fx = (f < 2) ? 1.0 : 0.0, fy = (f < 2) ? 0.0 : 1.0;
+      double nx = (f < 2) ? 1.0 : 0.0, ny = (f < 2) ? 0.0 : 1.0, sm = 1.0;
       int nb = -3;
       if (e < ne) {
-        const size_t fo = ((size_t)(f * N1 + k) * 2) * ne + e;
-        fx = a.lv.fvec[fo];
-        fy = a.lv.fvec[fo + ne];
+        const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
+        nx = a.lv.fvec[fo];
+        ny = a.lv.fvec[fo + ne];
+        sm = a.lv.fvec[fo + 2 * ne];
         nb = a.lv.nbr[f * ne + e];
       }
       double out[NV];
@@ -143,8 +166,6 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
           for (int v = 0; v < NV; ++v) out[v] += wn[m] * a.q[v * sstride + (size_t)pp * ne + nb];
         }
       } else if (nb == -1) {             // slip wall: reflect the normal velocity
-        const double inv = 1.0 / sqrt(fx * fx + fy * fy);
-        const double nx = fx * inv, ny = fy * inv;
         const double ua = a.lv.q_ref[1] + own[1], va = a.lv.q_ref[2] + own[2];
         const double un = ua * nx + va * ny;
         out[0] = own[0];
@@ -167,11 +188,11 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       if (f == 0 || f == 2) {            // the neighbour is the '-' side
 #pragma unroll
         for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
-        common_flux2(out_a, own_a, dq, fx, fy, a.gas, fh);
+        common_flux2(out_a, own_a, dq, nx, ny, sm, a.gas, fh);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
-        common_flux2(own_a, out_a, dq, fx, fy, a.gas, fh);
+        common_flux2(own_a, out_a, dq, nx, ny, sm, a.gas, fh);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) SJ(f, k, v, el) = fh[v] - floc[v];
@@ -182,7 +203,10 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   double Fv[NV];
   {
     double qc[NV];
-    conservative2(qa, a.gas, qc);
+    qc[0] = rho;
+    qc[1] = rho * qa[1];
+    qc[2] = rho * qa[2];
+    qc[3] = qa[0] * (1.0 / (a.gas.gamma - 1.0)) + 0.5 * rho * (qa[1] * qa[1] + qa[2] * qa[2]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double d = 0.0;
@@ -194,11 +218,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
         for (int k = 0; k < N1; ++k) d += o.D[j * N1 + k] * SG(v, i + N1 * k, el);
         d += o.gL[j] * SJ(2, i, v, el) + o.gR[j] * SJ(3, i, v, el);
       }
-      double fv = -d * ij - a.c_mass * qc[v];
-      if (valid) {
-        if (a.src) fv += a.src[v * sstride + gp];
-        if (a.S) fv -= a.S[v * sstride + gp];
-      }
+      const double fv = -d * ij - a.c_mass * qc[v] + srcv[v] - sv[v];
       Fv[v] = valid ? fv : 0.0;
     }
   }
@@ -315,8 +335,7 @@ static hipError_t launch_fr(int P, const ResArgs& a, int ne, hipStream_t st) {
 }
 
 int residual_blocks(const pmg_level_s& L) {
-  const int np = (L.P + 1) * (L.P + 1);
-  const int epw = (256 / np) > 0 ? (256 / np) : 1;
+  const int epw = epw_for(L.P);
   return (L.ne + epw - 1) / epw;
 }
 

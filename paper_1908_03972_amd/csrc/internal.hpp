@@ -28,7 +28,7 @@ struct Ops1D {
 struct LevelView {
   int ne;
   const double* met;    // [5][Np][Ne]: Sx, Sy (= y_eta, -x_eta), Tx, Ty (= -y_xi, x_xi), 1/|J|
-  const double* fvec;   // [4][n1][2][Ne]: +xi (faces 0,1) or +eta (faces 2,3) vector at flux points
+  const double* fvec;   // [4][n1][3][Ne]: unit +xi (faces 0,1) or +eta (faces 2,3) normal and its length |S|
   const int* nbr;       // [4][Ne]
   const int* nbf;       // [4][Ne]
   const int* ori;       // [4][Ne]
@@ -67,6 +67,10 @@ struct pmg_level_s {
   double* norms = nullptr;   // [Nv + 1]
   int* flag = nullptr;       // device error flags
   int part_blocks = 0;
+  // replayable V-cycle of the stage solve (finest level only), keyed by its arguments
+  hipGraphExec_t vc_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::vector<uintptr_t> vc_key;
   size_t state_elems() const { return (size_t)nv * np * ne; }
   pmg::LevelView view() const {
     pmg::LevelView v;
@@ -103,7 +107,8 @@ hipError_t launch_norm_finalize(const pmg_level_s& L, hipStream_t st);
 hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
                            pmg_factors_s& fac, hipStream_t st);
 hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
-                           double* xc, int nvar, hipStream_t st);
+                           double* xc, int nvar, hipStream_t st, double* xc2 = nullptr);
+hipError_t launch_copy(size_t n, const double* src, double* dst, hipStream_t st);
 hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
                           const double* xb, double* xf, int nvar, hipStream_t st);
 hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc, hipStream_t st);

@@ -149,21 +149,24 @@ template <>
 __device__ __forceinline__ Dual<4> lift<Dual<4>>(double x) { return dconst<4>(x); }
 
 // ---- thermodynamic state at one point ----------------------------------------------
-// Quantities of the preconditioned system at a primitive state (2-D).
+// Quantities of the preconditioned system at a primitive state (2-D). Reciprocals are formed
+// once (1/(R T), 1/U_r^2, 1/rho) and the ideal-gas identities 1/T = R rho_p, 1/c^2 = rho_p/gamma
+// replace further divisions.
 template <class T>
 struct State2 {
   T p, u, v, t;      // primitive variables
-  T rho, rho_p, rho_t, q2, h, c2;
+  T rho, rho_p, rho_t, inv_rho, q2, h, c2, inv_c2;
   T ur2, theta;      // U_r^2 and Theta of eq. (10)
 };
 
+// eps^2 with eps of eq. (11): min(1, Ma)^2 = min(1, Ma^2) and the cut-off likewise, so no square
+// root is needed
 template <class T>
-__device__ __forceinline__ T epsilon_from(const T& q2, const T& c2, const GasParams& g) {
-  // eq. (11): eps = min(1, max(kappa Ma_inf, Ma)); the "local" mode drops the cut-off
-  T ma = dsqrt(q2 / c2);
+__device__ __forceinline__ T epsilon2_from(const T& ma2, const GasParams& g) {
   T one = lift<T>(1.0);
-  if (g.eps_mode == 0) return rmin(one, ma);
-  return rmin(one, rmax(lift<T>(g.kappa * g.ma_inf), ma));
+  if (g.eps_mode == 0) return rmin(one, ma2);
+  const double km = g.kappa * g.ma_inf;
+  return rmin(one, rmax(lift<T>(km * km), ma2));
 }
 
 template <class T>
@@ -175,13 +178,16 @@ __device__ __forceinline__ State2<T> make_state(const T q[4], const GasParams& g
   s.t = q[3];
   s.rho_p = 1.0 / (g.rgas * s.t);
   s.rho = s.p * s.rho_p;
-  s.rho_t = -s.rho / s.t;
+  s.inv_rho = 1.0 / s.rho;
+  const T inv_t = g.rgas * s.rho_p;
+  s.rho_t = -s.rho * inv_t;
   s.q2 = s.u * s.u + s.v * s.v;
   s.h = g.cp * s.t + 0.5 * s.q2;          // H = E + p/rho for an ideal gas
   s.c2 = g.gamma * g.rgas * s.t;
-  T eps = epsilon_from(s.q2, s.c2, g);
-  s.ur2 = eps * eps * s.c2;
-  s.theta = 1.0 / s.ur2 + 1.0 / (g.cp * s.t);   // 1/U_r^2 - rho_T/(rho C_p), eq. (10)
+  s.inv_c2 = s.rho_p * (1.0 / g.gamma);
+  const T eps2 = epsilon2_from(s.q2 * s.inv_c2, g);
+  s.ur2 = eps2 * s.c2;
+  s.theta = 1.0 / s.ur2 + inv_t * (1.0 / g.cp);   // 1/U_r^2 - rho_T/(rho C_p), eq. (10)
   return s;
 }
 
@@ -193,6 +199,19 @@ __device__ __forceinline__ void conservative2(const T q[4], const GasParams& g, 
   out[1] = rho * q[1];
   out[2] = rho * q[2];
   out[3] = q[0] * (1.0 / (g.gamma - 1.0)) + 0.5 * rho * (q[1] * q[1] + q[2] * q[2]);
+}
+
+// inviscid flux along a (not necessarily unit) vector (sx, sy), density given
+template <class T>
+__device__ __forceinline__ void normal_flux2_rho(const T q[4], const T& rho, double sx, double sy,
+                                                 const GasParams& g, T out[4]) {
+  T un = q[1] * sx + q[2] * sy;
+  T mflux = rho * un;
+  T h = g.cp * q[3] + 0.5 * (q[1] * q[1] + q[2] * q[2]);
+  out[0] = mflux;
+  out[1] = mflux * q[1] + q[0] * sx;
+  out[2] = mflux * q[2] + q[0] * sy;
+  out[3] = mflux * h;
 }
 
 // inviscid flux along a (not necessarily unit) vector (sx, sy)
@@ -225,10 +244,10 @@ template <class T>
 __device__ __forceinline__ void gamma_solve(const State2<T>& s, const GasParams& g, const T y[4], T x[4]) {
   T z = y[3] - (s.h - s.q2) * y[0] - s.u * y[1] - s.v * y[2];
   T rcp = s.rho * g.cp;
-  T b = s.ur2 * (y[0] + s.theta * z) / rcp;
+  T b = s.ur2 * (y[0] + s.theta * z) * (s.inv_rho * (1.0 / g.cp));
   x[0] = rcp * b - z;
-  x[1] = (y[1] - s.u * y[0]) / s.rho;
-  x[2] = (y[2] - s.v * y[0]) / s.rho;
+  x[1] = (y[1] - s.u * y[0]) * s.inv_rho;
+  x[2] = (y[2] - s.v * y[0]) * s.inv_rho;
   x[3] = b;
 }
 
@@ -255,24 +274,24 @@ __device__ __forceinline__ void flux_jac_mul(const State2<T>& s, const GasParams
 // (Newton divided differences), so that
 //   Gamma |X| dq = |l1| G dq + f12 (A - l1 G) dq + f123 (A - l1 G) G^{-1} (A - l2 G) dq.
 template <class T>
-__device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], const T dq[4], double sx, double sy,
-                                             const GasParams& g, T out[4]) {
-  const double smag = sqrt(sx * sx + sy * sy);
-  const double nx = sx / smag, ny = sy / smag;
+__device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], const T dq[4], double nx, double ny,
+                                             double smag, const GasParams& g, T out[4]) {
   T qa[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) qa[k] = 0.5 * (qm[k] + qp[k]);
   const State2<T> s = make_state(qa, g);
   T un = s.u * nx + s.v * ny;
-  T alpha = 0.5 * (1.0 - s.ur2 / s.c2);          // beta = 1/c^2 for an ideal gas
+  T alpha = 0.5 * (1.0 - s.ur2 * s.inv_c2);     // beta = 1/c^2 for an ideal gas
   T cpr = dsqrt(alpha * alpha * un * un + s.ur2);
   T l1 = un;
   T l2 = un * (1.0 - alpha) + cpr;
   T l3 = un * (1.0 - alpha) - cpr;
   T a1 = rabs(l1), a2 = rabs(l2), a3 = rabs(l3);
-  T f12 = (a2 - a1) / (l2 - l1);
-  T f13 = (a3 - a1) / (l3 - l1);
-  T f123 = (f13 - f12) / (l3 - l2);
+  // divided differences of |x| at (l1, l2, l3) over one reciprocal
+  T d21 = l2 - l1, d31 = l3 - l1, d32 = l3 - l2;
+  T inv = 1.0 / (d21 * d31 * d32);
+  T f12 = (a2 - a1) * (d31 * d32) * inv;
+  T f123 = ((a3 - a1) * d21 - (a2 - a1) * d31) * inv;
 
   T gd[4], ad[4], w[4], y[4], ay[4];
   gamma_mul(s, g, dq, gd);

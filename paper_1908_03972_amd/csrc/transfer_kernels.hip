@@ -14,7 +14,8 @@ struct Mat1D {
 
 // x_c[v][a + nc b][e] = sum_{j,i} R[b][j] R[a][i] x_f[v][i + nf j][e]
 __global__ void __launch_bounds__(256) k_restrict(int ne, int nvar, int nf1, int nc1, Mat1D R,
-                                                  const double* __restrict__ xf, double* __restrict__ xc) {
+                                                  const double* __restrict__ xf, double* __restrict__ xc,
+                                                  double* __restrict__ xc2) {
   const size_t npc = (size_t)nc1 * nc1, npf = (size_t)nf1 * nf1;
   const size_t total = (size_t)nvar * npc * ne;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -32,6 +33,12 @@ __global__ void __launch_bounds__(256) k_restrict(int ne, int nvar, int nf1, int
     acc += R.m[b * nf1 + j] * row;
   }
   xc[idx] = acc;
+  if (xc2) xc2[idx] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_copy(size_t n, const double* __restrict__ src, double* __restrict__ dst) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) dst[idx] = src[idx];
 }
 
 // x_f[v][i + nf j][e] += sum_{b,a} I[j][b] I[i][a] (xa - xb)[v][a + nc b][e]
@@ -121,12 +128,19 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict_
 static unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
-                           double* xc, int nvar, hipStream_t st) {
+                           double* xc, int nvar, hipStream_t st, double* xc2) {
   Mat1D R{};
   for (int k = 0; k < Lc.n1 * Lf.n1; ++k) R.m[k] = R1[k];
   const size_t total = (size_t)nvar * Lc.np * Lc.ne;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_restrict, dim3(blocks_for(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf, xc);
+  hipLaunchKernelGGL(k_restrict, dim3(blocks_for(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf, xc,
+                     xc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(size_t n, const double* src, double* dst, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(256), 0, st, n, src, dst);
   return hipGetLastError();
 }
 
