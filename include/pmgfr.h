@@ -57,7 +57,8 @@ typedef struct pmg_factors_s* pmg_factors;
 /* Thread-local text of the last error, or "" if none. The pointer stays owned by the library. */
 const char* pmg_last_error(void);
 
-/* Version of this ABI (major * 100 + minor). */
+/* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
+#define PMG_ABI_VERSION 101
 int32_t pmg_abi_version(void);
 
 /*
@@ -110,6 +111,18 @@ pmg_status pmg_level_info(pmg_level L, int32_t* info);
 
 /* Physical solution-point coordinates, host output double[2][Np][Ne] (x then y). */
 pmg_status pmg_level_points(pmg_level L, double* xy_host);
+
+/* Element length scale of eqs. (32)-(33), host output double[Ne]: twice the smallest distance from
+ * the element's area centroid (6x6 Gauss rule on the exact mapping) to its four faces, each face
+ * taken as the segment between its two corner nodes. */
+pmg_status pmg_level_dx(pmg_level L, double* dx_host);
+
+/* pmg_dtau_min — the pseudo-time scale of eq. (33) at state q (device, stored form [Nv][Np][Ne]):
+ *   dtau_min = min over elements e and solution points of (dx_e / (P+1)) / (c + |v|)
+ * (inviscid part; the levels carry no viscosity). Writes the host double *dtau_min and
+ * synchronises the stream. Errors: PMG_E_ARG (null), PMG_E_NONFINITE (a point with T <= 0 or a
+ * non-finite value), PMG_E_HIP. */
+pmg_status pmg_dtau_min(pmg_level L, const double* q, double* dtau_min, void* stream);
 
 /* Read and clear the level's device fault flags (synchronises the device).
  * *flags bit 0: a zero/non-finite pivot was met; returns PMG_E_SINGULAR if set, else PMG_OK. */
@@ -197,6 +210,11 @@ typedef struct {
   double alpha_r;                 /* relaxation of eq. (30), 1 in the paper                      */
   int32_t use_graph;              /* 1: replay V-cycles without a block rebuild from a HIP graph
                                      captured once per argument set (same results, fewer launches) */
+  int32_t use_cfl;                /* 1: CFL form of eqs. (31)-(33): dtau_init = cfl_init dtau_min and
+                                     dtau_max = cfl_max dtau_min, with dtau_min of the finest level
+                                     at the initial guess (pmg_dtau_min); dtau_init/dtau_max unused */
+  double cfl_init;                /* 1e2 in Sec. 4.2                                             */
+  double cfl_max;                 /* 1e5 in Sec. 4.2                                             */
 } pmg_solve_opts;
 
 typedef struct {
@@ -208,6 +226,7 @@ typedef struct {
   int32_t history_capacity;
   pmg_status status;
   double seconds;                 /* host wall time of the stage solve                         */
+  double dtau_min;                /* dtau_min used by the CFL form, 0 otherwise                 */
 } pmg_solve_stats;
 
 /*

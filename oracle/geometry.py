@@ -71,3 +71,29 @@ class QuadGeometry:
                 self.fvec[:, f] = np.stack([deta_f[..., 1], -deta_f[..., 0]], axis=-1)
             else:
                 self.fvec[:, f] = np.stack([-dxi_f[..., 1], dxi_f[..., 0]], axis=-1)
+
+
+def element_dx(mesh, nq: int = 6) -> np.ndarray:
+    """Delta x of eqs. (32)-(33): twice the minimum distance from each element's barycentre to its
+    faces. Reading: the barycentre is the area centroid of the exact mapping (nq x nq Gauss rule);
+    the distance to a face is the distance to the segment joining the face's two corner nodes."""
+    from .basis import gauss_points
+    g = mesh.geom_order
+    xq, wq = gauss_points(nq - 1)
+    ii, jj = np.meshgrid(np.arange(nq), np.arange(nq), indexing="xy")
+    xi, eta = xq[ii.ravel()], xq[jj.ravel()]
+    w = (wq[:, None] * wq[None, :]).T.ravel()          # weight of point i + nq j is w_i w_j
+    x, dxi, deta = _map_derivs(mesh.nodes, g, xi, eta)
+    jac = dxi[..., 0] * deta[..., 1] - deta[..., 0] * dxi[..., 1]
+    area = jac @ w
+    cen = np.einsum("em,m,emd->ed", jac, w, x) / area[:, None]
+    n1 = g + 1
+    corner = {0: (0, n1 * g), 1: (g, g + n1 * g), 2: (0, g), 3: (n1 * g, g + n1 * g)}
+    dmin = np.full(mesh.n_elements, np.inf)
+    for f, (a, b) in corner.items():
+        pa, pb = mesh.nodes[:, a], mesh.nodes[:, b]
+        ab = pb - pa
+        t = np.clip(np.sum((cen - pa) * ab, axis=1) / np.sum(ab * ab, axis=1), 0.0, 1.0)
+        d = np.linalg.norm(cen - (pa + t[:, None] * ab), axis=1)
+        dmin = np.minimum(dmin, d)
+    return 2.0 * dmin

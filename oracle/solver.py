@@ -25,6 +25,7 @@ import numpy as np
 from . import gas as G
 from .basis import interpolation_1d, projection_1d
 from .fr import FRLevel
+from .geometry import element_dx
 from .jacobian import element_blocks
 
 
@@ -83,6 +84,11 @@ class PMGOptions:
     tol: float = 1e-8
     max_vcycles: int = 200
     alpha_r: float = 1.0
+    # CFL form of the pseudo-time step (eqs. (31)-(33)): dtau = CFL dtau_min, CFL from cfl_init
+    # to cfl_max by the same SER law (Sec. 4.2 uses 1e2 -> 1e5)
+    use_cfl: bool = False
+    cfl_init: float = 1e2
+    cfl_max: float = 1e5
 
 
 @dataclass
@@ -94,6 +100,7 @@ class StageStats:
     dtau_history: list = field(default_factory=list)
     refreshes: list = field(default_factory=list)
     converged: bool = False
+    dtau_scale: tuple = ()
 
 
 class PMGSolver:
@@ -147,6 +154,20 @@ class PMGSolver:
     def residual_norm(self, q):
         return float(np.sqrt(np.sum(self.F(0, q) ** 2)))
 
+    def dtau_min(self, q):
+        """dtau_min = min(dtau_inv, dtau_vis) of eq. (33) on the finest level at state q, with
+        dtau_inv = min over elements and points of (dx/(P+1)) / (c + |v|) and, when mu > 0,
+        dtau_vis = min of (dx/(P+1))^2 / (mu/rho)."""
+        lev = self.levels[0]
+        if not hasattr(self, "_dx"):
+            self._dx = element_dx(lev.mesh)
+        h = (self._dx / (lev.P + 1))[:, None]
+        speed = G.sound_speed(q, self.gas) + np.sqrt(np.sum(q[..., 1:-1] ** 2, axis=-1))
+        dt = np.min(h / speed)
+        if self.gas.mu > 0.0:
+            dt = min(dt, np.min(h * h * G.density(q, self.gas) / self.gas.mu))
+        return float(dt)
+
     # ---- pseudo-transient stage solve (Sec. 2.4, eqs. (27)-(31)) -----------------------
     def stage_solve(self, q, c_mass=0.0, src=None, max_vcycles=None):
         o = self.opts
@@ -156,14 +177,20 @@ class PMGSolver:
         nmax = o.max_vcycles if max_vcycles is None else max_vcycles
         self.dtau_last_refresh = None
         r_prev = None
+        if o.use_cfl:
+            scale = self.dtau_min(q)
+            dtau_init, dtau_max = o.cfl_init * scale, o.cfl_max * scale
+        else:
+            dtau_init, dtau_max = o.dtau_init, o.dtau_max
+        st.dtau_scale = (dtau_init, dtau_max)
         for m in range(nmax + 1):
             r = self.residual_norm(q)
             st.history.append(r)
             if m == 0:
                 st.r0 = r
-                self.dtau = o.dtau_init
+                self.dtau = dtau_init
             else:
-                self.dtau = min(self.dtau * (r_prev / r) ** o.ser_exp, o.dtau_max)
+                self.dtau = min(self.dtau * (r_prev / r) ** o.ser_exp, dtau_max)
             st.r_final = r
             if r == 0.0 or r / st.r0 <= o.tol:
                 st.converged = True
@@ -172,7 +199,7 @@ class PMGSolver:
                 break
             st.dtau_history.append(self.dtau)
             frozen = (o.freeze_at_max and self.dtau_last_refresh is not None
-                      and self.dtau_last_refresh >= o.dtau_max)
+                      and self.dtau_last_refresh >= dtau_max)
             self.refresh_now = m == 0 or (m % o.refresh_every == 0 and not frozen)
             if self.refresh_now:
                 self.build_D(0, q)

@@ -44,7 +44,7 @@ class SolveOpts(C.Structure):
         ("n_smooth", C.POINTER(C.c_int32)), ("dtau_init", C.c_double), ("dtau_max", C.c_double),
         ("ser_exponent", C.c_double), ("refresh_every", C.c_int32), ("freeze_at_max", C.c_int32),
         ("tol_rel", C.c_double), ("max_vcycles", C.c_int32), ("alpha_r", C.c_double),
-        ("use_graph", C.c_int32),
+        ("use_graph", C.c_int32), ("use_cfl", C.c_int32), ("cfl_init", C.c_double), ("cfl_max", C.c_double),
     ]
 
 
@@ -52,7 +52,7 @@ class SolveStats(C.Structure):
     _fields_ = [
         ("n_vcycles", C.c_int32), ("n_refresh", C.c_int32), ("r0", C.c_double), ("r_final", C.c_double),
         ("history", C.POINTER(C.c_double)), ("history_capacity", C.c_int32), ("status", C.c_int32),
-        ("seconds", C.c_double),
+        ("seconds", C.c_double), ("dtau_min", C.c_double),
     ]
 
 
@@ -66,6 +66,8 @@ SIGNATURES = {
     "pmg_level_info": (pmg_status, [pmg_level, C.POINTER(C.c_int32)]),
     "pmg_level_points": (pmg_status, [pmg_level, C.POINTER(C.c_double)]),
     "pmg_level_status": (pmg_status, [pmg_level, C.POINTER(C.c_int32)]),
+    "pmg_level_dx": (pmg_status, [pmg_level, C.POINTER(C.c_double)]),
+    "pmg_dtau_min": (pmg_status, [pmg_level, DP, C.POINTER(C.c_double), C.c_void_p]),
     "pmg_factors_create": (pmg_status, [pmg_level, C.c_int32, C.POINTER(pmg_factors)]),
     "pmg_factors_destroy": (pmg_status, [pmg_factors]),
     "fr_residual": (pmg_status, [pmg_level, DP, DP, DP, C.c_double, DP, DP, C.c_void_p]),

@@ -59,6 +59,12 @@ class Level:
                 "pmg_level_points")
         return out
 
+    def dx(self) -> np.ndarray:
+        """Element length scale of eqs. (32)-(33), [Ne]."""
+        out = np.empty(self.ne)
+        A.check(A.lib().pmg_level_dx(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))), "pmg_level_dx")
+        return out
+
     def new_state(self) -> torch.Tensor:
         return torch.zeros(self.shape, dtype=torch.float64, device=self.torch_device)
 
@@ -164,7 +170,7 @@ class StageSolver:
 
     def __init__(self, levels, factors, n_smooth, *, dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5,
                  refresh_every=10, freeze_at_max=True, tol_rel=1e-8, max_vcycles=200, alpha_r=1.0,
-                 use_graph=False):
+                 use_graph=False, use_cfl=False, cfl_init=1e2, cfl_max=1e5):
         self.levels = list(levels)
         self.factors = list(factors)
         nl = len(self.levels)
@@ -177,6 +183,7 @@ class StageSolver:
         o.refresh_every, o.freeze_at_max, o.tol_rel = refresh_every, int(freeze_at_max), tol_rel
         o.max_vcycles, o.alpha_r = max_vcycles, alpha_r
         o.use_graph = int(use_graph)
+        o.use_cfl, o.cfl_init, o.cfl_max = int(use_cfl), cfl_init, cfl_max
         self.opts = o
 
     def solve(self, q, *, omega=0.0, dt=0.0, qc_n=None, R_prev=(), a_row=(), R_out=None, stream=None,
@@ -194,10 +201,19 @@ class StageSolver:
                                             nprev, L0.check_state(q, "q", False), L0.check_state(R_out, "R_out"),
                                             C.byref(st), _stream(stream))
         out = {"status": status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh, "r0": st.r0,
-               "r_final": st.r_final, "history": list(hist[:min(st.n_vcycles + 1, cap)])}
+               "r_final": st.r_final, "seconds": st.seconds, "dtau_min": st.dtau_min,
+               "history": list(hist[:min(st.n_vcycles + 1, cap)])}
         if raise_on_error:
             A.check(status, "esdirk_stage_solve")
         return out
+
+
+def dtau_min(level: Level, q, stream=None) -> float:
+    """``pmg_dtau_min``: the pseudo-time scale of eq. (33) at state q (synchronises)."""
+    out = C.c_double(0.0)
+    A.check(A.lib().pmg_dtau_min(level.handle, level.check_state(q, "q", False), C.byref(out), _stream(stream)),
+            "pmg_dtau_min")
+    return out.value
 
 
 def esdirk_stages(scheme: int) -> int:
@@ -223,7 +239,7 @@ def esdirk_step(solver: StageSolver, scheme: int, dt: float, q, work, stream=Non
     status = A.lib().esdirk_step(C.byref(solver.opts), scheme, dt, L0.check_state(q, "q", False),
                                  C.c_void_p(work.data_ptr()), stats, s - 1, _stream(stream))
     out = [{"status": st.status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh, "r0": st.r0,
-            "r_final": st.r_final, "seconds": st.seconds,
+            "r_final": st.r_final, "seconds": st.seconds, "dtau_min": st.dtau_min,
             "history": list(h[:min(st.n_vcycles + 1, cap)])} for st, h in zip(stats, hists)]
     if raise_on_error:
         A.check(status, "esdirk_step")

@@ -195,6 +195,38 @@ MapEval map_at(const double* nodes, int g, double xi, double eta) {
   return m;
 }
 
+// Twice the smallest distance from the element's area centroid to its faces (eqs. (32)-(33)); the
+// centroid integrates the exact mapping with a 6x6 Gauss rule, a face is the segment joining its
+// two corner nodes.
+double element_length(const double* nodes, int g) {
+  std::vector<double> xq, wq;
+  gauss_legendre(6, xq, wq);
+  double area = 0.0, cx = 0.0, cy = 0.0;
+  for (int j = 0; j < 6; ++j)
+    for (int i = 0; i < 6; ++i) {
+      const MapEval m = map_at(nodes, g, xq[i], xq[j]);
+      const double wj = wq[i] * wq[j] * (m.x_xi * m.y_eta - m.x_eta * m.y_xi);
+      area += wj;
+      cx += wj * m.x;
+      cy += wj * m.y;
+    }
+  cx /= area;
+  cy /= area;
+  const int n1 = g + 1;
+  const int corners[4][2] = {{0, n1 * g}, {g, g + n1 * g}, {0, g}, {n1 * g, g + n1 * g}};
+  double dmin = std::numeric_limits<double>::infinity();
+  for (const auto& c : corners) {
+    const double ax = nodes[2 * c[0]], ay = nodes[2 * c[0] + 1];
+    const double bx = nodes[2 * c[1]], by = nodes[2 * c[1] + 1];
+    const double ex = bx - ax, ey = by - ay;
+    double t = ((cx - ax) * ex + (cy - ay) * ey) / (ex * ex + ey * ey);
+    t = std::min(1.0, std::max(0.0, t));
+    const double dx = cx - (ax + t * ex), dy = cy - (ay + t * ey);
+    dmin = std::min(dmin, std::sqrt(dx * dx + dy * dy));
+  }
+  return 2.0 * dmin;
+}
+
 template <class T>
 pmg_status upload(T** dst, const std::vector<T>& src) {
   hipError_t e = hipMalloc(dst, src.size() * sizeof(T));
@@ -216,8 +248,8 @@ void free_level(pmg_level_s* L) {
   if (!L) return;
   if (L->vc_exec) (void)hipGraphExecDestroy(L->vc_exec);
   if (L->capture_stream) (void)hipStreamDestroy(L->capture_stream);
-  void* ptrs[] = {L->met, L->fvec, L->nbr, L->nbf, L->ori, L->wq,    L->wF,
-                  L->wS,  L->wqb,  L->wql, L->wsrc, L->part, L->norms, L->flag};
+  void* ptrs[] = {L->met, L->fvec, L->nbr,  L->nbf,   L->ori,  L->wq,  L->wF,     L->wS,
+                  L->wqb, L->wql,  L->wsrc, L->part, L->norms, L->flag, L->hdx, L->dtpart, L->dtmin};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete L;
@@ -259,7 +291,7 @@ extern "C" {
 
 const char* pmg_last_error(void) { return g_error.c_str(); }
 
-int32_t pmg_abi_version(void) { return 100; }
+int32_t pmg_abi_version(void) { return PMG_ABI_VERSION; }
 
 pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   if (!d || !out) return fail(PMG_E_ARG, "null descriptor or output");
@@ -352,6 +384,12 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
         fvec[o + 2 * ne] = len;
       }
   }
+  L->dx_host.resize(ne);
+  std::vector<double> hdx(ne);
+  for (int e = 0; e < ne; ++e) {
+    L->dx_host[e] = element_length(d->nodes + (size_t)e * nn * 2, g);
+    hdx[e] = L->dx_host[e] / n1;
+  }
   std::vector<int> nbr((size_t)4 * ne), nbf((size_t)4 * ne), ori((size_t)4 * ne);
   for (int e = 0; e < ne; ++e)
     for (int f = 0; f < 4; ++f) {
@@ -361,7 +399,7 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
     }
   pmg_status s = PMG_OK;
   if ((s = upload(&L->met, met)) || (s = upload(&L->fvec, fvec)) || (s = upload(&L->nbr, nbr)) ||
-      (s = upload(&L->nbf, nbf)) || (s = upload(&L->ori, ori))) {
+      (s = upload(&L->nbf, nbf)) || (s = upload(&L->ori, ori)) || (s = upload(&L->hdx, hdx))) {
     free_level(L);
     return s;
   }
@@ -369,7 +407,8 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   L->part_blocks = pmg::residual_blocks(*L);
   if ((s = alloc_zero(&L->wq, ns)) || (s = alloc_zero(&L->wF, ns)) || (s = alloc_zero(&L->wS, ns)) ||
       (s = alloc_zero(&L->wqb, ns)) || (s = alloc_zero(&L->wql, ns)) || (s = alloc_zero(&L->wsrc, ns)) ||
-      (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1))) {
+      (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
+      (s = alloc_zero(&L->dtpart, pmg::dtau_blocks(*L))) || (s = alloc_zero(&L->dtmin, 1))) {
     free_level(L);
     return s;
   }
@@ -410,6 +449,27 @@ pmg_status pmg_level_points(pmg_level L, double* xy_host) {
   if (pmg_status s = check_level(L)) return s;
   if (!xy_host) return fail(PMG_E_ARG, "null output");
   std::memcpy(xy_host, L->xy_host.data(), L->xy_host.size() * sizeof(double));
+  return PMG_OK;
+}
+
+pmg_status pmg_level_dx(pmg_level L, double* dx_host) {
+  if (pmg_status e = check_level(L)) return e;
+  if (!dx_host) return fail(PMG_E_ARG, "null output");
+  std::memcpy(dx_host, L->dx_host.data(), L->dx_host.size() * sizeof(double));
+  return PMG_OK;
+}
+
+pmg_status pmg_dtau_min(pmg_level L, const double* q, double* dtau_min, void* stream) {
+  if (pmg_status e = check_level(L)) return e;
+  if (!q || !dtau_min) return fail(PMG_E_ARG, "null q or output");
+  DeviceGuard guard(L->device);
+  const hipStream_t st = as_stream(stream);
+  PMG_HIP(pmg::launch_dtau_min(*L, q, st));
+  double h = 0.0;
+  PMG_HIP(hipMemcpyAsync(&h, L->dtmin, sizeof(double), hipMemcpyDeviceToHost, st));
+  PMG_HIP(hipStreamSynchronize(st));
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(PMG_E_NONFINITE, "non-physical state in the pseudo-time scale");
+  *dtau_min = h;
   return PMG_OK;
 }
 
@@ -670,7 +730,11 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
     for (int k = 0; k < 5; ++k)
       if (o->levels[l]->q_ref[k] != o->levels[0]->q_ref[k]) return fail(PMG_E_SHAPE, "levels have different q_ref");
   }
-  if (!(o->dtau_init > 0.0) || !(o->dtau_max >= o->dtau_init)) return fail(PMG_E_ARG, "bad dtau range");
+  if (o->use_cfl) {
+    if (!(o->cfl_init > 0.0) || !(o->cfl_max >= o->cfl_init)) return fail(PMG_E_ARG, "bad CFL range");
+  } else if (!(o->dtau_init > 0.0) || !(o->dtau_max >= o->dtau_init)) {
+    return fail(PMG_E_ARG, "bad dtau range");
+  }
   if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
   const bool steady = !(dt > 0.0);
   if (!steady) {
@@ -699,10 +763,18 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
   }
   for (int l = 0; l < o->n_levels; ++l) PMG_HIP(hipMemsetAsync(o->levels[l]->flag, 0, sizeof(int), s.st));
 
+  // pseudo-time range: given directly, or as CFL numbers times dtau_min of eq. (33) at q^0
+  double dtau_init = o->dtau_init, dtau_max = o->dtau_max, dtmin = 0.0;
+  if (o->use_cfl) {
+    if (pmg_status e = pmg_dtau_min(L0, q, &dtmin, stream)) return e;
+    dtau_init = o->cfl_init * dtmin;
+    dtau_max = o->cfl_max * dtmin;
+  }
+  if (stats) stats->dtau_min = dtmin;
   double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
   int m = 0;
   pmg_status result = PMG_E_NOT_CONVERGED;
-  s.dtau = o->dtau_init;
+  s.dtau = dtau_init;
   if (stats) stats->n_refresh = 0;
   // r_0 = ||F(q^0)||; every V-cycle ends with the norm of its result, r_{m+1}
   PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, s.st));
@@ -717,7 +789,7 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
     if (m == 0) {
       r0 = r;
     } else {
-      s.dtau = std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), o->dtau_max);   // eq. (31)
+      s.dtau = std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), dtau_max);   // eq. (31)
     }
     if (r == 0.0 || r / r0 <= o->tol_rel) {
       result = PMG_OK;
@@ -727,7 +799,7 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
       result = fail(PMG_E_NOT_CONVERGED, "stage solve reached max_vcycles");
       break;
     }
-    const bool frozen = o->freeze_at_max && dtau_last_refresh >= o->dtau_max;
+    const bool frozen = o->freeze_at_max && dtau_last_refresh >= dtau_max;
     s.refresh = (m == 0) || (m % o->refresh_every == 0 && !frozen);
     if (s.refresh) {
       PMG_HIP(pmg::launch_jacobian(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));

@@ -67,6 +67,10 @@ struct pmg_level_s {
   double* norms = nullptr;   // [Nv + 1]
   int* flag = nullptr;       // device error flags
   int part_blocks = 0;
+  std::vector<double> dx_host;     // [Ne] element length scale of eqs. (32)-(33)
+  double* hdx = nullptr;           // [Ne] device: dx_e / (P + 1)
+  double* dtpart = nullptr;        // per-workgroup partial minima of the pseudo-time scale
+  double* dtmin = nullptr;         // device scalar: dtau_min
   // replayable V-cycle of the stage solve (finest level only), keyed by its arguments
   hipGraphExec_t vc_exec = nullptr;
   hipStream_t capture_stream = nullptr;
@@ -115,5 +119,7 @@ hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc
 hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
                                int n_prev, double dt, double c_mass, double* src, hipStream_t st);
 int residual_blocks(const pmg_level_s& L);
+int dtau_blocks(const pmg_level_s& L);
+hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st);
 
 }  // namespace pmg

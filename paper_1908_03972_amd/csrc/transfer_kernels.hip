@@ -127,6 +127,45 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict_
 
 static unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
+// Pseudo-time scale of eq. (33), inviscid part: per solution point h_e / (c + |v|) with
+// h_e = dx_e / (P+1); a point with T <= 0 or a non-finite value yields -1 so the minimum flags it.
+__global__ void __launch_bounds__(256) k_dtau_partial(int ne, int np, const double* __restrict__ q,
+                                                      const double* __restrict__ hdx, Ref4 ref, double gr,
+                                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  const size_t total = (size_t)np * ne, st = total;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double val = 1.0e300;
+  if (i < total) {
+    const int e = (int)(i % (size_t)ne);
+    const double u = q[st + i] + ref.v[1], v = q[2 * st + i] + ref.v[2], t = q[3 * st + i] + ref.v[3];
+    const double speed = sqrt(gr * t) + sqrt(u * u + v * v);
+    const double h = hdx[e] / speed;
+    val = (t > 0.0 && h > 0.0 && h < 1.0e300) ? h : -1.0;
+  }
+  red[threadIdx.x] = val;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_dtau_final(const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 1.0e300;
+  for (int b = threadIdx.x; b < nblk; b += 256) m = fmin(m, part[b]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
                            double* xc, int nvar, hipStream_t st, double* xc2) {
   Mat1D R{};
@@ -180,6 +219,18 @@ hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const d
 
 hipError_t launch_norm_finalize(const pmg_level_s& L, hipStream_t st) {
   hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, L.part, residual_blocks(L), L.nv, L.norms);
+  return hipGetLastError();
+}
+
+int dtau_blocks(const pmg_level_s& L) { return (int)blocks_for((size_t)L.np * L.ne); }
+
+hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st) {
+  Ref4 ref{};
+  for (int k = 0; k < 4; ++k) ref.v[k] = L.q_ref[k];
+  const int nblk = dtau_blocks(L);
+  hipLaunchKernelGGL(k_dtau_partial, dim3(nblk), dim3(256), 0, st, L.ne, L.np, q, L.hdx, ref,
+                     L.gas.gamma * L.gas.rgas, L.dtpart);
+  hipLaunchKernelGGL(k_dtau_final, dim3(1), dim3(256), 0, st, L.dtpart, nblk, L.dtmin);
   return hipGetLastError();
 }
 

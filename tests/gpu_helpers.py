@@ -61,3 +61,23 @@ def tolerance(floor):
     """Per-variable parity bound: the FP64 target, or ten times the rounding floor where the
     method's own cancellation makes the target unreachable."""
     return np.maximum(PARITY_REL, 10.0 * floor)
+
+
+def fp32_solver_class():
+    """The oracle's PMG solver with the smoother's block inverses rounded to FP32 and the
+    block-vector products taken in FP32: the rounding the mixed-precision smoother introduces,
+    reproduced on the CPU so that its effect sizes the FP32 parity tolerance (at Ma <= 1e-3 the
+    temperature update amplifies it far beyond u_32)."""
+    from oracle import solver as OS
+
+    class PMGSolverFP32(OS.PMGSolver):
+        def smooth(self, l, q, S, nsweep):
+            lev = self.levels[l]
+            winv = np.linalg.inv(self.D[l]).astype(np.float32)
+            for _ in range(nsweep):
+                Fq = self.F(l, q, S).reshape(lev.ne, lev.n, 1).astype(np.float32)
+                dq = np.matmul(winv, Fq).astype(np.float64)
+                q = q + self.opts.alpha_r * dq.reshape(q.shape)
+            return q
+
+    return PMGSolverFP32

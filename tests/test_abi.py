@@ -32,7 +32,10 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     lib.pmg_abi_version.restype = ctypes.c_int32
-    assert lib.pmg_abi_version() == 100
+    import re
+    with open(HEADER) as f:
+        version = int(re.search(r"#define PMG_ABI_VERSION (\d+)", f.read()).group(1))
+    assert lib.pmg_abi_version() == version
     lib.pmg_last_error.restype = ctypes.c_char_p
     assert lib.pmg_last_error() == b""
 

@@ -167,3 +167,82 @@ def vortex_config1() -> tuple[Mesh, VortexSpec]:
 def vortex_config2() -> tuple[Mesh, VortexSpec]:
     """64x64 periodic quads on [-5,5]^2, vertices jittered by +-10% of the cell size."""
     return periodic_quad_mesh(64, 10.0, jitter=0.1, seed=JITTER_SEED), VortexSpec(length=10.0)
+
+
+# ---- airfoil O-mesh (synthetic stand-in for the NACA0012 meshes of Sec. 4.2) --------------
+def naca4_symmetric_half_thickness(x: np.ndarray, t: float = 0.12) -> np.ndarray:
+    """Half thickness of the symmetric 4-digit profile with the closed-trailing-edge coefficient."""
+    x = np.clip(np.asarray(x, float), 0.0, 1.0)
+    return 5.0 * t * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x ** 2 + 0.2843 * x ** 3 - 0.1036 * x ** 4)
+
+
+def airfoil_o_mesh(n_wrap: int = 128, n_radial: int = 64, ratio: float = 1.1, r_far: float = 20.0,
+                   thickness: float = 0.12, annulus: bool = False) -> Mesh:
+    """9-node quadratic O-mesh around a closed-TE symmetric 4-digit profile (chord 1).
+
+    Wrap direction (xi): surface points at angle theta = 2 pi s / n_wrap (s in half steps for the
+    mid-edge nodes), x = (1 + cos theta)/2 (cosine clustering), y = -y_t(x) for sin theta > 0 and
+    +y_t(x) otherwise, i.e. the surface is walked clockwise so that (xi, eta) is right-handed.
+    Radial direction (eta): straight lines from each surface point to the far-field circle point
+    (0.5 + r_far cos theta, -r_far sin theta), node fractions (ratio^k - 1)/(ratio^n - 1) with k in
+    half steps (first cell height ~ r_far * (ratio - 1)/(ratio^n - 1)).
+    Faces: xi faces wrap periodically; eta = -1 of the first layer is a slip wall, eta = +1 of the
+    last layer far field. With annulus=True the profile is replaced by the unit circle and the
+    inner boundary is also far field (a curved mesh for free-stream tests).
+    Element e = i + n_wrap * j.
+    """
+    nw, nr = n_wrap, n_radial
+    s_half = np.arange(2 * nw + 1) / 2.0                       # wrap positions in half cells
+    theta = 2.0 * np.pi * s_half / nw
+    if annulus:
+        xs, ys = np.cos(theta), -np.sin(theta)
+        cx = 0.0
+    else:
+        xs = 0.5 * (1.0 + np.cos(theta))
+        yt = naca4_symmetric_half_thickness(xs, thickness)
+        ys = np.where(np.sin(theta) > 0.0, -yt, yt)
+        ys[np.abs(np.sin(theta)) < 1e-15] = 0.0
+        cx = 0.5
+    xf, yf = cx + r_far * np.cos(theta), -r_far * np.sin(theta)
+    k_half = np.arange(2 * nr + 1) / 2.0
+    frac = (ratio ** k_half - 1.0) / (ratio ** nr - 1.0)
+    X = xs[:, None] + frac[None, :] * (xf - xs)[:, None]        # [2nw+1, 2nr+1]
+    Y = ys[:, None] + frac[None, :] * (yf - ys)[:, None]
+    ne = nw * nr
+    nodes = np.zeros((ne, 9, 2))
+    nbr = np.zeros((ne, 4), np.int32)
+    nbf = np.zeros((ne, 4), np.int32)
+    for j in range(nr):
+        for i in range(nw):
+            e = i + nw * j
+            for b in range(3):
+                for a in range(3):
+                    nodes[e, a + 3 * b] = (X[2 * i + a, 2 * j + b], Y[2 * i + a, 2 * j + b])
+            nbr[e, 0] = (i - 1) % nw + nw * j
+            nbr[e, 1] = (i + 1) % nw + nw * j
+            nbr[e, 2] = (i + nw * (j - 1)) if j > 0 else (BC_FAR_FIELD if annulus else BC_SLIP_WALL)
+            nbr[e, 3] = (i + nw * (j + 1)) if j < nr - 1 else BC_FAR_FIELD
+            nbf[e] = (1, 0, 3, 2)
+    name = f"{'annulus' if annulus else 'airfoil'}_o{nw}x{nr}"
+    return Mesh(2, 2, nodes, nbr, nbf, np.zeros_like(nbr), name=name,
+                info={"ratio": ratio, "r_far": r_far, "thickness": thickness, "annulus": annulus})
+
+
+@dataclass
+class FreeStreamSpec:
+    """Uniform low-Mach free stream at incidence (Sec. 4.2): rho = 1, |V| = 1, c = |V|/Ma, R = 1."""
+    gamma: float = 1.4
+    rgas: float = 1.0
+    ma_inf: float = 0.001
+    alpha_deg: float = 2.0
+
+    def freestream(self) -> np.ndarray:
+        a = math.radians(self.alpha_deg)
+        c = 1.0 / self.ma_inf
+        t = c * c / (self.gamma * self.rgas)
+        return np.array([self.rgas * t, math.cos(a), math.sin(a), t])
+
+
+def airfoil_config3(n_wrap: int = 128, n_radial: int = 64) -> tuple[Mesh, FreeStreamSpec]:
+    """Inviscid flow at Ma 0.001, 2 degrees incidence around the 12% symmetric profile."""
+    return airfoil_o_mesh(n_wrap, n_radial), FreeStreamSpec()
