@@ -128,7 +128,70 @@ def run_form(api, torch, levels, q0, form, scheme, dt, steps, warmup, max_vcycle
     return facs, solver, q, stage_stats, elapsed
 
 
+AIRFOIL_HIERARCHIES = (("P4-2-1", (4, 2, 1), (5, 10, 20)), ("P4-3-2-1-0", (4, 3, 2, 1, 0), (5, 10, 20, 20, 20)))
+
+
+def airfoil_block(api, torch, forms, max_vcycles, kernel_reps):
+    """Steady inviscid flow at Ma 0.001, 2 degrees, around the 12% symmetric profile on the
+    128 x 64 quadratic O-mesh, P = 4 (Sec. 4.2): for each hierarchy and block precision, one
+    steady solve from the free stream with CFL 1e2 -> 1e5 (blocks rebuilt every 10 V-cycles),
+    its V-cycle rate, residual history and time to each tolerance, and the live duration of the
+    fine-level fused sweep."""
+    mesh, fs = W.airfoil_config3()
+    qinf = fs.freestream()
+    out = {"workload": "NACA-type 12% symmetric profile, O-mesh 128x64 quadratic quads, Ma 0.001, 2 deg, "
+                       "slip wall + far field, cut-off eps (kappa 1), steady, CFL 1e2 -> 1e5, "
+                       "blocks rebuilt every 10 V-cycles", "elements": mesh.n_elements}
+    for name, plev, nsm in AIRFOIL_HIERARCHIES:
+        levels = [api.Level(mesh, P, gamma=fs.gamma, rgas=fs.rgas, eps_mode=1, ma_inf=fs.ma_inf, kappa=1.0,
+                            q_inf=qinf, q_ref=qinf) for P in plev]
+        per_vc = dof_updates_per_vcycle(levels[0].ne, plev, nsm)
+        res = {"dof_updates_per_vcycle": per_vc, "n_smooth": list(nsm)}
+        for form in forms:
+            prec, graph = FORMS[form]
+            facs = [api.Factors(lv, prec) for lv in levels]
+            kw = dict(tol_rel=1e-8, use_graph=graph, use_cfl=True, cfl_init=1e2, cfl_max=1e5, freeze_at_max=False)
+            q = levels[0].new_state()                    # the free stream (zero offset)
+            api.StageSolver(levels, facs, nsm, max_vcycles=12, **kw).solve(q, raise_on_error=False)   # warm-up
+            q.zero_()
+            solver = api.StageSolver(levels, facs, nsm, max_vcycles=max_vcycles, **kw)
+            torch.cuda.synchronize()
+            st = solver.solve(q, raise_on_error=False)
+            h = np.asarray(st["history"]) / st["history"][0]
+            per = st["seconds"] / max(st["n_vcycles"], 1)
+            ttt = {}
+            for t in TOLS:
+                hit = np.nonzero(h <= t)[0]
+                ttt[f"{t:.0e}"] = float(hit[0] * per) if hit.size else None
+            fin = np.isfinite(h)
+            # live duration of the fine-level fused residual + sweep (alpha_r = 0 keeps q fixed)
+            qk = q.clone()
+            api.ejacobi_sweep(levels[0], facs[0], qk, 2, alpha_r=0.0)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            api.ejacobi_sweep(levels[0], facs[0], qk, kernel_reps, alpha_r=0.0)
+            ev1.record()
+            torch.cuda.synchronize()
+            k_ms = ev0.elapsed_time(ev1) / kernel_reps
+            n = levels[0].n
+            bpd = (4 if prec == 32 else 8) * n + 24
+            kbytes = levels[0].ne * n * bpd
+            res[form] = {"status": st["status"], "vcycles": st["n_vcycles"], "block_rebuilds": st["n_refresh"],
+                         "seconds": st["seconds"], "ms_per_vcycle": 1e3 * per,
+                         "dof_updates_per_s": per_vc * st["n_vcycles"] / st["seconds"],
+                         "time_to_tol_s": ttt, "min_rel_residual": float(np.min(h[fin])),
+                         "final_rel_residual": float(h[fin][-1]), "dtau_min": st["dtau_min"],
+                         "history_every_25": [float(x) for x in h[::25]],
+                         "fine_sweep_kernel_ms": k_ms, "fine_sweep_bytes_per_launch": kbytes,
+                         "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "fine_sweep_traffic": measured_traffic(PROFILE_PMC_AIRFOIL) if prec == 32 else None}
+            del facs, solver
+        out[name] = res
+    return out
+
+
 PROFILE_PMC = os.path.join(ROOT, "profiles", "k_fr_sweep_vortex64_P321_pmc.txt")
+PROFILE_PMC_AIRFOIL = os.path.join(ROOT, "profiles", "k_fr_sweep_airfoil128x64_P4_pmc.txt")
 
 
 def kernel_source_hash():
@@ -140,11 +203,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused P=3 sweep from the committed counter summary, or None
+def measured_traffic(path=PROFILE_PMC):
+    """HBM bytes per launch of the dominant fused sweep from a committed counter summary, or None
     when the kernel sources have changed since the counters were taken."""
     try:
-        vals = dict(line.split(": ", 1) for line in open(PROFILE_PMC).read().splitlines()
+        vals = dict(line.split(": ", 1) for line in open(path).read().splitlines()
                     if line.startswith(("traffic_bytes_per_launch:", "kernel_source_hash:")))
     except (OSError, ValueError):
         return None
@@ -163,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the 8x8 time-to-1e-8 measurement")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
+    ap.add_argument("--airfoil-vcycles", type=int, default=600)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -289,6 +354,9 @@ def main():
             small["speedup_time_to_1e-8_mixed_over_fp64"] = (small["fp64"]["time_to_1e-8_s_total"]
                                                              / small["mixed"]["time_to_1e-8_s_total"])
         line["time_to_1e-8_8x8_P210_esdirk2"] = small
+    if not args.no_airfoil:
+        line["airfoil_128x64_P4_steady"] = airfoil_block(api, torch, args.forms.split(","), args.airfoil_vcycles,
+                                                         args.kernel_reps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -1,14 +1,15 @@
 // Element blocks of the pseudo-transient linearisation (eqs. (28)-(30)) and their inverses.
 //
-// One workgroup per element:
+// One workgroup of ceil(n / 64) wavefronts per element:
 //   1. pointwise Jacobians of the transformed fluxes dF~/dq, dG~/dq (forward-mode duals, one
 //      tangent per thread) and the diagonal term Gamma/dtau + c_mass M at every solution point;
 //   2. the Jacobian of the common flux of eq. (21) with respect to the element's own trace at
 //      every flux point, including the dependence of the mean state, eigenvalues and Gamma;
-//   3. assembly of D_e = Gamma/dtau + c_mass M - dR_e/dq_e from the tensor-line structure: a
-//      point couples only to points on its own xi- and eta-lines;
-//   4. row equilibration by powers of two and in-place Gauss-Jordan inversion with partial
-//      pivoting in FP64 LDS;
+//   3. assembly of D_e = Gamma/dtau + c_mass M - dR_e/dq_e from the tensor-line structure (a
+//      point couples only to points on its own xi- and eta-lines), one row per thread in
+//      registers;
+//   4. row equilibration by powers of two and Gauss-Jordan inversion in FP64 registers with
+//      partial pivoting;
 //   5. the inverse is written column-major per element ([c][e][r]) at the factor precision,
 //      the layout the sweep kernel streams.
 #include "internal.hpp"
@@ -28,396 +29,184 @@ struct JacArgs {
   int* flag;
 };
 
-template <int P>
-struct JCfg {
-  static constexpr int N1 = P + 1;
-  static constexpr int NP = N1 * N1;
-  static constexpr int NV = 4;
-  static constexpr int N = NV * NP;
-  static constexpr int LD = N + 1;       // padded LDS row pitch
-  static constexpr size_t lds_doubles() {
-    return (size_t)N * LD + NV * NP + 3 * NP * 16 + 4 * N1 * 16 + 3 * N;
+// Pointwise task t = pp * NV + w: column w of the flux Jacobians dF~/dq, dG~/dq at solution point
+// pp (forward-mode duals seeded in component w) and of the diagonal term Gamma/dtau + c_mass M.
+__device__ __forceinline__ void point_jacobian(const JacArgs& a, int e, const double* sq, int t, int NP, int ne,
+                                               size_t sstride, double* sAF, double* sAG, double* sDg) {
+  constexpr int NV = 4;
+  const int pp = t / NV, w = t % NV;
+  Dual<1> qd[NV];
+  double qv[NV];                         // absolute state: q_ref + stored offset
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    qv[v] = a.lv.q_ref[v] + sq[v * NP + pp];
+    qd[v] = dconst<1>(qv[v]);
   }
-  static constexpr size_t lds_bytes() { return lds_doubles() * 8 + (N + 4) * sizeof(int); }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qd[v].d[0] = (v == w) ? 1.0 : 0.0;   // seed without a dynamic index
+  const size_t gp = (size_t)pp * ne + e;
+  const double* m = a.lv.met;
+  Dual<1> fs[NV], ft[NV], qc[NV];
+  normal_flux2(qd, m[gp], m[sstride + gp], a.gas, fs);
+  normal_flux2(qd, m[2 * sstride + gp], m[3 * sstride + gp], a.gas, ft);
+  conservative2(qd, a.gas, qc);
+  const State2<double> s = make_state(qv, a.gas);
+  double ew[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ew[v] = (v == w) ? 1.0 : 0.0;
+  double gcol[NV];
+  gamma_mul(s, a.gas, ew, gcol);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    sAF[(pp * NV + v) * NV + w] = fs[v].d[0];
+    sAG[(pp * NV + v) * NV + w] = ft[v].d[0];
+    sDg[(pp * NV + v) * NV + w] = gcol[v] * a.inv_dtau + a.c_mass * qc[v].d[0];
+  }
+}
+
+// Face task t = (f * N1 + k) * NV + w: column w of the Jacobian of the common flux of eq. (21) at
+// flux point k of face f with respect to the element's own trace (neighbour trace fixed; wall ghost
+// and far-field state as in the residual), including the dependence of the mean state.
+__device__ __forceinline__ void face_jacobian(const JacArgs& a, int e, const double* sq, int t, int N1, int NP,
+                                              int ne, size_t sstride, double* sB) {
+  constexpr int NV = 4;
+  const Ops1D& o = a.ops;
+  const int f = t / (N1 * NV), k = (t / NV) % N1, w = t % NV;
+  const double* wt = (f == 0 || f == 2) ? o.lm : o.lp;
+  double ownv[NV] = {0.0, 0.0, 0.0, 0.0};
+  for (int mm = 0; mm < N1; ++mm) {
+    const int pp = (f < 2) ? (mm + N1 * k) : (k + N1 * mm);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ownv[v] += wt[mm] * sq[v * NP + pp];
+  }
+  Dual<1> own[NV], out[NV];              // stored offsets; own seeded in component w
+#pragma unroll
+  for (int v = 0; v < NV; ++v) own[v] = dconst<1>(ownv[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) own[v].d[0] = (v == w) ? 1.0 : 0.0;
+  const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
+  const double nx = a.lv.fvec[fo], ny = a.lv.fvec[fo + ne], sm = a.lv.fvec[fo + 2 * ne];
+  const int nb = a.lv.nbr[f * ne + e];
+  if (nb >= 0) {
+    const int nf = a.lv.nbf[f * ne + e];
+    const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
+    const double* wn = (nf == 0 || nf == 2) ? o.lm : o.lp;
+    double ov[NV] = {0.0, 0.0, 0.0, 0.0};
+    for (int mm = 0; mm < N1; ++mm) {
+      const int pp = (nf < 2) ? (mm + N1 * kk) : (kk + N1 * mm);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ov[v] += wn[mm] * a.q[v * sstride + (size_t)pp * ne + nb];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = dconst<1>(ov[v]);
+  } else if (nb == -1) {                 // slip wall: mirrored absolute velocity
+    Dual<1> ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2];
+    Dual<1> un = ua * nx + va * ny;
+    out[0] = own[0];
+    out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+    out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
+    out[3] = own[3];
+  } else {                               // far field
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.qinf_g[v]);
+  }
+  Dual<1> own_a[NV], out_a[NV], dq[NV], fh[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    own_a[v] = own[v] + a.lv.q_ref[v];
+    out_a[v] = out[v] + a.lv.q_ref[v];
+  }
+  if (f == 0 || f == 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
+    common_flux2(out_a, own_a, dq, nx, ny, sm, a.gas, fh);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
+    common_flux2(own_a, out_a, dq, nx, ny, sm, a.gas, fh);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sB[((f * N1 + k) * NV + v) * NV + w] = fh[v].d[0];
+}
+
+// Same blocks for any P <= 4 with each row of D_e held in registers by S threads (S = 1, or 2
+// for n >= 64: thread 2r holds columns [0, n/2) of row r, thread 2r+1 columns [n/2, n)), in
+// ceil(S n / 64) wavefronts per element. The elimination is Gauss-Jordan with implicit partial
+// pivoting (the pivot row is chosen among rows not yet used; no rows move) in the
+// column-cycling form: step k always eliminates with the first stored column, every row shifts
+// left by one and the new column of the inverse enters at the right end, so that after n steps
+// the stored array is the in-place inverse and no register array is ever indexed by a run-time
+// value. Each wavefront's pivot candidate publishes its row to LDS before the cross-wave choice,
+// so one barrier per step suffices (two slot sets alternate between steps).
+template <int P, int S>
+struct RowsCfg {
+  static constexpr int N1 = P + 1, NP = N1 * N1, NV = 4, N = NV * NP;
+  static constexpr int H = N / S;                 // columns per thread
+  static constexpr int NW = (S * N + 63) / 64;
+  static constexpr int NT = 64 * NW;
+  static_assert(N % S == 0 && (S == 1 || S == 2), "one or two threads per row");
+  static_assert(S * N <= 254, "pivot keys carry the thread index in 8 bits");
 };
 
-template <int P>
-__global__ void __launch_bounds__(256) k_jac(JacArgs a) {
-  using C = JCfg<P>;
-  constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, LD = C::LD;
-  extern __shared__ double smem[];
-  double* sD = smem;                    // [N][LD]
-  double* sq = sD + N * LD;             // [NV][NP]
-  double* sAF = sq + NV * NP;           // [NP][NV][NV]  dF~/dq
-  double* sAG = sAF + NP * 16;          // [NP][NV][NV]  dG~/dq
-  double* sDg = sAG + NP * 16;          // [NP][NV][NV]  Gamma/dtau + c_mass M
-  double* sB = sDg + NP * 16;           // [4][N1][NV][NV] dF^/dq_own
-  double* scol = sB + 4 * N1 * 16;      // [N]
-  double* srow = scol + N;              // [N]
-  double* sscl = srow + N;              // [N]
-  int* sperm = reinterpret_cast<int*>(sscl + N);  // [N]
-  int* spiv = sperm + N;
+// Maximum of an unsigned value over the 64 lanes of a wavefront, returned to every lane: DPP
+// rotations within each row of 16 lanes, then the four row maxima through scalar registers.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xf, 0xf, false));   // row_ror:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xf, 0xf, false));   // row_ror:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));   // row_ror:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));   // row_ror:8
+  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// A double from a fixed lane of each pair (lane 2m or 2m+1) with a DPP quad permutation.
+template <int CTRL>
+__device__ __forceinline__ double pair_dpp(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kQuadEven = 0xA0;   // quad_perm [0,0,2,2]: the even lane of each pair
+constexpr int kQuadOdd = 0xF5;    // quad_perm [1,1,3,3]: the odd lane of each pair
+
+template <int P, int S>
+__global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
+  using C = RowsCfg<P, S>;
+  constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, H = C::H, NW = C::NW, NT = C::NT;
+  __shared__ double sq[NV * NP];
+  __shared__ double sAF[NP * 16], sAG[NP * 16], sDg[NP * 16];
+  __shared__ double sB[4 * N1 * 16];
+  __shared__ double sscl[N];
+  __shared__ int sperm[N];
+  __shared__ double slot[2][NW][N];      // pivot candidates' rows, alternating between steps
+  __shared__ unsigned skey[2][NW];
 
   const int ne = a.lv.ne;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const size_t sstride = (size_t)NP * ne;
   const Ops1D& o = a.ops;
 
-  for (int t = tid; t < NV * NP; t += blockDim.x) {
+  for (int t = tid; t < NV * NP; t += NT) {
     const int v = t / NP, pp = t % NP;
     sq[t] = a.q[v * sstride + (size_t)pp * ne + e];
   }
   __syncthreads();
-
-  // (1) pointwise flux Jacobians and the diagonal pseudo-time / mass term
-  for (int t = tid; t < NP * NV; t += blockDim.x) {
-    const int pp = t / NV, w = t % NV;
-    Dual<1> qd[NV];
-    double qv[NV];                       // absolute state: q_ref + stored offset
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      qv[v] = a.lv.q_ref[v] + sq[v * NP + pp];
-      qd[v] = dconst<1>(qv[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) qd[v].d[0] = (v == w) ? 1.0 : 0.0;   // seed without a dynamic index
-    const size_t gp = (size_t)pp * ne + e;
-    const double* m = a.lv.met;
-    Dual<1> fs[NV], ft[NV], qc[NV];
-    normal_flux2(qd, m[gp], m[sstride + gp], a.gas, fs);
-    normal_flux2(qd, m[2 * sstride + gp], m[3 * sstride + gp], a.gas, ft);
-    conservative2(qd, a.gas, qc);
-    const State2<double> s = make_state(qv, a.gas);
-    double ew[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ew[v] = (v == w) ? 1.0 : 0.0;
-    double gcol[NV];
-    gamma_mul(s, a.gas, ew, gcol);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      sAF[(pp * NV + v) * NV + w] = fs[v].d[0];
-      sAG[(pp * NV + v) * NV + w] = ft[v].d[0];
-      sDg[(pp * NV + v) * NV + w] = gcol[v] * a.inv_dtau + a.c_mass * qc[v].d[0];
-    }
-  }
-
-  // (2) Jacobian of the common flux at every flux point w.r.t. the element's own trace
-  for (int t = tid; t < 4 * N1 * NV; t += blockDim.x) {
-    const int f = t / (N1 * NV), k = (t / NV) % N1, w = t % NV;
-    const double* wt = (f == 0 || f == 2) ? o.lm : o.lp;
-    double ownv[NV] = {0.0, 0.0, 0.0, 0.0};
-    for (int mm = 0; mm < N1; ++mm) {
-      const int pp = (f < 2) ? (mm + N1 * k) : (k + N1 * mm);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ownv[v] += wt[mm] * sq[v * NP + pp];
-    }
-    Dual<1> own[NV], out[NV];            // stored offsets; own seeded in component w
-#pragma unroll
-    for (int v = 0; v < NV; ++v) own[v] = dconst<1>(ownv[v]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) own[v].d[0] = (v == w) ? 1.0 : 0.0;
-    const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
-    const double nx = a.lv.fvec[fo], ny = a.lv.fvec[fo + ne], sm = a.lv.fvec[fo + 2 * ne];
-    const int nb = a.lv.nbr[f * ne + e];
-    if (nb >= 0) {
-      const int nf = a.lv.nbf[f * ne + e];
-      const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
-      const double* wn = (nf == 0 || nf == 2) ? o.lm : o.lp;
-      double ov[NV] = {0.0, 0.0, 0.0, 0.0};
-      for (int mm = 0; mm < N1; ++mm) {
-        const int pp = (nf < 2) ? (mm + N1 * kk) : (kk + N1 * mm);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) ov[v] += wn[mm] * a.q[v * sstride + (size_t)pp * ne + nb];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(ov[v]);
-    } else if (nb == -1) {
-      Dual<1> ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2];
-      Dual<1> un = ua * nx + va * ny;
-      out[0] = own[0];
-      out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
-      out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
-      out[3] = own[3];
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.qinf_g[v]);
-    }
-    Dual<1> own_a[NV], out_a[NV], dq[NV], fh[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      own_a[v] = own[v] + a.lv.q_ref[v];
-      out_a[v] = out[v] + a.lv.q_ref[v];
-    }
-    if (f == 0 || f == 2) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
-      common_flux2(out_a, own_a, dq, nx, ny, sm, a.gas, fh);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
-      common_flux2(own_a, out_a, dq, nx, ny, sm, a.gas, fh);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sB[((f * N1 + k) * NV + v) * NV + w] = fh[v].d[0];
-  }
+  for (int t = tid; t < NP * NV; t += NT) point_jacobian(a, e, sq, t, NP, ne, sstride, sAF, sAG, sDg);
+  for (int t = tid; t < 4 * N1 * NV; t += NT) face_jacobian(a, e, sq, t, N1, NP, ne, sstride, sB);
   __syncthreads();
 
-  // (3) assembly of D_e
-  for (int idx = tid; idx < N * N; idx += blockDim.x) {
-    const int r = idx / N, c = idx % N;
-    const int pp = r / NV, v = r % NV, ss = c / NV, w = c % NV;
-    const int i = pp % N1, j = pp / N1, k = ss % N1, l = ss / N1;
-    double acc = 0.0;
-    if (l == j) {   // xi-line of point (i, j)
-      const double cx = o.D[i * N1 + k] - o.gL[i] * o.lm[k] - o.gR[i] * o.lp[k];
-      acc += cx * sAF[(ss * NV + v) * NV + w] + o.gL[i] * o.lm[k] * sB[((0 * N1 + j) * NV + v) * NV + w] +
-             o.gR[i] * o.lp[k] * sB[((1 * N1 + j) * NV + v) * NV + w];
-    }
-    if (k == i) {   // eta-line
-      const double cy = o.D[j * N1 + l] - o.gL[j] * o.lm[l] - o.gR[j] * o.lp[l];
-      acc += cy * sAG[(ss * NV + v) * NV + w] + o.gL[j] * o.lm[l] * sB[((2 * N1 + i) * NV + v) * NV + w] +
-             o.gR[j] * o.lp[l] * sB[((3 * N1 + i) * NV + v) * NV + w];
-    }
-    const double ijac = a.lv.met[4 * sstride + (size_t)pp * ne + e];
-    double dval = acc * ijac;             // -dR/dq, with R = -(1/|J|) div
-    if (pp == ss) dval += sDg[(pp * NV + v) * NV + w];
-    sD[r * LD + c] = dval;
-    if (a.D_out) a.D_out[((size_t)e * N + r) * N + c] = dval;
-  }
-  __syncthreads();
-
-  // (4) row equilibration by powers of two, then Gauss-Jordan with partial pivoting
-  for (int r = tid; r < N; r += blockDim.x) {
-    double mx = 0.0;
-    for (int c = 0; c < N; ++c) mx = fmax(mx, fabs(sD[r * LD + c]));
-    int ex = 0;
-    frexp(mx, &ex);
-    sscl[r] = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < N * N; idx += blockDim.x) {
-    const int r = idx / N, c = idx % N;
-    sD[r * LD + c] *= sscl[r];
-  }
-  __syncthreads();
-
-  for (int kk = 0; kk < N; ++kk) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = kk;
-      for (int r = kk + tid; r < N; r += 64) {
-        const double av = fabs(sD[r * LD + kk]);
-        if (av > best) {
-          best = av;
-          bi = r;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (tid == 0) {
-        spiv[0] = bi;
-        sperm[kk] = bi;
-      }
-    }
-    __syncthreads();
-    const int pr = spiv[0];
-    if (pr != kk) {
-      for (int c = tid; c < N; c += blockDim.x) {
-        const double tmp = sD[kk * LD + c];
-        sD[kk * LD + c] = sD[pr * LD + c];
-        sD[pr * LD + c] = tmp;
-      }
-    }
-    __syncthreads();
-    for (int t = tid; t < N; t += blockDim.x) {
-      scol[t] = sD[t * LD + kk];
-      srow[t] = sD[kk * LD + t];
-    }
-    __syncthreads();
-    double piv = scol[kk];
-    if (piv == 0.0 || !isfinite(piv)) {
-      if (tid == 0) *a.flag = 1;
-      piv = 1.0;
-    }
-    const double ip = 1.0 / piv;
-    for (int idx = tid; idx < N * N; idx += blockDim.x) {
-      const int r = idx / N, c = idx % N;
-      double nv;
-      if (r == kk)
-        nv = (c == kk) ? ip : srow[c] * ip;
-      else if (c == kk)
-        nv = -scol[r] * ip;
-      else
-        nv = sD[r * LD + c] - scol[r] * (srow[c] * ip);
-      sD[r * LD + c] = nv;
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, last first
-  for (int kk = N - 1; kk >= 0; --kk) {
-    const int pr = sperm[kk];
-    if (pr != kk) {
-      for (int r = tid; r < N; r += blockDim.x) {
-        const double tmp = sD[r * LD + kk];
-        sD[r * LD + kk] = sD[r * LD + pr];
-        sD[r * LD + pr] = tmp;
-      }
-    }
-    __syncthreads();
-  }
-
-  // (5) D^{-1} = (S_r D)^{-1} S_r: scale column c by the row scale of row c; store [c][e][r]
-  for (int idx = tid; idx < N * N; idx += blockDim.x) {
-    const int c = idx / N, r = idx % N;
-    const double val = sD[r * LD + c] * sscl[c];
-    const size_t o_ = ((size_t)c * ne + e) * N + r;
-    if (a.precision == 32)
-      static_cast<float*>(a.W)[o_] = (float)val;
-    else
-      static_cast<double*>(a.W)[o_] = val;
-  }
-}
-
-// Broadcast a double from a wave-uniform lane (two 32-bit lane reads into scalar registers).
-__device__ __forceinline__ double read_lane(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-
-// Same blocks for n = 4 (P+1)^2 <= 64 with one wavefront per element: lane r builds row r of
-// D_e in registers and the Gauss-Jordan elimination runs with implicit partial pivoting (the
-// pivot row is chosen among rows not yet used and broadcast by lane reads, no row swaps and no
-// workgroup barriers); the inverse comes out with rows and columns permuted by the pivot order,
-// which the final store undoes.
-template <int P>
-__global__ void __launch_bounds__(64) k_jac_wave(JacArgs a) {
-  constexpr int N1 = P + 1, NP = N1 * N1, NV = 4, N = NV * NP;
-  static_assert(N <= 64, "one row per lane");
-  __shared__ double sq[NV * NP];
-  __shared__ double sAF[NP * 16], sAG[NP * 16], sDg[NP * 16];
-  __shared__ double sB[4 * N1 * 16];
-  __shared__ double sscl[64];
-  __shared__ int sperm[64];
-
-  const int ne = a.lv.ne;
-  const int e = blockIdx.x;
-  const int lane = threadIdx.x;
-  const size_t sstride = (size_t)NP * ne;
-  const Ops1D& o = a.ops;
-
-  for (int t = lane; t < NV * NP; t += 64) {
-    const int v = t / NP, pp = t % NP;
-    sq[t] = a.q[v * sstride + (size_t)pp * ne + e];
-  }
-  __syncthreads();
-
-  for (int t = lane; t < NP * NV; t += 64) {     // pointwise flux Jacobians and diagonal term
-    const int pp = t / NV, w = t % NV;
-    Dual<1> qd[NV];
-    double qv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      qv[v] = a.lv.q_ref[v] + sq[v * NP + pp];
-      qd[v] = dconst<1>(qv[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) qd[v].d[0] = (v == w) ? 1.0 : 0.0;   // seed without a dynamic index
-    const size_t gp = (size_t)pp * ne + e;
-    const double* m = a.lv.met;
-    Dual<1> fs[NV], ft[NV], qc[NV];
-    normal_flux2(qd, m[gp], m[sstride + gp], a.gas, fs);
-    normal_flux2(qd, m[2 * sstride + gp], m[3 * sstride + gp], a.gas, ft);
-    conservative2(qd, a.gas, qc);
-    const State2<double> s = make_state(qv, a.gas);
-    double ew[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ew[v] = (v == w) ? 1.0 : 0.0;
-    double gcol[NV];
-    gamma_mul(s, a.gas, ew, gcol);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      sAF[(pp * NV + v) * NV + w] = fs[v].d[0];
-      sAG[(pp * NV + v) * NV + w] = ft[v].d[0];
-      sDg[(pp * NV + v) * NV + w] = gcol[v] * a.inv_dtau + a.c_mass * qc[v].d[0];
-    }
-  }
-  for (int t = lane; t < 4 * N1 * NV; t += 64) {  // common-flux Jacobians w.r.t. the own trace
-    const int f = t / (N1 * NV), k = (t / NV) % N1, w = t % NV;
-    const double* wt = (f == 0 || f == 2) ? o.lm : o.lp;
-    double ownv[NV] = {0.0, 0.0, 0.0, 0.0};
-    for (int mm = 0; mm < N1; ++mm) {
-      const int pp = (f < 2) ? (mm + N1 * k) : (k + N1 * mm);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ownv[v] += wt[mm] * sq[v * NP + pp];
-    }
-    Dual<1> own[NV], out[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) own[v] = dconst<1>(ownv[v]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) own[v].d[0] = (v == w) ? 1.0 : 0.0;
-    const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
-    const double nx = a.lv.fvec[fo], ny = a.lv.fvec[fo + ne], sm = a.lv.fvec[fo + 2 * ne];
-    const int nb = a.lv.nbr[f * ne + e];
-    if (nb >= 0) {
-      const int nf = a.lv.nbf[f * ne + e];
-      const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
-      const double* wn = (nf == 0 || nf == 2) ? o.lm : o.lp;
-      double ov[NV] = {0.0, 0.0, 0.0, 0.0};
-      for (int mm = 0; mm < N1; ++mm) {
-        const int pp = (nf < 2) ? (mm + N1 * kk) : (kk + N1 * mm);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) ov[v] += wn[mm] * a.q[v * sstride + (size_t)pp * ne + nb];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(ov[v]);
-    } else if (nb == -1) {
-      Dual<1> ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2];
-      Dual<1> un = ua * nx + va * ny;
-      out[0] = own[0];
-      out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
-      out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
-      out[3] = own[3];
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.qinf_g[v]);
-    }
-    Dual<1> own_a[NV], out_a[NV], dq[NV], fh[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      own_a[v] = own[v] + a.lv.q_ref[v];
-      out_a[v] = out[v] + a.lv.q_ref[v];
-    }
-    if (f == 0 || f == 2) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
-      common_flux2(out_a, own_a, dq, nx, ny, sm, a.gas, fh);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
-      common_flux2(own_a, out_a, dq, nx, ny, sm, a.gas, fh);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sB[((f * N1 + k) * NV + v) * NV + w] = fh[v].d[0];
-  }
-  __syncthreads();
-
-  // row r = lane of D_e (rows beyond n stay zero)
-  const bool has_row = lane < N;
-  const int r = has_row ? lane : 0;
+  const bool has_row = tid < S * N;
+  const int r = has_row ? tid / S : 0;
+  const int h = (S == 2) ? (tid & 1) : 0;         // which half of the row this thread holds
   const int pp = r / NV, v = r % NV, i = pp % N1, jj = pp / N1;
   const double ijac = a.lv.met[4 * sstride + (size_t)pp * ne + e];
-  double row[N];
+  double row[H];
 #pragma unroll
-  for (int c = 0; c < N; ++c) {
+  for (int j = 0; j < H; ++j) {
+    const int c = h * H + j;
     const int ss = c / NV, w = c % NV, k = ss % N1, l = ss / N1;
     double acc = 0.0;
     if (l == jj) {
@@ -432,73 +221,105 @@ __global__ void __launch_bounds__(64) k_jac_wave(JacArgs a) {
     }
     double dval = acc * ijac;
     if (pp == ss) dval += sDg[(pp * NV + v) * NV + w];
-    row[c] = has_row ? dval : 0.0;
+    row[j] = has_row ? dval : 0.0;
   }
   if (a.D_out && has_row) {
 #pragma unroll
-    for (int c = 0; c < N; ++c) a.D_out[((size_t)e * N + r) * N + c] = row[c];
+    for (int j = 0; j < H; ++j) a.D_out[((size_t)e * N + r) * N + h * H + j] = row[j];
   }
-  // row equilibration by a power of two
-  double mx = 0.0;
+  double mx = 0.0;                        // row equilibration by a power of two
 #pragma unroll
-  for (int c = 0; c < N; ++c) mx = fmax(mx, fabs(row[c]));
+  for (int j = 0; j < H; ++j) mx = fmax(mx, fabs(row[j]));
+  if (S == 2) mx = fmax(mx, __shfl_xor(mx, 1, 64));
   int ex = 0;
   frexp(mx, &ex);
   const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
 #pragma unroll
-  for (int c = 0; c < N; ++c) row[c] *= scl;
-  sscl[lane] = scl;
+  for (int j = 0; j < H; ++j) row[j] *= scl;
+  if (has_row && h == 0) sscl[r] = scl;
 
+  // Pivot rows are left unnormalised: a row keeps its scale d = pivot from the step it served
+  // as pivot (it is never a pivot again), every later update of it is the same formula as for
+  // any other row, and the scale is divided out once at the end. All threads therefore run one
+  // fused multiply-add per column per step with no divergent branch.
+  //
+  // Pivot choice: a 32-bit key per row (on the thread holding its first column), the upper word
+  // of |f| (sign 0, exponent, 20 mantissa bits) with its low 8 bits replaced by 255 - thread,
+  // and 0 for rows already used; the largest key wins. The pivot is therefore within a factor
+  // 1 + 2^-12 of the largest candidate, and ties go to the lowest row.
   bool used = !has_row;
   int my_step = 0;
+  double my_inv = 1.0;
   bool bad = false;
   for (int k = 0; k < N; ++k) {
-    double f = 0.0;                      // this row's entry in column k
+    const int par = k & 1;
+    const double f = (S == 2) ? pair_dpp<kQuadEven>(row[0]) : row[0];   // this row's entry in column k
+    const unsigned key = (used || h != 0) ? 0u
+                         : ((((unsigned)__double2hiint(fabs(f))) & ~0xFFu) | (unsigned)(255 - tid));
+    const unsigned wkey = wave_max_u32(key);
+    const int wtid = 255 - (int)(wkey & 0xFFu);
+    if (wkey != 0u && (tid == wtid || (S == 2 && tid == wtid + 1))) {   // publish the candidate row
 #pragma unroll
-    for (int c = 0; c < N; ++c) f = (c == k) ? row[c] : f;
-    double best = used ? -1.0 : fabs(f);
-    int bi = lane;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
+      for (int j = 0; j < H; ++j) slot[par][wv][h * H + j] = row[j];
     }
-    const int p = __builtin_amdgcn_readfirstlane(bi);
-    double piv = read_lane(f, p);
+    if (lane == 0) skey[par][wv] = wkey;
+    __syncthreads();
+    int win = 0;
+    unsigned bk = skey[par][0];
+#pragma unroll
+    for (int w2 = 1; w2 < NW; ++w2) {
+      const unsigned k2 = skey[par][w2];
+      win = (k2 > bk) ? w2 : win;
+      bk = (k2 > bk) ? k2 : bk;
+    }
+    int p = (255 - (int)(bk & 0xFFu)) / S;
+    if (bk == 0u || p >= N) {             // no unused row left: only reachable with non-finite entries
+      bad = true;
+      p = (p < N && p >= 0) ? p : N - 1;
+    }
+    const double* pr = slot[par][win];
+    double piv = pr[0];
     if (piv == 0.0 || !isfinite(piv)) {
       bad = true;
       piv = 1.0;
     }
     const double ip = 1.0 / piv;
-    const bool is_p = (lane == p);
+    const bool is_p = has_row && (r == p);
+    if (tid == 0) sperm[k] = p;
+    const double g = is_p ? 0.0 : f * ip;
     if (is_p) {
       used = true;
       my_step = k;
+      my_inv = ip;
     }
-    if (lane == 0) sperm[k] = p;
+    const double nb = (S == 2) ? pair_dpp<kQuadOdd>(row[0]) : 0.0;   // first column of the second half
+    const double* prh = pr + h * H;
+    // pivot-row values in batches, so that a batch of LDS reads is in flight at once
+    constexpr int B = 16;
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      const double pc = read_lane(row[c], p);
-      double nv;
-      if (is_p)
-        nv = (c == k) ? ip : pc * ip;
-      else
-        nv = (c == k) ? -f * ip : row[c] - f * (pc * ip);
-      row[c] = nv;
+    for (int j0 = 0; j0 < H - 1; j0 += B) {
+      double buf[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j0 + j < H - 1) buf[j] = prh[j0 + j + 1];
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j0 + j < H - 1) row[j0 + j] = fma(-g, buf[j], row[j0 + j + 1]);
     }
+    if (S == 2 && h == 0)
+      row[H - 1] = fma(-g, pr[H], nb);
+    else
+      row[H - 1] = is_p ? 1.0 : -g;
   }
-  if (bad && lane == 0) *a.flag = 1;
+  if (bad) *a.flag = 1;
   __syncthreads();
-  // lane L (pivot of step k_L) holds B[L][j] = (S_r D)^{-1}[k_L][perm[j]]; D^{-1} = (S_r D)^{-1} S_r
+  // row r (pivot of step k_r, scale 1/my_inv) holds B[r][c] = (S_r D)^{-1}[k_r][perm[c]] / my_inv;
+  // D^{-1} = (S_r D)^{-1} S_r
   if (has_row) {
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      const int col = sperm[c];
-      const double val = row[c] * sscl[col];
+    for (int j = 0; j < H; ++j) {
+      const int col = sperm[h * H + j];
+      const double val = row[j] * my_inv * sscl[col];
       const size_t o_ = ((size_t)col * ne + e) * N + my_step;
       if (a.precision == 32)
         static_cast<float*>(a.W)[o_] = (float)val;
@@ -508,19 +329,9 @@ __global__ void __launch_bounds__(64) k_jac_wave(JacArgs a) {
   }
 }
 
-template <int P>
-static hipError_t launch_jac_p(const JacArgs& a, int ne, hipStream_t st) {
-  const size_t bytes = JCfg<P>::lds_bytes();
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jac<P>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_jac<P>), dim3(ne), dim3(256), bytes, st, a);
-  return hipGetLastError();
-}
-
-template <int P>
-static hipError_t launch_jac_wave(const JacArgs& a, int ne, hipStream_t st) {
-  hipLaunchKernelGGL((k_jac_wave<P>), dim3(ne), dim3(64), 0, st, a);
+template <int P, int S>
+static hipError_t launch_jac_rows(const JacArgs& a, int ne, hipStream_t st) {
+  hipLaunchKernelGGL((k_jac_rows<P, S>), dim3(ne), dim3(RowsCfg<P, S>::NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -538,11 +349,11 @@ hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, d
   a.precision = fac.precision;
   a.flag = L.flag;
   switch (L.P) {
-    case 0: return launch_jac_wave<0>(a, L.ne, st);
-    case 1: return launch_jac_wave<1>(a, L.ne, st);
-    case 2: return launch_jac_wave<2>(a, L.ne, st);
-    case 3: return launch_jac_wave<3>(a, L.ne, st);
-    case 4: return launch_jac_p<4>(a, L.ne, st);
+    case 0: return launch_jac_rows<0, 1>(a, L.ne, st);
+    case 1: return launch_jac_rows<1, 1>(a, L.ne, st);
+    case 2: return launch_jac_rows<2, 1>(a, L.ne, st);
+    case 3: return launch_jac_rows<3, 1>(a, L.ne, st);
+    case 4: return launch_jac_rows<4, 2>(a, L.ne, st);
     default: return hipErrorInvalidValue;
   }
 }
