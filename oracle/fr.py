@@ -12,8 +12,12 @@ where F~_L,j = sum_k l_k(-1) F~_kj is the interpolated local flux at the face an
 F^ = |S| f_com is the common flux of eq. (21) in the +xi direction.
 
 Boundary states (the paper does not state them): periodic faces are identified;
-a slip wall uses the ghost (p, u - 2(u.n)n, T); a far-field face uses the free
-stream q_inf; both pass through the same common flux.
+a slip wall uses the ghost (p, u - 2(u.n)n, T); a no-slip adiabatic wall the ghost
+(p, -u, -v, T); a far-field face uses the free stream q_inf; all pass through the same
+common flux.
+
+With a viscosity mu > 0 the BR2 viscous terms of ``oracle.viscous`` are subtracted from
+the transformed fluxes and the common fluxes (R = -div(f_inv - f_vis)).
 """
 from __future__ import annotations
 
@@ -22,9 +26,11 @@ import numpy as np
 from . import gas as G
 from .basis import Ops1D
 from .geometry import QuadGeometry
+from .viscous import BR2
 
 BC_SLIP_WALL = -1
 BC_FAR_FIELD = -2
+BC_NOSLIP_WALL = -3
 
 
 class FRLevel:
@@ -43,6 +49,7 @@ class FRLevel:
         self.n = self.nv * self.npts
         self.ne = mesh.n_elements
         self.q_inf = None if q_inf is None else np.asarray(q_inf, float)
+        self.br2 = BR2(self) if gas.mu > 0.0 else None
 
     # ---- face traces -------------------------------------------------------------
     def traces(self, q):
@@ -55,18 +62,28 @@ class FRLevel:
         tt = np.einsum("k,ekiv->eiv", o.lp, q4)
         return np.stack([tl, tr, tb, tt], axis=1)
 
-    def outside_states(self, own, nbr_tr):
-        """State across each face: the neighbour's trace, or a boundary ghost."""
+    def neighbour_face_values(self, x):
+        """For per-face values x [Ne, 4, P+1, ...] of every element, the neighbour's values on
+        the shared face seen from each (element, face), in this face's point order (zero on
+        boundary faces)."""
         m = self.mesh
-        out = np.empty_like(own)
+        out = np.zeros_like(x)
         for f in range(4):
             nb = m.face_nbr[:, f]
             inner = nb >= 0
             idx = np.where(inner, nb, 0)
-            tr = nbr_tr[idx, m.face_nbr_face[:, f]]           # [Ne, P+1, Nv]
-            flip = m.face_orient[:, f] == 1
-            tr = np.where(flip[:, None, None], tr[:, ::-1], tr)
-            out[:, f] = np.where(inner[:, None, None], tr, 0.0)
+            tr = x[idx, m.face_nbr_face[:, f]]
+            flip = (m.face_orient[:, f] == 1).reshape((-1,) + (1,) * (tr.ndim - 1))
+            tr = np.where(flip, tr[:, ::-1], tr)
+            out[:, f] = np.where(inner.reshape((-1,) + (1,) * (tr.ndim - 1)), tr, 0.0)
+        return out
+
+    def outside_states(self, own, nbr_tr):
+        """State across each face: the neighbour's trace, or a boundary ghost."""
+        m = self.mesh
+        out = self.neighbour_face_values(nbr_tr).astype(np.result_type(own, nbr_tr))
+        for f in range(4):
+            nb = m.face_nbr[:, f]
             wall = nb == BC_SLIP_WALL
             if np.any(wall):
                 nvec = self.geo.fvec[:, f]
@@ -76,10 +93,30 @@ class FRLevel:
                 ghost = own[:, f].copy()
                 ghost[..., 1:3] = u - 2.0 * un[..., None] * nunit
                 out[:, f] = np.where(wall[:, None, None], ghost, out[:, f])
+            noslip = nb == BC_NOSLIP_WALL
+            if np.any(noslip):
+                ghost = own[:, f].copy()
+                ghost[..., 1:3] = -own[:, f, :, 1:3]
+                out[:, f] = np.where(noslip[:, None, None], ghost, out[:, f])
             far = nb == BC_FAR_FIELD
             if np.any(far):
                 out[:, f] = np.where(far[:, None, None], self.q_inf, out[:, f])
         return out
+
+    def viscous_terms(self, q, q_nbr, own, out):
+        """BR2 transformed viscous fluxes at the solution points and common viscous fluxes at
+        the faces (``oracle.viscous``); the neighbours' gradients come from q_nbr (default q)."""
+        br2, m, g = self.br2, self.mesh, self.geo
+        qn = q if q_nbr is None else q_nbr
+        qcom = 0.5 * (own + out)
+        # the outside side's grad q + r on each interior face: the neighbour's local gradient
+        # and its lifting of that face, whose jump q_com - q+ uses this element's trace
+        gl_n = self.neighbour_face_values(br2.face_local_gradients(qn))
+        n_vec = self.neighbour_face_values(g.fvec)
+        n_lam = self.neighbour_face_values(br2.lam)
+        out_grad = gl_n + br2.penalty * (qcom - out)[..., None] * n_vec[:, :, :, None, :] * n_lam[..., None, None]
+        one_sided = m.face_nbr < 0
+        return br2.terms(q, own, out, out_grad, one_sided, m.face_nbr == BC_NOSLIP_WALL)
 
     # ---- residual ----------------------------------------------------------------
     def residual(self, q, q_nbr=None):
@@ -101,6 +138,11 @@ class FRLevel:
               G.common_flux(own[:, 3], out[:, 3], fv[:, 3], self.gas)]
         ft = G.normal_flux(q, g.S_sp, self.gas).reshape(ne, n1, n1, nv)  # [e, j, i, v]
         gt = G.normal_flux(q, g.T_sp, self.gas).reshape(ne, n1, n1, nv)
+        if self.br2 is not None:            # total flux f_inv - f_vis
+            fvt, gvt, fhv = self.viscous_terms(q, q_nbr, own, out)
+            ft = ft - fvt
+            gt = gt - gvt
+            fh = [fh[f] - fhv[:, f] for f in range(4)]
         fl = np.einsum("k,ejkv->ejv", o.lm, ft)
         fr = np.einsum("k,ejkv->ejv", o.lp, ft)
         gb = np.einsum("k,ekiv->eiv", o.lm, gt)

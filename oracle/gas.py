@@ -24,6 +24,8 @@ class Gas:
     eps_mode: str = "local"
     ma_inf: float = 0.0
     kappa: float = 1.0
+    # penalty of the BR2 common gradient (oracle.viscous)
+    br2_penalty: float = 4.0
 
     @property
     def cp(self) -> float:

@@ -149,3 +149,31 @@ def test_cfl_stage_solve_scales_pseudo_time():
     assert st.dtau_history[0] == 1e2 * dmin
     assert max(st.dtau_history) <= 1e5 * dmin
     assert st.history[-1] < 0.1 * st.history[0]
+
+
+def test_wall_element_block_matches_central_differences():
+    """The element block of a slip-wall element against central differences of the residual
+    (the wall ghost depends on the element's own trace)."""
+    from oracle.jacobian import element_dFdq
+    mesh = W.airfoil_o_mesh(8, 3, ratio=1.3, r_far=6.0)
+    gas = cutoff_gas()
+    qinf = FS.freestream()
+    lev = FRLevel(mesh, 2, gas, q_inf=qinf)
+    x, y = lev.geo.xy[..., 0], lev.geo.xy[..., 1]
+    q = np.broadcast_to(qinf, x.shape + (4,)).copy()
+    q[..., 0] += 0.8 * np.sin(0.7 * x) * np.cos(0.5 * y)
+    q[..., 1] += 0.2 * np.cos(0.9 * x - 0.4 * y)
+    q[..., 2] += 0.15 * np.sin(0.6 * y + 0.2 * x)
+    J = element_dFdq(lev, q)
+    for e in (1, 13):                   # a wall element (j = 0) and one of the next layer
+        assert (mesh.face_nbr[e, 2] == W.BC_SLIP_WALL) == (e < 8)
+        Jfd = np.zeros((lev.n, lev.n))
+        for c in range(lev.n):
+            p, v = divmod(c, 4)
+            h = 1e-4 * abs(q[e, p, v])
+            qp, qm = q.copy(), q.copy()
+            qp[e, p, v] += h
+            qm[e, p, v] -= h
+            Jfd[:, c] = (lev.residual(qp)[e] - lev.residual(qm)[e]).ravel() / (2 * h)
+        colmax = np.max(np.abs(J[e]), axis=0)
+        assert np.max(np.abs(Jfd - J[e]) / colmax) < 1e-6

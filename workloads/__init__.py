@@ -30,6 +30,7 @@ import numpy as np
 
 BC_SLIP_WALL = -1
 BC_FAR_FIELD = -2
+BC_NOSLIP_WALL = -3
 
 JITTER_SEED = 20190811
 
@@ -98,6 +99,29 @@ def periodic_rect_mesh(nx: int, ny: int, lx: float = 10.0, ly: float = 10.0, jit
     return Mesh(2, 1, nodes, nbr, nbf, ori, name=f"periodic{nx}x{ny}",
                 info={"length": (lx, ly), "origin": (ox, oy), "jitter": jitter,
                       "seed": seed if jitter > 0 else None, "periodic": True})
+
+
+def channel_mesh(nx: int, ny: int, lx: float = 10.0, ly: float = 2.0, jitter: float = 0.0,
+                 seed: int = JITTER_SEED, wall: int = BC_NOSLIP_WALL) -> Mesh:
+    """Bilinear quads on [0, lx] x [0, ly], periodic in x, with a wall of type ``wall`` at
+    y = 0 and y = ly (interior vertices jittered as in ``periodic_rect_mesh``; wall vertices keep
+    their y)."""
+    m = periodic_rect_mesh(nx, ny, lx, ly, jitter, seed, ox=0.0, oy=0.0)
+    nodes = m.nodes.copy()
+    nbr = m.face_nbr.copy()
+    for j in range(ny):
+        for i in range(nx):
+            e = i + nx * j
+            for b in range(2):
+                if j + b in (0, ny):          # vertices on a wall stay on it
+                    for a in range(2):
+                        nodes[e, a + 2 * b, 1] = 0.0 if j + b == 0 else ly
+            if j == 0:
+                nbr[e, 2] = wall
+            if j == ny - 1:
+                nbr[e, 3] = wall
+    return Mesh(2, 1, nodes, nbr, m.face_nbr_face, m.face_orient, name=f"channel{nx}x{ny}",
+                info={"length": (lx, ly), "jitter": jitter, "seed": seed if jitter > 0 else None, "wall": wall})
 
 
 @dataclass
