@@ -50,6 +50,8 @@ typedef int32_t pmg_status;
 
 #define PMG_BC_SLIP_WALL (-1)   /* face_nbr tag: slip wall, ghost (p, u - 2(u.n)n, T)         */
 #define PMG_BC_FAR_FIELD (-2)   /* face_nbr tag: far field, ghost = q_inf                     */
+#define PMG_BC_NOSLIP_WALL (-3) /* face_nbr tag: no-slip adiabatic wall, ghost (p, -u, -v, T);
+                                   viscous: one-sided common gradient without its normal grad T */
 
 typedef struct pmg_level_s* pmg_level;
 typedef struct pmg_factors_s* pmg_factors;
@@ -58,7 +60,7 @@ typedef struct pmg_factors_s* pmg_factors;
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 101
+#define PMG_ABI_VERSION 102
 int32_t pmg_abi_version(void);
 
 /*
@@ -80,6 +82,12 @@ int32_t pmg_abi_version(void);
  *   q_ref        reference state subtracted from every stored state (see the conventions above);
  *                all levels of one solve must share it.
  *   device       HIP device ordinal on which the level lives.
+ *   mu           dynamic viscosity (Sec. 2.1); 0 = inviscid. With mu > 0 the residual carries the
+ *                viscous fluxes with the BR2 common gradient of eqs. (22)-(23) and the level
+ *                allocates a gradient-trace buffer and an n x n x Ne FP64 block buffer.
+ *   prandtl      Prandtl number (0.72 in Sec. 2.1); used when mu > 0.
+ *   br2_penalty  factor on the BR2 liftings in the common gradient (the number of element faces,
+ *                4, is the stable choice); used when mu > 0.
  */
 typedef struct {
   int32_t dim;
@@ -98,6 +106,9 @@ typedef struct {
   double q_inf[5];
   double q_ref[5];
   int32_t device;
+  double mu;
+  double prandtl;
+  double br2_penalty;
 } pmg_level_desc;
 
 /* Create a level: computes the Gauss solution/flux points, the 1-D operators, the metrics from
@@ -118,8 +129,8 @@ pmg_status pmg_level_points(pmg_level L, double* xy_host);
 pmg_status pmg_level_dx(pmg_level L, double* dx_host);
 
 /* pmg_dtau_min — the pseudo-time scale of eq. (33) at state q (device, stored form [Nv][Np][Ne]):
- *   dtau_min = min over elements e and solution points of (dx_e / (P+1)) / (c + |v|)
- * (inviscid part; the levels carry no viscosity). Writes the host double *dtau_min and
+ *   dtau_min = min over elements e and solution points of (dx_e / (P+1)) / (c + |v|), and, when the
+ *   level has mu > 0, of (dx_e / (P+1))^2 rho / mu. Writes the host double *dtau_min and
  * synchronises the stream. Errors: PMG_E_ARG (null), PMG_E_NONFINITE (a point with T <= 0 or a
  * non-finite value), PMG_E_HIP. */
 pmg_status pmg_dtau_min(pmg_level L, const double* q, double* dtau_min, void* stream);

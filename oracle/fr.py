@@ -116,7 +116,7 @@ class FRLevel:
         n_lam = self.neighbour_face_values(br2.lam)
         out_grad = gl_n + br2.penalty * (qcom - out)[..., None] * n_vec[:, :, :, None, :] * n_lam[..., None, None]
         one_sided = m.face_nbr < 0
-        return br2.terms(q, own, out, out_grad, one_sided, m.face_nbr == BC_NOSLIP_WALL)
+        return br2.terms(q, own, out, out_grad, one_sided, m.face_nbr == BC_NOSLIP_WALL, m.face_nbr == BC_FAR_FIELD)
 
     # ---- residual ----------------------------------------------------------------
     def residual(self, q, q_nbr=None):

@@ -26,10 +26,13 @@ Readings (the paper names BR2 and gives eqs. (22)-(23) only):
   BR2's stability analysis asks for (``Gas.br2_penalty``). With eta = 1 the discrete compressible
   stress operator is indefinite (one mode grows) for P >= 2; from eta = 2 on it is symmetric and
   negative semi-definite (tested).
-* Boundary faces: the ghost state of the boundary condition enters q_com; the gradient is
-  one-sided, grad q_com = grad q- + r-. No-slip adiabatic wall: ghost (p, -u, -v, T) for both the
-  inviscid and the viscous flux, and the wall-normal component of grad T removed from
-  grad q_com, so no heat crosses the wall.
+* Boundary faces: q_com is the boundary state and the gradient is one-sided,
+  grad q_com = grad q- + eta r-, with r- lifting q_com - q-: the far field takes q_com = q_inf;
+  at walls q_com is the mean of the trace and its ghost, which is the boundary state itself
+  (slip wall: normal velocity removed; no-slip adiabatic wall: ghost (p, -u, -v, T), so
+  q_com = (p, 0, 0, T), and the wall-normal component of grad T is removed from grad q_com, so no
+  heat crosses the wall). Taking the mean with the far-field ghost instead would make the discrete
+  viscous operator unsymmetric (tested).
 * The common viscous flux on a face is N . f_vis(q_com, grad q_com); the element's local
   viscous flux at the face is the Lagrange interpolant of its transformed viscous flux, as for
   the inviscid part.
@@ -121,17 +124,18 @@ class BR2:
         g4 = self.local_gradient(q).reshape(lev.ne, lev.n1, lev.n1, 4, 2)
         return np.stack([line_extrapolate(lev.ops, g4, f) for f in range(4)], axis=1)
 
-    def terms(self, q, own, out, out_grad, one_sided, wall_noslip):
+    def terms(self, q, own, out, out_grad, one_sided, wall_noslip, far_field):
         """Viscous transformed fluxes at the solution points (F~v, G~v, each [Ne, n1(j), n1(i), 4])
         and common viscous fluxes N . f_vis at the flux points of each face ([Ne, 4, n1, 4]).
 
         own, out: own traces and outside states [Ne, 4, n1, 4]; out_grad: the outside side's
         (grad q + r) at each flux point [Ne, 4, n1, 4, 2] (ignored on one-sided faces);
-        one_sided, wall_noslip: [Ne, 4] masks of boundary faces and of no-slip adiabatic walls.
+        one_sided, wall_noslip, far_field: [Ne, 4] masks of boundary faces, of no-slip adiabatic
+        walls and of far-field faces (where q_com is the free stream itself).
         """
         lev = self.lev
         g, ne, n1, gas = lev.geo, lev.ne, lev.n1, lev.gas
-        qcom = 0.5 * (own + out)
+        qcom = np.where(far_field[:, :, None, None], out, 0.5 * (own + out))
         jump = qcom - own
         grad = self.local_gradient(q)
         gcor = grad + self.liftings(jump).sum(axis=0)

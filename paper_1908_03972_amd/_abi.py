@@ -22,6 +22,7 @@ PMG_E_NOT_CONVERGED = -6
 PMG_E_NOMEM = -7
 PMG_BC_SLIP_WALL = -1
 PMG_BC_FAR_FIELD = -2
+PMG_BC_NOSLIP_WALL = -3
 
 STATUS_NAMES = {0: "PMG_OK", -1: "PMG_E_ARG", -2: "PMG_E_SHAPE", -3: "PMG_E_HIP", -4: "PMG_E_SINGULAR",
                 -5: "PMG_E_NONFINITE", -6: "PMG_E_NOT_CONVERGED", -7: "PMG_E_NOMEM"}
@@ -34,7 +35,7 @@ class LevelDesc(C.Structure):
         ("face_nbr_face", C.POINTER(C.c_int32)), ("face_orient", C.POINTER(C.c_int32)),
         ("gamma", C.c_double), ("rgas", C.c_double), ("eps_mode", C.c_int32),
         ("ma_inf", C.c_double), ("kappa", C.c_double), ("q_inf", C.c_double * 5), ("q_ref", C.c_double * 5),
-        ("device", C.c_int32),
+        ("device", C.c_int32), ("mu", C.c_double), ("prandtl", C.c_double), ("br2_penalty", C.c_double),
     ]
 
 

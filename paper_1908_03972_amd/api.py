@@ -20,7 +20,8 @@ class Level:
     """One P-level of a quadrilateral mesh (a ``pmg_level`` handle)."""
 
     def __init__(self, mesh, P: int, *, gamma: float = 1.4, rgas: float = 1.0, eps_mode: int = 0,
-                 ma_inf: float = 0.0, kappa: float = 1.0, q_inf=None, q_ref=None, device: int = 0):
+                 ma_inf: float = 0.0, kappa: float = 1.0, q_inf=None, q_ref=None, device: int = 0,
+                 mu: float = 0.0, prandtl: float = 0.72, br2_penalty: float = 4.0):
         lib = A.lib()
         nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64)
         nbr = np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)
@@ -43,6 +44,7 @@ class Level:
         d.q_ref = (C.c_double * 5)(*qr)
         self.q_ref = qr[:4].copy()
         d.device = device
+        d.mu, d.prandtl, d.br2_penalty = mu, prandtl, br2_penalty
         h = A.pmg_level()
         A.check(lib.pmg_level_create(C.byref(d), C.byref(h)), "pmg_level_create")
         self.handle = h

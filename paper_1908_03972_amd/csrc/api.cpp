@@ -248,8 +248,8 @@ void free_level(pmg_level_s* L) {
   if (!L) return;
   if (L->vc_exec) (void)hipGraphExecDestroy(L->vc_exec);
   if (L->capture_stream) (void)hipStreamDestroy(L->capture_stream);
-  void* ptrs[] = {L->met, L->fvec, L->nbr,  L->nbf,   L->ori,  L->wq,  L->wF,     L->wS,
-                  L->wqb, L->wql,  L->wsrc, L->part, L->norms, L->flag, L->hdx, L->dtpart, L->dtmin};
+  void* ptrs[] = {L->met,  L->fvec,   L->nbr,   L->nbf, L->ori, L->wq,    L->wF,     L->wS,  L->wqb, L->wql,
+                  L->wsrc, L->part,   L->norms, L->flag, L->hdx, L->dtpart, L->dtmin, L->lam, L->gface, L->Dv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete L;
@@ -304,10 +304,14 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
     return fail(PMG_E_ARG, "null mesh array");
   if (!(d->gamma > 1.0) || !(d->rgas > 0.0)) return fail(PMG_E_ARG, "gamma must exceed 1 and rgas be positive");
   if (d->eps_mode != 0 && d->eps_mode != 1) return fail(PMG_E_ARG, "eps_mode must be 0 or 1");
+  if (!(d->mu >= 0.0)) return fail(PMG_E_ARG, "mu must be non-negative");
+  if (d->mu > 0.0 && (!(d->prandtl > 0.0) || !(d->br2_penalty > 0.0)))
+    return fail(PMG_E_ARG, "a viscous level needs prandtl > 0 and br2_penalty > 0");
+  if (d->mu > 0.0 && d->P > 4) return fail(PMG_E_ARG, "viscous levels support P <= 4");
   const int ne = d->n_elements;
   for (int k = 0; k < 4 * ne; ++k) {
     const int nb = d->face_nbr[k];
-    if (nb >= ne || nb < PMG_BC_FAR_FIELD) return fail(PMG_E_ARG, "face_nbr entry out of range");
+    if (nb >= ne || nb < PMG_BC_NOSLIP_WALL) return fail(PMG_E_ARG, "face_nbr entry out of range");
     if (nb >= 0 && (d->face_nbr_face[k] < 0 || d->face_nbr_face[k] > 3))
       return fail(PMG_E_ARG, "face_nbr_face entry out of range");
     if (d->face_orient[k] != 0 && d->face_orient[k] != 1) return fail(PMG_E_ARG, "face_orient must be 0 or 1");
@@ -334,6 +338,10 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   L->gas.ma_inf = d->ma_inf;
   L->gas.kappa = d->kappa;
   L->gas.eps_mode = d->eps_mode;
+  L->gas.mu = d->mu;
+  L->gas.kcond = d->mu > 0.0 ? d->mu * L->gas.cp / d->prandtl : 0.0;
+  L->gas.br2_eta = d->mu > 0.0 ? d->br2_penalty : 0.0;
+  L->visc = d->mu > 0.0 ? 1 : 0;
   for (int k = 0; k < 5; ++k) {
     L->q_inf[k] = d->q_inf[k];
     L->q_ref[k] = d->q_ref[k];
@@ -342,7 +350,7 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
 
   // metrics from the exact mapping at solution and flux points
   const int n1 = L->n1, np = L->np, g = d->geom_order, nn = (g + 1) * (g + 1);
-  std::vector<double> met((size_t)5 * np * ne), fvec((size_t)4 * n1 * 3 * ne);
+  std::vector<double> met((size_t)5 * np * ne), fvec((size_t)4 * n1 * 3 * ne), jacp((size_t)np * ne);
   L->xy_host.assign((size_t)2 * np * ne, 0.0);
   for (int e = 0; e < ne; ++e) {
     const double* nodes = d->nodes + (size_t)e * nn * 2;
@@ -361,6 +369,7 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
         met[2 * st + o] = -m.y_xi;
         met[3 * st + o] = m.x_xi;
         met[4 * st + o] = 1.0 / jac;
+        jacp[o] = jac;
         L->xy_host[o] = m.x;
         L->xy_host[st + o] = m.y;
       }
@@ -383,6 +392,27 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
         fvec[o + ne] = vy / len;
         fvec[o + 2 * ne] = len;
       }
+  }
+  // BR2 lifting factor of each flux point: lambda_f,k = sum_m l_m(face) g_f'(x_m) / |J_m| along the
+  // tensor line through the point (viscous levels)
+  std::vector<double> lam;
+  if (L->visc) {
+    lam.assign((size_t)4 * n1 * ne, 0.0);
+    std::vector<double> lmv(n1), lpv(n1);
+    for (int m = 0; m < n1; ++m) {
+      lmv[m] = L->ops.lm[m];
+      lpv[m] = L->ops.lp[m];
+    }
+    for (int e = 0; e < ne; ++e)
+      for (int k = 0; k < n1; ++k)
+        for (int m = 0; m < n1; ++m) {
+          const double jx = jacp[(size_t)(m + n1 * k) * ne + e];     // point (m, k): line eta = x_k
+          const double je = jacp[(size_t)(k + n1 * m) * ne + e];     // point (k, m): line xi = x_k
+          lam[(size_t)(0 * n1 + k) * ne + e] += lmv[m] * L->ops.gL[m] / jx;
+          lam[(size_t)(1 * n1 + k) * ne + e] += lpv[m] * L->ops.gR[m] / jx;
+          lam[(size_t)(2 * n1 + k) * ne + e] += lmv[m] * L->ops.gL[m] / je;
+          lam[(size_t)(3 * n1 + k) * ne + e] += lpv[m] * L->ops.gR[m] / je;
+        }
   }
   L->dx_host.resize(ne);
   std::vector<double> hdx(ne);
@@ -409,6 +439,11 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
       (s = alloc_zero(&L->wqb, ns)) || (s = alloc_zero(&L->wql, ns)) || (s = alloc_zero(&L->wsrc, ns)) ||
       (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
       (s = alloc_zero(&L->dtpart, pmg::dtau_blocks(*L))) || (s = alloc_zero(&L->dtmin, 1))) {
+    free_level(L);
+    return s;
+  }
+  if (L->visc && ((s = upload(&L->lam, lam)) || (s = alloc_zero(&L->gface, (size_t)4 * n1 * 8 * ne)) ||
+                  (s = alloc_zero(&L->Dv, (size_t)L->n * L->n * ne)))) {
     free_level(L);
     return s;
   }

@@ -7,6 +7,10 @@
 //      neighbour's trace (extrapolated from the neighbour's state) or a boundary ghost, the
 //      common flux of eq. (21) and its jump against the interpolated local flux;
 //   3. R = -(1/|J|)[line derivatives + g_L'/g_R' corrections] (eq. (20)), F = R - c q_c + src - S.
+// With a viscosity (VISC) the BR2 terms of Sec. 2.3 join: local gradients at the points (chain
+// rule), each face's jump (q_com - q) N, the common viscous flux from both sides' gradient traces
+// and liftings (the neighbour's traces come from the pre-pass k_grad), the corrected gradient
+// grad q + sum of the liftings, and the viscous fluxes are subtracted from F~, G~ and F^.
 // The sweep variant then multiplies F by the element's stored inverse block (eq. (30)), with the
 // workgroup re-mapped element-major so that the n x n block stream is read fully coalesced, and
 // writes q + alpha D^{-1} F to a second buffer (synchronous Jacobi: neighbours are read from the
@@ -14,6 +18,8 @@
 #include "internal.hpp"
 
 namespace pmg {
+
+constexpr int kPadding = -100;   // neighbour tag of the padding elements of the last workgroup
 
 // Elements per workgroup: small workgroups (64-128 lanes) so that even the coarsest level of a
 // few thousand elements spreads over all 256 CUs; each W column a workgroup streams is then
@@ -50,15 +56,20 @@ struct ResArgs {
 };
 
 // MODE 0: residual only; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
-template <int P, int MODE>
+template <int P, int MODE, bool VISC>
 __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   using C = Cfg<P>;
   constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, EPW = C::EPW;
+  constexpr int VS = VISC ? 1 : 0;          // viscous LDS arrays exist only when used
   __shared__ double s_q[NV * NP * EPW];
   __shared__ double s_f[NV * NP * EPW];
   __shared__ double s_g[NV * NP * EPW];
   __shared__ double s_j[4 * N1 * NV * EPW];
   __shared__ double s_red[C::NW * NV];
+  __shared__ double s_gl[VS * NV * 2 * NP * EPW + 1];      // local gradients
+  __shared__ double s_jn[VS * 4 * N1 * NV * 2 * EPW + 1];  // (q_com - q) N per flux point
+  __shared__ double s_fv[VS * NV * NP * EPW + 1];          // viscous F~v
+  __shared__ double s_gv[VS * NV * NP * EPW + 1];          // viscous G~v
 
   const int ne = a.lv.ne;
   const int tid = threadIdx.x;
@@ -75,6 +86,10 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #define SF(v, pp, ee) s_f[((v) * NP + (pp)) * EPW + (ee)]
 #define SG(v, pp, ee) s_g[((v) * NP + (pp)) * EPW + (ee)]
 #define SJ(f, k, v, ee) s_j[(((f) * N1 + (k)) * NV + (v)) * EPW + (ee)]
+#define SGL(v, d, pp, ee) s_gl[((((v) * 2 + (d)) * NP) + (pp)) * EPW + (ee)]
+#define SJN(f, k, v, d, ee) s_jn[(((((f) * N1 + (k)) * NV + (v)) * 2) + (d)) * EPW + (ee)]
+#define SFV(v, pp, ee) s_fv[((v) * NP + (pp)) * EPW + (ee)]
+#define SGV(v, pp, ee) s_gv[((v) * NP + (pp)) * EPW + (ee)]
 
   const size_t gp = (size_t)p * ne + e;     // offset of (v=0, p, e)
   double qv[NV];
@@ -124,6 +139,23 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   }
   __syncthreads();
 
+  if constexpr (VISC) {                     // local gradient (chain rule) at this point
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double dxi = 0.0, deta = 0.0;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+          dxi += o.D[i * N1 + k] * SQ(v, k + N1 * j, el);
+          deta += o.D[j * N1 + k] * SQ(v, i + N1 * k, el);
+        }
+        SGL(v, 0, p, el) = ij * (sx * dxi + tx * deta);
+        SGL(v, 1, p, el) = ij * (sy * dxi + ty * deta);
+      }
+    }
+    __syncthreads();
+  }
+
   if (act) {
     for (int t = p; t < 4 * N1; t += NP) {
       const int f = t / N1, k = t % N1;
@@ -144,7 +176,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
         }
       }
       double nx = (f < 2) ? 1.0 : 0.0, ny = (f < 2) ? 0.0 : 1.0, sm = 1.0;
-      int nb = -3;
+      int nb = kPadding;
       if (e < ne) {
         const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
         nx = a.lv.fvec[fo];
@@ -175,6 +207,11 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       } else if (nb == -2) {             // far field
 #pragma unroll
         for (int v = 0; v < NV; ++v) out[v] = a.lv.qinf_g[v];
+      } else if (nb == -3) {             // no-slip wall: reverse the velocity
+        out[0] = own[0];
+        out[1] = -(a.lv.q_ref[1] + own[1]) - a.lv.q_ref[1];
+        out[2] = -(a.lv.q_ref[2] + own[2]) - a.lv.q_ref[2];
+        out[3] = own[3];
       } else {                           // padding element of the last workgroup
 #pragma unroll
         for (int v = 0; v < NV; ++v) out[v] = own[v];
@@ -194,11 +231,82 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
         for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
         common_flux2(own_a, out_a, dq, nx, ny, sm, a.gas, fh);
       }
+      if constexpr (VISC) {
+        double gown[NV][2], gout[NV][2], jn[NV][2], fhv[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) SJ(f, k, v, el) = fh[v] - floc[v];
+        for (int v = 0; v < NV; ++v) {
+          gown[v][0] = gown[v][1] = gout[v][0] = gout[v][1] = 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          const int pp = (f < 2) ? (m + N1 * k) : (k + N1 * m);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            gown[v][0] += w[m] * SGL(v, 0, pp, el);
+            gown[v][1] += w[m] * SGL(v, 1, pp, el);
+          }
+        }
+        double lam = 0.0, nbx = 0.0, nby = 0.0, nbsm = 0.0, nblam = 0.0;
+        int kind = 1;
+        if (e < ne) lam = a.lv.lam[(size_t)(f * N1 + k) * ne + e];
+        if (nb >= 0) {
+          kind = 0;
+          const int nf = a.lv.nbf[f * ne + e];
+          const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
+          const size_t fo = ((size_t)(nf * N1 + kk) * 3) * ne + nb;
+          nbx = a.lv.fvec[fo];
+          nby = a.lv.fvec[fo + ne];
+          nbsm = a.lv.fvec[fo + 2 * ne];
+          nblam = a.lv.lam[(size_t)(nf * N1 + kk) * ne + nb];
+          const double* gf = a.lv.gface + (size_t)((nf * N1 + kk) * NV * 2) * ne + nb;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            gout[v][0] = gf[(size_t)(v * 2) * ne];
+            gout[v][1] = gf[(size_t)(v * 2 + 1) * ne];
+          }
+        } else if (nb == -3) {
+          kind = 2;
+        } else if (nb == -2) {
+          kind = 3;
+        }
+        visc_face2(own, out, a.lv.q_ref, gown, gout, nx, ny, sm, lam, nbx, nby, nbsm, nblam, kind, a.gas, jn,
+                   fhv);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          SJ(f, k, v, el) = fh[v] - floc[v] - fhv[v];
+          SJN(f, k, v, 0, el) = jn[v][0];
+          SJN(f, k, v, 1, el) = jn[v][1];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) SJ(f, k, v, el) = fh[v] - floc[v];
+      }
     }
   }
   __syncthreads();
+
+  if constexpr (VISC) {                     // corrected gradient and the viscous point fluxes
+    if (act) {
+      double gc[NV][2];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          const double lift = o.gL[i] * SJN(0, j, v, d, el) + o.gR[i] * SJN(1, j, v, d, el) +
+                              o.gL[j] * SJN(2, i, v, d, el) + o.gR[j] * SJN(3, i, v, d, el);
+          gc[v][d] = SGL(v, d, p, el) + ij * lift;
+        }
+      }
+      double fx[NV], fy[NV];
+      visc_flux2(qa[1], qa[2], gc, a.gas, fx, fy);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        SFV(v, p, el) = sx * fx[v] + sy * fy[v];
+        SGV(v, p, el) = tx * fx[v] + ty * fy[v];
+      }
+    }
+    __syncthreads();
+  }
 
   double Fv[NV];
   {
@@ -211,12 +319,27 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
     for (int v = 0; v < NV; ++v) {
       double d = 0.0;
       if (act) {
+        if constexpr (VISC) {             // total flux f_inv - f_vis; the jumps gain the
+          double fl0 = 0.0, fl1 = 0.0, gl2 = 0.0, gl3 = 0.0;   // interpolated local viscous flux
 #pragma unroll
-        for (int k = 0; k < N1; ++k) d += o.D[i * N1 + k] * SF(v, k + N1 * j, el);
-        d += o.gL[i] * SJ(0, j, v, el) + o.gR[i] * SJ(1, j, v, el);
+          for (int k = 0; k < N1; ++k) {
+            const double fvk = SFV(v, k + N1 * j, el), gvk = SGV(v, i + N1 * k, el);
+            d += o.D[i * N1 + k] * (SF(v, k + N1 * j, el) - fvk) + o.D[j * N1 + k] * (SG(v, i + N1 * k, el) - gvk);
+            fl0 += o.lm[k] * fvk;
+            fl1 += o.lp[k] * fvk;
+            gl2 += o.lm[k] * gvk;
+            gl3 += o.lp[k] * gvk;
+          }
+          d += o.gL[i] * (SJ(0, j, v, el) + fl0) + o.gR[i] * (SJ(1, j, v, el) + fl1);
+          d += o.gL[j] * (SJ(2, i, v, el) + gl2) + o.gR[j] * (SJ(3, i, v, el) + gl3);
+        } else {
 #pragma unroll
-        for (int k = 0; k < N1; ++k) d += o.D[j * N1 + k] * SG(v, i + N1 * k, el);
-        d += o.gL[j] * SJ(2, i, v, el) + o.gR[j] * SJ(3, i, v, el);
+          for (int k = 0; k < N1; ++k) d += o.D[i * N1 + k] * SF(v, k + N1 * j, el);
+          d += o.gL[i] * SJ(0, j, v, el) + o.gR[i] * SJ(1, j, v, el);
+#pragma unroll
+          for (int k = 0; k < N1; ++k) d += o.D[j * N1 + k] * SG(v, i + N1 * k, el);
+          d += o.gL[j] * SJ(2, i, v, el) + o.gR[j] * SJ(3, i, v, el);
+        }
       }
       const double fv = -d * ij - a.c_mass * qc[v] + srcv[v] - sv[v];
       Fv[v] = valid ? fv : 0.0;
@@ -310,26 +433,118 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #undef SF
 #undef SG
 #undef SJ
+#undef SGL
+#undef SJN
+#undef SFV
+#undef SGV
+}
+
+// Local gradients (chain rule on the solution polynomial) extrapolated to the flux points of
+// every face, gface[f][k][v][d][e]: what the BR2 common gradient of a viscous residual needs from
+// each neighbour. Same thread layout as k_fr.
+template <int P>
+__global__ void __launch_bounds__(Cfg<P>::NT) k_grad(LevelView lv, Ops1D o, const double* __restrict__ q,
+                                                     double* __restrict__ gface) {
+  using C = Cfg<P>;
+  constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, EPW = C::EPW;
+  __shared__ double s_q[NV * NP * EPW];
+  __shared__ double s_gl[NV * 2 * NP * EPW];
+  const int ne = lv.ne;
+  const int tid = threadIdx.x;
+  const bool act = tid < C::NACT;
+  const int el = tid % EPW;
+  const int p = act ? tid / EPW : 0;
+  const int e = blockIdx.x * EPW + el;
+  const bool valid = act && e < ne;
+  const int i = p % N1, j = p / N1;
+  const size_t sstride = (size_t)NP * ne, gp = (size_t)p * ne + e;
+  double sx = 1.0, sy = 0.0, tx = 0.0, ty = 1.0, ij = 0.0;
+  if (valid) {
+    sx = lv.met[gp];
+    sy = lv.met[sstride + gp];
+    tx = lv.met[2 * sstride + gp];
+    ty = lv.met[3 * sstride + gp];
+    ij = lv.met[4 * sstride + gp];
+  }
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s_q[(v * NP + p) * EPW + el] = valid ? q[v * sstride + gp] : 0.0;
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double dxi = 0.0, deta = 0.0;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        dxi += o.D[i * N1 + k] * s_q[(v * NP + k + N1 * j) * EPW + el];
+        deta += o.D[j * N1 + k] * s_q[(v * NP + i + N1 * k) * EPW + el];
+      }
+      s_gl[((v * 2 + 0) * NP + p) * EPW + el] = ij * (sx * dxi + tx * deta);
+      s_gl[((v * 2 + 1) * NP + p) * EPW + el] = ij * (sy * dxi + ty * deta);
+    }
+  }
+  __syncthreads();
+  if (act && e < ne) {
+    for (int t = p; t < 4 * N1; t += NP) {
+      const int f = t / N1, k = t % N1;
+      const double* w = (f == 0 || f == 2) ? o.lm : o.lp;
+#pragma unroll
+      for (int vd = 0; vd < NV * 2; ++vd) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          const int pp = (f < 2) ? (m + N1 * k) : (k + N1 * m);
+          acc += w[m] * s_gl[(vd * NP + pp) * EPW + el];
+        }
+        gface[((size_t)(f * N1 + k) * NV * 2 + vd) * ne + e] = acc;
+      }
+    }
+  }
 }
 
 template <int P, int MODE>
-static hipError_t launch_fr_p(const ResArgs& a, int ne, hipStream_t st) {
+static hipError_t launch_fr_p(const ResArgs& a, int ne, bool visc, hipStream_t st) {
   using C = Cfg<P>;
   const int blocks = (ne + C::EPW - 1) / C::EPW;
-  hipLaunchKernelGGL((k_fr<P, MODE>), dim3(blocks), dim3(C::NT), 0, st, a);
+  if (visc)
+    hipLaunchKernelGGL((k_fr<P, MODE, true>), dim3(blocks), dim3(C::NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_fr<P, MODE, false>), dim3(blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t launch_fr(int P, const ResArgs& a, int ne, hipStream_t st) {
+static hipError_t launch_fr(int P, const ResArgs& a, int ne, bool visc, hipStream_t st) {
   switch (P) {
-    case 0: return launch_fr_p<0, MODE>(a, ne, st);
-    case 1: return launch_fr_p<1, MODE>(a, ne, st);
-    case 2: return launch_fr_p<2, MODE>(a, ne, st);
-    case 3: return launch_fr_p<3, MODE>(a, ne, st);
-    case 4: return launch_fr_p<4, MODE>(a, ne, st);
-    case 5: return launch_fr_p<5, MODE>(a, ne, st);
-    case 6: return launch_fr_p<6, MODE>(a, ne, st);
+    case 0: return launch_fr_p<0, MODE>(a, ne, visc, st);
+    case 1: return launch_fr_p<1, MODE>(a, ne, visc, st);
+    case 2: return launch_fr_p<2, MODE>(a, ne, visc, st);
+    case 3: return launch_fr_p<3, MODE>(a, ne, visc, st);
+    case 4: return launch_fr_p<4, MODE>(a, ne, visc, st);
+    case 5: return launch_fr_p<5, MODE>(a, ne, visc, st);
+    case 6: return launch_fr_p<6, MODE>(a, ne, visc, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P>
+static hipError_t launch_grad_p(const pmg_level_s& L, const double* q, hipStream_t st) {
+  using C = Cfg<P>;
+  const int blocks = (L.ne + C::EPW - 1) / C::EPW;
+  hipLaunchKernelGGL((k_grad<P>), dim3(blocks), dim3(C::NT), 0, st, L.view(), L.ops, q, L.gface);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStream_t st) {
+  switch (L.P) {
+    case 0: return launch_grad_p<0>(L, q, st);
+    case 1: return launch_grad_p<1>(L, q, st);
+    case 2: return launch_grad_p<2>(L, q, st);
+    case 3: return launch_grad_p<3>(L, q, st);
+    case 4: return launch_grad_p<4>(L, q, st);
+    case 5: return launch_grad_p<5>(L, q, st);
+    case 6: return launch_grad_p<6>(L, q, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -356,7 +571,11 @@ hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* 
   a.c_mass = c_mass;
   a.F = F;
   a.part = want_norms ? L.part : nullptr;
-  return launch_fr<0>(L.P, a, L.ne, st);
+  if (L.visc) {
+    const hipError_t e = launch_gradient_traces(L, q, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_fr<0>(L.P, a, L.ne, L.visc != 0, st);
 }
 
 hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
@@ -371,8 +590,12 @@ hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const do
   a.W = fac.W;
   a.alpha = alpha;
   a.q_out = q_out;
-  if (fac.precision == 32) return launch_fr<2>(L.P, a, L.ne, st);
-  return launch_fr<1>(L.P, a, L.ne, st);
+  if (L.visc) {
+    const hipError_t e = launch_gradient_traces(L, q_in, st);
+    if (e != hipSuccess) return e;
+  }
+  if (fac.precision == 32) return launch_fr<2>(L.P, a, L.ne, L.visc != 0, st);
+  return launch_fr<1>(L.P, a, L.ne, L.visc != 0, st);
 }
 
 }  // namespace pmg

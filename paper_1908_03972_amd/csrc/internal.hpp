@@ -34,6 +34,8 @@ struct LevelView {
   const int* ori;       // [4][Ne]
   double q_ref[4];      // stored states are q - q_ref
   double qinf_g[4];     // far-field state in stored form, q_inf - q_ref
+  const double* lam;    // [4][n1][Ne] BR2 lifting factor of each flux point (viscous levels)
+  const double* gface;  // [4][n1][4][2][Ne] local gradient traces of the current state (viscous levels)
 };
 
 struct KernelStatus {
@@ -71,6 +73,10 @@ struct pmg_level_s {
   double* hdx = nullptr;           // [Ne] device: dx_e / (P + 1)
   double* dtpart = nullptr;        // per-workgroup partial minima of the pseudo-time scale
   double* dtmin = nullptr;         // device scalar: dtau_min
+  int visc = 0;                    // mu > 0: BR2 viscous terms
+  double* lam = nullptr;           // [4][n1][Ne] lambda_f,k = sum_m l_m(face) g_f'(x_m) / |J_m|
+  double* gface = nullptr;         // [4][n1][4][2][Ne] local gradient traces (pre-pass output)
+  double* Dv = nullptr;            // [Ne][n][n] viscous part dR_vis/dq of the element blocks
   // replayable V-cycle of the stage solve (finest level only), keyed by its arguments
   hipGraphExec_t vc_exec = nullptr;
   hipStream_t capture_stream = nullptr;
@@ -88,6 +94,8 @@ struct pmg_level_s {
       v.q_ref[k] = q_ref[k];
       v.qinf_g[k] = q_inf[k] - q_ref[k];
     }
+    v.lam = lam;
+    v.gface = gface;
     return v;
   }
 };
@@ -119,6 +127,8 @@ hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc
 hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
                                int n_prev, double dt, double c_mass, double* src, hipStream_t st);
 int residual_blocks(const pmg_level_s& L);
+hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStream_t st);
+hipError_t launch_visc_jacobian(const pmg_level_s& L, const double* q, hipStream_t st);
 int dtau_blocks(const pmg_level_s& L);
 hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st);
 

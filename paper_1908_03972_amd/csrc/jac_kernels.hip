@@ -27,6 +27,7 @@ struct JacArgs {
   void* W;
   int precision;
   int* flag;
+  const double* Dv;     // [Ne][n][n] viscous part dR_vis/dq, or null
 };
 
 // Pointwise task t = pp * NV + w: column w of the flux Jacobians dF~/dq, dG~/dq at solution point
@@ -105,6 +106,11 @@ __device__ __forceinline__ void face_jacobian(const JacArgs& a, int e, const dou
     out[0] = own[0];
     out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
     out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
+    out[3] = own[3];
+  } else if (nb == -3) {                 // no-slip wall: reversed absolute velocity
+    out[0] = own[0];
+    out[1] = -(own[1] + a.lv.q_ref[1]) - a.lv.q_ref[1];
+    out[2] = -(own[2] + a.lv.q_ref[2]) - a.lv.q_ref[2];
     out[3] = own[3];
   } else {                               // far field
 #pragma unroll
@@ -221,6 +227,7 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
     }
     double dval = acc * ijac;
     if (pp == ss) dval += sDg[(pp * NV + v) * NV + w];
+    if (a.Dv && has_row) dval -= a.Dv[((size_t)e * N + r) * N + c];
     row[j] = has_row ? dval : 0.0;
   }
   if (a.D_out && has_row) {
@@ -335,6 +342,206 @@ static hipError_t launch_jac_rows(const JacArgs& a, int ne, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Viscous part of the element blocks, dR_vis,e/dq_e (BR2, Sec. 2.3), by forward-mode duals: one
+// workgroup per element, K columns of the block per pass. Each pass seeds K unknowns of the
+// element, evaluates the element's viscous residual with the neighbours' states and gradient
+// traces held fixed (as the inviscid blocks do), and writes the K tangent columns to Dv.
+template <int P, int K>
+__global__ void __launch_bounds__(64) k_visc_jac(JacArgs a, double* __restrict__ Dv) {
+  constexpr int N1 = P + 1, NP = N1 * N1, NV = 4, N = NV * NP, NF = 4 * N1, KD = K + 1;
+  static_assert(NP <= 64 && NF <= 64, "one point or face task per thread");
+  using T = Dual<K>;
+  __shared__ double sq[NV * NP];
+  __shared__ double sgl[NV * 2 * NP * KD];      // local gradients
+  __shared__ double sjn[NF * NV * 2 * KD];      // (q_com - q) N per flux point
+  __shared__ double sfh[NF * NV * KD];          // common viscous flux N . f_vis
+  __shared__ double sfv[NV * NP * KD];          // F~v
+  __shared__ double sgv[NV * NP * KD];          // G~v
+  const int ne = a.lv.ne;
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const size_t sstride = (size_t)NP * ne;
+  const Ops1D& o = a.ops;
+  auto st = [](double* dst, const T& x) {
+    dst[0] = x.v;
+#pragma unroll
+    for (int k = 0; k < K; ++k) dst[1 + k] = x.d[k];
+  };
+  auto ld = [](const double* src) {
+    T x;
+    x.v = src[0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) x.d[k] = src[1 + k];
+    return x;
+  };
+  for (int t = tid; t < NV * NP; t += 64) {
+    const int v = t / NP, pp = t % NP;
+    sq[t] = a.q[v * sstride + (size_t)pp * ne + e];
+  }
+  // per point: metrics; per face task: geometry, neighbour data, the fixed outside state
+  const bool pt = tid < NP;
+  const int p = pt ? tid : 0, i = p % N1, j = p / N1;
+  const size_t gp = (size_t)p * ne + e;
+  const double sx = a.lv.met[gp], sy = a.lv.met[sstride + gp], tx = a.lv.met[2 * sstride + gp],
+               ty = a.lv.met[3 * sstride + gp], ij = a.lv.met[4 * sstride + gp];
+  const bool ft = tid < NF;
+  const int f = ft ? tid / N1 : 0, kf = ft ? tid % N1 : 0;
+  const size_t fo = ((size_t)(f * N1 + kf) * 3) * ne + e;
+  const double nx = a.lv.fvec[fo], ny = a.lv.fvec[fo + ne], sm = a.lv.fvec[fo + 2 * ne];
+  const double lam = a.lv.lam[(size_t)(f * N1 + kf) * ne + e];
+  const int nb = a.lv.nbr[f * ne + e];
+  double nbx = 0.0, nby = 0.0, nbsm = 0.0, nblam = 0.0, outv[NV] = {0.0, 0.0, 0.0, 0.0};
+  double goutv[NV][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  int kind = (nb == -3) ? 2 : (nb == -2) ? 3 : 1;
+  if (ft && nb >= 0) {
+    kind = 0;
+    const int nf = a.lv.nbf[f * ne + e];
+    const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - kf) : kf;
+    const size_t fn = ((size_t)(nf * N1 + kk) * 3) * ne + nb;
+    nbx = a.lv.fvec[fn];
+    nby = a.lv.fvec[fn + ne];
+    nbsm = a.lv.fvec[fn + 2 * ne];
+    nblam = a.lv.lam[(size_t)(nf * N1 + kk) * ne + nb];
+    const double* wn = (nf == 0 || nf == 2) ? o.lm : o.lp;
+    for (int m = 0; m < N1; ++m) {
+      const int pp = (nf < 2) ? (m + N1 * kk) : (kk + N1 * m);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) outv[v] += wn[m] * a.q[v * sstride + (size_t)pp * ne + nb];
+    }
+    const double* gf = a.lv.gface + (size_t)((nf * N1 + kk) * NV * 2) * ne + nb;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      goutv[v][0] = gf[(size_t)(v * 2) * ne];
+      goutv[v][1] = gf[(size_t)(v * 2 + 1) * ne];
+    }
+  } else if (nb == -2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) outv[v] = a.lv.qinf_g[v];
+  }
+  __syncthreads();
+
+  for (int c0 = 0; c0 < N; c0 += K) {
+    // the element's state as duals: unknown (point m, variable v) carries tangent kk iff
+    // m * NV + v == c0 + kk
+    auto qd = [&](int v, int m) {
+      T x = dconst<K>(sq[v * NP + m]);
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) x.d[kk] = (m * NV + v == c0 + kk) ? 1.0 : 0.0;
+      return x;
+    };
+    if (pt) {                                         // local gradients
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T dxi = dconst<K>(0.0), deta = dconst<K>(0.0);
+        for (int k = 0; k < N1; ++k) {
+          dxi = dxi + o.D[i * N1 + k] * qd(v, k + N1 * j);
+          deta = deta + o.D[j * N1 + k] * qd(v, i + N1 * k);
+        }
+        st(&sgl[((v * 2 + 0) * NP + p) * KD], ij * (sx * dxi + tx * deta));
+        st(&sgl[((v * 2 + 1) * NP + p) * KD], ij * (sy * dxi + ty * deta));
+      }
+    }
+    __syncthreads();
+    if (ft) {                                         // common viscous flux and jumps
+      const double* w = (f == 0 || f == 2) ? o.lm : o.lp;
+      T own[NV], out[NV], gown[NV][2], gout[NV][2], jn[NV][2], fhv[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        own[v] = dconst<K>(0.0);
+        gown[v][0] = gown[v][1] = dconst<K>(0.0);
+        gout[v][0] = dconst<K>(goutv[v][0]);
+        gout[v][1] = dconst<K>(goutv[v][1]);
+      }
+      for (int m = 0; m < N1; ++m) {
+        const int pp = (f < 2) ? (m + N1 * kf) : (kf + N1 * m);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          own[v] = own[v] + w[m] * qd(v, pp);
+          gown[v][0] = gown[v][0] + w[m] * ld(&sgl[((v * 2 + 0) * NP + pp) * KD]);
+          gown[v][1] = gown[v][1] + w[m] * ld(&sgl[((v * 2 + 1) * NP + pp) * KD]);
+        }
+      }
+      if (nb == -1) {                                 // slip wall ghost
+        const T ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2];
+        const T un = ua * nx + va * ny;
+        out[0] = own[0];
+        out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+        out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
+        out[3] = own[3];
+      } else if (nb == -3) {                          // no-slip wall ghost
+        out[0] = own[0];
+        out[1] = -(own[1] + a.lv.q_ref[1]) - a.lv.q_ref[1];
+        out[2] = -(own[2] + a.lv.q_ref[2]) - a.lv.q_ref[2];
+        out[3] = own[3];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = dconst<K>(outv[v]);
+      }
+      visc_face2(own, out, a.lv.q_ref, gown, gout, nx, ny, sm, lam, nbx, nby, nbsm, nblam, kind, a.gas, jn, fhv);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        st(&sjn[((tid * NV + v) * 2 + 0) * KD], jn[v][0]);
+        st(&sjn[((tid * NV + v) * 2 + 1) * KD], jn[v][1]);
+        st(&sfh[(tid * NV + v) * KD], fhv[v]);
+      }
+    }
+    __syncthreads();
+    if (pt) {                                         // corrected gradient, viscous point fluxes
+      T gc[NV][2];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          const T lift = o.gL[i] * ld(&sjn[(((0 * N1 + j) * NV + v) * 2 + d) * KD]) +
+                         o.gR[i] * ld(&sjn[(((1 * N1 + j) * NV + v) * 2 + d) * KD]) +
+                         o.gL[j] * ld(&sjn[(((2 * N1 + i) * NV + v) * 2 + d) * KD]) +
+                         o.gR[j] * ld(&sjn[(((3 * N1 + i) * NV + v) * 2 + d) * KD]);
+          gc[v][d] = ld(&sgl[((v * 2 + d) * NP + p) * KD]) + ij * lift;
+        }
+      }
+      const T u = qd(1, p) + a.lv.q_ref[1], vv = qd(2, p) + a.lv.q_ref[2];
+      T fx[NV], fy[NV];
+      visc_flux2(u, vv, gc, a.gas, fx, fy);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        st(&sfv[(v * NP + p) * KD], sx * fx[v] + sy * fy[v]);
+        st(&sgv[(v * NP + p) * KD], tx * fx[v] + ty * fy[v]);
+      }
+    }
+    __syncthreads();
+    if (pt) {                                         // R_vis = (1/|J|)[div F~v + g'(F^v - F~v,f)]
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T d = dconst<K>(0.0), fl0 = dconst<K>(0.0), fl1 = dconst<K>(0.0), gl2 = dconst<K>(0.0),
+          gl3 = dconst<K>(0.0);
+        for (int k = 0; k < N1; ++k) {
+          const T fvk = ld(&sfv[(v * NP + k + N1 * j) * KD]), gvk = ld(&sgv[(v * NP + i + N1 * k) * KD]);
+          d = d + o.D[i * N1 + k] * fvk + o.D[j * N1 + k] * gvk;
+          fl0 = fl0 + o.lm[k] * fvk;
+          fl1 = fl1 + o.lp[k] * fvk;
+          gl2 = gl2 + o.lm[k] * gvk;
+          gl3 = gl3 + o.lp[k] * gvk;
+        }
+        d = d + o.gL[i] * (ld(&sfh[((0 * N1 + j) * NV + v) * KD]) - fl0) +
+            o.gR[i] * (ld(&sfh[((1 * N1 + j) * NV + v) * KD]) - fl1) +
+            o.gL[j] * (ld(&sfh[((2 * N1 + i) * NV + v) * KD]) - gl2) +
+            o.gR[j] * (ld(&sfh[((3 * N1 + i) * NV + v) * KD]) - gl3);
+        double* row = Dv + ((size_t)e * N + p * NV + v) * N;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+          if (c0 + kk < N) row[c0 + kk] = ij * d.d[kk];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int P>
+static hipError_t launch_visc_jac_p(const JacArgs& a, double* Dv, int ne, hipStream_t st) {
+  hipLaunchKernelGGL((k_visc_jac<P, 4>), dim3(ne), dim3(64), 0, st, a, Dv);
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
                            pmg_factors_s& fac, hipStream_t st) {
   JacArgs a{};
@@ -348,6 +555,21 @@ hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, d
   a.W = fac.W;
   a.precision = fac.precision;
   a.flag = L.flag;
+  a.Dv = nullptr;
+  if (L.visc) {                          // viscous blocks first: gradient traces, then the duals
+    hipError_t err = launch_gradient_traces(L, q, st);
+    if (err != hipSuccess) return err;
+    switch (L.P) {
+      case 0: err = launch_visc_jac_p<0>(a, L.Dv, L.ne, st); break;
+      case 1: err = launch_visc_jac_p<1>(a, L.Dv, L.ne, st); break;
+      case 2: err = launch_visc_jac_p<2>(a, L.Dv, L.ne, st); break;
+      case 3: err = launch_visc_jac_p<3>(a, L.Dv, L.ne, st); break;
+      case 4: err = launch_visc_jac_p<4>(a, L.Dv, L.ne, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess) return err;
+    a.Dv = L.Dv;
+  }
   switch (L.P) {
     case 0: return launch_jac_rows<0, 1>(a, L.ne, st);
     case 1: return launch_jac_rows<1, 1>(a, L.ne, st);

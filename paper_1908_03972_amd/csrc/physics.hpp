@@ -16,6 +16,9 @@ struct GasParams {
   double ma_inf;
   double kappa;
   int eps_mode;     // 0: eps = min(1, Ma) (cut-off off); 1: eps = min(1, max(kappa Ma_inf, Ma)), eq. (11)
+  double mu;        // dynamic viscosity (0: inviscid)
+  double kcond;     // mu C_p / Pr
+  double br2_eta;   // penalty of the BR2 common gradient
 };
 
 // ---- forward-mode dual numbers ------------------------------------------------------
@@ -145,6 +148,8 @@ template <class T>
 __device__ __forceinline__ T lift(double x) { return T(x); }
 template <>
 __device__ __forceinline__ Dual<1> lift<Dual<1>>(double x) { return dconst<1>(x); }
+template <>
+__device__ __forceinline__ Dual<2> lift<Dual<2>>(double x) { return dconst<2>(x); }
 template <>
 __device__ __forceinline__ Dual<4> lift<Dual<4>>(double x) { return dconst<4>(x); }
 
@@ -309,6 +314,75 @@ __device__ __forceinline__ void common_flux2(const T qm[4], const T qp[4], const
     T diss = a1 * gd[k] + f12 * (ad[k] - l1 * gd[k]) + f123 * (ay[k] - l1 * w[k]);
     out[k] = smag * (0.5 * (fm[k] + fp[k]) - 0.5 * diss);
   }
+}
+
+}  // namespace pmg
+
+namespace pmg {
+
+// ---- viscous terms (Sec. 2.1 fluxes, Sec. 2.3 BR2 common gradient) ----------------------
+// Viscous flux of Sec. 2.1 in 2-D from the absolute velocity (u, v) and the gradients g[v][d] of
+// the primitive variables (d = x, y): tau = 2 mu (S - div u / 3 I), K = -(mu C_p / Pr) grad T,
+// f_vis,j = (0, tau_1j, tau_2j, u_i tau_ij - K_j).
+template <class T>
+__device__ __forceinline__ void visc_flux2(const T& u, const T& v, const T g[4][2], const GasParams& gp, T fx[4],
+                                           T fy[4]) {
+  const T div = g[1][0] + g[2][1];
+  const T txx = 2.0 * gp.mu * (g[1][0] - div * (1.0 / 3.0));
+  const T tyy = 2.0 * gp.mu * (g[2][1] - div * (1.0 / 3.0));
+  const T txy = gp.mu * (g[1][1] + g[2][0]);
+  fx[0] = lift<T>(0.0);
+  fx[1] = txx;
+  fx[2] = txy;
+  fx[3] = u * txx + v * txy + gp.kcond * g[3][0];
+  fy[0] = lift<T>(0.0);
+  fy[1] = txy;
+  fy[2] = tyy;
+  fy[3] = u * txy + v * tyy + gp.kcond * g[3][1];
+}
+
+// Common viscous flux at one flux point of a face, N . f_vis(q_com, grad q_com), with
+// q_com = (q- + q+)/2 and the BR2 common gradient of eq. (23): each side contributes its local
+// gradient trace plus eta times its lifting of this face, (q_com - q_side) N_side lambda_side,
+// lambda = sum_m l_m(face) g'(x_m) / |J_m| along the side's line. kind 0: interior face (mean of
+// both sides); 1: wall face (q_com = mean with the ghost, which is the wall state; own side
+// only); 2: no-slip adiabatic wall (as 1, and the wall-normal component of grad T removed);
+// 3: far field (q_com = the free stream out; own side only). States are stored offsets, qref turns
+// them into absolute values. Also returns jn = (q_com - own) N, the jump the own side lifts into
+// its volume gradient.
+template <class T>
+__device__ __forceinline__ void visc_face2(const T own[4], const T out[4], const double qref[4], const T gown[4][2],
+                                           const T gout[4][2], double nx, double ny, double sm, double lam,
+                                           double nbx, double nby, double nbsm, double nblam, int kind,
+                                           const GasParams& gp, T jn[4][2], T fhv[4]) {
+  const double Nx = nx * sm, Ny = ny * sm;
+  T qc[4], gc[4][2];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const T half = (kind == 3) ? (out[v] - own[v]) : 0.5 * (out[v] - own[v]);   // q_com - own
+    qc[v] = own[v] + half + qref[v];
+    jn[v][0] = half * Nx;
+    jn[v][1] = half * Ny;
+    const T lo0 = gown[v][0] + gp.br2_eta * lam * jn[v][0];
+    const T lo1 = gown[v][1] + gp.br2_eta * lam * jn[v][1];
+    if (kind == 0) {
+      const double fb = -gp.br2_eta * nblam * nbsm;   // q_com - out = -half
+      gc[v][0] = 0.5 * (lo0 + gout[v][0] + fb * nbx * half);
+      gc[v][1] = 0.5 * (lo1 + gout[v][1] + fb * nby * half);
+    } else {
+      gc[v][0] = lo0;
+      gc[v][1] = lo1;
+    }
+  }
+  if (kind == 2) {
+    const T gn = gc[3][0] * nx + gc[3][1] * ny;
+    gc[3][0] = gc[3][0] - gn * nx;
+    gc[3][1] = gc[3][1] - gn * ny;
+  }
+  T fx[4], fy[4];
+  visc_flux2(qc[1], qc[2], gc, gp, fx, fy);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) fhv[v] = Nx * fx[v] + Ny * fy[v];
 }
 
 }  // namespace pmg

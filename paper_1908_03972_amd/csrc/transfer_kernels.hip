@@ -131,7 +131,7 @@ static unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 // h_e = dx_e / (P+1); a point with T <= 0 or a non-finite value yields -1 so the minimum flags it.
 __global__ void __launch_bounds__(256) k_dtau_partial(int ne, int np, const double* __restrict__ q,
                                                       const double* __restrict__ hdx, Ref4 ref, double gr,
-                                                      double* __restrict__ part) {
+                                                      double rgas, double mu, double* __restrict__ part) {
   __shared__ double red[256];
   const size_t total = (size_t)np * ne, st = total;
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -140,7 +140,11 @@ __global__ void __launch_bounds__(256) k_dtau_partial(int ne, int np, const doub
     const int e = (int)(i % (size_t)ne);
     const double u = q[st + i] + ref.v[1], v = q[2 * st + i] + ref.v[2], t = q[3 * st + i] + ref.v[3];
     const double speed = sqrt(gr * t) + sqrt(u * u + v * v);
-    const double h = hdx[e] / speed;
+    double h = hdx[e] / speed;
+    if (mu > 0.0) {                       // viscous limit (dx/(P+1))^2 rho / mu
+      const double rho = (q[i] + ref.v[0]) / (rgas * t);
+      h = fmin(h, hdx[e] * hdx[e] * rho / mu);
+    }
     val = (t > 0.0 && h > 0.0 && h < 1.0e300) ? h : -1.0;
   }
   red[threadIdx.x] = val;
@@ -229,7 +233,7 @@ hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st
   for (int k = 0; k < 4; ++k) ref.v[k] = L.q_ref[k];
   const int nblk = dtau_blocks(L);
   hipLaunchKernelGGL(k_dtau_partial, dim3(nblk), dim3(256), 0, st, L.ne, L.np, q, L.hdx, ref,
-                     L.gas.gamma * L.gas.rgas, L.dtpart);
+                     L.gas.gamma * L.gas.rgas, L.gas.rgas, L.gas.mu, L.dtpart);
   hipLaunchKernelGGL(k_dtau_final, dim3(1), dim3(256), 0, st, L.dtpart, nblk, L.dtmin);
   return hipGetLastError();
 }

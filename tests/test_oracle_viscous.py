@@ -62,8 +62,8 @@ def _linear_operator(lev, lev0, base, var_in, var_out):
 def test_heat_conduction_operator_is_symmetric_negative(P, jitter):
     """At rest, the BR2 energy residual is the discrete div(k grad T): in the quadrature inner
     product (weights w |J|) it must be symmetric and negative semi-definite with the constants
-    as its null space, on curved-free but distorted meshes. A lifting with the wrong sign or
-    scale, or an unsymmetric common gradient, breaks this."""
+    as its null space, on distorted periodic meshes. A lifting with the wrong sign or scale, or
+    an unsymmetric common gradient, breaks this."""
     mesh = W.periodic_rect_mesh(4, 3, 4.0, 3.0, jitter=jitter, seed=2)
     lev, lev0 = FRLevel(mesh, P, vgas()), FRLevel(mesh, P, vgas(mu=0.0))
     base = np.zeros((lev.ne, lev.npts, 4))
@@ -76,6 +76,45 @@ def test_heat_conduction_operator_is_symmetric_negative(P, jitter):
     assert ev.max() <= 1e-12 * scale
     assert np.sum(ev > -1e-9 * scale) == 1              # one zero eigenvalue: the constants
     assert np.abs(A.sum(axis=1)).max() <= 1e-10 * np.abs(A).max()
+
+
+def curved_periodic_mesh(n=3, L=3.0, amp=0.08):
+    """Periodic box of biquadratic elements whose nodes are moved by a smooth periodic field."""
+    m = W.periodic_rect_mesh(n, n, L, L, ox=0.0, oy=0.0)
+    h = L / n
+    nodes = np.zeros((m.n_elements, 9, 2))
+    for e in range(m.n_elements):
+        i, j = e % n, e // n
+        for b in range(3):
+            for a in range(3):
+                x, y = (i + a / 2) * h, (j + b / 2) * h
+                nodes[e, a + 3 * b] = (x + amp * np.sin(2 * np.pi * y / L) * np.sin(2 * np.pi * x / L),
+                                       y + amp * np.sin(2 * np.pi * x / L) * np.cos(2 * np.pi * y / L))
+    return W.Mesh(2, 2, nodes, m.face_nbr, m.face_nbr_face, m.face_orient)
+
+
+@pytest.mark.parametrize("case", ["curved_periodic", "far_field_box"])
+def test_heat_operator_symmetric_on_curved_elements_and_far_field(case):
+    """The same symmetry on biquadratic (curved) elements, and with far-field boundaries, where
+    q_com is the free stream itself (the mean with the ghost would break it); there the
+    boundary makes the operator negative definite."""
+    if case == "curved_periodic":
+        mesh = curved_periodic_mesh()
+    else:
+        mesh = W.channel_mesh(4, 3, 4.0, 3.0, jitter=0.1, seed=2, wall=W.BC_FAR_FIELD)
+    q_inf = np.array([100.0, 0.0, 0.0, 80.0])
+    lev, lev0 = FRLevel(mesh, 3, vgas(), q_inf=q_inf), FRLevel(mesh, 3, vgas(mu=0.0), q_inf=q_inf)
+    assert np.all(lev.geo.jac > 0)
+    base = np.zeros((lev.ne, lev.npts, 4))
+    base[..., 0], base[..., 3] = 100.0, 80.0
+    A = _linear_operator(lev, lev0, base, 3, 3)
+    B = weights(3, lev).reshape(-1)[:, None] * A
+    scale = np.abs(B).max()
+    assert np.abs(B - B.T).max() <= 1e-12 * scale
+    top = np.linalg.eigvalsh(0.5 * (B + B.T)).max()
+    assert top <= 1e-12 * scale
+    if case == "far_field_box":
+        assert top < -1e-4 * scale
 
 
 @pytest.mark.parametrize("P,penalty,definite", [(2, 4.0, True), (3, 4.0, True), (2, 2.0, True), (2, 1.0, False),

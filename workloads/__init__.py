@@ -201,7 +201,7 @@ def naca4_symmetric_half_thickness(x: np.ndarray, t: float = 0.12) -> np.ndarray
 
 
 def airfoil_o_mesh(n_wrap: int = 128, n_radial: int = 64, ratio: float = 1.1, r_far: float = 20.0,
-                   thickness: float = 0.12, annulus: bool = False) -> Mesh:
+                   thickness: float = 0.12, annulus: bool = False, wall: int = BC_SLIP_WALL) -> Mesh:
     """9-node quadratic O-mesh around a closed-TE symmetric 4-digit profile (chord 1).
 
     Wrap direction (xi): surface points at angle theta = 2 pi s / n_wrap (s in half steps for the
@@ -210,8 +210,8 @@ def airfoil_o_mesh(n_wrap: int = 128, n_radial: int = 64, ratio: float = 1.1, r_
     Radial direction (eta): straight lines from each surface point to the far-field circle point
     (0.5 + r_far cos theta, -r_far sin theta), node fractions (ratio^k - 1)/(ratio^n - 1) with k in
     half steps (first cell height ~ r_far * (ratio - 1)/(ratio^n - 1)).
-    Faces: xi faces wrap periodically; eta = -1 of the first layer is a slip wall, eta = +1 of the
-    last layer far field. With annulus=True the profile is replaced by the unit circle and the
+    Faces: xi faces wrap periodically; eta = -1 of the first layer is a wall of type ``wall`` (slip
+    by default, ``BC_NOSLIP_WALL`` for viscous flow), eta = +1 of the last layer far field. With annulus=True the profile is replaced by the unit circle and the
     inner boundary is also far field (a curved mesh for free-stream tests).
     Element e = i + n_wrap * j.
     """
@@ -244,7 +244,7 @@ def airfoil_o_mesh(n_wrap: int = 128, n_radial: int = 64, ratio: float = 1.1, r_
                     nodes[e, a + 3 * b] = (X[2 * i + a, 2 * j + b], Y[2 * i + a, 2 * j + b])
             nbr[e, 0] = (i - 1) % nw + nw * j
             nbr[e, 1] = (i + 1) % nw + nw * j
-            nbr[e, 2] = (i + nw * (j - 1)) if j > 0 else (BC_FAR_FIELD if annulus else BC_SLIP_WALL)
+            nbr[e, 2] = (i + nw * (j - 1)) if j > 0 else (BC_FAR_FIELD if annulus else wall)
             nbr[e, 3] = (i + nw * (j + 1)) if j < nr - 1 else BC_FAR_FIELD
             nbf[e] = (1, 0, 3, 2)
     name = f"{'annulus' if annulus else 'airfoil'}_o{nw}x{nr}"
