@@ -55,12 +55,13 @@ typedef int32_t pmg_status;
 
 typedef struct pmg_level_s* pmg_level;
 typedef struct pmg_factors_s* pmg_factors;
+typedef struct pmg_batch_s* pmg_batch;
 
 /* Thread-local text of the last error, or "" if none. The pointer stays owned by the library. */
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 102
+#define PMG_ABI_VERSION 103
 int32_t pmg_abi_version(void);
 
 /*
@@ -277,6 +278,41 @@ pmg_status esdirk_step(const pmg_solve_opts* opts, int32_t scheme, double dt, do
 
 /* Number of stages of an ESDIRK scheme id (3 or 4), or 0 for an unknown id. */
 int32_t esdirk_stages(int32_t scheme);
+
+/*
+ * Batches of independent cases (several meshes, degrees or flow conditions advanced together).
+ *
+ * pmg_batch_create copies the case options (the level and factor handles stay owned by the
+ * caller and must outlive the batch; no two cases may share a level). The batch owns one HIP
+ * stream per case (default priority) and a small pinned host buffer.
+ * Errors: PMG_E_ARG (null, n_cases outside 1..64, shared levels), PMG_E_SHAPE (cases on different
+ * devices), PMG_E_HIP, PMG_E_NOMEM.
+ */
+pmg_status pmg_batch_create(const pmg_solve_opts* cases, int32_t n_cases, pmg_batch* out);
+pmg_status pmg_batch_destroy(pmg_batch B);
+int32_t pmg_batch_size(pmg_batch B);
+
+/*
+ * esdirk_stage_solve_batched — esdirk_stage_solve for every case of the batch, with per-case
+ * arguments (arrays of length n_cases; dt[c] <= 0 makes case c steady and its qc_n, R_prev, a_row,
+ * n_prev entries unused; R_out may be NULL, or hold NULL entries; stats may be NULL or an array of
+ * n_cases). The cases are forked from `stream`, solved concurrently on the batch's streams and
+ * joined back into `stream`; every case stops at its own tolerance. Returns PMG_OK, or
+ * PMG_E_NOT_CONVERGED if some case hit max_vcycles (its stats say which), or the first hard error.
+ */
+pmg_status esdirk_stage_solve_batched(pmg_batch B, const double* omega, const double* dt,
+                                      const double* const* qc_n, const double* const* const* R_prev,
+                                      const double* const* a_row, const int32_t* n_prev, double* const* q,
+                                      double* const* R_out, pmg_solve_stats* stats, void* stream);
+
+/*
+ * esdirk_step_batched — one time step of ESDIRK scheme `scheme` (2 or 3) for every case, per-case
+ * dt[c] > 0; q[c] in: q^n, out: q^{n+1}; work[c]: device scratch of esdirk_stages(scheme) states of
+ * that case's finest level; stats: NULL or [n_cases][stages - 1] (case-major). Stage solves that
+ * stop at max_vcycles continue with their last iterate, as in esdirk_step. Synchronises `stream`.
+ */
+pmg_status esdirk_step_batched(pmg_batch B, int32_t scheme, const double* dt, double* const* q, double* const* work,
+                               pmg_solve_stats* stats, void* stream);
 
 #ifdef __cplusplus
 }

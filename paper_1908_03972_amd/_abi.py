@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libpmgfr.so")
 pmg_status = C.c_int32
 pmg_level = C.c_void_p
 pmg_factors = C.c_void_p
+pmg_batch = C.c_void_p
 
 PMG_OK = 0
 PMG_E_ARG = -1
@@ -84,6 +85,15 @@ SIGNATURES = {
     "esdirk_step": (pmg_status, [C.POINTER(SolveOpts), C.c_int32, C.c_double, DP, DP, C.POINTER(SolveStats),
                                  C.c_int32, C.c_void_p]),
     "esdirk_stages": (C.c_int32, [C.c_int32]),
+    "pmg_batch_create": (pmg_status, [C.POINTER(SolveOpts), C.c_int32, C.POINTER(pmg_batch)]),
+    "pmg_batch_destroy": (pmg_status, [pmg_batch]),
+    "pmg_batch_size": (C.c_int32, [pmg_batch]),
+    "esdirk_stage_solve_batched": (pmg_status, [pmg_batch, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                                C.POINTER(DP), C.POINTER(C.POINTER(DP)), C.POINTER(C.POINTER(C.c_double)),
+                                                C.POINTER(C.c_int32), C.POINTER(DP), C.POINTER(DP),
+                                                C.POINTER(SolveStats), C.c_void_p]),
+    "esdirk_step_batched": (pmg_status, [pmg_batch, C.c_int32, C.POINTER(C.c_double), C.POINTER(DP), C.POINTER(DP),
+                                         C.POINTER(SolveStats), C.c_void_p]),
 }
 
 _lib = None

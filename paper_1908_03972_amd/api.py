@@ -246,3 +246,109 @@ def esdirk_step(solver: StageSolver, scheme: int, dt: float, q, work, stream=Non
     if raise_on_error:
         A.check(status, "esdirk_step")
     return out
+
+
+class Batch:
+    """Independent cases advanced together (a ``pmg_batch``): each case is a StageSolver (its own
+    levels, factors and options); the library runs them concurrently, one stream per case."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        self._opts = (A.SolveOpts * n)(*[sv.opts for sv in self.solvers])
+        h = A.pmg_batch()
+        A.check(A.lib().pmg_batch_create(self._opts, n, C.byref(h)), "pmg_batch_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            A.lib().pmg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def esdirk_step(self, scheme: int, dt, q, work, stream=None, raise_on_error=True):
+        """One ESDIRK time step of every case: dt a sequence (one per case), q and work lists of
+        device tensors (work[c] of shape (stages, Nv, Np, Ne) of case c). Returns, per case, one
+        stats dict per implicit stage."""
+        n = len(self.solvers)
+        s = esdirk_stages(scheme)
+        if s == 0:
+            raise ValueError(f"unknown ESDIRK scheme {scheme}")
+        qp = (C.c_void_p * n)(*[sv.levels[0].check_state(x, "q", False) for sv, x in zip(self.solvers, q)])
+        for sv, w in zip(self.solvers, work):
+            L0 = sv.levels[0]
+            if w.dtype != torch.float64 or not w.is_contiguous() or tuple(w.shape) != (s,) + L0.shape \
+                    or w.device != L0.torch_device:
+                raise ValueError(f"work must be a contiguous float64 tensor of shape {(s,) + L0.shape}")
+        wp = (C.c_void_p * n)(*[w.data_ptr() for w in work])
+        dts = (C.c_double * n)(*dt)
+        stats = (A.SolveStats * (n * (s - 1)))()
+        hists = []
+        for c, sv in enumerate(self.solvers):
+            cap = sv.opts.max_vcycles + 1
+            for i in range(s - 1):
+                h = (C.c_double * cap)()
+                hists.append(h)
+                st = stats[c * (s - 1) + i]
+                st.history = C.cast(h, C.POINTER(C.c_double))
+                st.history_capacity = cap
+        status = A.lib().esdirk_step_batched(self.handle, scheme, dts, qp, wp, stats, _stream(stream))
+        out = []
+        for c, sv in enumerate(self.solvers):
+            cap = sv.opts.max_vcycles + 1
+            per = []
+            for i in range(s - 1):
+                st, h = stats[c * (s - 1) + i], hists[c * (s - 1) + i]
+                per.append({"status": st.status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh,
+                            "r0": st.r0, "r_final": st.r_final, "seconds": st.seconds,
+                            "history": list(h[:min(st.n_vcycles + 1, cap)])})
+            out.append(per)
+        if raise_on_error:
+            A.check(status, "esdirk_step_batched")
+        return out
+
+    def solve(self, q, omega=None, dt=None, qc_n=None, R_prev=None, a_row=None, R_out=None, stream=None,
+              raise_on_error=True):
+        """esdirk_stage_solve_batched; every argument but q is a per-case list (dt[c] <= 0 or None:
+        steady case c)."""
+        n = len(self.solvers)
+        dt = [0.0] * n if dt is None else [0.0 if d is None else d for d in dt]
+        omega = [0.0] * n if omega is None else list(omega)
+        L0s = [sv.levels[0] for sv in self.solvers]
+        qp = (C.c_void_p * n)(*[L.check_state(x, "q", False) for L, x in zip(L0s, q)])
+        qcp = (C.c_void_p * n)(*[(L.check_state(qc_n[c], "qc_n") if qc_n and qc_n[c] is not None else None)
+                                for c, L in enumerate(L0s)])
+        keep = []
+        rpp = (C.POINTER(C.c_void_p) * n)()
+        arp = (C.POINTER(C.c_double) * n)()
+        npv = (C.c_int32 * n)()
+        for c, L in enumerate(L0s):
+            rs = R_prev[c] if R_prev and R_prev[c] else []
+            arr = (C.c_void_p * max(len(rs), 1))(*[L.check_state(r, "R_prev", False) for r in rs])
+            av = (C.c_double * max(len(rs), 1))(*(a_row[c] if a_row and a_row[c] else []))
+            keep += [arr, av]
+            rpp[c] = C.cast(arr, C.POINTER(C.c_void_p))
+            arp[c] = C.cast(av, C.POINTER(C.c_double))
+            npv[c] = len(rs)
+        rop = (C.c_void_p * n)(*[(L.check_state(R_out[c], "R_out") if R_out and R_out[c] is not None else None)
+                                for c, L in enumerate(L0s)])
+        stats = (A.SolveStats * n)()
+        hists = []
+        for c, sv in enumerate(self.solvers):
+            h = (C.c_double * (sv.opts.max_vcycles + 1))()
+            hists.append(h)
+            stats[c].history = C.cast(h, C.POINTER(C.c_double))
+            stats[c].history_capacity = sv.opts.max_vcycles + 1
+        status = A.lib().esdirk_stage_solve_batched(self.handle, (C.c_double * n)(*omega), (C.c_double * n)(*dt),
+                                                    qcp, rpp, arp, npv, qp, rop, stats, _stream(stream))
+        out = [{"status": st.status, "n_vcycles": st.n_vcycles, "n_refresh": st.n_refresh, "r0": st.r0,
+                "r_final": st.r_final, "seconds": st.seconds, "dtau_min": st.dtau_min,
+                "history": list(h[:min(st.n_vcycles + 1, len(h))])} for st, h in zip(stats, hists)]
+        if raise_on_error:
+            A.check(status, "esdirk_stage_solve_batched")
+        return out

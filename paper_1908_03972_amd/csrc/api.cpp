@@ -739,20 +739,26 @@ pmg_status vcycle_graph(Solve& s, double* q) {
   return PMG_OK;
 }
 
-pmg_status read_norm(pmg_level L, hipStream_t st, double& r) {
-  double h[8];
-  PMG_HIP(hipMemcpyAsync(h, L->norms, (L->nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-  PMG_HIP(hipStreamSynchronize(st));
-  r = h[L->nv];
-  return PMG_OK;
-}
+// ---- one stage solve as a state machine between V-cycles ----------------------------------------
+// The single and the batched entry points share it: stage_begin enqueues the set-up and the norm of
+// q^0, stage_advance consumes the latest norm (host copy), applies the SER law of eq. (31) and
+// enqueues the next V-cycle with its norm, stage_finish checks the fault flags and fills the stats.
+struct StageRun {
+  Solve s;
+  pmg_solve_stats* stats = nullptr;
+  double* q = nullptr;
+  double* R_out = nullptr;
+  double dtau_max = 0.0;
+  double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
+  int m = 0;                    // V-cycles done
+  bool active = false;          // a norm is in flight and more V-cycles may follow
+  pmg_status result = PMG_E_NOT_CONVERGED;
+  std::chrono::steady_clock::time_point t_start;
+  double* host_norms = nullptr; // [Nv + 1] host copy of the finest-level norms
+};
 
-}  // namespace
-
-extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, double dt, const double* qc_n,
-                                         const double* const* R_prev, const double* a_row, int32_t n_prev,
-                                         double* q, double* R_out, pmg_solve_stats* stats, void* stream) {
-  if (!o || !q) return fail(PMG_E_ARG, "null options or q");
+pmg_status check_opts(const pmg_solve_opts* o) {
+  if (!o) return fail(PMG_E_ARG, "null options");
   if (o->n_levels < 1 || o->n_levels > 8 || !o->levels || !o->factors || !o->n_smooth)
     return fail(PMG_E_ARG, "bad level list");
   for (int l = 0; l < o->n_levels; ++l) {
@@ -771,108 +777,162 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
     return fail(PMG_E_ARG, "bad dtau range");
   }
   if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
+  return PMG_OK;
+}
+
+pmg_status enqueue_norm_copy(StageRun& R) {
+  pmg_level L0 = R.s.o->levels[0];
+  PMG_HIP(hipMemcpyAsync(R.host_norms, L0->norms, (L0->nv + 1) * sizeof(double), hipMemcpyDeviceToHost, R.s.st));
+  return PMG_OK;
+}
+
+pmg_status stage_begin(StageRun& R, const pmg_solve_opts* o, double omega, double dt, const double* qc_n,
+                       const double* const* R_prev, const double* a_row, int32_t n_prev, double* q, double* R_out,
+                       pmg_solve_stats* stats, hipStream_t st) {
+  if (!q) return fail(PMG_E_ARG, "null q");
+  if (pmg_status e = check_opts(o)) return e;
   const bool steady = !(dt > 0.0);
   if (!steady) {
     if (!(omega > 0.0)) return fail(PMG_E_ARG, "omega must be positive");
     if (!qc_n || n_prev < 1 || n_prev > 8 || !R_prev || !a_row) return fail(PMG_E_ARG, "bad ESDIRK history");
   }
   pmg_level L0 = o->levels[0];
-  DeviceGuard guard(L0->device);
-  const auto t_start = std::chrono::steady_clock::now();
-  Solve s;
+  R.t_start = std::chrono::steady_clock::now();
+  R.stats = stats;
+  R.q = q;
+  R.R_out = R_out;
+  Solve& s = R.s;
   s.o = o;
-  s.st = as_stream(stream);
+  s.st = st;
   s.c_mass = steady ? 0.0 : 1.0 / (omega * dt);
   s.src = nullptr;
   s.refresh = false;
   s.n_refresh = 0;
-  s.R1.resize(o->n_levels);
-  s.I1.resize(o->n_levels);
+  s.R1.assign(o->n_levels, {});
+  s.I1.assign(o->n_levels, {});
   for (int l = 0; l + 1 < o->n_levels; ++l) {
     projection_matrix(*o->levels[l], *o->levels[l + 1], s.R1[l]);
     interpolation_matrix(*o->levels[l + 1], *o->levels[l], s.I1[l]);
   }
   if (!steady) {
-    PMG_HIP(pmg::launch_stage_source(*L0, qc_n, R_prev, a_row, n_prev, dt, s.c_mass, L0->wsrc, s.st));
+    PMG_HIP(pmg::launch_stage_source(*L0, qc_n, R_prev, a_row, n_prev, dt, s.c_mass, L0->wsrc, st));
     s.src = L0->wsrc;
   }
-  for (int l = 0; l < o->n_levels; ++l) PMG_HIP(hipMemsetAsync(o->levels[l]->flag, 0, sizeof(int), s.st));
-
+  for (int l = 0; l < o->n_levels; ++l) PMG_HIP(hipMemsetAsync(o->levels[l]->flag, 0, sizeof(int), st));
   // pseudo-time range: given directly, or as CFL numbers times dtau_min of eq. (33) at q^0
-  double dtau_init = o->dtau_init, dtau_max = o->dtau_max, dtmin = 0.0;
+  double dtau_init = o->dtau_init, dtmin = 0.0;
+  R.dtau_max = o->dtau_max;
   if (o->use_cfl) {
-    if (pmg_status e = pmg_dtau_min(L0, q, &dtmin, stream)) return e;
+    if (pmg_status e = pmg_dtau_min(L0, q, &dtmin, st)) return e;
     dtau_init = o->cfl_init * dtmin;
-    dtau_max = o->cfl_max * dtmin;
+    R.dtau_max = o->cfl_max * dtmin;
   }
-  if (stats) stats->dtau_min = dtmin;
-  double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
-  int m = 0;
-  pmg_status result = PMG_E_NOT_CONVERGED;
-  s.dtau = dtau_init;
-  if (stats) stats->n_refresh = 0;
-  // r_0 = ||F(q^0)||; every V-cycle ends with the norm of its result, r_{m+1}
-  PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, s.st));
-  PMG_HIP(pmg::launch_norm_finalize(*L0, s.st));
-  if (pmg_status e = read_norm(L0, s.st, r)) return e;
-  for (m = 0;; ++m) {
-    if (stats && stats->history && m < stats->history_capacity) stats->history[m] = r;
-    if (!std::isfinite(r)) {
-      result = fail(PMG_E_NONFINITE, "non-finite residual norm");
-      break;
-    }
-    if (m == 0) {
-      r0 = r;
-    } else {
-      s.dtau = std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), dtau_max);   // eq. (31)
-    }
-    if (r == 0.0 || r / r0 <= o->tol_rel) {
-      result = PMG_OK;
-      break;
-    }
-    if (m >= o->max_vcycles) {
-      result = fail(PMG_E_NOT_CONVERGED, "stage solve reached max_vcycles");
-      break;
-    }
-    const bool frozen = o->freeze_at_max && dtau_last_refresh >= dtau_max;
-    s.refresh = (m == 0) || (m % o->refresh_every == 0 && !frozen);
-    if (s.refresh) {
-      PMG_HIP(pmg::launch_jacobian(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
-      ++s.n_refresh;
-      dtau_last_refresh = s.dtau;
-      if (pmg_status e = vcycle_and_norm(s, q)) return e;
-    } else if (o->use_graph) {
-      if (pmg_status e = vcycle_graph(s, q)) return e;
-    } else {
-      if (pmg_status e = vcycle_and_norm(s, q)) return e;
-    }
-    r_prev = r;
-    if (pmg_status e = read_norm(L0, s.st, r)) return e;
-  }
-  if (result != PMG_E_NONFINITE) {
-    int h = 0;
-    PMG_HIP(hipMemcpyAsync(&h, L0->flag, sizeof(int), hipMemcpyDeviceToHost, s.st));
-    for (int l = 1; l < o->n_levels; ++l) {
-      int hl = 0;
-      PMG_HIP(hipMemcpyAsync(&hl, o->levels[l]->flag, sizeof(int), hipMemcpyDeviceToHost, s.st));
-      PMG_HIP(hipStreamSynchronize(s.st));
-      h |= hl;
-    }
-    PMG_HIP(hipStreamSynchronize(s.st));
-    if (h & 1) result = fail(PMG_E_SINGULAR, "zero or non-finite pivot in an element block");
-  }
-  if (R_out && result == PMG_OK)
-    PMG_HIP(pmg::launch_residual(*L0, q, nullptr, nullptr, 0.0, R_out, false, s.st));
   if (stats) {
-    stats->n_vcycles = m;
-    stats->n_refresh = s.n_refresh;
-    stats->r0 = r0;
-    stats->r_final = r;
-    stats->status = result;
+    stats->dtau_min = dtmin;
+    stats->n_refresh = 0;
   }
-  PMG_HIP(hipStreamSynchronize(s.st));
-  if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  s.dtau = dtau_init;
+  R.m = 0;
+  R.dtau_last_refresh = -1.0;
+  R.result = PMG_E_NOT_CONVERGED;
+  // r_0 = ||F(q^0)||; every V-cycle ends with the norm of its result, r_{m+1}
+  PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, st));
+  PMG_HIP(pmg::launch_norm_finalize(*L0, st));
+  if (pmg_status e = enqueue_norm_copy(R)) return e;
+  R.active = true;
+  return PMG_OK;
+}
+
+// The norm enqueued last must have arrived in R.host_norms (the caller synchronised R.s.st).
+pmg_status stage_advance(StageRun& R) {
+  const pmg_solve_opts* o = R.s.o;
+  pmg_level L0 = o->levels[0];
+  Solve& s = R.s;
+  const int m = R.m;
+  R.r = R.host_norms[L0->nv];
+  if (R.stats && R.stats->history && m < R.stats->history_capacity) R.stats->history[m] = R.r;
+  R.active = false;
+  if (!std::isfinite(R.r)) {
+    R.result = fail(PMG_E_NONFINITE, "non-finite residual norm");
+    return PMG_OK;
+  }
+  if (m == 0) {
+    R.r0 = R.r;
+  } else {
+    s.dtau = std::min(s.dtau * std::pow(R.r_prev / R.r, o->ser_exponent), R.dtau_max);   // eq. (31)
+  }
+  if (R.r == 0.0 || R.r / R.r0 <= o->tol_rel) {
+    R.result = PMG_OK;
+    return PMG_OK;
+  }
+  if (m >= o->max_vcycles) {
+    R.result = fail(PMG_E_NOT_CONVERGED, "stage solve reached max_vcycles");
+    return PMG_OK;
+  }
+  const bool frozen = o->freeze_at_max && R.dtau_last_refresh >= R.dtau_max;
+  s.refresh = (m == 0) || (m % o->refresh_every == 0 && !frozen);
+  if (s.refresh) {
+    PMG_HIP(pmg::launch_jacobian(*L0, R.q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
+    ++s.n_refresh;
+    R.dtau_last_refresh = s.dtau;
+    if (pmg_status e = vcycle_and_norm(s, R.q)) return e;
+  } else if (o->use_graph) {
+    if (pmg_status e = vcycle_graph(s, R.q)) return e;
+  } else {
+    if (pmg_status e = vcycle_and_norm(s, R.q)) return e;
+  }
+  R.r_prev = R.r;
+  R.m = m + 1;
+  if (pmg_status e = enqueue_norm_copy(R)) return e;
+  R.active = true;
+  return PMG_OK;
+}
+
+pmg_status stage_finish(StageRun& R) {
+  const pmg_solve_opts* o = R.s.o;
+  pmg_level L0 = o->levels[0];
+  hipStream_t st = R.s.st;
+  pmg_status result = R.result;
+  if (result != PMG_E_NONFINITE) {
+    std::vector<int> h(o->n_levels, 0);
+    for (int l = 0; l < o->n_levels; ++l)
+      PMG_HIP(hipMemcpyAsync(&h[l], o->levels[l]->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    PMG_HIP(hipStreamSynchronize(st));
+    int any = 0;
+    for (int v : h) any |= v;
+    if (any & 1) result = fail(PMG_E_SINGULAR, "zero or non-finite pivot in an element block");
+  }
+  if (R.R_out && result == PMG_OK)
+    PMG_HIP(pmg::launch_residual(*L0, R.q, nullptr, nullptr, 0.0, R.R_out, false, st));
+  if (R.stats) {
+    R.stats->n_vcycles = R.m;
+    R.stats->n_refresh = R.s.n_refresh;
+    R.stats->r0 = R.r0;
+    R.stats->r_final = R.r;
+    R.stats->status = result;
+  }
+  PMG_HIP(hipStreamSynchronize(st));
+  if (R.stats) R.stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t_start).count();
   return result;
+}
+
+}  // namespace
+
+extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, double dt, const double* qc_n,
+                                         const double* const* R_prev, const double* a_row, int32_t n_prev,
+                                         double* q, double* R_out, pmg_solve_stats* stats, void* stream) {
+  if (pmg_status e = check_opts(o)) return e;
+  DeviceGuard guard(o->levels[0]->device);
+  StageRun R;
+  double hn[8];
+  R.host_norms = hn;
+  const hipStream_t st = as_stream(stream);
+  if (pmg_status e = stage_begin(R, o, omega, dt, qc_n, R_prev, a_row, n_prev, q, R_out, stats, st)) return e;
+  while (R.active) {
+    PMG_HIP(hipStreamSynchronize(st));
+    if (pmg_status e = stage_advance(R)) return e;
+  }
+  return stage_finish(R);
 }
 
 // ---- ESDIRK time step ----------------------------------------------------------------------------
@@ -945,5 +1005,244 @@ extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, doubl
     }
   }
   if (worst != PMG_OK) return fail(worst, "a stage solve reached max_vcycles");
+  return PMG_OK;
+}
+
+// ---- batches of independent cases -----------------------------------------------------------------
+// Each case has its own levels (mesh, P) and factors; the batch owns one stream per case. A batched
+// call forks the cases from the caller's stream, runs their stage solves concurrently (each on its
+// stream, V-cycles replayed from each case's graph), synchronising case by case to read the norms
+// the SER law needs, and joins them back into the caller's stream.
+struct pmg_batch_s {
+  int device = 0;
+  std::vector<pmg_solve_opts> opts;
+  std::vector<std::vector<pmg_level>> levels;
+  std::vector<std::vector<pmg_factors>> factors;
+  std::vector<std::vector<int32_t>> n_smooth;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
+  double* host_norms = nullptr;   // pinned, [cases][8]
+};
+
+namespace {
+
+void free_batch(pmg_batch_s* B) {
+  if (!B) return;
+  for (hipStream_t s : B->streams)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : B->done)
+    if (e) (void)hipEventDestroy(e);
+  if (B->fork) (void)hipEventDestroy(B->fork);
+  if (B->host_norms) (void)hipHostFree(B->host_norms);
+  delete B;
+}
+
+pmg_status batch_fork(pmg_batch B, hipStream_t caller) {
+  PMG_HIP(hipEventRecord(B->fork, caller));
+  for (hipStream_t s : B->streams) PMG_HIP(hipStreamWaitEvent(s, B->fork, 0));
+  return PMG_OK;
+}
+
+pmg_status batch_join(pmg_batch B, hipStream_t caller) {
+  for (size_t c = 0; c < B->streams.size(); ++c) {
+    PMG_HIP(hipEventRecord(B->done[c], B->streams[c]));
+    PMG_HIP(hipStreamWaitEvent(caller, B->done[c], 0));
+  }
+  return PMG_OK;
+}
+
+}  // namespace
+
+extern "C" pmg_status pmg_batch_create(const pmg_solve_opts* cases, int32_t n_cases, pmg_batch* out) {
+  if (!cases || !out) return fail(PMG_E_ARG, "null argument");
+  *out = nullptr;
+  if (n_cases < 1 || n_cases > 64) return fail(PMG_E_ARG, "n_cases must be in 1..64");
+  for (int c = 0; c < n_cases; ++c) {
+    if (pmg_status e = check_opts(&cases[c])) return e;
+    if (cases[c].levels[0]->device != cases[0].levels[0]->device)
+      return fail(PMG_E_SHAPE, "all cases of a batch must live on one device");
+    for (int d = 0; d < c; ++d)
+      for (int l = 0; l < cases[c].n_levels; ++l)
+        for (int k = 0; k < cases[d].n_levels; ++k)
+          if (cases[c].levels[l] == cases[d].levels[k])
+            return fail(PMG_E_ARG, "cases of a batch must not share levels (their workspaces would race)");
+  }
+  pmg_batch_s* B = new pmg_batch_s();
+  B->device = cases[0].levels[0]->device;
+  DeviceGuard guard(B->device);
+  B->opts.assign(cases, cases + n_cases);
+  B->levels.resize(n_cases);
+  B->factors.resize(n_cases);
+  B->n_smooth.resize(n_cases);
+  for (int c = 0; c < n_cases; ++c) {
+    const pmg_solve_opts& o = cases[c];
+    B->levels[c].assign(o.levels, o.levels + o.n_levels);
+    B->factors[c].assign(o.factors, o.factors + o.n_levels);
+    B->n_smooth[c].assign(o.n_smooth, o.n_smooth + o.n_levels);
+    B->opts[c].levels = B->levels[c].data();
+    B->opts[c].factors = B->factors[c].data();
+    B->opts[c].n_smooth = B->n_smooth[c].data();
+  }
+  B->streams.assign(n_cases, nullptr);
+  B->done.assign(n_cases, nullptr);
+  for (int c = 0; c < n_cases; ++c) {
+    if (hipStreamCreateWithFlags(&B->streams[c], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->done[c], hipEventDisableTiming) != hipSuccess) {
+      free_batch(B);
+      return fail(PMG_E_HIP, "stream or event creation failed");
+    }
+  }
+  if (hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&B->host_norms), sizeof(double) * 8 * n_cases) != hipSuccess) {
+    free_batch(B);
+    return fail(PMG_E_NOMEM, "batch host buffers");
+  }
+  *out = B;
+  return PMG_OK;
+}
+
+extern "C" pmg_status pmg_batch_destroy(pmg_batch B) {
+  if (!B) return PMG_OK;
+  DeviceGuard guard(B->device);
+  for (hipStream_t s : B->streams)
+    if (s) (void)hipStreamSynchronize(s);
+  free_batch(B);
+  return PMG_OK;
+}
+
+extern "C" int32_t pmg_batch_size(pmg_batch B) { return B ? (int32_t)B->opts.size() : 0; }
+
+namespace {
+
+// The cases with run[c] set, each solved as by esdirk_stage_solve; a case's own failure (a
+// non-finite residual, a singular block, max_vcycles) ends only that case, and its status is
+// left in status[c].
+pmg_status stage_solve_cases(pmg_batch B, const std::vector<char>& run, const double* omega, const double* dt,
+                             const double* const* qc_n, const double* const* const* R_prev,
+                             const double* const* a_row, const int32_t* n_prev, double* const* q,
+                             double* const* R_out, pmg_solve_stats* stats, std::vector<pmg_status>& status,
+                             hipStream_t caller) {
+  const int n = (int)B->opts.size();
+  if (pmg_status e = batch_fork(B, caller)) return e;
+  std::vector<StageRun> runs(n);
+  std::vector<char> begun(n, 0);
+  for (int c = 0; c < n; ++c) {
+    status[c] = PMG_OK;
+    if (!run[c]) continue;
+    runs[c].host_norms = B->host_norms + 8 * c;
+    const bool steady = !(dt[c] > 0.0);
+    status[c] = stage_begin(runs[c], &B->opts[c], omega[c], dt[c], steady ? nullptr : qc_n[c],
+                            steady ? nullptr : R_prev[c], steady ? nullptr : a_row[c], steady ? 0 : n_prev[c], q[c],
+                            R_out ? R_out[c] : nullptr, stats ? &stats[c] : nullptr, B->streams[c]);
+    begun[c] = status[c] == PMG_OK;
+  }
+  for (bool any = true; any;) {
+    any = false;
+    for (int c = 0; c < n; ++c) {
+      if (!begun[c] || !runs[c].active) continue;
+      PMG_HIP(hipStreamSynchronize(B->streams[c]));
+      if (pmg_status e = stage_advance(runs[c])) {
+        (void)batch_join(B, caller);
+        return e;
+      }
+      any = any || runs[c].active;
+    }
+  }
+  for (int c = 0; c < n; ++c)
+    if (begun[c]) status[c] = stage_finish(runs[c]);
+  return batch_join(B, caller);
+}
+
+pmg_status worst_of(const std::vector<pmg_status>& status) {
+  pmg_status worst = PMG_OK;
+  for (pmg_status r : status)
+    if (r != PMG_OK && (worst == PMG_OK || worst == PMG_E_NOT_CONVERGED)) worst = r;
+  return worst;
+}
+
+}  // namespace
+
+extern "C" pmg_status esdirk_stage_solve_batched(pmg_batch B, const double* omega, const double* dt,
+                                                 const double* const* qc_n, const double* const* const* R_prev,
+                                                 const double* const* a_row, const int32_t* n_prev, double* const* q,
+                                                 double* const* R_out, pmg_solve_stats* stats, void* stream) {
+  if (!B || !omega || !dt || !q) return fail(PMG_E_ARG, "null argument");
+  const int n = (int)B->opts.size();
+  DeviceGuard guard(B->device);
+  std::vector<char> run(n, 1);
+  std::vector<pmg_status> status(n, PMG_OK);
+  if (pmg_status e = stage_solve_cases(B, run, omega, dt, qc_n, R_prev, a_row, n_prev, q, R_out, stats, status,
+                                       as_stream(stream)))
+    return e;
+  const pmg_status worst = worst_of(status);
+  if (worst == PMG_E_NOT_CONVERGED) return fail(worst, "a stage solve of the batch reached max_vcycles");
+  return worst;
+}
+
+extern "C" pmg_status esdirk_step_batched(pmg_batch B, int32_t scheme, const double* dt, double* const* q,
+                                          double* const* work, pmg_solve_stats* stats, void* stream) {
+  double A[64];
+  const int s = esdirk_tableau(scheme, A);
+  if (s == 0) return fail(PMG_E_ARG, "unknown ESDIRK scheme");
+  if (!B || !dt || !q || !work) return fail(PMG_E_ARG, "null argument");
+  const int n = (int)B->opts.size();
+  for (int c = 0; c < n; ++c)
+    if (!q[c] || !work[c] || !(dt[c] > 0.0)) return fail(PMG_E_ARG, "null state or non-positive dt");
+  DeviceGuard guard(B->device);
+  const hipStream_t caller = as_stream(stream);
+  // per case: q_c^n and R(q^n) into the first two work slots (on the caller's stream)
+  std::vector<std::vector<const double*>> R(n, std::vector<const double*>(s));
+  std::vector<const double*> qc(n);
+  for (int c = 0; c < n; ++c) {
+    pmg_level L0 = B->opts[c].levels[0];
+    const size_t ns = L0->state_elems();
+    qc[c] = work[c];
+    for (int k = 0; k < s - 1; ++k) R[c][k] = work[c] + (size_t)(k + 1) * ns;
+    PMG_HIP(pmg::launch_conservative(*L0, q[c], work[c], caller));
+    PMG_HIP(pmg::launch_residual(*L0, q[c], nullptr, nullptr, 0.0, const_cast<double*>(R[c][0]), false, caller));
+  }
+  const double omega = A[1 * s + 1];
+  std::vector<double> om(n, omega);
+  std::vector<const double* const*> Rp(n);
+  std::vector<int32_t> np(n);
+  std::vector<double*> Rout(n);
+  std::vector<pmg_solve_stats> st_i(n);
+  std::vector<char> run(n, 1);                   // cases still advancing (a hard failure stops one)
+  std::vector<pmg_status> step_status(n, PMG_OK), status(n, PMG_OK);
+  for (int i = 1; i < s; ++i) {
+    double a_row[8];
+    for (int j = 0; j < i; ++j) a_row[j] = A[i * s + j];
+    std::vector<const double*> ar(n, a_row);
+    for (int c = 0; c < n; ++c) {
+      Rp[c] = R[c].data();
+      np[c] = i;
+      Rout[c] = (i < s - 1) ? const_cast<double*>(R[c][i]) : nullptr;
+      st_i[c] = stats ? stats[c * (s - 1) + (i - 1)] : pmg_solve_stats{};
+      if (!stats) st_i[c].history = nullptr;
+    }
+    if (pmg_status e = stage_solve_cases(B, run, om.data(), dt, qc.data(), Rp.data(), ar.data(), np.data(), q,
+                                         Rout.data(), st_i.data(), status, caller))
+      return e;
+    for (int c = 0; c < n; ++c) {
+      if (!run[c]) {
+        st_i[c].status = step_status[c];          // a case stopped earlier in this step
+        st_i[c].n_vcycles = 0;
+      } else if (status[c] == PMG_E_NOT_CONVERGED) {
+        // the last iterate stands in for the stage value; later stages still run
+        if (step_status[c] == PMG_OK) step_status[c] = PMG_E_NOT_CONVERGED;
+        if (Rout[c])
+          PMG_HIP(pmg::launch_residual(*B->opts[c].levels[0], q[c], nullptr, nullptr, 0.0, Rout[c], false, caller));
+      } else if (status[c] != PMG_OK) {
+        step_status[c] = status[c];
+        run[c] = 0;
+      }
+      if (stats) stats[c * (s - 1) + (i - 1)] = st_i[c];
+    }
+  }
+  PMG_HIP(hipStreamSynchronize(caller));
+  const pmg_status worst = worst_of(step_status);
+  if (worst == PMG_E_NOT_CONVERGED) return fail(worst, "a stage solve of the batch reached max_vcycles");
+  if (worst != PMG_OK) return fail(worst, "a case of the batch failed (see its stats)");
   return PMG_OK;
 }
