@@ -190,6 +190,78 @@ def airfoil_block(api, torch, forms, max_vcycles, kernel_reps):
     return out
 
 
+def viscous_batch_block(api, torch, vcycles_per_stage, steps=1):
+    """Eight independent viscous cases (Re 5000, Ma 0.001, no-slip adiabatic wall, 256 x 96
+    O-mesh, seeded incidence and P in {2, 3, 4}), one ESDIRK3 step of dt = 0.05 from a free stream
+    ramped to zero at the wall, every stage run for a fixed budget of V-cycles (CFL 1 -> 1e2).
+    Two forms on the same work: all cases as one batch with FP32 blocks and graph replay, and
+    the cases one after another with FP64 blocks (eager)."""
+    mesh, cases = W.viscous_config4()
+    nsm_of = {4: (5, 10, 20, 20), 3: (5, 10, 20), 2: (5, 10, 20)}
+    stages = api.esdirk_stages(3)
+    dt = 0.05
+    starts, per_vc = [], []
+    sample_levels = {}
+    for c in cases:
+        if c.P not in sample_levels:
+            sample_levels[c.P] = api.Level(mesh, c.P, q_inf=c.spec.freestream())
+        xy = np.moveaxis(sample_levels[c.P].points(), 0, -1)
+        starts.append(W.viscous_start_state(c.spec, xy) - c.spec.freestream())
+        per_vc.append(dof_updates_per_vcycle(mesh.n_elements, c.p_levels, nsm_of[c.P]))
+    del sample_levels
+
+    def solvers_for(prec, graph):
+        out = []
+        for c in cases:
+            qinf = c.spec.freestream()
+            levels = [api.Level(mesh, P, gamma=c.spec.gamma, rgas=c.spec.rgas, eps_mode=1, ma_inf=c.spec.ma_inf,
+                                kappa=1.0, q_inf=qinf, q_ref=qinf, mu=c.mu, prandtl=c.prandtl) for P in c.p_levels]
+            facs = [api.Factors(lv, prec) for lv in levels]
+            out.append(api.StageSolver(levels, facs, nsm_of[c.P], use_graph=graph, use_cfl=True, cfl_init=1.0,
+                                       cfl_max=1e2, freeze_at_max=False, tol_rel=1e-30,
+                                       max_vcycles=vcycles_per_stage))
+        return out
+
+    res = {"workload": "8 viscous cases, Re 5000, Ma 0.001, no-slip adiabatic wall, O-mesh 256x96 "
+                       "(24576 elements), incidence U[0,6] deg and P in {2,3,4} from default_rng(5000), "
+                       "ESDIRK3 dt 0.05 from a wall-ramped free stream, CFL 1 -> 1e2, "
+                       f"{vcycles_per_stage} V-cycles per stage",
+           "cases": [{"alpha_deg": c.alpha_deg, "P": c.P, "p_levels": list(c.p_levels)} for c in cases]}
+    for form, (prec, graph, batched) in (("mixed_batched", (32, True, True)), ("fp64_sequential", (64, False, False))):
+        solvers = solvers_for(prec, graph)
+        qs = [torch.from_numpy(np.ascontiguousarray(np.moveaxis(q0, -1, 0))).cuda() for q0 in starts]
+        works = [torch.zeros((stages,) + sv.levels[0].shape, dtype=torch.float64, device="cuda") for sv in solvers]
+        batch = api.Batch(solvers) if batched else None
+
+        def one_step(qq):
+            if batched:
+                return batch.esdirk_step(3, [dt] * len(cases), qq, works, raise_on_error=False)
+            return [api.esdirk_step(sv, 3, dt, q, w, raise_on_error=False) for sv, q, w in zip(solvers, qq, works)]
+
+        one_step([q.clone() for q in qs])                      # warm-up (graph capture, first touch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = []
+        for _ in range(steps):
+            st = one_step(qs)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        upd = sum(per_vc[c] * sum(x["n_vcycles"] for x in st[c]) for c in range(len(cases))) * steps
+        res[form] = {"elapsed_s": el, "dof_updates_per_s": upd / el, "dof_updates": upd,
+                     "stage_status": [[x["status"] for x in st[c]] for c in range(len(cases))],
+                     "stage_vcycles": [[x["n_vcycles"] for x in st[c]] for c in range(len(cases))],
+                     "stage_rel_residual": [[(x["history"][-1] / x["history"][0]) if x["history"] and x["history"][0]
+                                             else None for x in st[c]] for c in range(len(cases))]}
+        if batch is not None:
+            batch.close()
+        del solvers, works, qs
+        torch.cuda.empty_cache()
+    if res["fp64_sequential"]["elapsed_s"] > 0:
+        res["speedup_mixed_batched_over_fp64_sequential"] = (res["fp64_sequential"]["elapsed_s"]
+                                                             / res["mixed_batched"]["elapsed_s"])
+    return res
+
+
 PROFILE_PMC = os.path.join(ROOT, "profiles", "k_fr_sweep_vortex64_P321_pmc.txt")
 PROFILE_PMC_AIRFOIL = os.path.join(ROOT, "profiles", "k_fr_sweep_airfoil128x64_P4_pmc.txt")
 
@@ -228,6 +300,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
+    ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
+    ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -357,6 +431,8 @@ def main():
     if not args.no_airfoil:
         line["airfoil_128x64_P4_steady"] = airfoil_block(api, torch, args.forms.split(","), args.airfoil_vcycles,
                                                          args.kernel_reps)
+    if not args.no_viscous:
+        line["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -270,3 +270,57 @@ class FreeStreamSpec:
 def airfoil_config3(n_wrap: int = 128, n_radial: int = 64) -> tuple[Mesh, FreeStreamSpec]:
     """Inviscid flow at Ma 0.001, 2 degrees incidence around the 12% symmetric profile."""
     return airfoil_o_mesh(n_wrap, n_radial), FreeStreamSpec()
+
+
+@dataclass
+class ViscousCase:
+    """One case of the viscous batch: incidence, solution degree and its P-level hierarchy."""
+    alpha_deg: float
+    P: int
+    p_levels: tuple
+    spec: FreeStreamSpec
+    mu: float
+    prandtl: float = 0.72
+
+
+VISCOUS_SEED = 5000
+# P-level hierarchies of the viscous cases: P-jumps of one at P = 4 (with BR2 the P4 -> P2 coarse
+# correction diverges on the stretched O-mesh, in the CPU reference as well)
+VISCOUS_HIERARCHY = {4: (4, 3, 2, 1), 3: (3, 2, 1), 2: (2, 1, 0)}
+
+
+def viscous_config4(n_wrap: int = 256, n_radial: int = 96, n_cases: int = 8, reynolds: float = 5000.0,
+                    seed: int = VISCOUS_SEED) -> tuple[Mesh, list]:
+    """Viscous flow at Re 5000 (mu = rho |V| c / Re with rho = |V| = c = 1), Ma 0.001, around the
+    12% profile on the O-mesh refined to n_wrap x n_radial with a no-slip adiabatic wall; n_cases
+    independent cases with incidence U[0, 6] degrees and P in {2, 3, 4} drawn from
+    default_rng(seed) (incidences first, then degrees)."""
+    mesh = airfoil_o_mesh(n_wrap, n_radial, wall=BC_NOSLIP_WALL)
+    rng = np.random.default_rng(seed)
+    alphas = rng.uniform(0.0, 6.0, n_cases)
+    degrees = rng.choice([2, 3, 4], n_cases)
+    cases = [ViscousCase(float(a), int(P), VISCOUS_HIERARCHY[int(P)], FreeStreamSpec(alpha_deg=float(a)),
+                         mu=1.0 / reynolds) for a, P in zip(alphas, degrees)]
+    return mesh, cases
+
+
+def wall_distance(xy: np.ndarray, thickness: float = 0.12, n_surface: int = 4001) -> np.ndarray:
+    """Distance of points xy [..., 2] to the closed-TE symmetric profile (chord 1), by the nearest
+    of n_surface cosine-spaced surface points."""
+    from scipy.spatial import cKDTree
+    x = 0.5 * (1.0 - np.cos(np.linspace(0.0, np.pi, n_surface // 2 + 1)))
+    yt = naca4_symmetric_half_thickness(x, thickness)
+    surf = np.concatenate([np.stack([x, yt], -1), np.stack([x, -yt], -1)])
+    d, _ = cKDTree(surf).query(xy.reshape(-1, 2))
+    return d.reshape(xy.shape[:-1])
+
+
+def viscous_start_state(spec: FreeStreamSpec, xy: np.ndarray, delta: float = 0.05) -> np.ndarray:
+    """Initial state of the viscous cases: the free stream with its velocity ramped to zero at the
+    wall, u = u_inf tanh(d / delta) (d: wall distance), p and T uniform; it replaces the impulsive
+    start of a uniform flow against a no-slip wall."""
+    q = np.broadcast_to(spec.freestream(), xy.shape[:-1] + (4,)).copy()
+    ramp = np.tanh(wall_distance(xy) / delta)
+    q[..., 1] *= ramp
+    q[..., 2] *= ramp
+    return q
