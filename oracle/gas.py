@@ -199,7 +199,7 @@ def common_flux(qm, qp, svec, gas: Gas):
     pointing from left to right whose length is the face area element; the return
     value is |S| f_com(q-, q+; S/|S|).
 
-    Readings: the "averaged values" are the arithmetic mean of the primitive
+    Readings: the averaged state of eq. (21) is the arithmetic mean of the primitive
     variables, and eps (hence U_r) is evaluated from that mean; no entropy fix.
     |Gamma^{-1} A_n| = R |Lambda| R^{-1} is formed from its spectral projectors
     (Sylvester's formula over the three distinct eigenvalues), the textbook
