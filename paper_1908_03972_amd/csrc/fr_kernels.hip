@@ -1,7 +1,8 @@
 // FR/CPR residual and fused element-Jacobi sweep kernels (2-D quadrilaterals).
 //
-// One workgroup owns EPW elements; thread (p, el) owns solution point p of element el, so that
-// loads of the [Nv][Np][Ne] state are coalesced over consecutive elements. Per workgroup:
+// One workgroup owns EPW elements; thread (p, el) owns solution point p of element el (and flux
+// point p of the element's faces), so that loads of the [Nv][Np][Ne] state are coalesced over
+// consecutive elements. Per workgroup:
 //   1. point states and transformed fluxes F~ = f.S, G~ = f.T go to LDS;
 //   2. each element's 4(P+1) flux points: own trace (extrapolated along the tensor line), the
 //      neighbour's trace (extrapolated from the neighbour's state) or a boundary ghost, the
@@ -21,12 +22,14 @@ namespace pmg {
 
 constexpr int kPadding = -100;   // neighbour tag of the padding elements of the last workgroup
 
-// Elements per workgroup: small workgroups (64-128 lanes) so that even the coarsest level of a
-// few thousand elements spreads over all 256 CUs; each W column a workgroup streams is then
-// EPW * n * 4 B ~ 1 KB contiguous.
+// Elements per workgroup: small workgroups (64-256 lanes) so that even the coarsest level of a
+// few thousand elements spreads over all 256 CUs. Each element gets max((P+1)^2, 4(P+1)) lanes, so
+// that every flux point of its four faces has a lane of its own (at P <= 2 the faces have more
+// flux points than the element has solution points).
 constexpr int epw_for(int P) {
-  return P == 0 ? 64 : P == 1 ? 16 : P == 2 ? 7 : P == 3 ? 4 : P == 4 ? 5 : P == 5 ? 3 : 5;
+  return P == 0 ? 16 : P == 1 ? 8 : P == 2 ? 5 : P == 3 ? 4 : P == 4 ? 5 : P == 5 ? 3 : 5;
 }
+constexpr int lanes_per_element(int P) { return (P + 1) * (P + 1) > 4 * (P + 1) ? (P + 1) * (P + 1) : 4 * (P + 1); }
 
 template <int P>
 struct Cfg {
@@ -35,7 +38,9 @@ struct Cfg {
   static constexpr int NV = 4;
   static constexpr int N = NV * NP;
   static constexpr int EPW = epw_for(P);
-  static constexpr int NACT = EPW * NP;
+  static constexpr int LPE = lanes_per_element(P);
+  static constexpr int NACT = EPW * LPE;   // lanes with an element slot
+  static constexpr int NPT = EPW * NP;     // lanes that own a solution point
   static constexpr int NT = ((NACT + 63) / 64) * 64;
   static constexpr int NW = NT / 64;
 };
@@ -76,8 +81,9 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   const bool act = tid < C::NACT;
   const int el = tid % EPW;
   const int p = act ? tid / EPW : 0;
+  const bool pt = act && p < NP;            // this lane owns solution point p
   const int e = blockIdx.x * EPW + el;
-  const bool valid = act && e < ne;
+  const bool valid = pt && e < ne;
   const int i = p % N1, j = p / N1;
   const Ops1D& o = a.ops;
   const size_t sstride = (size_t)NP * ne;   // stride between variables in the state layout
@@ -128,7 +134,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
     double fs[NV], ft[NV];
     normal_flux2_rho(qa, rho, sx, sy, a.gas, fs);
     normal_flux2_rho(qa, rho, tx, ty, a.gas, ft);
-    if (act) {
+    if (pt) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         SQ(v, p, el) = qv[v];
@@ -140,7 +146,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   __syncthreads();
 
   if constexpr (VISC) {                     // local gradient (chain rule) at this point
-    if (act) {
+    if (pt) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double dxi = 0.0, deta = 0.0;
@@ -157,7 +163,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   }
 
   if (act) {
-    for (int t = p; t < 4 * N1; t += NP) {
+    for (int t = p; t < 4 * N1; t += C::LPE) {
       const int f = t / N1, k = t % N1;
       const double* w = (f == 0 || f == 2) ? o.lm : o.lp;
       double own[NV], floc[NV];
@@ -286,7 +292,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   __syncthreads();
 
   if constexpr (VISC) {                     // corrected gradient and the viscous point fluxes
-    if (act) {
+    if (pt) {
       double gc[NV][2];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -318,7 +324,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double d = 0.0;
-      if (act) {
+      if (pt) {
         if constexpr (VISC) {             // total flux f_inv - f_vis; the jumps gain the
           double fl0 = 0.0, fl1 = 0.0, gl2 = 0.0, gl3 = 0.0;   // interpolated local viscous flux
 #pragma unroll
@@ -380,12 +386,12 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
     __syncthreads();                      // all reads of s_f / s_g are done
     double* s_fe = s_g;                   // [EPW][N], index p*Nv + v
     double* s_dq = s_f;                   // [EPW][N]
-    if (act) {
+    if (pt) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) s_fe[el * N + p * NV + v] = Fv[v];
     }
     __syncthreads();
-    if (act) {
+    if (tid < C::NPT) {
       const int el2 = tid / NP, p2 = tid % NP;
       const int e2 = blockIdx.x * EPW + el2;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -454,8 +460,9 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_grad(LevelView lv, Ops1D o, cons
   const bool act = tid < C::NACT;
   const int el = tid % EPW;
   const int p = act ? tid / EPW : 0;
+  const bool pt = act && p < NP;
   const int e = blockIdx.x * EPW + el;
-  const bool valid = act && e < ne;
+  const bool valid = pt && e < ne;
   const int i = p % N1, j = p / N1;
   const size_t sstride = (size_t)NP * ne, gp = (size_t)p * ne + e;
   double sx = 1.0, sy = 0.0, tx = 0.0, ty = 1.0, ij = 0.0;
@@ -466,12 +473,12 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_grad(LevelView lv, Ops1D o, cons
     ty = lv.met[3 * sstride + gp];
     ij = lv.met[4 * sstride + gp];
   }
-  if (act) {
+  if (pt) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) s_q[(v * NP + p) * EPW + el] = valid ? q[v * sstride + gp] : 0.0;
   }
   __syncthreads();
-  if (act) {
+  if (pt) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double dxi = 0.0, deta = 0.0;
@@ -486,7 +493,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_grad(LevelView lv, Ops1D o, cons
   }
   __syncthreads();
   if (act && e < ne) {
-    for (int t = p; t < 4 * N1; t += NP) {
+    for (int t = p; t < 4 * N1; t += C::LPE) {
       const int f = t / N1, k = t % N1;
       const double* w = (f == 0 || f == 2) ? o.lm : o.lp;
 #pragma unroll
