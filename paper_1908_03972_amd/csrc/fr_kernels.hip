@@ -21,6 +21,31 @@
 namespace pmg {
 
 constexpr int kPadding = -100;   // neighbour tag of the padding elements of the last workgroup
+// LDS budget of a one-wave sweep workgroup that stages inverse-block columns ahead of its matvec:
+// 8 such workgroups (the 2 waves per SIMD that ~200 VGPRs allow) share a CU's 160 KB
+constexpr int kLdsTarget = 19968;
+
+// Block columns (of n) that fit in `bytes` of LDS when staged 64 chunks of 16 B at a time, cl chunks
+// per column.
+constexpr int staged_columns(int n, int cl, int bytes) {
+  int c = 0;
+  while (c < n && ((c + 1) * cl + 63) / 64 * 1024 <= bytes) ++c;
+  return c;
+}
+
+// Workgroup barrier. A one-wave workgroup needs none: the LDS accesses of a wave complete in
+// program order, so wavefront-scope fences (which order the compiler, and wait for nothing) suffice;
+// in particular they do not wait for the direct global->LDS loads still in flight.
+template <int NT>
+__device__ __forceinline__ void block_sync() {
+  if constexpr (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // Elements per workgroup: small workgroups (64-256 lanes) so that even the coarsest level of a
 // few thousand elements spreads over all 256 CUs. Each element gets max((P+1)^2, 4(P+1)) lanes, so
@@ -67,14 +92,32 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, EPW = C::EPW;
   constexpr int VS = VISC ? 1 : 0;          // viscous LDS arrays exist only when used
   __shared__ double s_q[NV * NP * EPW];
-  __shared__ double s_f[NV * NP * EPW];
-  __shared__ double s_g[NV * NP * EPW];
+  // F~ then G~ in one array: LDS accesses index their variable directly (no selected pointers),
+  // which lets them be told apart from the staged block columns
+  __shared__ double s_fg[2 * NV * NP * EPW];
   __shared__ double s_j[4 * N1 * NV * EPW];
   __shared__ double s_red[C::NW * NV];
+  // the 1-D operators: dynamically indexed, so they would otherwise be global loads from the
+  // argument block in the middle of the kernel, queued behind any block columns being staged
+  __shared__ double s_ops[N1 * N1 + 4 * N1];
   __shared__ double s_gl[VS * NV * 2 * NP * EPW + 1];      // local gradients
   __shared__ double s_jn[VS * 4 * N1 * NV * 2 * EPW + 1];  // (q_com - q) N per flux point
   __shared__ double s_fv[VS * NV * NP * EPW + 1];          // viscous F~v
   __shared__ double s_gv[VS * NV * NP * EPW + 1];          // viscous G~v
+  // FP32 sweeps at P <= 3 stage the first CPF columns of the workgroup's inverse blocks in LDS
+  // with direct global->LDS loads issued in the middle of the residual phase, so that part of
+  // the block stream is in flight while the common fluxes and the divergence are computed
+  constexpr bool PREF = (MODE == 2) && (P == 3) && !VISC && (C::NT == 64);
+  constexpr int BASE_LDS = 8 * (3 * NV * NP * EPW + 4 * N1 * NV * EPW + C::NW * NV + N1 * N1 + 4 * N1) + 64;
+  constexpr int SW_CL = EPW * N / 4;        // 16-B chunks per block column of the workgroup
+  constexpr int CPF = PREF ? staged_columns(N, SW_CL, kLdsTarget - BASE_LDS) : 0;
+  constexpr int SW_CHUNKS = CPF * SW_CL;
+  constexpr int SW_INSTR = (SW_CHUNKS + 63) / 64;
+  __shared__ __align__(16) float s_w[PREF ? SW_INSTR * 256 : 1];
+  // block columns a lane requests before it waits for the first: enough 16-B loads in flight per
+  // wave to cover the memory latency at the one or two waves per SIMD these kernels run at
+  constexpr int MV_UNROLL = (N - CPF) <= 40 ? 40 : 8;
+  constexpr int MV_UNROLL64 = N <= 20 ? 20 : 8;
 
   const int ne = a.lv.ne;
   const int tid = threadIdx.x;
@@ -85,12 +128,26 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
   const int e = blockIdx.x * EPW + el;
   const bool valid = pt && e < ne;
   const int i = p % N1, j = p / N1;
-  const Ops1D& o = a.ops;
+  static_assert(N1 * N1 + 4 * N1 <= C::NT, "one lane per operator entry");
+  double opv = 0.0;                         // this lane's operator entry, stored before the first barrier
+  {
+    // lm, lp, gL, gR follow D in the operator block, each kMaxN1 entries long
+    static_assert(offsetof(Ops1D, lm) == offsetof(Ops1D, D) + 8 * kMaxN1 * kMaxN1 &&
+                      offsetof(Ops1D, gR) == offsetof(Ops1D, lm) + 8 * 3 * kMaxN1,
+                  "operator block layout");
+    const int r = tid - N1 * N1;
+    const int idx = tid < N1 * N1 ? tid : kMaxN1 * kMaxN1 + (r / N1) * kMaxN1 + r % N1;
+    const double* ops = reinterpret_cast<const double*>(reinterpret_cast<const char*>(&a.ops) + offsetof(Ops1D, D));
+    if (tid < N1 * N1 + 4 * N1) opv = ops[idx];
+  }
+  struct {
+    const double *D, *lm, *lp, *gL, *gR;
+  } const o = {s_ops, s_ops + N1 * N1, s_ops + N1 * N1 + N1, s_ops + N1 * N1 + 2 * N1, s_ops + N1 * N1 + 3 * N1};
   const size_t sstride = (size_t)NP * ne;   // stride between variables in the state layout
 
 #define SQ(v, pp, ee) s_q[((v) * NP + (pp)) * EPW + (ee)]
-#define SF(v, pp, ee) s_f[((v) * NP + (pp)) * EPW + (ee)]
-#define SG(v, pp, ee) s_g[((v) * NP + (pp)) * EPW + (ee)]
+#define SF(v, pp, ee) s_fg[((v) * NP + (pp)) * EPW + (ee)]
+#define SG(v, pp, ee) s_fg[((NV + (v)) * NP + (pp)) * EPW + (ee)]
 #define SJ(f, k, v, ee) s_j[(((f) * N1 + (k)) * NV + (v)) * EPW + (ee)]
 #define SGL(v, d, pp, ee) s_gl[((((v) * 2 + (d)) * NP) + (pp)) * EPW + (ee)]
 #define SJN(f, k, v, d, ee) s_jn[(((((f) * N1 + (k)) * NV + (v)) * 2) + (d)) * EPW + (ee)]
@@ -98,9 +155,12 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #define SGV(v, pp, ee) s_gv[((v) * NP + (pp)) * EPW + (ee)]
 
   const size_t gp = (size_t)p * ne + e;     // offset of (v=0, p, e)
+  // every lane loads a state without a branch: lanes without a point of a real element take a
+  // point of the last element (a physical state that keeps their discarded arithmetic finite)
+  const size_t gpl = (size_t)(pt ? p : 0) * ne + (e < ne ? e : ne - 1);
   double qv[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) qv[v] = valid ? a.q[v * sstride + gp] : a.lv.qinf_g[v];
+  for (int v = 0; v < NV; ++v) qv[v] = a.q[v * sstride + gpl];
   double qa[NV];                            // absolute primitive state q_ref + stored offset
 #pragma unroll
   for (int v = 0; v < NV; ++v) qa[v] = a.lv.q_ref[v] + qv[v];
@@ -129,6 +189,38 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       for (int v = 0; v < NV; ++v) sv[v] = a.S[v * sstride + gp];
     }
   }
+  // this lane's flux point of its element's faces (each element has a lane for every one of its
+  // 4 (P+1) flux points): face vector and neighbour, then the neighbour's state along the tensor
+  // line through the point, in flight while the point fluxes are computed. The gathers and the
+  // block-column staging are issued by every lane without a branch, so that the wait for the
+  // gathers in the face phase is a count that leaves the staged columns in flight.
+  static_assert(C::LPE >= 4 * N1, "one lane per flux point");
+  const bool fpt = act && p < 4 * N1;
+  const int f = p / N1, k = p % N1;
+  double nx = (f < 2) ? 1.0 : 0.0, ny = (f < 2) ? 0.0 : 1.0, sm = 1.0;
+  int nb = kPadding, nf = 0, ori = 0;
+  if (fpt && e < ne) {
+    const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
+    nx = a.lv.fvec[fo];
+    ny = a.lv.fvec[fo + ne];
+    sm = a.lv.fvec[fo + 2 * ne];
+    nb = a.lv.nbr[f * ne + e];
+    nf = a.lv.nbf[f * ne + e];
+    ori = a.lv.ori[f * ne + e];
+  }
+  const int kk = ori ? (N1 - 1 - k) : k;
+  double nq[N1][NV];                        // the neighbour's states on the line through the flux point
+  const bool hasn = nb >= 0;                // without a neighbour, any element's values (unused)
+  const int nfc = hasn ? nf : 0;
+  {
+    const int nbc = hasn ? nb : 0, kkc = hasn ? kk : 0;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      const int pp = (nfc < 2) ? (m + N1 * kkc) : (kkc + N1 * m);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) nq[m][v] = a.q[v * sstride + (size_t)pp * ne + nbc];
+    }
+  }
   const double rho = qa[0] / (a.gas.rgas * qa[3]);
   {
     double fs[NV], ft[NV];
@@ -143,7 +235,8 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       }
     }
   }
-  __syncthreads();
+  if (tid < N1 * N1 + 4 * N1) s_ops[tid] = opv;
+  block_sync<C::NT>();
 
   if constexpr (VISC) {                     // local gradient (chain rule) at this point
     if (pt) {
@@ -159,69 +252,81 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
         SGL(v, 1, p, el) = ij * (sy * dxi + ty * deta);
       }
     }
-    __syncthreads();
+    block_sync<C::NT>();
   }
 
-  if (act) {
-    for (int t = p; t < 4 * N1; t += C::LPE) {
-      const int f = t / N1, k = t % N1;
-      const double* w = (f == 0 || f == 2) ? o.lm : o.lp;
-      double own[NV], floc[NV];
+  const double* w = o.lm + ((f == 0 || f == 2) ? 0 : N1);   // lm or lp along this face's lines
+  double own[NV], floc[NV], out[NV];        // own trace, interpolated local flux, outside state
+  {
+    // the neighbour's trace, formed by every lane so that every path has consumed the gathers
+    // before the direct-to-LDS loads below are issued
+    const double* wn = o.lm + ((nfc == 0 || nfc == 2) ? 0 : N1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] += wn[m] * nq[m][v];
+    }
+  }
+  if (fpt) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      own[v] = 0.0;
+      floc[v] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      const int pp = (f < 2) ? (m + N1 * k) : (k + N1 * m);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        own[v] = 0.0;
-        floc[v] = 0.0;
+        own[v] += w[m] * SQ(v, pp, el);
+        floc[v] += w[m] * s_fg[(((f < 2 ? 0 : NV) + v) * NP + pp) * EPW + el];
       }
+    }
+    if (nb >= 0) {                     // interior face: the neighbour's trace formed above
+    } else if (nb == -1) {             // slip wall: reflect the normal velocity
+      const double ua = a.lv.q_ref[1] + own[1], va = a.lv.q_ref[2] + own[2];
+      const double un = ua * nx + va * ny;
+      out[0] = own[0];
+      out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+      out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
+      out[3] = own[3];
+    } else if (nb == -2) {             // far field
 #pragma unroll
-      for (int m = 0; m < N1; ++m) {
-        const int pp = (f < 2) ? (m + N1 * k) : (k + N1 * m);
+      for (int v = 0; v < NV; ++v) out[v] = a.lv.qinf_g[v];
+    } else if (nb == -3) {             // no-slip wall: reverse the velocity
+      out[0] = own[0];
+      out[1] = -(a.lv.q_ref[1] + own[1]) - a.lv.q_ref[1];
+      out[2] = -(a.lv.q_ref[2] + own[2]) - a.lv.q_ref[2];
+      out[3] = own[3];
+    } else {                           // padding element of the last workgroup
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          own[v] += w[m] * SQ(v, pp, el);
-          floc[v] += w[m] * ((f < 2) ? SF(v, pp, el) : SG(v, pp, el));
-        }
-      }
-      double nx = (f < 2) ? 1.0 : 0.0, ny = (f < 2) ? 0.0 : 1.0, sm = 1.0;
-      int nb = kPadding;
-      if (e < ne) {
-        const size_t fo = ((size_t)(f * N1 + k) * 3) * ne + e;
-        nx = a.lv.fvec[fo];
-        ny = a.lv.fvec[fo + ne];
-        sm = a.lv.fvec[fo + 2 * ne];
-        nb = a.lv.nbr[f * ne + e];
-      }
-      double out[NV];
-      if (nb >= 0) {
-        const int nf = a.lv.nbf[f * ne + e];
-        const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
-        const double* wn = (nf == 0 || nf == 2) ? o.lm : o.lp;
+      for (int v = 0; v < NV; ++v) out[v] = own[v];
+    }
+  }
+  if constexpr (PREF) {
+    // The workgroup's part of the first CPF block columns is CPF x EPW N/4 chunks of 16 B,
+    // contiguous per column; wave instruction it stages chunks 64 it .. 64 it + 63 (lane l writes
+    // s_w[4 (64 it + l)], the layout [column][element][row]); lanes past the last chunk and chunks
+    // of elements past the end re-read a valid chunk into the padding or an unused slot. Issued
+    // once the neighbour gathers are consumed: the compiler's wait for any load issued before a
+    // direct-to-LDS load also waits for the latter.
+    const int e0 = blockIdx.x * EPW;
+    const float* wb = static_cast<const float*>(a.W);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) out[v] = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-          const int pp = (nf < 2) ? (m + N1 * kk) : (kk + N1 * m);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) out[v] += wn[m] * a.q[v * sstride + (size_t)pp * ne + nb];
-        }
-      } else if (nb == -1) {             // slip wall: reflect the normal velocity
-        const double ua = a.lv.q_ref[1] + own[1], va = a.lv.q_ref[2] + own[2];
-        const double un = ua * nx + va * ny;
-        out[0] = own[0];
-        out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
-        out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
-        out[3] = own[3];
-      } else if (nb == -2) {             // far field
-#pragma unroll
-        for (int v = 0; v < NV; ++v) out[v] = a.lv.qinf_g[v];
-      } else if (nb == -3) {             // no-slip wall: reverse the velocity
-        out[0] = own[0];
-        out[1] = -(a.lv.q_ref[1] + own[1]) - a.lv.q_ref[1];
-        out[2] = -(a.lv.q_ref[2] + own[2]) - a.lv.q_ref[2];
-        out[3] = own[3];
-      } else {                           // padding element of the last workgroup
-#pragma unroll
-        for (int v = 0; v < NV; ++v) out[v] = own[v];
-      }
+    for (int it = 0; it < SW_INSTR; ++it) {
+      int g = it * 64 + tid;
+      g = g < SW_CHUNKS ? g : SW_CHUNKS - 1;
+      const int c = g / SW_CL, r4 = 4 * (g - c * SW_CL);
+      int ee = e0 + r4 / N;
+      ee = ee < ne ? ee : ne - 1;
+      __builtin_amdgcn_global_load_lds((const void*)(wb + ((size_t)c * ne + ee) * N + r4 % N),
+                                       (void*)(s_w + it * 256), 16, 0, 0);
+    }
+  }
+  if (fpt) {
+    {
       double own_a[NV], out_a[NV], dq[NV], fh[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -257,8 +362,6 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
         if (e < ne) lam = a.lv.lam[(size_t)(f * N1 + k) * ne + e];
         if (nb >= 0) {
           kind = 0;
-          const int nf = a.lv.nbf[f * ne + e];
-          const int kk = a.lv.ori[f * ne + e] ? (N1 - 1 - k) : k;
           const size_t fo = ((size_t)(nf * N1 + kk) * 3) * ne + nb;
           nbx = a.lv.fvec[fo];
           nby = a.lv.fvec[fo + ne];
@@ -289,7 +392,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       }
     }
   }
-  __syncthreads();
+  block_sync<C::NT>();
 
   if constexpr (VISC) {                     // corrected gradient and the viscous point fluxes
     if (pt) {
@@ -311,7 +414,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
         SGV(v, p, el) = tx * fx[v] + ty * fy[v];
       }
     }
-    __syncthreads();
+    block_sync<C::NT>();
   }
 
   double Fv[NV];
@@ -366,7 +469,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) s_red[wave * NV + v] = s2[v];
     }
-    __syncthreads();
+    block_sync<C::NT>();
     if (tid == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -383,14 +486,15 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
       for (int v = 0; v < NV; ++v) a.F[v * sstride + gp] = Fv[v];
     }
   } else {
-    __syncthreads();                      // all reads of s_f / s_g are done
-    double* s_fe = s_g;                   // [EPW][N], index p*Nv + v
-    double* s_dq = s_f;                   // [EPW][N]
+    if constexpr (PREF) __builtin_amdgcn_s_waitcnt(0);   // the staged block columns have landed
+    block_sync<C::NT>();                  // all reads of F~ / G~ are done
+    double* s_fe = s_fg + NV * NP * EPW;  // [EPW][N], index p*Nv + v
+    double* s_dq = s_fg;                  // [EPW][N]
     if (pt) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) s_fe[el * N + p * NV + v] = Fv[v];
     }
-    __syncthreads();
+    block_sync<C::NT>();
     if (tid < C::NPT) {
       const int el2 = tid / NP, p2 = tid % NP;
       const int e2 = blockIdx.x * EPW + el2;
@@ -402,7 +506,16 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
           const float* w0 = static_cast<const float*>(a.W) + (size_t)e2 * N + 4 * p2;
           float accf[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 8
-          for (int c = 0; c < N; ++c) {
+          for (int c = 0; c < CPF; ++c) {
+            const float4 w = *reinterpret_cast<const float4*>(s_w + c * EPW * N + el2 * N + 4 * p2);
+            const float fc = (float)fe[c];
+            accf[0] = fmaf(w.x, fc, accf[0]);
+            accf[1] = fmaf(w.y, fc, accf[1]);
+            accf[2] = fmaf(w.z, fc, accf[2]);
+            accf[3] = fmaf(w.w, fc, accf[3]);
+          }
+#pragma unroll MV_UNROLL
+          for (int c = CPF; c < N; ++c) {
             const float4 w = *reinterpret_cast<const float4*>(w0 + c * cs);
             const float fc = (float)fe[c];
             accf[0] = fmaf(w.x, fc, accf[0]);
@@ -414,7 +527,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
           for (int v = 0; v < 4; ++v) acc[v] = (double)accf[v];
         } else {
           const double* w0 = static_cast<const double*>(a.W) + (size_t)e2 * N + 4 * p2;
-#pragma unroll 4
+#pragma unroll MV_UNROLL64
           for (int c = 0; c < N; ++c) {
             const double2 wa = *reinterpret_cast<const double2*>(w0 + c * cs);
             const double2 wb = *reinterpret_cast<const double2*>(w0 + c * cs + 2);
@@ -429,7 +542,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) s_dq[el2 * N + p2 * NV + v] = acc[v];
     }
-    __syncthreads();
+    block_sync<C::NT>();
     if (valid) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.q_out[v * sstride + gp] = qv[v] + a.alpha * s_dq[el * N + p * NV + v];
