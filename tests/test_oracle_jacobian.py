@@ -67,3 +67,37 @@ def test_block_sparsity_is_line_structured():
             blk = J[:, 4 * p:4 * p + 4, 4 * s:4 * s + 4]
             if k != i and l != j:
                 assert np.max(np.abs(blk)) == 0.0
+
+
+@pytest.mark.parametrize("case", ["periodic", "airfoil", "viscous"])
+def test_patch_block_equals_whole_mesh_block(case):
+    """The block of an element evaluated on its patch (the element and its face neighbours) equals
+    the block from the whole mesh: the property the full-size GPU tests rely on to check sampled
+    elements of meshes too large for the whole-mesh oracle blocks."""
+    from patches import patch_block
+    if case == "periodic":
+        mesh = W.periodic_rect_mesh(7, 5, 10.0, 10.0, jitter=0.1, seed=3)
+        gas, qinf, P = GAS, None, 2
+        lev = FRLevel(mesh, P, gas)
+        vs = W.VortexSpec(length=10.0)
+        q = vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1])
+        picks = [0, 6, 17, 34]
+    else:
+        wall = W.BC_SLIP_WALL if case == "airfoil" else W.BC_NOSLIP_WALL
+        mesh = W.airfoil_o_mesh(12, 4, ratio=1.3, r_far=6.0, wall=wall)
+        fs = W.FreeStreamSpec(ma_inf=0.01)
+        qinf = fs.freestream()
+        gas = G.Gas(gamma=1.4, rgas=1.0, eps_mode="cutoff", ma_inf=0.01, kappa=1.0,
+                    mu=(2e-3 if case == "viscous" else 0.0))
+        P = 2
+        lev = FRLevel(mesh, P, gas, q_inf=qinf)
+        x, y = lev.geo.xy[..., 0], lev.geo.xy[..., 1]
+        q = np.broadcast_to(qinf, x.shape + (4,)).copy()
+        q[..., 0] += 0.5 * np.sin(0.7 * x) * np.cos(0.5 * y)
+        q[..., 1] += 0.2 * np.cos(0.9 * x - 0.4 * y)
+        q[..., 2] += 0.15 * np.sin(0.6 * y + 0.2 * x)
+        picks = [0, 5, 11, 13, 40, 47]            # wall (incl. both trailing-edge sides), interior, far field
+    full = element_blocks(lev, q, 0.3, 2.0)
+    for e in picks:
+        got = patch_block(mesh, gas, P, q, e, 0.3, 2.0, qinf)
+        assert np.array_equal(got, full[e]) or np.max(np.abs(got - full[e])) <= 1e-13 * np.max(np.abs(full[e]))
