@@ -25,7 +25,9 @@ import numpy as np
 from . import gas as G
 from .basis import interpolation_1d, projection_1d
 from .fr import FRLevel
+from .fr3 import FRLevel3
 from .geometry import element_dx
+from .geometry3d import element_dx3
 from .jacobian import element_blocks
 
 
@@ -54,22 +56,28 @@ def esdirk_tableau(name: str) -> np.ndarray:
 
 
 # ---- transfers (Sec. 3, eqs. (39), (42) restriction; (44), (45) prolongation) --------
-def restrict(x, Pf: int, Pc: int):
-    """Tensor-product L2 projection of a [Ne, (Pf+1)^2, Nv] field onto degree Pc."""
-    R1 = projection_1d(Pf, Pc)
-    ne, _, nv = x.shape
-    x4 = x.reshape(ne, Pf + 1, Pf + 1, nv)                  # [e, j, i, v]
-    y4 = np.einsum("bj,ai,ejiv->ebav", R1, R1, x4)
-    return y4.reshape(ne, (Pc + 1) ** 2, nv)
+def _tensor_apply(A1, x, n_in: int, dim=None):
+    """Apply the 1-D matrix A1 along every reference direction of point values x [Ne, n_in^d, Nv]
+    (d = 2 or 3, points ordered with the first direction fastest; d from the point count unless
+    given, which it must be for n_in = 1)."""
+    ne, npts, nv = x.shape
+    d = dim if dim is not None else (2 if npts == n_in ** 2 else 3)
+    n_out = A1.shape[0]
+    if d == 2:
+        y = np.einsum("bj,ai,ejiv->ebav", A1, A1, x.reshape(ne, n_in, n_in, nv))
+        return y.reshape(ne, n_out ** 2, nv)
+    y = np.einsum("ck,bj,ai,ekjiv->ecbav", A1, A1, A1, x.reshape(ne, n_in, n_in, n_in, nv))
+    return y.reshape(ne, n_out ** 3, nv)
 
 
-def prolong(x, Pc: int, Pf: int):
+def restrict(x, Pf: int, Pc: int, dim=None):
+    """Tensor-product L2 projection of a [Ne, (Pf+1)^d, Nv] field onto degree Pc."""
+    return _tensor_apply(projection_1d(Pf, Pc), x, Pf + 1, dim)
+
+
+def prolong(x, Pc: int, Pf: int, dim=None):
     """Tensor-product interpolation of a degree-Pc field at the degree-Pf points."""
-    I1 = interpolation_1d(Pc, Pf)
-    ne, _, nv = x.shape
-    x4 = x.reshape(ne, Pc + 1, Pc + 1, nv)
-    y4 = np.einsum("bj,ai,ejiv->ebav", I1, I1, x4)
-    return y4.reshape(ne, (Pf + 1) ** 2, nv)
+    return _tensor_apply(interpolation_1d(Pc, Pf), x, Pc + 1, dim)
 
 
 @dataclass
@@ -109,7 +117,8 @@ class PMGSolver:
     def __init__(self, mesh, gas: G.Gas, opts: PMGOptions, q_inf=None):
         self.opts = opts
         self.gas = gas
-        self.levels = [FRLevel(mesh, P, gas, q_inf) for P in opts.p_levels]
+        level_cls = FRLevel if mesh.dim == 2 else FRLevel3
+        self.levels = [level_cls(mesh, P, gas, q_inf) for P in opts.p_levels]
         self.D = [None] * len(self.levels)
         self.c_mass = 0.0
         self.src = None
@@ -145,10 +154,11 @@ class PMGSolver:
             return q
         Pf, Pc = o.p_levels[l], o.p_levels[l + 1]
         d = -self.F(l, q, S)                                # d_l = S_l - F_l(q^a), eqs. (38), (41)
-        qb = restrict(q, Pf, Pc)                            # q^b_{l+1}, eqs. (39), (42)
-        S1 = self.F(l + 1, qb) + restrict(d, Pf, Pc)        # S_{l+1}, eqs. (40), (43)
+        dim = self.levels[0].mesh.dim
+        qb = restrict(q, Pf, Pc, dim)                       # q^b_{l+1}, eqs. (39), (42)
+        S1 = self.F(l + 1, qb) + restrict(d, Pf, Pc, dim)   # S_{l+1}, eqs. (40), (43)
         qa1 = self.vcycle(l + 1, qb, S1)
-        q = q + prolong(qa1 - qb, Pc, Pf)                   # q^{c,b}_l, eqs. (44), (45)
+        q = q + prolong(qa1 - qb, Pc, Pf, dim)              # q^{c,b}_l, eqs. (44), (45)
         return self.smooth(l, q, S, o.n_smooth[l])          # q^{c,a}_l
 
     def residual_norm(self, q):
@@ -160,7 +170,7 @@ class PMGSolver:
         dtau_vis = min of (dx/(P+1))^2 / (mu/rho)."""
         lev = self.levels[0]
         if not hasattr(self, "_dx"):
-            self._dx = element_dx(lev.mesh)
+            self._dx = element_dx(lev.mesh) if lev.mesh.dim == 2 else element_dx3(lev.mesh)
         h = (self._dx / (lev.P + 1))[:, None]
         speed = G.sound_speed(q, self.gas) + np.sqrt(np.sum(q[..., 1:-1] ** 2, axis=-1))
         dt = np.min(h / speed)

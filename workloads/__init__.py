@@ -20,6 +20,12 @@ Conventions
 * ``face_nbr_face[e, f]`` is the neighbour's face index and ``face_orient[e, f]``
   is 0 when flux point k meets the neighbour's flux point k, 1 when it meets
   point ``P-k`` (reversed edge direction).
+* Hexahedra (``dim == 3``): node ``a + (g+1)*b + (g+1)^2*c`` sits at
+  ``(-1 + 2a/g, -1 + 2b/g, -1 + 2c/g)``; faces 0/1 = (xi = -1/+1), 2/3 = (eta = -1/+1),
+  4/5 = (zeta = -1/+1). A face's points are indexed (k1, k2) along its two tangential
+  reference directions in increasing order ((eta, zeta), (xi, zeta), (xi, eta)).
+  ``face_orient`` (0..7) maps (k1, k2) to the neighbour's face point: swap the pair if bit 0
+  is set, then reverse the first index (``P - k``) if bit 1 is set and the second if bit 2 is.
 """
 from __future__ import annotations
 
@@ -324,3 +330,155 @@ def viscous_start_state(spec: FreeStreamSpec, xy: np.ndarray, delta: float = 0.0
     q[..., 1] *= ramp
     q[..., 2] *= ramp
     return q
+
+
+# ---- 3-D: cubed sphere (Sec. 4.2's sphere setting at the sizes of the synthetic config) ------
+
+def face_point_map(orient: int, k1, k2, n1: int):
+    """The neighbour's face point (k1', k2') met by point (k1, k2) of a hexahedron face, for the
+    ``face_orient`` code documented above (n1 points per direction)."""
+    a, b = (k2, k1) if orient & 1 else (k1, k2)
+    if orient & 2:
+        a = n1 - 1 - a
+    if orient & 4:
+        b = n1 - 1 - b
+    return a, b
+
+
+_HEX_FACE_CENTER = (12, 14, 10, 16, 4, 22)      # node at the middle of each face (27-node hex)
+
+
+def _hex_face_nodes(f: int) -> np.ndarray:
+    """27-node indices of face f as a 3x3 array [k1][k2] in the face's tangential order."""
+    fixed = (0, 2, 0, 2, 0, 2)[f]
+    out = np.zeros((3, 3), int)
+    for k1 in range(3):
+        for k2 in range(3):
+            if f < 2:
+                a, b, c = fixed, k1, k2
+            elif f < 4:
+                a, b, c = k1, fixed, k2
+            else:
+                a, b, c = k1, k2, fixed
+            out[k1, k2] = a + 3 * b + 9 * c
+    return out
+
+
+def connect_hex_mesh(nodes: np.ndarray, boundary_tag) -> tuple:
+    """Face neighbours, neighbour faces and orientation codes of a conforming 27-node hex mesh, by
+    matching face-centre nodes and then the 3x3 face node grids; ``boundary_tag(e, f)`` gives the
+    tag of faces without a partner."""
+    ne = nodes.shape[0]
+    scale = float(np.max(np.abs(nodes)))
+    centers = nodes[:, list(_HEX_FACE_CENTER)].reshape(ne * 6, 3)
+    keys = np.round(centers / scale * 1e9).astype(np.int64)
+    _, inv, counts = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    if np.any(counts > 2):
+        raise ValueError("more than two faces share a centre")
+    order = np.argsort(inv, kind="stable")
+    nbr = np.zeros(ne * 6, np.int32)
+    nbf = np.zeros(ne * 6, np.int32)
+    ori = np.zeros(ne * 6, np.int32)
+    grids = np.stack([_hex_face_nodes(f) for f in range(6)])          # [6, 3, 3]
+    perms = np.zeros((8, 3, 3, 2), int)
+    for o in range(8):
+        for k1 in range(3):
+            for k2 in range(3):
+                perms[o, k1, k2] = face_point_map(o, k1, k2, 3)
+    sorted_inv = inv[order]
+    starts = np.r_[0, np.nonzero(np.diff(sorted_inv))[0] + 1]
+    ends = np.r_[starts[1:], len(order)]
+    pairs = [(order[a_], order[a_ + 1]) for a_, b_ in zip(starts, ends) if b_ - a_ == 2]
+    singles = [order[a_] for a_, b_ in zip(starts, ends) if b_ - a_ == 1]
+    for x in singles:
+        nbr[x] = boundary_tag(x // 6, x % 6)
+    if pairs:
+        pa = np.array(pairs)
+        for side in (0, 1):
+            me, th = pa[:, side], pa[:, 1 - side]
+            e, f, g, h = me // 6, me % 6, th // 6, th % 6
+            mine = nodes[e[:, None, None], grids[f]]                    # [m, 3, 3, 3]
+            theirs = nodes[g[:, None, None], grids[h]]
+            best = np.full(len(me), -1)
+            for o in range(7, -1, -1):
+                t = theirs[:, perms[o, :, :, 0], perms[o, :, :, 1]]
+                ok = np.all(np.abs(mine - t) <= 1e-9 * scale, axis=(1, 2, 3))
+                best = np.where(ok, o, best)
+            if np.any(best < 0):
+                raise ValueError("face node grids do not match")
+            nbr[me], nbf[me], ori[me] = g, h, best
+    return nbr.reshape(ne, 6), nbf.reshape(ne, 6), ori.reshape(ne, 6)
+
+
+# cube-face frames (t1, t2, n) of the six patches, right-handed (t1 x t2 = n)
+_CUBE_FRAMES = (
+    ((0, 1, 0), (0, 0, 1), (1, 0, 0)),
+    ((0, 0, 1), (0, 1, 0), (-1, 0, 0)),
+    ((0, 0, 1), (1, 0, 0), (0, 1, 0)),
+    ((1, 0, 0), (0, 0, 1), (0, -1, 0)),
+    ((1, 0, 0), (0, 1, 0), (0, 0, 1)),
+    ((0, 1, 0), (1, 0, 0), (0, 0, -1)),
+)
+
+
+def cubed_sphere_mesh(n: int = 16, n_shells: int = 24, ratio: float = 1.1, r_far: float = 20.0,
+                      r_in: float = 1.0, inner: int = BC_SLIP_WALL) -> Mesh:
+    """Equiangular cubed sphere of 27-node hexahedra between radii r_in and r_far.
+
+    Six patches (cube faces) of n x n cells: on a patch with frame (t1, t2, n) the direction of the
+    angles (a, b) in [-pi/4, pi/4]^2 is (n + tan a t1 + tan b t2) normalised (xi along a, eta along
+    b). Radial shells (zeta, outwards): node fractions (ratio^k - 1)/(ratio^n_shells - 1) with k in
+    half steps (first shell height (r_far - r_in)(ratio - 1)/(ratio^n_shells - 1)). Nodes lie on the
+    exact map; zeta = -1 of the first shell is the sphere (tag ``inner``), zeta = +1 of the last
+    shell far field. Element e = i + n (j + n (patch + 6 k)) for cell (i, j) of a patch and shell k.
+    """
+    ang = -0.25 * np.pi + 0.5 * np.pi * np.arange(2 * n + 1) / (2 * n)
+    k_half = np.arange(2 * n_shells + 1) / 2.0
+    rad = r_in + (r_far - r_in) * (ratio ** k_half - 1.0) / (ratio ** n_shells - 1.0)
+    ne = 6 * n * n * n_shells
+    nodes = np.zeros((n_shells, 6, n, n, 3, 3, 3, 3))              # [k, p, j, i, c, b, a, xyz]
+    ta = np.tan(ang)
+    ia = 2 * np.arange(n)[:, None] + np.arange(3)[None, :]         # [cell, node] half-step index
+    for p, (t1, t2, nn) in enumerate(_CUBE_FRAMES):
+        t1, t2, nn = np.array(t1, float), np.array(t2, float), np.array(nn, float)
+        d = (nn[None, None, None, None, :] + ta[ia][None, None, :, :, None] * t1
+             + ta[ia][:, :, None, None, None] * t2)                  # [j, b, i, a, xyz]
+        d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+        r = rad[2 * np.arange(n_shells)[:, None] + np.arange(3)[None, :]]   # [k, c]
+        # -> [k, j, i, c, b, a, xyz]
+        x = r[:, None, None, :, None, None, None] * np.transpose(d, (0, 2, 1, 3, 4))[None, :, :, None, :, :, :]
+        nodes[:, p] = x
+    nodes = nodes.reshape(ne, 27, 3)
+    cells = n * n * 6
+
+    def tag(e, f):
+        if f == 4 and e < cells:
+            return inner
+        if f == 5 and e >= cells * (n_shells - 1):
+            return BC_FAR_FIELD
+        raise ValueError(f"unmatched interior face ({e},{f})")
+
+    nbr, nbf, ori = connect_hex_mesh(nodes, tag)
+    return Mesh(3, 2, nodes, nbr, nbf, ori, name=f"cubed_sphere_{n}x{n}x{n_shells}",
+                info={"ratio": ratio, "r_far": r_far, "r_in": r_in})
+
+
+@dataclass
+class FreeStream3Spec:
+    """Uniform low-Mach free stream along +x (Sec. 4.2 sphere setting): rho = 1, |V| = 1,
+    c = |V|/Ma, R = 1; primitive variables (p, u, v, w, T)."""
+    gamma: float = 1.4
+    rgas: float = 1.0
+    ma_inf: float = 0.001
+
+    def freestream(self) -> np.ndarray:
+        c = 1.0 / self.ma_inf
+        t = c * c / (self.gamma * self.rgas)
+        return np.array([self.rgas * t, 1.0, 0.0, 0.0, t])
+
+
+def sphere_config5(n: int = 16, n_shells: int = 24) -> tuple[Mesh, FreeStream3Spec]:
+    """Inviscid flow at Ma 0.001 past the unit sphere on the 6 x 16 x 16 x 24 cubed sphere."""
+    return cubed_sphere_mesh(n, n_shells), FreeStream3Spec()
+
