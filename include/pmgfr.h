@@ -61,21 +61,30 @@ typedef struct pmg_batch_s* pmg_batch;
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 103
+#define PMG_ABI_VERSION 104
 int32_t pmg_abi_version(void);
 
 /*
- * One P-level of a mesh (Sec. 2.3: FR/CPR on quadrilaterals with tensor-product corrections).
- * All arrays are host memory and are deep-copied; the descriptor may be freed after the call.
- *   dim          2 (quadrilaterals). 3 is reserved and rejected with PMG_E_ARG.
- *   P            solution degree, 0..6 (element blocks need P <= 4).
- *   geom_order   1 (bilinear, 4 nodes) or 2 (biquadratic, 9 nodes).
- *   nodes        [Ne][(g+1)^2][2] geometry nodes in tensor order, xi fastest, at reference
- *                coordinates (-1 + 2a/g, -1 + 2b/g).
- *   face_nbr     [Ne][4] neighbour element across faces (xi=-1, xi=+1, eta=-1, eta=+1), or a
- *                negative PMG_BC_* tag.
- *   face_nbr_face[Ne][4] the neighbour's face index (ignored for boundary faces).
- *   face_orient  [Ne][4] 0 if flux point k meets the neighbour's point k, 1 if point P-k.
+ * One P-level of a mesh (Sec. 2.3: FR/CPR on quadrilaterals or hexahedra with tensor-product
+ * corrections). All arrays are host memory and are deep-copied; the descriptor may be freed after
+ * the call.
+ *   dim          2 (quadrilaterals) or 3 (hexahedra: inviscid, P <= 2, slip wall and far field,
+ *                primitive variables (p, u, v, w, T), Nv = 5).
+ *   P            solution degree, 0..6 in 2-D (element blocks need P <= 4), 0..2 in 3-D.
+ *   geom_order   1 (bilinear / trilinear) or 2 (9-node / 27-node quadratic).
+ *   nodes        2-D [Ne][(g+1)^2][2], 3-D [Ne][(g+1)^3][3] geometry nodes in tensor order, xi
+ *                fastest, at reference coordinates (-1 + 2a/g, -1 + 2b/g[, -1 + 2c/g]).
+ *   face_nbr     [Ne][2 dim] neighbour element across faces (xi=-1, xi=+1, eta=-1, eta=+1[,
+ *                zeta=-1, zeta=+1]), or a negative PMG_BC_* tag.
+ *   face_nbr_face[Ne][2 dim] the neighbour's face index (ignored for boundary faces).
+ *   face_orient  2-D [Ne][4]: 0 if flux point k meets the neighbour's point k, 1 if point P-k.
+ *                3-D [Ne][6]: a hexahedron face's points are (k1, k2) along its two tangential
+ *                reference directions in increasing order ((eta, zeta), (xi, zeta), (xi, eta)); the
+ *                code (0..7) maps (k1, k2) to the neighbour's face point: swap the pair if bit 0 is
+ *                set, then reverse the first index (P - k) if bit 1 is set and the second if bit 2.
+ *                3-D metric terms are taken in the conservative curl form (Gauss-Lobatto
+ *                interpolant of X_l grad X_m), which keeps a uniform flow exactly uniform on curved
+ *                elements for P >= 1.
  *   gamma, rgas  ratio of specific heats and gas constant (eqs. (1)-(6), ideal gas).
  *   eps_mode     reference velocity U_r = eps c of eq. (11): 0 = eps = min(1, Ma) (cut-off
  *                off), 1 = eps = min(1, max(kappa Ma_inf, Ma)).
@@ -121,12 +130,13 @@ pmg_status pmg_level_destroy(pmg_level L);
 /* info[0..7] = dim, P, Np, Nv, n (= Nv Np, the element block size), Ne, device, geom_order. */
 pmg_status pmg_level_info(pmg_level L, int32_t* info);
 
-/* Physical solution-point coordinates, host output double[2][Np][Ne] (x then y). */
+/* Physical solution-point coordinates, host output double[dim][Np][Ne] (x, y[, z]). */
 pmg_status pmg_level_points(pmg_level L, double* xy_host);
 
 /* Element length scale of eqs. (32)-(33), host output double[Ne]: twice the smallest distance from
  * the element's area centroid (6x6 Gauss rule on the exact mapping) to its four faces, each face
- * taken as the segment between its two corner nodes. */
+ * taken as the segment between its two corner nodes; in 3-D from the volume centroid (5^3 Gauss
+ * rule) to the six face planes (through the face's centre node, normal to its corner diagonals). */
 pmg_status pmg_level_dx(pmg_level L, double* dx_host);
 
 /* pmg_dtau_min — the pseudo-time scale of eq. (33) at state q (device, stored form [Nv][Np][Ne]):

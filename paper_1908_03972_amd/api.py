@@ -17,7 +17,7 @@ def _stream(stream=None) -> C.c_void_p:
 
 
 class Level:
-    """One P-level of a quadrilateral mesh (a ``pmg_level`` handle)."""
+    """One P-level of a quadrilateral or hexahedral mesh (a ``pmg_level`` handle)."""
 
     def __init__(self, mesh, P: int, *, gamma: float = 1.4, rgas: float = 1.0, eps_mode: int = 0,
                  ma_inf: float = 0.0, kappa: float = 1.0, q_inf=None, q_ref=None, device: int = 0,
@@ -42,7 +42,6 @@ class Level:
         if q_ref is not None:
             qr[:len(q_ref)] = q_ref
         d.q_ref = (C.c_double * 5)(*qr)
-        self.q_ref = qr[:4].copy()
         d.device = device
         d.mu, d.prandtl, d.br2_penalty = mu, prandtl, br2_penalty
         h = A.pmg_level()
@@ -52,11 +51,12 @@ class Level:
         A.check(lib.pmg_level_info(h, info), "pmg_level_info")
         self.dim, self.P, self.np, self.nv, self.n, self.ne, self.device, self.geom_order = list(info)
         self.shape = (self.nv, self.np, self.ne)
+        self.q_ref = qr[:self.nv].copy()
         self.torch_device = torch.device("cuda", self.device)
 
     def points(self) -> np.ndarray:
-        """Solution-point coordinates [2, Np, Ne]."""
-        out = np.empty((2, self.np, self.ne))
+        """Solution-point coordinates [dim, Np, Ne]."""
+        out = np.empty((self.dim, self.np, self.ne))
         A.check(A.lib().pmg_level_points(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))),
                 "pmg_level_points")
         return out
@@ -157,12 +157,16 @@ def ejacobi_sweep(level: Level, factors: Factors, q, n_sweeps: int, src=None, S=
                                   _stream(stream)), "ejacobi_sweep")
 
 
-def pmg_restrict(fine: Level, coarse: Level, x_f, x_c, nvar: int = 4, stream=None):
+def pmg_restrict(fine: Level, coarse: Level, x_f, x_c, nvar: int | None = None, stream=None):
+    """x_c = restriction of x_f (all Nv variables unless nvar is given)."""
+    nvar = fine.nv if nvar is None else nvar
     A.check(A.lib().pmg_restrict(fine.handle, coarse.handle, fine.check_state(x_f, "x_f", False),
                                  coarse.check_state(x_c, "x_c", False), nvar, _stream(stream)), "pmg_restrict")
 
 
-def pmg_prolong(coarse: Level, fine: Level, dx_c, x_f, nvar: int = 4, stream=None):
+def pmg_prolong(coarse: Level, fine: Level, dx_c, x_f, nvar: int | None = None, stream=None):
+    """x_f += prolongation of dx_c (all Nv variables unless nvar is given)."""
+    nvar = fine.nv if nvar is None else nvar
     A.check(A.lib().pmg_prolong(coarse.handle, fine.handle, coarse.check_state(dx_c, "dx_c", False),
                                 fine.check_state(x_f, "x_f", False), nvar, _stream(stream)), "pmg_prolong")
 

@@ -293,10 +293,100 @@ const char* pmg_last_error(void) { return g_error.c_str(); }
 
 int32_t pmg_abi_version(void) { return PMG_ABI_VERSION; }
 
+// A hexahedral level (dim = 3): P <= 2, inviscid, slip-wall and far-field boundaries, face
+// orientation codes 0..7 (see the header).
+static pmg_status create_hex_level(const pmg_level_desc* d, pmg_level* out) {
+  if (d->P < 0 || d->P > 2) return fail(PMG_E_ARG, "3-D levels support P in 0..2");
+  if (d->geom_order != 1 && d->geom_order != 2) return fail(PMG_E_ARG, "geom_order must be 1 or 2");
+  if (d->n_elements <= 0) return fail(PMG_E_ARG, "n_elements must be positive");
+  if (!d->nodes || !d->face_nbr || !d->face_nbr_face || !d->face_orient) return fail(PMG_E_ARG, "null mesh array");
+  if (!(d->gamma > 1.0) || !(d->rgas > 0.0)) return fail(PMG_E_ARG, "gamma must exceed 1 and rgas be positive");
+  if (d->eps_mode != 0 && d->eps_mode != 1) return fail(PMG_E_ARG, "eps_mode must be 0 or 1");
+  if (d->mu != 0.0) return fail(PMG_E_ARG, "3-D levels are inviscid (mu must be 0)");
+  const int ne = d->n_elements;
+  for (int k = 0; k < 6 * ne; ++k) {
+    const int nb = d->face_nbr[k];
+    if (nb >= ne || nb < PMG_BC_FAR_FIELD) return fail(PMG_E_ARG, "face_nbr entry out of range (3-D: >= -2)");
+    if (nb >= 0 && (d->face_nbr_face[k] < 0 || d->face_nbr_face[k] > 5))
+      return fail(PMG_E_ARG, "face_nbr_face entry out of range");
+    if (d->face_orient[k] < 0 || d->face_orient[k] > 7) return fail(PMG_E_ARG, "face_orient must be in 0..7");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || d->device < 0 || d->device >= ndev)
+    return fail(PMG_E_ARG, "invalid HIP device ordinal");
+  DeviceGuard guard(d->device);
+  if (!guard.ok) return fail(PMG_E_HIP, "hipSetDevice failed");
+
+  pmg_level_s* L = new pmg_level_s();
+  L->dim = 3;
+  L->P = d->P;
+  L->n1 = d->P + 1;
+  L->np = L->n1 * L->n1 * L->n1;
+  L->nv = 5;
+  L->n = L->nv * L->np;
+  L->npad = (L->n + 3) / 4 * 4;
+  L->ne = ne;
+  L->geom_order = d->geom_order;
+  L->device = d->device;
+  L->gas.gamma = d->gamma;
+  L->gas.rgas = d->rgas;
+  L->gas.cp = d->gamma * d->rgas / (d->gamma - 1.0);
+  L->gas.ma_inf = d->ma_inf;
+  L->gas.kappa = d->kappa;
+  L->gas.eps_mode = d->eps_mode;
+  for (int k = 0; k < 5; ++k) {
+    L->q_inf[k] = d->q_inf[k];
+    L->q_ref[k] = d->q_ref[k];
+  }
+  build_ops(d->P, L->ops, L->x1, L->w1);
+  std::vector<double> met, fvec, dx;
+  const std::string why = pmg::build_hex_geometry(d->nodes, ne, d->geom_order, d->P, L->x1, met, fvec, L->xy_host, dx);
+  if (!why.empty()) {
+    free_level(L);
+    return fail(PMG_E_ARG, why);
+  }
+  L->dx_host = dx;
+  std::vector<double> hdx(ne);
+  for (int e = 0; e < ne; ++e) hdx[e] = dx[e] / L->n1;
+  std::vector<int> nbr((size_t)6 * ne), nbf((size_t)6 * ne), ori((size_t)6 * ne);
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < 6; ++f) {
+      nbr[(size_t)f * ne + e] = d->face_nbr[6 * e + f];
+      nbf[(size_t)f * ne + e] = d->face_nbr_face[6 * e + f];
+      ori[(size_t)f * ne + e] = d->face_orient[6 * e + f];
+    }
+  pmg_status s = PMG_OK;
+  if ((s = upload(&L->met, met)) || (s = upload(&L->fvec, fvec)) || (s = upload(&L->nbr, nbr)) ||
+      (s = upload(&L->nbf, nbf)) || (s = upload(&L->ori, ori)) || (s = upload(&L->hdx, hdx))) {
+    free_level(L);
+    return s;
+  }
+  const size_t ns = L->state_elems();
+  L->part_blocks = pmg::residual_blocks(*L);
+  if ((s = alloc_zero(&L->wq, ns)) || (s = alloc_zero(&L->wF, ns)) || (s = alloc_zero(&L->wS, ns)) ||
+      (s = alloc_zero(&L->wqb, ns)) || (s = alloc_zero(&L->wql, ns)) || (s = alloc_zero(&L->wsrc, ns)) ||
+      (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
+      (s = alloc_zero(&L->dtpart, pmg::dtau_blocks(*L))) || (s = alloc_zero(&L->dtmin, 1))) {
+    free_level(L);
+    return s;
+  }
+  if (hipMalloc(&L->flag, sizeof(int)) != hipSuccess) {
+    free_level(L);
+    return fail(PMG_E_NOMEM, "hipMalloc failed for the fault flag");
+  }
+  if (hipMemset(L->flag, 0, sizeof(int)) != hipSuccess) {
+    free_level(L);
+    return fail(PMG_E_HIP, "hipMemset fault flag");
+  }
+  *out = L;
+  return PMG_OK;
+}
+
 pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   if (!d || !out) return fail(PMG_E_ARG, "null descriptor or output");
   *out = nullptr;
-  if (d->dim != 2) return fail(PMG_E_ARG, "only dim = 2 (quadrilaterals) is supported");
+  if (d->dim == 3) return create_hex_level(d, out);
+  if (d->dim != 2) return fail(PMG_E_ARG, "dim must be 2 (quadrilaterals) or 3 (hexahedra)");
   if (d->P < 0 || d->P > 6) return fail(PMG_E_ARG, "P must be in 0..6");
   if (d->geom_order != 1 && d->geom_order != 2) return fail(PMG_E_ARG, "geom_order must be 1 or 2");
   if (d->n_elements <= 0) return fail(PMG_E_ARG, "n_elements must be positive");
@@ -329,6 +419,7 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   L->np = L->n1 * L->n1;
   L->nv = 4;
   L->n = L->nv * L->np;
+  L->npad = L->n;
   L->ne = ne;
   L->geom_order = d->geom_order;
   L->device = d->device;
@@ -525,11 +616,12 @@ pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) 
   if (!out) return fail(PMG_E_ARG, "null output");
   if (precision != 32 && precision != 64) return fail(PMG_E_ARG, "precision must be 32 or 64");
   if (L->P > 4) return fail(PMG_E_ARG, "element blocks are supported for P <= 4");
+  if (L->dim == 3 && L->P > 2) return fail(PMG_E_ARG, "3-D element blocks are supported for P <= 2");
   DeviceGuard guard(L->device);
   pmg_factors_s* F = new pmg_factors_s();
   F->L = L;
   F->precision = precision;
-  F->bytes = (size_t)L->n * L->n * L->ne * (precision / 8);
+  F->bytes = (size_t)L->n * L->npad * L->ne * (precision / 8);
   if (hipMalloc(&F->W, F->bytes) != hipSuccess) {
     delete F;
     return fail(PMG_E_NOMEM, "hipMalloc failed for element blocks");

@@ -1,0 +1,918 @@
+// Hexahedral (3-D) kernels: FR/CPR residual and fused element-Jacobi sweep, element blocks and
+// their inverses, P-level transfers and pointwise helpers.
+//
+// Layouts (Ne elements, Np = (P+1)^3 points p = i + (P+1) j + (P+1)^2 k, Nv = 5 variables):
+//   state            [Nv][Np][Ne]
+//   metrics          [10][Np][Ne]: J grad xi^d (component n at 3 d + n), then 1/|J|
+//   face data        [6][(P+1)^2][4][Ne]: unit +xi^(f/2) normal and its length |S|, face point
+//                    k1 + (P+1) k2 along the face's tangential directions ((eta, zeta), (xi, zeta),
+//                    (xi, eta))
+//   inverse blocks   [n][Ne][npad]: W[c][e][r] = D_e^{-1}[r][c], rows padded to npad = 4 ceil(n/4)
+//
+// The fused sweep follows the 2-D kernel: one lane per solution point and per face point of its
+// element; point and face loads first, then the neighbour gathers (branch-free), point fluxes
+// F~_d = f . (J grad xi^d) to LDS, the common flux of eq. (21) per face point, the divergence with
+// the g_DG corrections of eq. (20) along the three tensor lines, and for a sweep the matvec with
+// the element's inverse block, float4 loads over four consecutive rows.
+#include "internal.hpp"
+#include "physics3.hpp"
+
+namespace pmg {
+
+constexpr int kPad3 = -100;   // neighbour tag of the padding elements of the last workgroup
+
+constexpr int epw3_for(int P) { return P == 0 ? 10 : P == 1 ? 2 : 1; }
+
+template <int P>
+struct Cfg3 {
+  static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
+  static constexpr int NPAD = (N + 3) / 4 * 4;
+  static constexpr int EPW = epw3_for(P);
+  static constexpr int LPE = NP > 6 * NF ? NP : 6 * NF;   // lanes per element
+  static constexpr int NACT = EPW * LPE;
+  static constexpr int NT = ((NACT + 63) / 64) * 64;
+  static constexpr int NW = NT / 64;
+  static constexpr int MVL = NPAD / 4;                     // matvec lanes per element
+};
+
+struct ResArgs3 {
+  LevelView lv;
+  Ops1D ops;
+  GasParams gas;
+  const double* q;
+  const double* src;
+  const double* S;
+  double c_mass;
+  double* F;
+  double* part;
+  const void* W;
+  double alpha;
+  double* q_out;
+};
+
+// solution point m of the tensor line through face point (k1, k2) of face f (m along the normal)
+__device__ __forceinline__ int line_point3(int f, int k1, int k2, int m, int n1) {
+  if (f < 2) return m + n1 * (k1 + n1 * k2);
+  if (f < 4) return k1 + n1 * (m + n1 * k2);
+  return k1 + n1 * (k2 + n1 * m);
+}
+
+// the neighbour's face point met by (k1, k2): swap (bit 0), reverse first (bit 1), second (bit 2)
+__device__ __forceinline__ void orient3(int o, int k1, int k2, int n1, int& a, int& b) {
+  a = (o & 1) ? k2 : k1;
+  b = (o & 1) ? k1 : k2;
+  if (o & 2) a = n1 - 1 - a;
+  if (o & 4) b = n1 - 1 - b;
+}
+
+template <int NT>
+__device__ __forceinline__ void sync3() {
+  if constexpr (NT == 64) {   // one wave: its LDS accesses complete in program order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// MODE 0: residual; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
+template <int P, int MODE>
+__global__ void __launch_bounds__(Cfg3<P>::NT) k_fr3(ResArgs3 a) {
+  using C = Cfg3<P>;
+  constexpr int N1 = C::N1, NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, EPW = C::EPW;
+  __shared__ double s_q[NV * NP * EPW];
+  __shared__ double s_fgh[3 * NV * NP * EPW];
+  __shared__ double s_j[6 * NF * NV * EPW];
+  __shared__ double s_ops[N1 * N1 + 4 * N1];
+  __shared__ double s_red[C::NW * NV];
+  __shared__ double s_mv[(MODE == 0) ? 1 : 2 * NPAD * EPW];   // F of the element, then D^{-1} F
+
+  const int ne = a.lv.ne;
+  const int tid = threadIdx.x;
+  const bool act = tid < C::NACT;
+  const int el = tid % EPW;
+  const int p = act ? tid / EPW : 0;
+  const bool pt = act && p < NP;
+  const int e = blockIdx.x * EPW + el;
+  const bool valid = pt && e < ne;
+  const int i = p % N1, j = (p / N1) % N1, k = p / (N1 * N1);
+  const size_t sstride = (size_t)NP * ne;
+  static_assert(N1 * N1 + 4 * N1 <= C::NT, "one lane per operator entry");
+  double opv = 0.0;
+  {
+    const int r = tid - N1 * N1;
+    const int idx = tid < N1 * N1 ? tid : kMaxN1 * kMaxN1 + (r / N1) * kMaxN1 + r % N1;
+    const double* ops = reinterpret_cast<const double*>(reinterpret_cast<const char*>(&a.ops) + offsetof(Ops1D, D));
+    if (tid < N1 * N1 + 4 * N1) opv = ops[idx];
+  }
+  struct {
+    const double *D, *lm, *lp, *gL, *gR;
+  } const o = {s_ops, s_ops + N1 * N1, s_ops + N1 * N1 + N1, s_ops + N1 * N1 + 2 * N1, s_ops + N1 * N1 + 3 * N1};
+
+#define SQ(v, pp, ee) s_q[((v) * NP + (pp)) * EPW + (ee)]
+#define SF(d, v, pp, ee) s_fgh[(((d) * NV + (v)) * NP + (pp)) * EPW + (ee)]
+#define SJ(f, kf, v, ee) s_j[(((f) * NF + (kf)) * NV + (v)) * EPW + (ee)]
+
+  // point operands (every lane loads a state; lanes without a point of a real element take a point
+  // of the last element)
+  const size_t gp = (size_t)p * ne + e;
+  const size_t gpl = (size_t)(pt ? p : 0) * ne + (e < ne ? e : ne - 1);
+  double qv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qv[v] = a.q[v * sstride + gpl];
+  double mt[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+  double ij = 0.0;
+  double srcv[NV], sv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) srcv[v] = sv[v] = 0.0;
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) mt[c] = a.lv.met[c * sstride + gp];
+    ij = a.lv.met[9 * sstride + gp];
+    if (a.src) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) srcv[v] = a.src[v * sstride + gp];
+    }
+    if (a.S) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sv[v] = a.S[v * sstride + gp];
+    }
+  }
+  // this lane's face point: face data, neighbour, and the neighbour's line of states
+  const bool fpt = act && p < 6 * NF;
+  const int f = p / NF, kf = p % NF, k1 = kf % N1, k2 = kf / N1;
+  double nx = 1.0, ny = 0.0, nz = 0.0, sm = 1.0;
+  int nb = kPad3, nf = 0, ori = 0;
+  if (fpt && e < ne) {
+    const size_t fo = ((size_t)(f * NF + kf) * 4) * ne + e;
+    nx = a.lv.fvec[fo];
+    ny = a.lv.fvec[fo + ne];
+    nz = a.lv.fvec[fo + 2 * ne];
+    sm = a.lv.fvec[fo + 3 * ne];
+    nb = a.lv.nbr[f * ne + e];
+    nf = a.lv.nbf[f * ne + e];
+    ori = a.lv.ori[f * ne + e];
+  }
+  const bool hasn = nb >= 0;
+  const int nbc = hasn ? nb : 0, nfc = hasn ? nf : 0;
+  int na, nbb;
+  orient3(hasn ? ori : 0, k1, k2, N1, na, nbb);
+  double nq[N1][NV];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    const int pp = line_point3(nfc, na, nbb, m, N1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) nq[m][v] = a.q[v * sstride + (size_t)pp * ne + nbc];
+  }
+
+  double qa[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qa[v] = a.lv.q_ref[v] + qv[v];
+  const double rho = qa[0] / (a.gas.rgas * qa[4]);
+  {
+    double fl[3][NV];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) normal_flux3_rho(qa, rho, mt[3 * d], mt[3 * d + 1], mt[3 * d + 2], a.gas, fl[d]);
+    if (pt) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        SQ(v, p, el) = qv[v];
+        SF(0, v, p, el) = fl[0][v];
+        SF(1, v, p, el) = fl[1][v];
+        SF(2, v, p, el) = fl[2][v];
+      }
+    }
+  }
+  if (tid < N1 * N1 + 4 * N1) s_ops[tid] = opv;
+  sync3<C::NT>();
+
+  // face phase: common flux minus the interpolated local flux at every face point
+  {
+    double out[NV];
+    {
+      const double* wn = o.lm + ((nfc % 2 == 0) ? 0 : N1);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] += wn[m] * nq[m][v];
+      }
+    }
+    if (fpt) {
+      const int d = f / 2;
+      const double* w = o.lm + ((f % 2 == 0) ? 0 : N1);
+      double own[NV], floc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) own[v] = floc[v] = 0.0;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+        const int pp = line_point3(f, k1, k2, m, N1);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          own[v] += w[m] * SQ(v, pp, el);
+          floc[v] += w[m] * s_fgh[((d * NV + v) * NP + pp) * EPW + el];
+        }
+      }
+      if (nb >= 0) {
+      } else if (nb == -1) {             // slip wall: reflect the normal velocity
+        const double ua = a.lv.q_ref[1] + own[1], va = a.lv.q_ref[2] + own[2], wa = a.lv.q_ref[3] + own[3];
+        const double un = ua * nx + va * ny + wa * nz;
+        out[0] = own[0];
+        out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+        out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
+        out[3] = wa - 2.0 * un * nz - a.lv.q_ref[3];
+        out[4] = own[4];
+      } else if (nb == -2) {             // far field
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = a.lv.qinf_g[v];
+      } else {                           // padding element of the last workgroup
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = own[v];
+      }
+      double own_a[NV], out_a[NV], dq[NV], fh[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        own_a[v] = a.lv.q_ref[v] + own[v];
+        out_a[v] = a.lv.q_ref[v] + out[v];
+      }
+      if (f % 2 == 0) {                  // the neighbour is the '-' side
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
+        common_flux3(out_a, own_a, dq, nx, ny, nz, sm, a.gas, fh);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
+        common_flux3(own_a, out_a, dq, nx, ny, nz, sm, a.gas, fh);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) SJ(f, kf, v, el) = fh[v] - floc[v];
+    }
+  }
+  sync3<C::NT>();
+
+  double Fv[NV];
+  {
+    double qc[NV];
+    conservative3(qa, a.gas, qc);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double dv = 0.0;
+      if (pt) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          dv += o.D[i * N1 + m] * SF(0, v, m + N1 * (j + N1 * k), el);
+          dv += o.D[j * N1 + m] * SF(1, v, i + N1 * (m + N1 * k), el);
+          dv += o.D[k * N1 + m] * SF(2, v, i + N1 * (j + N1 * m), el);
+        }
+        dv += o.gL[i] * SJ(0, j + N1 * k, v, el) + o.gR[i] * SJ(1, j + N1 * k, v, el);
+        dv += o.gL[j] * SJ(2, i + N1 * k, v, el) + o.gR[j] * SJ(3, i + N1 * k, v, el);
+        dv += o.gL[k] * SJ(4, i + N1 * j, v, el) + o.gR[k] * SJ(5, i + N1 * j, v, el);
+      }
+      const double fv = -dv * ij - a.c_mass * qc[v] + srcv[v] - sv[v];
+      Fv[v] = valid ? fv : 0.0;
+    }
+  }
+
+  if (a.part) {   // per-workgroup sums of F^2 per variable (fixed order, no atomics)
+    double s2[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s2[v] = Fv[v] * Fv[v];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s2[v] += __shfl_xor(s2[v], off, 64);
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_red[wave * NV + v] = s2[v];
+    }
+    sync3<C::NT>();
+    if (tid == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double t = 0.0;
+        for (int w = 0; w < C::NW; ++w) t += s_red[w * NV + v];
+        a.part[(size_t)blockIdx.x * NV + v] = t;
+      }
+    }
+  }
+
+  if constexpr (MODE == 0) {
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.F[v * sstride + gp] = Fv[v];
+    }
+  } else {
+    double* s_fe = s_mv;                  // [EPW][NPAD], index p Nv + v (padding rows zero)
+    double* s_dq = s_mv + NPAD * EPW;
+    if (pt) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_fe[el * NPAD + p * NV + v] = Fv[v];
+    }
+    if constexpr (NPAD > N) {
+      if (tid < EPW * (NPAD - N)) s_fe[(tid / (NPAD - N)) * NPAD + N + tid % (NPAD - N)] = 0.0;
+    }
+    sync3<C::NT>();
+    if (tid < EPW * C::MVL) {
+      const int el2 = tid / C::MVL, l = tid % C::MVL;
+      const int e2 = blockIdx.x * EPW + el2;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (e2 < ne) {
+        const double* fe = s_fe + el2 * NPAD;
+        const size_t cs = (size_t)ne * NPAD;
+        if constexpr (MODE == 2) {
+          const float* w0 = static_cast<const float*>(a.W) + (size_t)e2 * NPAD + 4 * l;
+          float accf[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+          for (int c = 0; c < N; ++c) {
+            const float4 w = *reinterpret_cast<const float4*>(w0 + c * cs);
+            const float fc = (float)fe[c];
+            accf[0] = fmaf(w.x, fc, accf[0]);
+            accf[1] = fmaf(w.y, fc, accf[1]);
+            accf[2] = fmaf(w.z, fc, accf[2]);
+            accf[3] = fmaf(w.w, fc, accf[3]);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t] = (double)accf[t];
+        } else {
+          const double* w0 = static_cast<const double*>(a.W) + (size_t)e2 * NPAD + 4 * l;
+#pragma unroll 4
+          for (int c = 0; c < N; ++c) {
+            const double2 wa = *reinterpret_cast<const double2*>(w0 + c * cs);
+            const double2 wb = *reinterpret_cast<const double2*>(w0 + c * cs + 2);
+            const double fc = fe[c];
+            acc[0] = fma(wa.x, fc, acc[0]);
+            acc[1] = fma(wa.y, fc, acc[1]);
+            acc[2] = fma(wb.x, fc, acc[2]);
+            acc[3] = fma(wb.y, fc, acc[3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s_dq[el2 * NPAD + 4 * l + t] = acc[t];
+    }
+    sync3<C::NT>();
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.q_out[v * sstride + gp] = qv[v] + a.alpha * s_dq[el * NPAD + p * NV + v];
+    }
+  }
+#undef SQ
+#undef SF
+#undef SJ
+}
+
+// ---- element blocks (eqs. (28)-(30)) and their inverses ----------------------------------
+
+struct JacArgs3 {
+  LevelView lv;
+  Ops1D ops;
+  GasParams gas;
+  const double* q;
+  double inv_dtau;
+  double c_mass;
+  double* D_out;
+  void* W;
+  int precision;
+  int* flag;
+};
+
+// Rows of D_e in registers, S threads per row (S = 1, or 4 for n = 135 padded to 136 with an
+// identity row and column), the Gauss-Jordan elimination of the 2-D kernel: column cycling,
+// unnormalised pivot rows, a 32-bit pivot key (|f|'s upper word with the thread index in its low
+// 10 bits) reduced over each wave with DPP and across waves through LDS.
+template <int P, int S>
+struct Rows3 {
+  static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
+  static constexpr int NJ = (N + S - 1) / S * S;           // rows and columns including padding
+  static constexpr int NPAD = (N + 3) / 4 * 4;             // row stride of the stored inverse
+  static constexpr int H = NJ / S;
+  static constexpr int NW = (S * NJ + 63) / 64;
+  static constexpr int NT = 64 * NW;
+  static_assert(S == 1 || S == 4, "one or four threads per row");
+  static_assert(S * NJ <= 1023, "pivot keys carry the thread index in 10 bits");
+};
+
+__device__ __forceinline__ unsigned wave_max3(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xf, 0xf, false));   // row_ror:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xf, 0xf, false));   // row_ror:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));   // row_ror:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));   // row_ror:8
+  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// a double from a lane of the same quad selected by the DPP quad permutation CTRL
+template <int CTRL>
+__device__ __forceinline__ double quad_dpp(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kQuadFirst = 0x00;   // quad_perm [0,0,0,0]
+constexpr int kQuadNext = 0xF9;    // quad_perm [1,2,3,3]: the next lane of the quad
+
+template <int P, int S>
+__global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
+  using C = Rows3<P, S>;
+  constexpr int N1 = C::N1, NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NJ = C::NJ, H = C::H, NW = C::NW,
+                NT = C::NT, NPAD = C::NPAD;
+  __shared__ double sq[NV * NP];
+  __shared__ double sA[3][NP * NV * NV];     // dF~_d/dq at each point, [(pp NV + v) NV + w]
+  __shared__ double sDg[NP * NV * NV];       // Gamma/dtau + c_mass M at each point
+  __shared__ double sB[6 * NF * NV * NV];    // d(common flux)/d(own trace) at each face point
+  __shared__ double sscl[NJ];
+  __shared__ int sperm[NJ];
+  __shared__ double slot[2][NW][NJ];
+  __shared__ unsigned skey[2][NW];
+
+  const int ne = a.lv.ne;
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const size_t sstride = (size_t)NP * ne;
+  const Ops1D& o = a.ops;
+
+  for (int t = tid; t < NV * NP; t += NT) {
+    const int v = t / NP, pp = t % NP;
+    sq[t] = a.q[v * sstride + (size_t)pp * ne + e];
+  }
+  __syncthreads();
+  // pointwise tasks t = pp NV + w: column w of dF~_d/dq (duals seeded in w) and of the diagonal term
+  for (int t = tid; t < NP * NV; t += NT) {
+    const int pp = t / NV, w = t % NV;
+    Dual<1> qd[NV];
+    double qv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      qv[v] = a.lv.q_ref[v] + sq[v * NP + pp];
+      qd[v] = dconst<1>(qv[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qd[v].d[0] = (v == w) ? 1.0 : 0.0;
+    const size_t gp = (size_t)pp * ne + e;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Dual<1> fl[NV];
+      normal_flux3(qd, a.lv.met[(3 * d) * sstride + gp], a.lv.met[(3 * d + 1) * sstride + gp],
+                   a.lv.met[(3 * d + 2) * sstride + gp], a.gas, fl);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sA[d][(pp * NV + v) * NV + w] = fl[v].d[0];
+    }
+    Dual<1> qc[NV];
+    conservative3(qd, a.gas, qc);
+    const State3<double> s = make_state3(qv, a.gas);
+    double ew[NV], gcol[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ew[v] = (v == w) ? 1.0 : 0.0;
+    gamma_mul3(s, a.gas, ew, gcol);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sDg[(pp * NV + v) * NV + w] = gcol[v] * a.inv_dtau + a.c_mass * qc[v].d[0];
+  }
+  // face tasks t = (f NF + kf) NV + w: column w of the common flux's derivative with respect to the
+  // element's own trace (neighbour trace fixed; wall ghost and far-field state as in the residual)
+  for (int t = tid; t < 6 * NF * NV; t += NT) {
+    const int f = t / (NF * NV), kf = (t / NV) % NF, w = t % NV;
+    const int k1 = kf % N1, k2 = kf / N1;
+    const double* wt = (f % 2 == 0) ? o.lm : o.lp;
+    double ownv[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < N1; ++m) {
+      const int pp = line_point3(f, k1, k2, m, N1);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ownv[v] += wt[m] * sq[v * NP + pp];
+    }
+    Dual<1> own[NV], out[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) own[v] = dconst<1>(ownv[v]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) own[v].d[0] = (v == w) ? 1.0 : 0.0;
+    const size_t fo = ((size_t)(f * NF + kf) * 4) * ne + e;
+    const double nx = a.lv.fvec[fo], ny = a.lv.fvec[fo + ne], nz = a.lv.fvec[fo + 2 * ne],
+                 sm = a.lv.fvec[fo + 3 * ne];
+    const int nb = a.lv.nbr[f * ne + e];
+    if (nb >= 0) {
+      const int nfa = a.lv.nbf[f * ne + e];
+      int na, nbb;
+      orient3(a.lv.ori[f * ne + e], k1, k2, N1, na, nbb);
+      const double* wn = (nfa % 2 == 0) ? o.lm : o.lp;
+      double ov[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int m = 0; m < N1; ++m) {
+        const int pp = line_point3(nfa, na, nbb, m, N1);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ov[v] += wn[m] * a.q[v * sstride + (size_t)pp * ne + nb];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(ov[v]);
+    } else if (nb == -1) {
+      Dual<1> ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2], wa = own[3] + a.lv.q_ref[3];
+      Dual<1> un = ua * nx + va * ny + wa * nz;
+      out[0] = own[0];
+      out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
+      out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
+      out[3] = wa - 2.0 * un * nz - a.lv.q_ref[3];
+      out[4] = own[4];
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.qinf_g[v]);
+    }
+    Dual<1> own_a[NV], out_a[NV], dq[NV], fh[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      own_a[v] = own[v] + a.lv.q_ref[v];
+      out_a[v] = out[v] + a.lv.q_ref[v];
+    }
+    if (f % 2 == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
+      common_flux3(out_a, own_a, dq, nx, ny, nz, sm, a.gas, fh);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
+      common_flux3(own_a, out_a, dq, nx, ny, nz, sm, a.gas, fh);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sB[((f * NF + kf) * NV + v) * NV + w] = fh[v].d[0];
+  }
+  __syncthreads();
+
+  // assembly: a point couples to the points of its three tensor lines
+  const bool has_row = tid < S * NJ;
+  const int r = has_row ? tid / S : 0;
+  const int h = (S > 1) ? (tid % S) : 0;
+  const bool real_row = has_row && r < N;
+  const int pp = real_row ? r / NV : 0, v = r % NV;
+  const int ii = pp % N1, jj = (pp / N1) % N1, kk = pp / (N1 * N1);
+  const double ijac = a.lv.met[9 * sstride + (size_t)pp * ne + e];
+  double row[H];
+#pragma unroll
+  for (int jc = 0; jc < H; ++jc) {
+    const int c = h * H + jc;
+    double dval = 0.0;
+    if (real_row && c < N) {
+      const int ss = c / NV, w = c % NV;
+      const int ai = ss % N1, bj = (ss / N1) % N1, ck = ss / (N1 * N1);
+      double acc = 0.0;
+      if (bj == jj && ck == kk) {
+        const double cx = o.D[ii * N1 + ai] - o.gL[ii] * o.lm[ai] - o.gR[ii] * o.lp[ai];
+        const int kf = jj + N1 * kk;
+        acc += cx * sA[0][(ss * NV + v) * NV + w] + o.gL[ii] * o.lm[ai] * sB[((0 * NF + kf) * NV + v) * NV + w] +
+               o.gR[ii] * o.lp[ai] * sB[((1 * NF + kf) * NV + v) * NV + w];
+      }
+      if (ai == ii && ck == kk) {
+        const double cy = o.D[jj * N1 + bj] - o.gL[jj] * o.lm[bj] - o.gR[jj] * o.lp[bj];
+        const int kf = ii + N1 * kk;
+        acc += cy * sA[1][(ss * NV + v) * NV + w] + o.gL[jj] * o.lm[bj] * sB[((2 * NF + kf) * NV + v) * NV + w] +
+               o.gR[jj] * o.lp[bj] * sB[((3 * NF + kf) * NV + v) * NV + w];
+      }
+      if (ai == ii && bj == jj) {
+        const double cz = o.D[kk * N1 + ck] - o.gL[kk] * o.lm[ck] - o.gR[kk] * o.lp[ck];
+        const int kf = ii + N1 * jj;
+        acc += cz * sA[2][(ss * NV + v) * NV + w] + o.gL[kk] * o.lm[ck] * sB[((4 * NF + kf) * NV + v) * NV + w] +
+               o.gR[kk] * o.lp[ck] * sB[((5 * NF + kf) * NV + v) * NV + w];
+      }
+      dval = acc * ijac;
+      if (pp == ss) dval += sDg[(pp * NV + v) * NV + w];
+    } else if (has_row && !real_row) {
+      dval = (c == r) ? 1.0 : 0.0;                // padding: identity row
+    }
+    row[jc] = dval;
+  }
+  if (a.D_out && real_row) {
+#pragma unroll
+    for (int jc = 0; jc < H; ++jc)
+      if (h * H + jc < N) a.D_out[((size_t)e * N + r) * N + h * H + jc] = row[jc];
+  }
+  double mx = 0.0;
+#pragma unroll
+  for (int jc = 0; jc < H; ++jc) mx = fmax(mx, fabs(row[jc]));
+  if (S == 4) {
+    mx = fmax(mx, __shfl_xor(mx, 1, 64));
+    mx = fmax(mx, __shfl_xor(mx, 2, 64));
+  }
+  int ex = 0;
+  frexp(mx, &ex);
+  const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
+#pragma unroll
+  for (int jc = 0; jc < H; ++jc) row[jc] *= scl;
+  if (has_row && h == 0) sscl[r] = scl;
+
+  bool used = !has_row;
+  int my_step = 0;
+  double my_inv = 1.0;
+  bool bad = false;
+  for (int kstep = 0; kstep < NJ; ++kstep) {
+    const int par = kstep & 1;
+    const double fval = (S == 4) ? quad_dpp<kQuadFirst>(row[0]) : row[0];
+    const unsigned key = (used || h != 0) ? 0u
+                         : ((((unsigned)__double2hiint(fabs(fval))) & ~0x3FFu) | (unsigned)(1023 - tid));
+    const unsigned wkey = wave_max3(key);
+    const int wtid = 1023 - (int)(wkey & 0x3FFu);
+    if (wkey != 0u && tid >= wtid && tid < wtid + S) {
+#pragma unroll
+      for (int jc = 0; jc < H; ++jc) slot[par][wv][h * H + jc] = row[jc];
+    }
+    if (lane == 0) skey[par][wv] = wkey;
+    __syncthreads();
+    int win = 0;
+    unsigned bk = skey[par][0];
+#pragma unroll
+    for (int w2 = 1; w2 < NW; ++w2) {
+      const unsigned k2 = skey[par][w2];
+      win = (k2 > bk) ? w2 : win;
+      bk = (k2 > bk) ? k2 : bk;
+    }
+    int pr_row = (1023 - (int)(bk & 0x3FFu)) / S;
+    if (bk == 0u || pr_row >= NJ) {
+      bad = true;
+      pr_row = (pr_row < NJ && pr_row >= 0) ? pr_row : NJ - 1;
+    }
+    const double* prw = slot[par][win];
+    double piv = prw[0];
+    if (piv == 0.0 || !isfinite(piv)) {
+      bad = true;
+      piv = 1.0;
+    }
+    const double ip = 1.0 / piv;
+    const bool is_p = has_row && (r == pr_row);
+    if (tid == 0) sperm[kstep] = pr_row;
+    const double g = is_p ? 0.0 : fval * ip;
+    if (is_p) {
+      used = true;
+      my_step = kstep;
+      my_inv = ip;
+    }
+    const double nxt = (S == 4) ? quad_dpp<kQuadNext>(row[0]) : 0.0;
+    const double* prh = prw + h * H;
+    constexpr int B = 16;
+#pragma unroll
+    for (int j0 = 0; j0 < H - 1; j0 += B) {
+      double buf[B];
+#pragma unroll
+      for (int jb = 0; jb < B; ++jb)
+        if (j0 + jb < H - 1) buf[jb] = prh[j0 + jb + 1];
+#pragma unroll
+      for (int jb = 0; jb < B; ++jb)
+        if (j0 + jb < H - 1) row[j0 + jb] = fma(-g, buf[jb], row[j0 + jb + 1]);
+    }
+    if (S == 4 && h < S - 1)
+      row[H - 1] = fma(-g, prw[(h + 1) * H], nxt);
+    else
+      row[H - 1] = is_p ? 1.0 : -g;
+  }
+  if (bad) *a.flag = 1;
+  __syncthreads();
+  if (has_row && my_step < N) {
+#pragma unroll
+    for (int jc = 0; jc < H; ++jc) {
+      const int col = sperm[h * H + jc];
+      if (col >= N) continue;
+      const double val = row[jc] * my_inv * sscl[col];
+      const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
+      if (a.precision == 32)
+        static_cast<float*>(a.W)[o_] = (float)val;
+      else
+        static_cast<double*>(a.W)[o_] = val;
+    }
+  }
+}
+
+// ---- transfers and pointwise helpers ----------------------------------------------------------
+
+struct Mat1D3 {
+  double m[kMaxN1 * kMaxN1];
+};
+
+// x_c[v][pc][e] = sum R[c][k] R[b][j] R[a][i] x_f[v][i + nf j + nf^2 k][e]
+__global__ void __launch_bounds__(256) k_restrict3(int ne, int nvar, int nf1, int nc1, Mat1D3 R,
+                                                   const double* __restrict__ xf, double* __restrict__ xc,
+                                                   double* __restrict__ xc2) {
+  const size_t npc = (size_t)nc1 * nc1 * nc1, npf = (size_t)nf1 * nf1 * nf1;
+  const size_t total = (size_t)nvar * npc * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int pc = (int)(rest % npc);
+  const int v = (int)(rest / npc);
+  const int ca = pc % nc1, cb = (pc / nc1) % nc1, cc = pc / (nc1 * nc1);
+  const double* base = xf + (size_t)v * npf * ne + e;
+  double acc = 0.0;
+  for (int k = 0; k < nf1; ++k) {
+    double plane = 0.0;
+    for (int j = 0; j < nf1; ++j) {
+      double line = 0.0;
+      for (int i = 0; i < nf1; ++i) line += R.m[ca * nf1 + i] * base[(size_t)(i + nf1 * (j + nf1 * k)) * ne];
+      plane += R.m[cb * nf1 + j] * line;
+    }
+    acc += R.m[cc * nf1 + k] * plane;
+  }
+  xc[idx] = acc;
+  if (xc2) xc2[idx] = acc;
+}
+
+// x_f[v][pf][e] += sum I[k][c] I[j][b] I[i][a] (xa - xb)[v][a + nc b + nc^2 c][e]
+__global__ void __launch_bounds__(256) k_prolong3(int ne, int nvar, int nc1, int nf1, Mat1D3 I,
+                                                  const double* __restrict__ xa, const double* __restrict__ xb,
+                                                  double* __restrict__ xf) {
+  const size_t npc = (size_t)nc1 * nc1 * nc1, npf = (size_t)nf1 * nf1 * nf1;
+  const size_t total = (size_t)nvar * npf * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int pf = (int)(rest % npf);
+  const int v = (int)(rest / npf);
+  const int fi = pf % nf1, fj = (pf / nf1) % nf1, fk = pf / (nf1 * nf1);
+  const size_t off = (size_t)v * npc * ne + e;
+  double acc = 0.0;
+  for (int c = 0; c < nc1; ++c) {
+    double plane = 0.0;
+    for (int b = 0; b < nc1; ++b) {
+      double line = 0.0;
+      for (int a2 = 0; a2 < nc1; ++a2) {
+        const size_t o = off + (size_t)(a2 + nc1 * (b + nc1 * c)) * ne;
+        const double d = xb ? (xa[o] - xb[o]) : xa[o];
+        line += I.m[fi * nc1 + a2] * d;
+      }
+      plane += I.m[fj * nc1 + b] * line;
+    }
+    acc += I.m[fk * nc1 + c] * plane;
+  }
+  xf[idx] += acc;
+}
+
+struct Ref5 {
+  double v[5];
+};
+
+__global__ void __launch_bounds__(256) k_conservative3(int n_points, GasParams g, Ref5 ref,
+                                                       const double* __restrict__ q, double* __restrict__ qc) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n_points) return;
+  double qv[5], out[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qv[v] = ref.v[v] + q[(size_t)v * n_points + idx];
+  conservative3(qv, g, out);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qc[(size_t)v * n_points + idx] = out[v];
+}
+
+// pseudo-time scale of eq. (33) per solution point, h_e / (c + |v|), as the 2-D kernel
+__global__ void __launch_bounds__(256) k_dtau_partial3(int ne, int np, const double* __restrict__ q,
+                                                       const double* __restrict__ hdx, Ref5 ref, double gr,
+                                                       double* __restrict__ part) {
+  __shared__ double red[256];
+  const size_t total = (size_t)np * ne, st = total;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double val = 1.0e300;
+  if (i < total) {
+    const int e = (int)(i % (size_t)ne);
+    const double u = q[st + i] + ref.v[1], v = q[2 * st + i] + ref.v[2], w = q[3 * st + i] + ref.v[3];
+    const double t = q[4 * st + i] + ref.v[4];
+    const double speed = sqrt(gr * t) + sqrt(u * u + v * v + w * w);
+    const double h = hdx[e] / speed;
+    val = (t > 0.0 && h > 0.0 && h < 1.0e300) ? h : -1.0;
+  }
+  red[threadIdx.x] = val;
+  __syncthreads();
+  for (int w2 = 128; w2 > 0; w2 >>= 1) {
+    if ((int)threadIdx.x < w2) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---- launchers -------------------------------------------------------------------------------
+
+static unsigned blocks3(size_t n) { return (unsigned)((n + 255) / 256); }
+
+int residual_blocks3(const pmg_level_s& L) {
+  const int epw = epw3_for(L.P);
+  return (L.ne + epw - 1) / epw;
+}
+
+template <int P, int MODE>
+static hipError_t launch_fr3_p(const ResArgs3& a, int ne, hipStream_t st) {
+  using C = Cfg3<P>;
+  const int blocks = (ne + C::EPW - 1) / C::EPW;
+  hipLaunchKernelGGL((k_fr3<P, MODE>), dim3(blocks), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_fr3(int P, const ResArgs3& a, int ne, hipStream_t st) {
+  switch (P) {
+    case 0: return launch_fr3_p<0, MODE>(a, ne, st);
+    case 1: return launch_fr3_p<1, MODE>(a, ne, st);
+    case 2: return launch_fr3_p<2, MODE>(a, ne, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static ResArgs3 base_args3(const pmg_level_s& L) {
+  ResArgs3 a{};
+  a.lv = L.view();
+  a.ops = L.ops;
+  a.gas = L.gas;
+  return a;
+}
+
+hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double* src, const double* S,
+                            double c_mass, double* F, bool want_norms, hipStream_t st) {
+  ResArgs3 a = base_args3(L);
+  a.q = q;
+  a.src = src;
+  a.S = S;
+  a.c_mass = c_mass;
+  a.F = F;
+  a.part = want_norms ? L.part : nullptr;
+  return launch_fr3<0>(L.P, a, L.ne, st);
+}
+
+hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                         const double* src, const double* S, double c_mass, double alpha, bool want_norms,
+                         hipStream_t st) {
+  ResArgs3 a = base_args3(L);
+  a.q = q_in;
+  a.src = src;
+  a.S = S;
+  a.c_mass = c_mass;
+  a.part = want_norms ? L.part : nullptr;
+  a.W = fac.W;
+  a.alpha = alpha;
+  a.q_out = q_out;
+  if (fac.precision == 32) return launch_fr3<2>(L.P, a, L.ne, st);
+  return launch_fr3<1>(L.P, a, L.ne, st);
+}
+
+template <int P, int S>
+static hipError_t launch_jac3_p(const JacArgs3& a, int ne, hipStream_t st) {
+  hipLaunchKernelGGL((k_jac3_rows<P, S>), dim3(ne), dim3(Rows3<P, S>::NT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
+                            pmg_factors_s& fac, hipStream_t st) {
+  JacArgs3 a{};
+  a.lv = L.view();
+  a.ops = L.ops;
+  a.gas = L.gas;
+  a.q = q;
+  a.inv_dtau = 1.0 / dtau;
+  a.c_mass = c_mass;
+  a.D_out = D_out;
+  a.W = fac.W;
+  a.precision = fac.precision;
+  a.flag = L.flag;
+  switch (L.P) {
+    case 0: return launch_jac3_p<0, 1>(a, L.ne, st);
+    case 1: return launch_jac3_p<1, 1>(a, L.ne, st);
+    case 2: return launch_jac3_p<2, 4>(a, L.ne, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_restrict3(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
+                            double* xc, int nvar, hipStream_t st, double* xc2) {
+  Mat1D3 R{};
+  for (int k = 0; k < Lc.n1 * Lf.n1; ++k) R.m[k] = R1[k];
+  const size_t total = (size_t)nvar * Lc.np * Lc.ne;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restrict3, dim3(blocks3(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf, xc,
+                     xc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong3(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
+                           const double* xb, double* xf, int nvar, hipStream_t st) {
+  Mat1D3 I{};
+  for (int k = 0; k < Lc.n1 * Lf.n1; ++k) I.m[k] = I1[k];
+  const size_t total = (size_t)nvar * Lf.np * Lf.ne;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prolong3, dim3(blocks3(total)), dim3(256), 0, st, Lf.ne, nvar, Lc.n1, Lf.n1, I, xa, xb,
+                     xf);
+  return hipGetLastError();
+}
+
+hipError_t launch_conservative3(const pmg_level_s& L, const double* q, double* qc, hipStream_t st) {
+  const int npts = L.np * L.ne;
+  if (npts == 0) return hipSuccess;
+  Ref5 ref{};
+  for (int k = 0; k < 5; ++k) ref.v[k] = L.q_ref[k];
+  hipLaunchKernelGGL(k_conservative3, dim3(blocks3(npts)), dim3(256), 0, st, npts, L.gas, ref, q, qc);
+  return hipGetLastError();
+}
+
+hipError_t launch_dtau_partial3(const pmg_level_s& L, const double* q, int nblk, hipStream_t st) {
+  Ref5 ref{};
+  for (int k = 0; k < 5; ++k) ref.v[k] = L.q_ref[k];
+  hipLaunchKernelGGL(k_dtau_partial3, dim3(nblk), dim3(256), 0, st, L.ne, L.np, q, L.hdx, ref,
+                     L.gas.gamma * L.gas.rgas, L.dtpart);
+  return hipGetLastError();
+}
+
+}  // namespace pmg

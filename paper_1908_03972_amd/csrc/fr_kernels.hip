@@ -670,6 +670,7 @@ hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStre
 }
 
 int residual_blocks(const pmg_level_s& L) {
+  if (L.dim == 3) return residual_blocks3(L);
   const int epw = epw_for(L.P);
   return (L.ne + epw - 1) / epw;
 }
@@ -684,6 +685,7 @@ static ResArgs base_args(const pmg_level_s& L) {
 
 hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* src, const double* S,
                            double c_mass, double* F, bool want_norms, hipStream_t st) {
+  if (L.dim == 3) return launch_residual3(L, q, src, S, c_mass, F, want_norms, st);
   ResArgs a = base_args(L);
   a.q = q;
   a.src = src;
@@ -701,6 +703,7 @@ hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* 
 hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
                         const double* src, const double* S, double c_mass, double alpha, bool want_norms,
                         hipStream_t st) {
+  if (L.dim == 3) return launch_sweep3(L, fac, q_in, q_out, src, S, c_mass, alpha, want_norms, st);
   ResArgs a = base_args(L);
   a.q = q_in;
   a.src = src;

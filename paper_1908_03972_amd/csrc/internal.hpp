@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "physics.hpp"
@@ -27,13 +28,15 @@ struct Ops1D {
 // Device view of one level's geometry and connectivity.
 struct LevelView {
   int ne;
-  const double* met;    // [5][Np][Ne]: Sx, Sy (= y_eta, -x_eta), Tx, Ty (= -y_xi, x_xi), 1/|J|
-  const double* fvec;   // [4][n1][3][Ne]: unit +xi (faces 0,1) or +eta (faces 2,3) normal and its length |S|
-  const int* nbr;       // [4][Ne]
+  const double* met;    // 2-D [5][Np][Ne]: Sx, Sy (= y_eta, -x_eta), Tx, Ty (= -y_xi, x_xi), 1/|J|;
+                        // 3-D [10][Np][Ne]: J grad xi^d (component n at 3 d + n), 1/|J|
+  const double* fvec;   // 2-D [4][n1][3][Ne]: unit +xi (faces 0,1) or +eta (faces 2,3) normal and its
+                        // length |S|; 3-D [6][n1^2][4][Ne]: unit +xi^(f/2) normal and |S|
+  const int* nbr;       // [2 dim][Ne]
   const int* nbf;       // [4][Ne]
   const int* ori;       // [4][Ne]
-  double q_ref[4];      // stored states are q - q_ref
-  double qinf_g[4];     // far-field state in stored form, q_inf - q_ref
+  double q_ref[5];      // stored states are q - q_ref (4 variables in 2-D, 5 in 3-D)
+  double qinf_g[5];     // far-field state in stored form, q_inf - q_ref
   const double* lam;    // [4][n1][Ne] BR2 lifting factor of each flux point (viscous levels)
   const double* gface;  // [4][n1][4][2][Ne] local gradient traces of the current state (viscous levels)
 };
@@ -46,12 +49,13 @@ struct KernelStatus {
 
 struct pmg_level_s {
   int dim = 2, P = 0, n1 = 1, np = 1, nv = 4, n = 4, ne = 0, geom_order = 1, device = 0;
+  int npad = 4;                     // row stride of the stored inverse blocks (n, or n rounded up to 4 in 3-D)
   pmg::GasParams gas{};
   double q_inf[5] = {0, 0, 0, 0, 0};
   double q_ref[5] = {0, 0, 0, 0, 0};
   pmg::Ops1D ops{};
   std::vector<double> x1, w1;       // 1-D Gauss points/weights
-  std::vector<double> xy_host;      // [2][Np][Ne] solution-point coordinates
+  std::vector<double> xy_host;      // [dim][Np][Ne] solution-point coordinates
   // device geometry
   double* met = nullptr;
   double* fvec = nullptr;
@@ -90,7 +94,7 @@ struct pmg_level_s {
     v.nbr = nbr;
     v.nbf = nbf;
     v.ori = ori;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
       v.q_ref[k] = q_ref[k];
       v.qinf_g[k] = q_inf[k] - q_ref[k];
     }
@@ -103,7 +107,7 @@ struct pmg_level_s {
 struct pmg_factors_s {
   pmg_level_s* L = nullptr;
   int precision = 64;     // 64: FP64 inverse blocks; 32: FP32 inverse blocks
-  void* W = nullptr;      // [n][Ne][n] element inverse blocks, column-major per element
+  void* W = nullptr;      // [n][Ne][npad] element inverse blocks, column-major per element
   size_t bytes = 0;
 };
 
@@ -131,5 +135,26 @@ hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStre
 hipError_t launch_visc_jacobian(const pmg_level_s& L, const double* q, hipStream_t st);
 int dtau_blocks(const pmg_level_s& L);
 hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st);
+
+// hexahedral levels (fr3_kernels.hip)
+int residual_blocks3(const pmg_level_s& L);
+hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double* src, const double* S,
+                            double c_mass, double* F, bool want_norms, hipStream_t st);
+hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                         const double* src, const double* S, double c_mass, double alpha, bool want_norms,
+                         hipStream_t st);
+hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
+                            pmg_factors_s& fac, hipStream_t st);
+hipError_t launch_restrict3(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
+                            double* xc, int nvar, hipStream_t st, double* xc2);
+hipError_t launch_prolong3(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
+                           const double* xb, double* xf, int nvar, hipStream_t st);
+hipError_t launch_conservative3(const pmg_level_s& L, const double* q, double* qc, hipStream_t st);
+hipError_t launch_dtau_partial3(const pmg_level_s& L, const double* q, int nblk, hipStream_t st);
+
+// hexahedral geometry (hex_geometry.cpp)
+std::string build_hex_geometry(const double* nodes, int ne, int g, int P, const std::vector<double>& x1,
+                               std::vector<double>& met, std::vector<double>& fvec, std::vector<double>& xyz,
+                               std::vector<double>& dx);
 
 }  // namespace pmg

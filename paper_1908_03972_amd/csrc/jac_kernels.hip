@@ -544,6 +544,7 @@ static hipError_t launch_visc_jac_p(const JacArgs& a, double* Dv, int ne, hipStr
 
 hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
                            pmg_factors_s& fac, hipStream_t st) {
+  if (L.dim == 3) return launch_jacobian3(L, q, dtau, c_mass, D_out, fac, st);
   JacArgs a{};
   a.lv = L.view();
   a.ops = L.ops;

@@ -172,6 +172,7 @@ __global__ void __launch_bounds__(256) k_dtau_final(const double* __restrict__ p
 
 hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
                            double* xc, int nvar, hipStream_t st, double* xc2) {
+  if (Lf.dim == 3) return launch_restrict3(Lf, Lc, R1, xf, xc, nvar, st, xc2);
   Mat1D R{};
   for (int k = 0; k < Lc.n1 * Lf.n1; ++k) R.m[k] = R1[k];
   const size_t total = (size_t)nvar * Lc.np * Lc.ne;
@@ -189,6 +190,7 @@ hipError_t launch_copy(size_t n, const double* src, double* dst, hipStream_t st)
 
 hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
                           const double* xb, double* xf, int nvar, hipStream_t st) {
+  if (Lf.dim == 3) return launch_prolong3(Lc, Lf, I1, xa, xb, xf, nvar, st);
   Mat1D I{};
   for (int k = 0; k < Lc.n1 * Lf.n1; ++k) I.m[k] = I1[k];
   const size_t total = (size_t)nvar * Lf.np * Lf.ne;
@@ -199,6 +201,7 @@ hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const do
 }
 
 hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc, hipStream_t st) {
+  if (L.dim == 3) return launch_conservative3(L, q, qc, st);
   const int npts = L.np * L.ne;
   if (npts == 0) return hipSuccess;
   Ref4 ref{};
@@ -232,8 +235,13 @@ hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st
   Ref4 ref{};
   for (int k = 0; k < 4; ++k) ref.v[k] = L.q_ref[k];
   const int nblk = dtau_blocks(L);
-  hipLaunchKernelGGL(k_dtau_partial, dim3(nblk), dim3(256), 0, st, L.ne, L.np, q, L.hdx, ref,
-                     L.gas.gamma * L.gas.rgas, L.gas.rgas, L.gas.mu, L.dtpart);
+  if (L.dim == 3) {
+    const hipError_t e = launch_dtau_partial3(L, q, nblk, st);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_dtau_partial, dim3(nblk), dim3(256), 0, st, L.ne, L.np, q, L.hdx, ref,
+                       L.gas.gamma * L.gas.rgas, L.gas.rgas, L.gas.mu, L.dtpart);
+  }
   hipLaunchKernelGGL(k_dtau_final, dim3(1), dim3(256), 0, st, L.dtpart, nblk, L.dtmin);
   return hipGetLastError();
 }

@@ -35,7 +35,8 @@ def patch_mesh(mesh, e):
 def patch_block(mesh, gas, P, q, e, dtau, c_mass, q_inf):
     """The oracle's block D_e (eqs. (28), (30)) of element e of the whole mesh, from its patch."""
     from oracle.fr import FRLevel
+    from oracle.fr3 import FRLevel3
     from oracle.jacobian import element_blocks
     pm, elems = patch_mesh(mesh, e)
-    lev = FRLevel(pm, P, gas, q_inf=q_inf)
+    lev = (FRLevel if mesh.dim == 2 else FRLevel3)(pm, P, gas, q_inf=q_inf)
     return element_blocks(lev, q[elems], dtau, c_mass)[0]
