@@ -36,14 +36,14 @@ SCHEME = 3
 HBM_PEAK_GBS = 8000.0
 
 
-def dof_updates_per_vcycle(ne, p_levels, n_smooth, nv=4):
+def dof_updates_per_vcycle(ne, p_levels, n_smooth, nv=4, dim=2):
     """sum over levels of (sweeps per V-cycle) * DOF_l: 2 n_l sweeps on every level but the
     coarsest, which smooths n_L times once."""
     tot = 0
     last = len(p_levels) - 1
     for l, (P, n) in enumerate(zip(p_levels, n_smooth)):
         sweeps = n if l == last else 2 * n
-        tot += sweeps * ne * nv * (P + 1) ** 2
+        tot += sweeps * ne * nv * (P + 1) ** dim
     return tot
 
 
@@ -190,6 +190,61 @@ def airfoil_block(api, torch, forms, max_vcycles, kernel_reps):
     return out
 
 
+def sphere_block(api, torch, forms, max_vcycles, kernel_reps):
+    """Steady inviscid flow at Ma 0.001 past the unit sphere on the 6 x 16 x 16 x 24 cubed sphere of
+    27-node hexahedra (36 864 elements), P{2-1-0} (135 x 135 element blocks): for each block
+    precision one steady solve from the free stream with CFL 1e2 -> 1e5 (blocks rebuilt every 10
+    V-cycles), its V-cycle rate, residual history, time to each tolerance and the live duration of
+    the fine-level fused sweep."""
+    mesh, fs = W.sphere_config5()
+    qinf = fs.freestream()
+    plev, nsm = (2, 1, 0), (5, 10, 20)
+    levels = [api.Level(mesh, P, gamma=fs.gamma, rgas=fs.rgas, eps_mode=1, ma_inf=fs.ma_inf, kappa=1.0,
+                        q_inf=qinf, q_ref=qinf) for P in plev]
+    per_vc = dof_updates_per_vcycle(levels[0].ne, plev, nsm, nv=5, dim=3)
+    out = {"workload": "unit sphere, cubed sphere 6x16x16 cells x 24 shells (36864 quadratic hexahedra, far "
+                       "field at r = 20), Ma 0.001, slip wall + far field, cut-off eps (kappa 1), steady, "
+                       "P{2-1-0}, CFL 1e2 -> 1e5, blocks rebuilt every 10 V-cycles",
+           "elements": mesh.n_elements, "dof_updates_per_vcycle": per_vc, "n_smooth": list(nsm)}
+    for form in forms:
+        prec, graph = FORMS[form]
+        facs = [api.Factors(lv, prec) for lv in levels]
+        kw = dict(tol_rel=1e-8, use_graph=graph, use_cfl=True, cfl_init=1e2, cfl_max=1e5, freeze_at_max=False)
+        q = levels[0].new_state()
+        api.StageSolver(levels, facs, nsm, max_vcycles=12, **kw).solve(q, raise_on_error=False)   # warm-up
+        q.zero_()
+        solver = api.StageSolver(levels, facs, nsm, max_vcycles=max_vcycles, **kw)
+        torch.cuda.synchronize()
+        st = solver.solve(q, raise_on_error=False)
+        h = np.asarray(st["history"]) / st["history"][0]
+        per = st["seconds"] / max(st["n_vcycles"], 1)
+        ttt = {}
+        for t in TOLS:
+            hit = np.nonzero(h <= t)[0]
+            ttt[f"{t:.0e}"] = float(hit[0] * per) if hit.size else None
+        fin = np.isfinite(h)
+        qk = q.clone()
+        api.ejacobi_sweep(levels[0], facs[0], qk, 2, alpha_r=0.0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        api.ejacobi_sweep(levels[0], facs[0], qk, kernel_reps, alpha_r=0.0)
+        ev1.record()
+        torch.cuda.synchronize()
+        k_ms = ev0.elapsed_time(ev1) / kernel_reps
+        n = levels[0].n
+        kbytes = levels[0].ne * n * ((4 if prec == 32 else 8) * n + 24)
+        out[form] = {"status": st["status"], "vcycles": st["n_vcycles"], "block_rebuilds": st["n_refresh"],
+                     "seconds": st["seconds"], "ms_per_vcycle": 1e3 * per,
+                     "dof_updates_per_s": per_vc * st["n_vcycles"] / st["seconds"],
+                     "time_to_tol_s": ttt, "min_rel_residual": float(np.min(h[fin])) if fin.any() else None,
+                     "final_rel_residual": float(h[fin][-1]) if fin.any() else None, "dtau_min": st["dtau_min"],
+                     "history_every_25": [float(x) for x in h[::25]],
+                     "fine_sweep_kernel_ms": k_ms, "fine_sweep_bytes_per_launch": kbytes,
+                     "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del facs, solver
+    return out
+
+
 def viscous_batch_block(api, torch, vcycles_per_stage, steps=1):
     """Eight independent viscous cases (Re 5000, Ma 0.001, no-slip adiabatic wall, 256 x 96
     O-mesh, seeded incidence and P in {2, 3, 4}), one ESDIRK3 step of dt = 0.05 from a free stream
@@ -301,6 +356,8 @@ def main():
     ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
     ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere (P = 2) steady solves")
+    ap.add_argument("--sphere-vcycles", type=int, default=200)
     ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -433,6 +490,9 @@ def main():
                                                          args.kernel_reps)
     if not args.no_viscous:
         line["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
+    if not args.no_sphere:
+        line["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, args.forms.split(","),
+                                                                args.sphere_vcycles, args.kernel_reps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
