@@ -21,7 +21,10 @@ namespace pmg {
 
 constexpr int kPad3 = -100;   // neighbour tag of the padding elements of the last workgroup
 
-constexpr int epw3_for(int P) { return P == 0 ? 10 : P == 1 ? 2 : 1; }
+// Elements per workgroup. Lanes are (point, element) with the element fastest, so that a load of
+// one (variable, point) of the [Nv][Np][Ne] state by EPW consecutive lanes covers EPW consecutive
+// elements: with one element per workgroup every such load would touch a cache line of its own.
+constexpr int epw3_for(int P) { return P == 0 ? 32 : P == 1 ? 8 : 8; }
 
 template <int P>
 struct Cfg3 {
@@ -82,11 +85,12 @@ __global__ void __launch_bounds__(Cfg3<P>::NT) k_fr3(ResArgs3 a) {
   using C = Cfg3<P>;
   constexpr int N1 = C::N1, NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, EPW = C::EPW;
   __shared__ double s_q[NV * NP * EPW];
-  __shared__ double s_fgh[3 * NV * NP * EPW];
+  // F~, G~, H~ per point; after the divergence the matvec's F and D^{-1} F reuse it
+  constexpr int FGH = (3 * NV * NP > 2 * NPAD ? 3 * NV * NP : 2 * NPAD) * EPW;
+  __shared__ double s_fgh[FGH];
   __shared__ double s_j[6 * NF * NV * EPW];
   __shared__ double s_ops[N1 * N1 + 4 * N1];
   __shared__ double s_red[C::NW * NV];
-  __shared__ double s_mv[(MODE == 0) ? 1 : 2 * NPAD * EPW];   // F of the element, then D^{-1} F
 
   const int ne = a.lv.ne;
   const int tid = threadIdx.x;
@@ -306,8 +310,9 @@ __global__ void __launch_bounds__(Cfg3<P>::NT) k_fr3(ResArgs3 a) {
       for (int v = 0; v < NV; ++v) a.F[v * sstride + gp] = Fv[v];
     }
   } else {
-    double* s_fe = s_mv;                  // [EPW][NPAD], index p Nv + v (padding rows zero)
-    double* s_dq = s_mv + NPAD * EPW;
+    sync3<C::NT>();                       // every read of F~ is done: the matvec vectors reuse it
+    double* s_fe = s_fgh;                 // [EPW][NPAD], index p Nv + v (padding rows zero)
+    double* s_dq = s_fgh + NPAD * EPW;
     if (pt) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) s_fe[el * NPAD + p * NV + v] = Fv[v];
