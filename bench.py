@@ -240,7 +240,9 @@ def sphere_block(api, torch, forms, max_vcycles, kernel_reps):
                      "final_rel_residual": float(h[fin][-1]) if fin.any() else None, "dtau_min": st["dtau_min"],
                      "history_every_25": [float(x) for x in h[::25]],
                      "fine_sweep_kernel_ms": k_ms, "fine_sweep_bytes_per_launch": kbytes,
-                     "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                     "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "fine_sweep_traffic": (measured_traffic(PROFILE_PMC_SPHERE, KERNEL_SOURCES_3D)
+                                            if prec == 32 else None)}
         del facs, solver
     return out
 
@@ -319,18 +321,23 @@ def viscous_batch_block(api, torch, vcycles_per_stage, steps=1):
 
 PROFILE_PMC = os.path.join(ROOT, "profiles", "k_fr_sweep_vortex64_P321_pmc.txt")
 PROFILE_PMC_AIRFOIL = os.path.join(ROOT, "profiles", "k_fr_sweep_airfoil128x64_P4_pmc.txt")
+PROFILE_PMC_SPHERE = os.path.join(ROOT, "profiles", "k_fr3_sweep_sphere16x16x24_P2_pmc.txt")
 
 
-def kernel_source_hash():
+KERNEL_SOURCES_2D = ("fr_kernels.hip", "physics.hpp", "internal.hpp")
+KERNEL_SOURCES_3D = ("fr3_kernels.hip", "physics3.hpp", "physics.hpp", "internal.hpp")
+
+
+def kernel_source_hash(files=KERNEL_SOURCES_2D):
     import hashlib
     h = hashlib.sha256()
-    for f in ("fr_kernels.hip", "physics.hpp", "internal.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1908_03972_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=PROFILE_PMC):
+def measured_traffic(path=PROFILE_PMC, files=KERNEL_SOURCES_2D):
     """HBM bytes per launch of the dominant fused sweep from a committed counter summary, or None
     when the kernel sources have changed since the counters were taken."""
     try:
@@ -338,7 +345,7 @@ def measured_traffic(path=PROFILE_PMC):
                     if line.startswith(("traffic_bytes_per_launch:", "kernel_source_hash:")))
     except (OSError, ValueError):
         return None
-    if vals.get("kernel_source_hash", "").strip() != kernel_source_hash():
+    if vals.get("kernel_source_hash", "").strip() != kernel_source_hash(files):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
