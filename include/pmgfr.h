@@ -61,16 +61,16 @@ typedef struct pmg_batch_s* pmg_batch;
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 104
+#define PMG_ABI_VERSION 105
 int32_t pmg_abi_version(void);
 
 /*
  * One P-level of a mesh (Sec. 2.3: FR/CPR on quadrilaterals or hexahedra with tensor-product
  * corrections). All arrays are host memory and are deep-copied; the descriptor may be freed after
  * the call.
- *   dim          2 (quadrilaterals) or 3 (hexahedra: inviscid, P <= 2, slip wall and far field,
+ *   dim          2 (quadrilaterals) or 3 (hexahedra: inviscid, P <= 3, slip wall and far field,
  *                primitive variables (p, u, v, w, T), Nv = 5).
- *   P            solution degree, 0..6 in 2-D (element blocks need P <= 4), 0..2 in 3-D.
+ *   P            solution degree, 0..6 in 2-D (element blocks need P <= 4), 0..3 in 3-D.
  *   geom_order   1 (bilinear / trilinear) or 2 (9-node / 27-node quadratic).
  *   nodes        2-D [Ne][(g+1)^2][2], 3-D [Ne][(g+1)^3][3] geometry nodes in tensor order, xi
  *                fastest, at reference coordinates (-1 + 2a/g, -1 + 2b/g[, -1 + 2c/g]).
@@ -152,7 +152,9 @@ pmg_status pmg_level_status(pmg_level L, int32_t* flags);
 
 /* Storage for the element-Jacobi blocks of one level (Sec. 2.4, eq. (30)): the inverse of every
  * element block D_e, kept as n x n per element in `precision` 64 (FP64) or 32 (FP32).
- * Footprint: n * n * Ne * precision/8 bytes. */
+ * Footprint: n * npad * Ne * precision/8 bytes (npad = n in 2-D, n rounded up to 4 in 3-D); a 3-D
+ * P = 3 level (n = 320) adds an FP64 elimination work array of n * n * 8 bytes per slot, two slots
+ * per compute unit (about 420 MB on a 256-CU device), held until pmg_factors_destroy. */
 pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out);
 pmg_status pmg_factors_destroy(pmg_factors F);
 

@@ -293,10 +293,10 @@ const char* pmg_last_error(void) { return g_error.c_str(); }
 
 int32_t pmg_abi_version(void) { return PMG_ABI_VERSION; }
 
-// A hexahedral level (dim = 3): P <= 2, inviscid, slip-wall and far-field boundaries, face
+// A hexahedral level (dim = 3): P <= 3, inviscid, slip-wall and far-field boundaries, face
 // orientation codes 0..7 (see the header).
 static pmg_status create_hex_level(const pmg_level_desc* d, pmg_level* out) {
-  if (d->P < 0 || d->P > 2) return fail(PMG_E_ARG, "3-D levels support P in 0..2");
+  if (d->P < 0 || d->P > 3) return fail(PMG_E_ARG, "3-D levels support P in 0..3");
   if (d->geom_order != 1 && d->geom_order != 2) return fail(PMG_E_ARG, "geom_order must be 1 or 2");
   if (d->n_elements <= 0) return fail(PMG_E_ARG, "n_elements must be positive");
   if (!d->nodes || !d->face_nbr || !d->face_nbr_face || !d->face_orient) return fail(PMG_E_ARG, "null mesh array");
@@ -616,7 +616,7 @@ pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) 
   if (!out) return fail(PMG_E_ARG, "null output");
   if (precision != 32 && precision != 64) return fail(PMG_E_ARG, "precision must be 32 or 64");
   if (L->P > 4) return fail(PMG_E_ARG, "element blocks are supported for P <= 4");
-  if (L->dim == 3 && L->P > 2) return fail(PMG_E_ARG, "3-D element blocks are supported for P <= 2");
+  if (L->dim == 3 && L->P > 3) return fail(PMG_E_ARG, "3-D element blocks are supported for P <= 3");
   DeviceGuard guard(L->device);
   pmg_factors_s* F = new pmg_factors_s();
   F->L = L;
@@ -631,6 +631,17 @@ pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) 
     delete F;
     return fail(PMG_E_HIP, "hipMemset element blocks");
   }
+  if (L->dim == 3 && L->P == 3) {   // large blocks: one FP64 work slot per resident workgroup
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, L->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    F->ws_slots = 2 * cus < L->ne ? 2 * cus : L->ne;
+    if (hipMalloc(&F->ws, (size_t)F->ws_slots * L->n * L->n * sizeof(double)) != hipSuccess) {
+      (void)hipFree(F->W);
+      delete F;
+      return fail(PMG_E_NOMEM, "hipMalloc failed for the elimination work array");
+    }
+  }
   *out = F;
   return PMG_OK;
 }
@@ -639,6 +650,7 @@ pmg_status pmg_factors_destroy(pmg_factors F) {
   if (!F) return PMG_OK;
   DeviceGuard guard(F->L->device);
   if (F->W) (void)hipFree(F->W);
+  if (F->ws) (void)hipFree(F->ws);
   delete F;
   return PMG_OK;
 }

@@ -109,6 +109,8 @@ struct pmg_factors_s {
   int precision = 64;     // 64: FP64 inverse blocks; 32: FP32 inverse blocks
   void* W = nullptr;      // [n][Ne][npad] element inverse blocks, column-major per element
   size_t bytes = 0;
+  double* ws = nullptr;   // work array of the large-block elimination: ws_slots x n x n FP64 (3-D P = 3)
+  int ws_slots = 0;
 };
 
 namespace pmg {

@@ -1,7 +1,8 @@
 """GPU (HIP through the C ABI) against the CPU oracle on hexahedral levels (Sec. 2.3 in three
 dimensions, the sphere setting of Sec. 4.2): a small cubed sphere with rotated elements (every face
 orientation code occurs), slip wall on the sphere and far field outside, Ma 0.01 and Ma 0.001 with
-the cut-off reference velocity, P = 0..2; then the full 6 x 16 x 16 x 24 mesh on sampled elements."""
+the cut-off reference velocity, P = 0..3 (P = 3 blocks, n = 320, on a smaller sphere of 48 elements);
+then the full 6 x 16 x 16 x 24 mesh on sampled elements at P = 2 and P = 3."""
 import numpy as np
 import pytest
 
@@ -14,7 +15,7 @@ from oracle.jacobian import element_blocks
 
 from gpu_helpers import fp32_solver_class, from_dev, rel_err_per_var, rounding_floor, to_dev, tolerance
 from patches import patch_block
-from test_oracle_3d import small_sphere
+from test_oracle_3d import rotated, small_sphere
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +37,10 @@ def glevel(mesh, P, fs=FS):
 
 
 def disturbed(olev, qinf, seed=0):
-    x = olev.geo.xyz
+    return disturbed_at(olev.geo.xyz, qinf, seed)
+
+
+def disturbed_at(x, qinf, seed=0):
     q = np.broadcast_to(qinf, x.shape[:2] + (5,)).copy()
     s = np.sin(0.7 * x[..., 0] + 0.3 * seed) * np.cos(0.5 * x[..., 1]) * np.cos(0.4 * x[..., 2])
     q[..., 0] += 0.8 * s
@@ -59,6 +63,18 @@ def sphere():
     return small_sphere(inner=W.BC_SLIP_WALL)
 
 
+@pytest.fixture(scope="module")
+def tiny_sphere():
+    """6 x 2 x 2 x 2 hexes with rotated elements: the P = 3 cases, whose oracle blocks (320 x 320)
+    are slow to assemble."""
+    m = W.cubed_sphere_mesh(2, 2, ratio=1.3, r_far=4.0, inner=W.BC_SLIP_WALL)
+    return rotated(m, [0, 5, 11, 20, 26, 33, 38, 41, 44, 47, 13, 30], W.BC_SLIP_WALL)
+
+
+def pick(request, P, big=3):
+    return request.getfixturevalue("tiny_sphere" if P >= big else "sphere")
+
+
 def test_points_and_element_length(sphere):
     for P in (0, 1, 2):
         olev = FRLevel3(sphere, P, GAS, q_inf=QINF)
@@ -69,7 +85,7 @@ def test_points_and_element_length(sphere):
     assert np.max(np.abs(glev.dx() - ref) / ref) < 1e-12
 
 
-@pytest.mark.parametrize("P", [0, 1, 2])
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
 def test_residual_parity_3d(sphere, P):
     olev = FRLevel3(sphere, P, GAS, q_inf=QINF)
     glev = glevel(sphere, P)
@@ -84,7 +100,7 @@ def test_residual_parity_3d(sphere, P):
     assert np.all(err <= tol), (err, tol)
 
 
-@pytest.mark.parametrize("P", [1, 2])
+@pytest.mark.parametrize("P", [1, 2, 3])
 def test_freestream_on_gpu_3d(P):
     mesh = small_sphere(inner=W.BC_FAR_FIELD)
     glev = glevel(mesh, P)
@@ -97,8 +113,9 @@ def test_freestream_on_gpu_3d(P):
     assert np.max(np.abs(Fh[..., 4])) / scale < 1e-12 / FS.ma_inf ** 2
 
 
-@pytest.mark.parametrize("P", [0, 1, 2])
-def test_element_blocks_parity_3d(sphere, P):
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
+def test_element_blocks_parity_3d(request, P):
+    sphere = pick(request, P)
     olev = FRLevel3(sphere, P, GAS, q_inf=QINF)
     glev = glevel(sphere, P)
     q = disturbed(olev, QINF, 2)
@@ -116,8 +133,8 @@ def test_element_blocks_parity_3d(sphere, P):
 
 def test_transfers_3d_gpu(sphere):
     rng = np.random.default_rng(9)
-    lv = {P: glevel(sphere, P) for P in (2, 1, 0)}
-    for Pf, Pc in ((2, 1), (1, 0), (2, 0)):
+    lv = {P: glevel(sphere, P) for P in (3, 2, 1, 0)}
+    for Pf, Pc in ((3, 2), (2, 1), (1, 0), (2, 0), (3, 0)):
         xf = rng.standard_normal((sphere.n_elements, (Pf + 1) ** 3, 5))
         xc = lv[Pc].new_state()
         api.pmg_restrict(lv[Pf], lv[Pc], to_dev(xf), xc)
@@ -131,9 +148,10 @@ def test_transfers_3d_gpu(sphere):
         assert np.max(np.abs(from_dev(xo) - ref_f)) < 1e-13 * np.max(np.abs(ref_f))
 
 
-@pytest.mark.parametrize("P,prec", [(2, 64), (1, 64), (2, 32)])
-def test_sweep_parity_3d(sphere, P, prec):
+@pytest.mark.parametrize("P,prec", [(2, 64), (1, 64), (2, 32), (3, 64), (3, 32)])
+def test_sweep_parity_3d(request, P, prec):
     """Three steady element-Jacobi sweeps (eq. (30)) at 1e3 dtau_min."""
+    sphere = pick(request, P)
     def oracle_sweeps(q0, cls=OS.PMGSolver):
         sol = cls(sphere, GAS, OS.PMGOptions(p_levels=(P,), n_smooth=(3,)), q_inf=QINF)
         sol.c_mass, sol.src, sol.dtau = 0.0, None, 1e3 * sol.dtau_min(q0)
@@ -160,11 +178,12 @@ def test_sweep_parity_3d(sphere, P, prec):
     assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
 
 
-@pytest.mark.parametrize("prec", [64, 32])
-def test_steady_solve_parity_3d(sphere, prec):
-    """Four steady CFL V-cycles of P{2-1-0} (CFL 10 -> 1e3; from this start CFL 1e2 -> 1e5 makes the
-    oracle itself diverge) against the oracle."""
-    plev, nsm, nvc = (2, 1, 0), (3, 6, 10), 4
+@pytest.mark.parametrize("plev,prec", [((2, 1, 0), 64), ((2, 1, 0), 32), ((3, 2, 1, 0), 64), ((3, 2, 1, 0), 32)])
+def test_steady_solve_parity_3d(request, plev, prec):
+    """Four steady CFL V-cycles of P{2-1-0} and P{3-2-1-0} (CFL 10 -> 1e3; from this start CFL
+    1e2 -> 1e5 makes the oracle itself diverge) against the oracle."""
+    sphere = pick(request, plev[0])
+    nsm, nvc = (3, 6, 10, 10)[:len(plev)], 4
 
     def run_oracle(q0, cls=OS.PMGSolver):
         opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, max_vcycles=nvc, tol=1e-30, use_cfl=True,
@@ -237,3 +256,53 @@ def test_sphere_fullsize_residual_blocks_and_sweep():
         print("sphere e", e, "block err", berr, "update err", e_err, "floor", floor)
         assert berr < 1e-12
         assert np.all(e_err <= np.maximum(1e-11, 10.0 * floor)), (e, e_err, floor)
+
+
+def test_sphere_fullsize_p3_residual_and_sweep():
+    """P = 3 on the full sphere (n = 320; 15 GB of FP32 inverse blocks): the residual and one
+    sweep's update on sampled elements, among them elements that the elimination kernel's
+    workgroups take in their later passes over the mesh, against the oracle on each element's
+    patch (the element and its face neighbours)."""
+    from oracle.fr3 import FRLevel3 as OL3
+    from patches import patch_mesh
+    mesh, fs = W.sphere_config5()
+    qinf = fs.freestream()
+    gas = OG.Gas(gamma=fs.gamma, rgas=fs.rgas, eps_mode="cutoff", ma_inf=fs.ma_inf, kappa=1.0)
+    P = 3
+    glev = glevel(mesh, P, fs)
+    x = np.moveaxis(glev.points(), 0, -1).transpose(1, 0, 2)          # [Ne][Np][3]
+    q = disturbed_at(x, qinf, 6)
+    qd = to_dev(q - qinf)
+    Fg = glev.new_state()
+    api.fr_residual(glev, qd, Fg)
+    torch.cuda.synchronize()
+    Fh = from_dev(Fg)
+    speed = np.sqrt(fs.gamma * fs.rgas * q[..., 4]) + np.linalg.norm(q[..., 1:4], axis=-1)
+    dtau = 100.0 * float(np.min(glev.dx()[:, None] / (P + 1) / speed))
+    fac = api.Factors(glev, 32)
+    api.fr_element_jacobian(glev, qd, dtau, 0.0, fac)
+    q0 = qd.clone()
+    api.ejacobi_sweep(glev, fac, qd, 1)
+    torch.cuda.synchronize()
+    assert glev.status() == 0
+    dq = from_dev(qd - q0)
+    del fac
+    sample = [0, 511, 512, 1023, 1024, 6143, 20000, mesh.n_elements - 1] + \
+        np.random.default_rng(36865).choice(mesh.n_elements, 2, replace=False).tolist()
+    rng = np.random.default_rng(2)
+    for e in sample:
+        pm, elems = patch_mesh(mesh, e)
+        plev = OL3(pm, P, gas, q_inf=qinf)
+        qp = q[elems]
+        Fe = plev.residual(qp)[0]
+        Fe_pert = plev.residual(qp * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=qp.shape)))[0]
+        r_err = rel_err_per_var(Fh[e], Fe)
+        r_tol = tolerance(rel_err_per_var(Fe_pert, Fe))
+        Dref = patch_block(mesh, gas, P, q, e, dtau, 0.0, qinf)
+        ref = np.linalg.solve(Dref, Fe.ravel())
+        alt = (np.linalg.inv(Dref).astype(np.float32) @ Fe.ravel().astype(np.float32)).astype(np.float64)
+        u_err = rel_err_per_var(dq[e], ref.reshape(-1, 5))
+        floor = rel_err_per_var(alt.reshape(-1, 5), ref.reshape(-1, 5))
+        print("sphere P3 e", e, "residual err", r_err, "tol", r_tol, "update err", u_err, "floor", floor)
+        assert np.all(r_err <= r_tol), (e, r_err, r_tol)
+        assert np.all(u_err <= np.maximum(1e-11, 10.0 * floor)), (e, u_err, floor)
