@@ -190,26 +190,30 @@ def airfoil_block(api, torch, forms, max_vcycles, kernel_reps):
     return out
 
 
-def sphere_block(api, torch, forms, max_vcycles, kernel_reps):
+def sphere_block(api, torch, forms, max_vcycles, kernel_reps, plev=(2, 1, 0), nsm=(5, 10, 20),
+                 profile_pmc=None, cfl_init=1e2):
     """Steady inviscid flow at Ma 0.001 past the unit sphere on the 6 x 16 x 16 x 24 cubed sphere of
-    27-node hexahedra (36 864 elements), P{2-1-0} (135 x 135 element blocks): for each block
-    precision one steady solve from the free stream with CFL 1e2 -> 1e5 (blocks rebuilt every 10
-    V-cycles), its V-cycle rate, residual history, time to each tolerance and the live duration of
-    the fine-level fused sweep."""
+    27-node hexahedra (36 864 elements), P{2-1-0} (135 x 135 element blocks) or P{3-2-1-0} (320 x
+    320): for each block precision one steady solve from the free stream with CFL cfl_init -> 1e5
+    (blocks rebuilt every 10 V-cycles), its V-cycle rate, residual history, time to each
+    tolerance, and the live durations of the fine-level fused sweep and block rebuild. From the
+    impulsive start P{3-2-1-0} diverges at CFL_init 1e2 on this mesh and takes 30."""
+    profile_pmc = profile_pmc or PROFILE_PMC_SPHERE
     mesh, fs = W.sphere_config5()
     qinf = fs.freestream()
-    plev, nsm = (2, 1, 0), (5, 10, 20)
     levels = [api.Level(mesh, P, gamma=fs.gamma, rgas=fs.rgas, eps_mode=1, ma_inf=fs.ma_inf, kappa=1.0,
                         q_inf=qinf, q_ref=qinf) for P in plev]
     per_vc = dof_updates_per_vcycle(levels[0].ne, plev, nsm, nv=5, dim=3)
+    hier = "P{" + "-".join(str(P) for P in plev) + "}"
     out = {"workload": "unit sphere, cubed sphere 6x16x16 cells x 24 shells (36864 quadratic hexahedra, far "
                        "field at r = 20), Ma 0.001, slip wall + far field, cut-off eps (kappa 1), steady, "
-                       "P{2-1-0}, CFL 1e2 -> 1e5, blocks rebuilt every 10 V-cycles",
-           "elements": mesh.n_elements, "dof_updates_per_vcycle": per_vc, "n_smooth": list(nsm)}
+                       f"{hier}, CFL 1e2 -> 1e5, blocks rebuilt every 10 V-cycles",
+           "elements": mesh.n_elements, "block_size": levels[0].n, "dof_updates_per_vcycle": per_vc,
+           "n_smooth": list(nsm)}
     for form in forms:
         prec, graph = FORMS[form]
         facs = [api.Factors(lv, prec) for lv in levels]
-        kw = dict(tol_rel=1e-8, use_graph=graph, use_cfl=True, cfl_init=1e2, cfl_max=1e5, freeze_at_max=False)
+        kw = dict(tol_rel=1e-8, use_graph=graph, use_cfl=True, cfl_init=cfl_init, cfl_max=1e5, freeze_at_max=False)
         q = levels[0].new_state()
         api.StageSolver(levels, facs, nsm, max_vcycles=12, **kw).solve(q, raise_on_error=False)   # warm-up
         q.zero_()
@@ -231,6 +235,11 @@ def sphere_block(api, torch, forms, max_vcycles, kernel_reps):
         ev1.record()
         torch.cuda.synchronize()
         k_ms = ev0.elapsed_time(ev1) / kernel_reps
+        ev0.record()
+        api.fr_element_jacobian(levels[0], q, st["dtau_min"] * 1e2, 0.0, facs[0])
+        ev1.record()
+        torch.cuda.synchronize()
+        jac_ms = ev0.elapsed_time(ev1)
         n = levels[0].n
         kbytes = levels[0].ne * n * ((4 if prec == 32 else 8) * n + 24)
         out[form] = {"status": st["status"], "vcycles": st["n_vcycles"], "block_rebuilds": st["n_refresh"],
@@ -241,8 +250,10 @@ def sphere_block(api, torch, forms, max_vcycles, kernel_reps):
                      "history_every_25": [float(x) for x in h[::25]],
                      "fine_sweep_kernel_ms": k_ms, "fine_sweep_bytes_per_launch": kbytes,
                      "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "fine_sweep_traffic": (measured_traffic(PROFILE_PMC_SPHERE, KERNEL_SOURCES_3D)
-                                            if prec == 32 else None)}
+                     "fine_sweep_traffic": (measured_traffic(profile_pmc, KERNEL_SOURCES_3D)
+                                            if prec == 32 else None),
+                     "fine_block_rebuild_ms": jac_ms,
+                     "fine_block_rebuild_gj_tflops": levels[0].ne * 2.0 * n ** 3 / (jac_ms * 1e-3) / 1e12}
         del facs, solver
     return out
 
@@ -322,6 +333,7 @@ def viscous_batch_block(api, torch, vcycles_per_stage, steps=1):
 PROFILE_PMC = os.path.join(ROOT, "profiles", "k_fr_sweep_vortex64_P321_pmc.txt")
 PROFILE_PMC_AIRFOIL = os.path.join(ROOT, "profiles", "k_fr_sweep_airfoil128x64_P4_pmc.txt")
 PROFILE_PMC_SPHERE = os.path.join(ROOT, "profiles", "k_fr3_sweep_sphere16x16x24_P2_pmc.txt")
+PROFILE_PMC_SPHERE3 = os.path.join(ROOT, "profiles", "k_fr3_sweep_sphere16x16x24_P3_pmc.txt")
 
 
 KERNEL_SOURCES_2D = ("fr_kernels.hip", "physics.hpp", "internal.hpp")
@@ -363,7 +375,8 @@ def main():
     ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
     ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
-    ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere (P = 2) steady solves")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere steady solves")
+    ap.add_argument("--no-sphere-p3", action="store_true", help="skip the 3-D sphere P{3-2-1-0} steady solves")
     ap.add_argument("--sphere-vcycles", type=int, default=200)
     ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
     args = ap.parse_args()
@@ -500,6 +513,10 @@ def main():
     if not args.no_sphere:
         line["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, args.forms.split(","),
                                                                 args.sphere_vcycles, args.kernel_reps)
+        if not args.no_sphere_p3:
+            line["sphere_cubed_16x16x24_P3_steady"] = sphere_block(
+                api, torch, args.forms.split(","), args.sphere_vcycles, args.kernel_reps, plev=(3, 2, 1, 0),
+                nsm=(5, 10, 20, 20), profile_pmc=PROFILE_PMC_SPHERE3, cfl_init=30.0)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
