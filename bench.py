@@ -337,7 +337,7 @@ PROFILE_PMC_SPHERE3 = os.path.join(ROOT, "profiles", "k_fr3_sweep_sphere16x16x24
 
 
 KERNEL_SOURCES_2D = ("fr_kernels.hip", "physics.hpp", "internal.hpp")
-KERNEL_SOURCES_3D = ("fr3_kernels.hip", "physics3.hpp", "physics.hpp", "internal.hpp")
+KERNEL_SOURCES_3D = ("fr3_kernels.hip", "hex_points.hpp", "physics3.hpp", "physics.hpp", "internal.hpp")
 
 
 def kernel_source_hash(files=KERNEL_SOURCES_2D):

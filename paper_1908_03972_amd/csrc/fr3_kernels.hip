@@ -1,5 +1,5 @@
-// Hexahedral (3-D) kernels: FR/CPR residual and fused element-Jacobi sweep, element blocks and
-// their inverses, P-level transfers and pointwise helpers.
+// Hexahedral (3-D) kernels: FR/CPR residual and fused element-Jacobi sweep, P-level transfers and
+// pointwise helpers (the element blocks and their inverses are in jac3_kernels.hip).
 //
 // Layouts (Ne elements, Np = (P+1)^3 points p = i + (P+1) j + (P+1)^2 k, Nv = 5 variables):
 //   state            [Nv][Np][Ne]
@@ -15,6 +15,7 @@
 // the g_DG corrections of eq. (20) along the three tensor lines, and for a sweep the matvec with
 // the element's inverse block, float4 loads over four consecutive rows.
 #include "internal.hpp"
+#include "hex_points.hpp"
 #include "physics3.hpp"
 
 namespace pmg {
@@ -52,21 +53,6 @@ struct ResArgs3 {
   double alpha;
   double* q_out;
 };
-
-// solution point m of the tensor line through face point (k1, k2) of face f (m along the normal)
-__device__ __forceinline__ int line_point3(int f, int k1, int k2, int m, int n1) {
-  if (f < 2) return m + n1 * (k1 + n1 * k2);
-  if (f < 4) return k1 + n1 * (m + n1 * k2);
-  return k1 + n1 * (k2 + n1 * m);
-}
-
-// the neighbour's face point met by (k1, k2): swap (bit 0), reverse first (bit 1), second (bit 2)
-__device__ __forceinline__ void orient3(int o, int k1, int k2, int n1, int& a, int& b) {
-  a = (o & 1) ? k2 : k1;
-  b = (o & 1) ? k1 : k2;
-  if (o & 2) a = n1 - 1 - a;
-  if (o & 4) b = n1 - 1 - b;
-}
 
 template <int NT>
 __device__ __forceinline__ void sync3() {
@@ -370,519 +356,6 @@ __global__ void __launch_bounds__(Cfg3<P>::NT) k_fr3(ResArgs3 a) {
 #undef SJ
 }
 
-// ---- element blocks (eqs. (28)-(30)) and their inverses ----------------------------------
-
-struct JacArgs3 {
-  LevelView lv;
-  Ops1D ops;
-  GasParams gas;
-  const double* q;
-  double inv_dtau;
-  double c_mass;
-  double* D_out;
-  void* W;
-  int precision;
-  int* flag;
-};
-
-// Rows of D_e in registers, S threads per row (S = 1, or 4 for n = 135 padded to 136 with an
-// identity row and column), the Gauss-Jordan elimination of the 2-D kernel: column cycling,
-// unnormalised pivot rows, a 32-bit pivot key (|f|'s upper word with the thread index in its low
-// 10 bits) reduced over each wave with DPP and across waves through LDS.
-template <int P, int S>
-struct Rows3 {
-  static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
-  static constexpr int NJ = (N + S - 1) / S * S;           // rows and columns including padding
-  static constexpr int NPAD = (N + 3) / 4 * 4;             // row stride of the stored inverse
-  static constexpr int H = NJ / S;
-  static constexpr int NW = (S * NJ + 63) / 64;
-  static constexpr int NT = 64 * NW;
-  static_assert(S == 1 || S == 4, "one or four threads per row");
-  static_assert(S * NJ <= 1023, "pivot keys carry the thread index in 10 bits");
-};
-
-__device__ __forceinline__ unsigned wave_max3(unsigned v) {
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xf, 0xf, false));   // row_ror:1
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xf, 0xf, false));   // row_ror:2
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));   // row_ror:4
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));   // row_ror:8
-  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
-  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
-  return max(max(a, b), max(c, d));
-}
-
-// a double from a lane of the same quad selected by the DPP quad permutation CTRL
-template <int CTRL>
-__device__ __forceinline__ double quad_dpp(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-constexpr int kQuadFirst = 0x00;   // quad_perm [0,0,0,0]
-constexpr int kQuadNext = 0xF9;    // quad_perm [1,2,3,3]: the next lane of the quad
-
-// The element's state (sq, [Nv][Np]) and its pointwise derivatives into LDS, all threads of the
-// workgroup taking part: sA[d] = dF~_d/dq at each solution point ([(pp Nv + v) Nv + w], three
-// directions one after the other), sDg = Gamma/dtau + c_mass M at each point, and sB = d(common
-// flux)/d(own trace) at each face point, the neighbour's trace fixed and the wall ghost and far-field
-// state taken as in the residual. Columns w of the derivatives come from dual numbers seeded in w.
-template <int P, int NT>
-__device__ void element_point_jacobians3(const JacArgs3& a, int e, double* sq, double* sA, double* sDg,
-                                         double* sB) {
-  constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5;
-  const int ne = a.lv.ne;
-  const int tid = threadIdx.x;
-  const size_t sstride = (size_t)NP * ne;
-  const Ops1D& o = a.ops;
-  for (int t = tid; t < NV * NP; t += NT) {
-    const int v = t / NP, pp = t % NP;
-    sq[t] = a.q[v * sstride + (size_t)pp * ne + e];
-  }
-  __syncthreads();
-  for (int t = tid; t < NP * NV; t += NT) {
-    const int pp = t / NV, w = t % NV;
-    Dual<1> qd[NV];
-    double qv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      qv[v] = a.lv.q_ref[v] + sq[v * NP + pp];
-      qd[v] = dconst<1>(qv[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) qd[v].d[0] = (v == w) ? 1.0 : 0.0;
-    const size_t gp = (size_t)pp * ne + e;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      Dual<1> fl[NV];
-      normal_flux3(qd, a.lv.met[(3 * d) * sstride + gp], a.lv.met[(3 * d + 1) * sstride + gp],
-                   a.lv.met[(3 * d + 2) * sstride + gp], a.gas, fl);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sA[d * NP * NV * NV + (pp * NV + v) * NV + w] = fl[v].d[0];
-    }
-    Dual<1> qc[NV];
-    conservative3(qd, a.gas, qc);
-    const State3<double> s = make_state3(qv, a.gas);
-    double ew[NV], gcol[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ew[v] = (v == w) ? 1.0 : 0.0;
-    gamma_mul3(s, a.gas, ew, gcol);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sDg[(pp * NV + v) * NV + w] = gcol[v] * a.inv_dtau + a.c_mass * qc[v].d[0];
-  }
-  for (int t = tid; t < 6 * NF * NV; t += NT) {
-    const int f = t / (NF * NV), kf = (t / NV) % NF, w = t % NV;
-    const int k1 = kf % N1, k2 = kf / N1;
-    const double* wt = (f % 2 == 0) ? o.lm : o.lp;
-    double ownv[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int m = 0; m < N1; ++m) {
-      const int pp = line_point3(f, k1, k2, m, N1);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ownv[v] += wt[m] * sq[v * NP + pp];
-    }
-    Dual<1> own[NV], out[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) own[v] = dconst<1>(ownv[v]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) own[v].d[0] = (v == w) ? 1.0 : 0.0;
-    const size_t fo = ((size_t)(f * NF + kf) * 4) * ne + e;
-    const double nx = a.lv.fvec[fo], ny = a.lv.fvec[fo + ne], nz = a.lv.fvec[fo + 2 * ne],
-                 sm = a.lv.fvec[fo + 3 * ne];
-    const int nb = a.lv.nbr[f * ne + e];
-    if (nb >= 0) {
-      const int nfa = a.lv.nbf[f * ne + e];
-      int na, nbb;
-      orient3(a.lv.ori[f * ne + e], k1, k2, N1, na, nbb);
-      const double* wn = (nfa % 2 == 0) ? o.lm : o.lp;
-      double ov[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int m = 0; m < N1; ++m) {
-        const int pp = line_point3(nfa, na, nbb, m, N1);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) ov[v] += wn[m] * a.q[v * sstride + (size_t)pp * ne + nb];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(ov[v]);
-    } else if (nb == -1) {
-      Dual<1> ua = own[1] + a.lv.q_ref[1], va = own[2] + a.lv.q_ref[2], wa = own[3] + a.lv.q_ref[3];
-      Dual<1> un = ua * nx + va * ny + wa * nz;
-      out[0] = own[0];
-      out[1] = ua - 2.0 * un * nx - a.lv.q_ref[1];
-      out[2] = va - 2.0 * un * ny - a.lv.q_ref[2];
-      out[3] = wa - 2.0 * un * nz - a.lv.q_ref[3];
-      out[4] = own[4];
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = dconst<1>(a.lv.qinf_g[v]);
-    }
-    Dual<1> own_a[NV], out_a[NV], dq[NV], fh[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      own_a[v] = own[v] + a.lv.q_ref[v];
-      out_a[v] = out[v] + a.lv.q_ref[v];
-    }
-    if (f % 2 == 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dq[v] = own[v] - out[v];
-      common_flux3(out_a, own_a, dq, nx, ny, nz, sm, a.gas, fh);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dq[v] = out[v] - own[v];
-      common_flux3(own_a, out_a, dq, nx, ny, nz, sm, a.gas, fh);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sB[((f * NF + kf) * NV + v) * NV + w] = fh[v].d[0];
-  }
-}
-
-// Entry (row pp Nv + v, column ss Nv + w) of D_e from the pointwise derivatives: a point couples to
-// the points of its three tensor lines through the divergence and the g_DG corrections of its own
-// and the faces' fluxes (scaled by 1/|J| of the row's point), plus the diagonal term.
-template <int P>
-__device__ __forceinline__ double block_entry3(const Ops1D& o, const double* sA, const double* sDg,
-                                               const double* sB, int pp, int v, int ss, int w, double ijac) {
-  constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5;
-  const int ii = pp % N1, jj = (pp / N1) % N1, kk = pp / (N1 * N1);
-  const int ai = ss % N1, bj = (ss / N1) % N1, ck = ss / (N1 * N1);
-  double acc = 0.0;
-  if (bj == jj && ck == kk) {
-    const double cx = o.D[ii * N1 + ai] - o.gL[ii] * o.lm[ai] - o.gR[ii] * o.lp[ai];
-    const int kf = jj + N1 * kk;
-    acc += cx * sA[(ss * NV + v) * NV + w] + o.gL[ii] * o.lm[ai] * sB[((0 * NF + kf) * NV + v) * NV + w] +
-           o.gR[ii] * o.lp[ai] * sB[((1 * NF + kf) * NV + v) * NV + w];
-  }
-  if (ai == ii && ck == kk) {
-    const double cy = o.D[jj * N1 + bj] - o.gL[jj] * o.lm[bj] - o.gR[jj] * o.lp[bj];
-    const int kf = ii + N1 * kk;
-    acc += cy * sA[NP * NV * NV + (ss * NV + v) * NV + w] +
-           o.gL[jj] * o.lm[bj] * sB[((2 * NF + kf) * NV + v) * NV + w] +
-           o.gR[jj] * o.lp[bj] * sB[((3 * NF + kf) * NV + v) * NV + w];
-  }
-  if (ai == ii && bj == jj) {
-    const double cz = o.D[kk * N1 + ck] - o.gL[kk] * o.lm[ck] - o.gR[kk] * o.lp[ck];
-    const int kf = ii + N1 * jj;
-    acc += cz * sA[2 * NP * NV * NV + (ss * NV + v) * NV + w] +
-           o.gL[kk] * o.lm[ck] * sB[((4 * NF + kf) * NV + v) * NV + w] +
-           o.gR[kk] * o.lp[ck] * sB[((5 * NF + kf) * NV + v) * NV + w];
-  }
-  double dval = acc * ijac;
-  if (pp == ss) dval += sDg[(pp * NV + v) * NV + w];
-  return dval;
-}
-
-template <int P, int S>
-__global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
-  using C = Rows3<P, S>;
-  constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NJ = C::NJ, H = C::H, NW = C::NW, NT = C::NT,
-                NPAD = C::NPAD;
-  __shared__ double sq[NV * NP];
-  __shared__ double sA[3 * NP * NV * NV];
-  __shared__ double sDg[NP * NV * NV];
-  __shared__ double sB[6 * NF * NV * NV];
-  __shared__ double sscl[NJ];
-  __shared__ int sperm[NJ];
-  __shared__ double slot[2][NW][NJ];
-  __shared__ unsigned skey[2][NW];
-
-  const int ne = a.lv.ne;
-  const int e = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  const size_t sstride = (size_t)NP * ne;
-
-  element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
-  __syncthreads();
-
-  const bool has_row = tid < S * NJ;
-  const int r = has_row ? tid / S : 0;
-  const int h = (S > 1) ? (tid % S) : 0;
-  const bool real_row = has_row && r < N;
-  const int pp = real_row ? r / NV : 0, v = r % NV;
-  const double ijac = a.lv.met[9 * sstride + (size_t)pp * ne + e];
-  double row[H];
-#pragma unroll
-  for (int jc = 0; jc < H; ++jc) {
-    const int c = h * H + jc;
-    double dval = 0.0;
-    if (real_row && c < N) {
-      dval = block_entry3<P>(a.ops, sA, sDg, sB, pp, v, c / NV, c % NV, ijac);
-    } else if (has_row && !real_row) {
-      dval = (c == r) ? 1.0 : 0.0;                // padding: identity row
-    }
-    row[jc] = dval;
-  }
-  if (a.D_out && real_row) {
-#pragma unroll
-    for (int jc = 0; jc < H; ++jc)
-      if (h * H + jc < N) a.D_out[((size_t)e * N + r) * N + h * H + jc] = row[jc];
-  }
-  double mx = 0.0;
-#pragma unroll
-  for (int jc = 0; jc < H; ++jc) mx = fmax(mx, fabs(row[jc]));
-  if (S == 4) {
-    mx = fmax(mx, __shfl_xor(mx, 1, 64));
-    mx = fmax(mx, __shfl_xor(mx, 2, 64));
-  }
-  int ex = 0;
-  frexp(mx, &ex);
-  const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
-#pragma unroll
-  for (int jc = 0; jc < H; ++jc) row[jc] *= scl;
-  if (has_row && h == 0) sscl[r] = scl;
-
-  bool used = !has_row;
-  int my_step = 0;
-  double my_inv = 1.0;
-  bool bad = false;
-  for (int kstep = 0; kstep < NJ; ++kstep) {
-    const int par = kstep & 1;
-    const double fval = (S == 4) ? quad_dpp<kQuadFirst>(row[0]) : row[0];
-    const unsigned key = (used || h != 0) ? 0u
-                         : ((((unsigned)__double2hiint(fabs(fval))) & ~0x3FFu) | (unsigned)(1023 - tid));
-    const unsigned wkey = wave_max3(key);
-    const int wtid = 1023 - (int)(wkey & 0x3FFu);
-    if (wkey != 0u && tid >= wtid && tid < wtid + S) {
-#pragma unroll
-      for (int jc = 0; jc < H; ++jc) slot[par][wv][h * H + jc] = row[jc];
-    }
-    if (lane == 0) skey[par][wv] = wkey;
-    __syncthreads();
-    int win = 0;
-    unsigned bk = skey[par][0];
-#pragma unroll
-    for (int w2 = 1; w2 < NW; ++w2) {
-      const unsigned k2 = skey[par][w2];
-      win = (k2 > bk) ? w2 : win;
-      bk = (k2 > bk) ? k2 : bk;
-    }
-    int pr_row = (1023 - (int)(bk & 0x3FFu)) / S;
-    if (bk == 0u || pr_row >= NJ) {
-      bad = true;
-      pr_row = (pr_row < NJ && pr_row >= 0) ? pr_row : NJ - 1;
-    }
-    const double* prw = slot[par][win];
-    double piv = prw[0];
-    if (piv == 0.0 || !isfinite(piv)) {
-      bad = true;
-      piv = 1.0;
-    }
-    const double ip = 1.0 / piv;
-    const bool is_p = has_row && (r == pr_row);
-    if (tid == 0) sperm[kstep] = pr_row;
-    const double g = is_p ? 0.0 : fval * ip;
-    if (is_p) {
-      used = true;
-      my_step = kstep;
-      my_inv = ip;
-    }
-    const double nxt = (S == 4) ? quad_dpp<kQuadNext>(row[0]) : 0.0;
-    const double* prh = prw + h * H;
-    constexpr int B = 16;
-#pragma unroll
-    for (int j0 = 0; j0 < H - 1; j0 += B) {
-      double buf[B];
-#pragma unroll
-      for (int jb = 0; jb < B; ++jb)
-        if (j0 + jb < H - 1) buf[jb] = prh[j0 + jb + 1];
-#pragma unroll
-      for (int jb = 0; jb < B; ++jb)
-        if (j0 + jb < H - 1) row[j0 + jb] = fma(-g, buf[jb], row[j0 + jb + 1]);
-    }
-    if (S == 4 && h < S - 1)
-      row[H - 1] = fma(-g, prw[(h + 1) * H], nxt);
-    else
-      row[H - 1] = is_p ? 1.0 : -g;
-  }
-  if (bad) *a.flag = 1;
-  __syncthreads();
-  if (has_row && my_step < N) {
-#pragma unroll
-    for (int jc = 0; jc < H; ++jc) {
-      const int col = sperm[h * H + jc];
-      if (col >= N) continue;
-      const double val = row[jc] * my_inv * sscl[col];
-      const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
-      if (a.precision == 32)
-        static_cast<float*>(a.W)[o_] = (float)val;
-      else
-        static_cast<double*>(a.W)[o_] = val;
-    }
-  }
-}
-
-// Large element blocks (n = 320 at P = 3): the FP64 block is larger than a compute unit's LDS and
-// registers together, so each workgroup owns a slot of a global work array (n x n column-major,
-// X[c n + r]) and takes elements in turn, one thread per row. Gauss-Jordan elimination with partial
-// pivoting on the row-scaled block, in panels of B columns:
-//   * the panel's B steps run on each row's B panel entries held in registers; the pivot search and
-//     the broadcast of the pivot row go through LDS as in the register kernel. Eliminating in place
-//     (the pivot column's slot receives the transformed unit vector) leaves in the panel the columns
-//     e_p + u of T = I + U E^T, T the product of the panel's elementary transforms, E the unit
-//     vectors of the panel's pivot rows;
-//   * every other column c then takes x_c += U x_c[pivot rows] (U = panel minus the pivot unit
-//     vectors), a rank-B update streamed through the slot in groups of G columns, the pivot rows'
-//     old values staged in LDS.
-// Each thread reads and writes only its own row of the slot, so the slot needs no fences. At the
-// end, physical row p_i of the slot is row i of the inverse with its columns in pivot order:
-// D_e^{-1}[i][p_m] = X[m n + p_i] s_{p_m}, s the row scales.
-template <int P>
-struct Big3 {
-  static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
-  static constexpr int NPAD = (N + 3) / 4 * 4;
-  static constexpr int B = 32, G = 16;
-  static constexpr int NT = N, NW = NT / 64;
-  static constexpr int ASM = NV * NP + 4 * NP * NV * NV + 6 * NF * NV * NV;   // sq, sA, sDg, sB
-  static constexpr int GJ = 2 * NW * B + 2 * B * G;                           // pivot rows, staged x
-  static constexpr int POOL = ASM > GJ ? ASM : GJ;
-  static_assert(N % 64 == 0 && N % B == 0 && B % G == 0, "whole waves, panels and column groups");
-  static_assert(N <= 1023, "pivot keys carry the row in 10 bits");
-};
-
-template <int P>
-__global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __restrict__ ws) {
-  using C = Big3<P>;
-  constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, B = C::B, G = C::G, NW = C::NW,
-                NT = C::NT;
-  __shared__ double pool[C::POOL];
-  __shared__ double sscl[N];
-  __shared__ int sperm[N];
-  __shared__ unsigned skey[2][NW];
-  double* sq = pool;
-  double* sA = sq + NV * NP;
-  double* sDg = sA + 3 * NP * NV * NV;
-  double* sB = sDg + NP * NV * NV;
-  double* slot = pool;              // [2][NW][B], after the assembly
-  double* xs = pool + 2 * NW * B;   // [2][B][G]
-
-  const int ne = a.lv.ne;
-  const int r = threadIdx.x;
-  const int lane = r & 63, wv = r >> 6;
-  const size_t sstride = (size_t)NP * ne;
-  double* X = ws + (size_t)blockIdx.x * N * N;
-  const int pp = r / NV, v = r % NV;
-  const int ii = pp % (P + 1), jj = (pp / (P + 1)) % (P + 1), kk = pp / ((P + 1) * (P + 1));
-  bool bad = false;
-
-  for (int e = blockIdx.x; e < ne; e += gridDim.x) {
-    __syncthreads();                        // the previous element is done with the pool and sperm
-    element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
-    __syncthreads();
-
-    // row r of D_e: the largest entry lies on the row point's three tensor lines
-    const double ijac = a.lv.met[9 * sstride + (size_t)pp * ne + e];
-    double mx = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      for (int m = 0; m <= P; ++m) {
-        const int ss = d == 0 ? m + (P + 1) * (jj + (P + 1) * kk)
-                              : d == 1 ? ii + (P + 1) * (m + (P + 1) * kk) : ii + (P + 1) * (jj + (P + 1) * m);
-        for (int w = 0; w < NV; ++w) mx = fmax(mx, fabs(block_entry3<P>(a.ops, sA, sDg, sB, pp, v, ss, w, ijac)));
-      }
-    }
-    int ex = 0;
-    frexp(mx, &ex);
-    const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
-    sscl[r] = scl;
-    for (int c = 0; c < N; ++c) {
-      const double dval = block_entry3<P>(a.ops, sA, sDg, sB, pp, v, c / NV, c % NV, ijac);
-      X[(size_t)c * N + r] = dval * scl;
-      if (a.D_out) a.D_out[((size_t)e * N + r) * N + c] = dval;
-    }
-    __syncthreads();                        // the pool now holds pivot rows and staged values
-
-    bool used = false;
-    int my_step = 0;
-    for (int k0 = 0; k0 < N; k0 += B) {
-      double row[B];
-#pragma unroll
-      for (int j = 0; j < B; ++j) row[j] = X[(size_t)(k0 + j) * N + r];
-      // column cycling: before step j the row holds columns k0 + j .. k0 + B - 1, then the slots
-      // of steps 0 .. j - 1; each step consumes entry 0 and appends its own slot, so after the
-      // panel the row holds the B slots in step order
-#pragma unroll 1
-      for (int j = 0; j < B; ++j) {
-        const int par = j & 1;
-        const double fv = row[0];
-        const unsigned key =
-            used ? 0u : ((((unsigned)__double2hiint(fabs(fv))) & ~0x3FFu) | (unsigned)(1023 - r));
-        const unsigned wkey = wave_max3(key);
-        if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {
-#pragma unroll
-          for (int c = 0; c < B; ++c) slot[(par * NW + wv) * B + c] = row[c];
-        }
-        if (lane == 0) skey[par][wv] = wkey;
-        __syncthreads();
-        int win = 0;
-        unsigned bk = skey[par][0];
-#pragma unroll
-        for (int w2 = 1; w2 < NW; ++w2) {
-          const unsigned k2 = skey[par][w2];
-          win = (k2 > bk) ? w2 : win;
-          bk = (k2 > bk) ? k2 : bk;
-        }
-        int pr = 1023 - (int)(bk & 0x3FFu);
-        if (bk == 0u || pr >= N) {
-          bad = true;
-          pr = 0;
-        }
-        const double* prw = slot + (par * NW + win) * B;
-        double piv = prw[0];
-        if (piv == 0.0 || !isfinite(piv)) {
-          bad = true;
-          piv = 1.0;
-        }
-        const double ip = 1.0 / piv;
-        const bool is_p = (r == pr);
-        if (r == 0) sperm[k0 + j] = pr;
-        if (is_p) {
-          used = true;
-          my_step = k0 + j;
-        }
-        const double g = is_p ? 0.0 : fv * ip;
-        const double mul = is_p ? ip : 1.0;
-#pragma unroll
-        for (int c = 0; c < B - 1; ++c) row[c] = fma(-g, prw[c + 1], row[c + 1] * mul);
-        row[B - 1] = is_p ? ip : -g;
-      }
-      const int ms = (used && my_step >= k0) ? my_step - k0 : -1;   // this row's step in the panel
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        X[(size_t)(k0 + j) * N + r] = row[j];
-        if (j == ms) row[j] -= 1.0;         // row now holds U's row
-      }
-      int buf = 0;
-      for (int cg = 0; cg < N; cg += G) {
-        if (cg >= k0 && cg < k0 + B) continue;
-        double* xb = xs + buf * B * G;
-        double av[G];
-#pragma unroll
-        for (int t = 0; t < G; ++t) av[t] = X[(size_t)(cg + t) * N + r];
-        if (ms >= 0) {
-#pragma unroll
-          for (int t = 0; t < G; ++t) xb[ms * G + t] = av[t];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < B; ++m) {
-#pragma unroll
-          for (int t = 0; t < G; ++t) av[t] = fma(row[m], xb[m * G + t], av[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < G; ++t) X[(size_t)(cg + t) * N + r] = av[t];
-        buf ^= 1;
-      }
-    }
-    __syncthreads();                        // sperm and sscl complete
-    for (int m = 0; m < N; ++m) {
-      const int col = sperm[m];
-      const double val = X[(size_t)m * N + r] * sscl[col];
-      const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
-      if (a.precision == 32)
-        static_cast<float*>(a.W)[o_] = (float)val;
-      else
-        static_cast<double*>(a.W)[o_] = val;
-    }
-  }
-  if (bad) *a.flag = 1;
-}
-
 // ---- transfers and pointwise helpers ----------------------------------------------------------
 
 struct Mat1D3 {
@@ -1051,39 +524,6 @@ hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const d
   a.q_out = q_out;
   if (fac.precision == 32) return launch_fr3<2>(L.P, a, L.ne, st);
   return launch_fr3<1>(L.P, a, L.ne, st);
-}
-
-template <int P, int S>
-static hipError_t launch_jac3_p(const JacArgs3& a, int ne, hipStream_t st) {
-  hipLaunchKernelGGL((k_jac3_rows<P, S>), dim3(ne), dim3(Rows3<P, S>::NT), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
-                            pmg_factors_s& fac, hipStream_t st) {
-  JacArgs3 a{};
-  a.lv = L.view();
-  a.ops = L.ops;
-  a.gas = L.gas;
-  a.q = q;
-  a.inv_dtau = 1.0 / dtau;
-  a.c_mass = c_mass;
-  a.D_out = D_out;
-  a.W = fac.W;
-  a.precision = fac.precision;
-  a.flag = L.flag;
-  switch (L.P) {
-    case 0: return launch_jac3_p<0, 1>(a, L.ne, st);
-    case 1: return launch_jac3_p<1, 1>(a, L.ne, st);
-    case 2: return launch_jac3_p<2, 4>(a, L.ne, st);
-    case 3: {
-      if (!fac.ws || fac.ws_slots <= 0) return hipErrorInvalidValue;
-      const int grid = fac.ws_slots < L.ne ? fac.ws_slots : L.ne;
-      hipLaunchKernelGGL(k_jac3_big<3>, dim3(grid), dim3(Big3<3>::NT), 0, st, a, fac.ws);
-      return hipGetLastError();
-    }
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_restrict3(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,

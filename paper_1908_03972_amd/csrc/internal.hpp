@@ -138,7 +138,7 @@ hipError_t launch_visc_jacobian(const pmg_level_s& L, const double* q, hipStream
 int dtau_blocks(const pmg_level_s& L);
 hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st);
 
-// hexahedral levels (fr3_kernels.hip)
+// hexahedral levels (fr3_kernels.hip; element blocks in jac3_kernels.hip)
 int residual_blocks3(const pmg_level_s& L);
 hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double* src, const double* S,
                             double c_mass, double* F, bool want_norms, hipStream_t st);
