@@ -377,6 +377,7 @@ def main():
     ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
     ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere steady solves")
     ap.add_argument("--no-sphere-p3", action="store_true", help="skip the 3-D sphere P{3-2-1-0} steady solves")
+    ap.add_argument("--no-sphere-p2", action="store_true", help="skip the 3-D sphere P{2-1-0} steady solves")
     ap.add_argument("--sphere-vcycles", type=int, default=200)
     ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
     args = ap.parse_args()
@@ -511,8 +512,9 @@ def main():
     if not args.no_viscous:
         line["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
     if not args.no_sphere:
-        line["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, args.forms.split(","),
-                                                                args.sphere_vcycles, args.kernel_reps)
+        if not args.no_sphere_p2:
+            line["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, args.forms.split(","),
+                                                                    args.sphere_vcycles, args.kernel_reps)
         if not args.no_sphere_p3:
             line["sphere_cubed_16x16x24_P3_steady"] = sphere_block(
                 api, torch, args.forms.split(","), args.sphere_vcycles, args.kernel_reps, plev=(3, 2, 1, 0),

@@ -13,6 +13,8 @@ namespace pmg {
 
 // ---- element blocks (eqs. (28)-(30)) and their inverses ----------------------------------
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 struct JacArgs3 {
   LevelView lv;
   Ops1D ops;
@@ -359,21 +361,23 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
 //     e_p + u of T = I + U E^T, T the product of the panel's elementary transforms, E the unit
 //     vectors of the panel's pivot rows;
 //   * every other column c then takes x_c += U x_c[pivot rows] (U = panel minus the pivot unit
-//     vectors), a rank-B update streamed through the slot in groups of G columns, the pivot rows'
-//     old values staged in LDS.
-// Each thread reads and writes only its own row of the slot, so the slot needs no fences. At the
-// end, physical row p_i of the slot is row i of the inverse with its columns in pivot order:
+//     vectors), a rank-B update streamed through the slot in groups of 16 columns on the FP64
+//     matrix cores (16x16x4 tiles), every wave reading its old values before a barrier and
+//     writing after it.
+// Barriers order the slot's accesses across the lanes of a wave. At the end, physical row p_i of
+// the slot is row i of the inverse with its columns in pivot order:
 // D_e^{-1}[i][p_m] = X[m n + p_i] s_{p_m}, s the row scales.
 template <int P>
 struct Big3 {
   static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
   static constexpr int NPAD = (N + 3) / 4 * 4;
-  static constexpr int B = 32, G = 16;
+  static constexpr int B = 32, G = 16;   // panel width; columns per matrix-core tile
   static constexpr int NT = N, NW = NT / 64;
   static constexpr int ASM = NV * NP + 4 * NP * NV * NV + 6 * NF * NV * NV;   // sq, sA, sDg, sB
-  static constexpr int GJ = 2 * NW * B + 2 * B * G;                           // pivot rows, staged x
+  static constexpr int GJ = 2 * NW * B;                                       // pivot rows
   static constexpr int POOL = ASM > GJ ? ASM : GJ;
-  static_assert(N % 64 == 0 && N % B == 0 && B % G == 0, "whole waves, panels and column groups");
+  static_assert(N % 64 == 0 && N % B == 0 && B % G == 0 && B % 4 == 0 && G == 16,
+                "whole waves of four 16-row tiles, panels and 16-column groups");
   static_assert(N <= 1023, "pivot keys carry the row in 10 bits");
 };
 
@@ -391,7 +395,6 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
   double* sDg = sA + 3 * NP * NV * NV;
   double* sB = sDg + NP * NV * NV;
   double* slot = pool;              // [2][NW][B], after the assembly
-  double* xs = pool + 2 * NW * B;   // [2][B][G]
 
   const int ne = a.lv.ne;
   const int r = threadIdx.x;
@@ -482,33 +485,51 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
         for (int c = 0; c < B - 1; ++c) row[c] = fma(-g, prw[c + 1], row[c + 1] * mul);
         row[B - 1] = is_p ? ip : -g;
       }
-      const int ms = (used && my_step >= k0) ? my_step - k0 : -1;   // this row's step in the panel
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        X[(size_t)(k0 + j) * N + r] = row[j];
-        if (j == ms) row[j] -= 1.0;         // row now holds U's row
+      for (int j = 0; j < B; ++j) X[(size_t)(k0 + j) * N + r] = row[j];
+      __syncthreads();                      // the panel is visible to the other lanes of each wave
+      // Rank-B update of every other column on the FP64 matrix cores, wave wv taking rows
+      // 64 wv .. 64 wv + 63 as four tiles of 16: per 16 columns cg.., D = X_p^T U^T + C with
+      //   A[i][k] = X_p[k][i]: lane i + 16 k holds the old value of column cg + i in the pivot row
+      //             of step k0 + 4 s + k,
+      //   B[k][j] = U[r0 + j][4 s + k]: lane j + 16 k (U = panel minus the pivot unit vectors),
+      //   C, D[i][j] = X[cg + i][r0 + j]: lane j + 16 (i mod 4), register i / 4,
+      // so that the 16 lanes of a register cover 16 consecutive rows of one column.
+      const int lr = lane & 15, lk = lane >> 4;
+      double uop[4][B / 4];
+#pragma unroll
+      for (int T = 0; T < 4; ++T) {
+#pragma unroll
+        for (int s4 = 0; s4 < B / 4; ++s4) {
+          const int row_ = 64 * wv + 16 * T + lr, m = 4 * s4 + lk;
+          const double u = X[(size_t)(k0 + m) * N + row_];
+          uop[T][s4] = (sperm[k0 + m] == row_) ? u - 1.0 : u;
+        }
       }
-      int buf = 0;
       for (int cg = 0; cg < N; cg += G) {
         if (cg >= k0 && cg < k0 + B) continue;
-        double* xb = xs + buf * B * G;
-        double av[G];
+        double xop[B / 4];
 #pragma unroll
-        for (int t = 0; t < G; ++t) av[t] = X[(size_t)(cg + t) * N + r];
-        if (ms >= 0) {
+        for (int s4 = 0; s4 < B / 4; ++s4) xop[s4] = X[(size_t)(cg + lr) * N + sperm[k0 + 4 * s4 + lk]];
+        dbl4 acc[4];
 #pragma unroll
-          for (int t = 0; t < G; ++t) xb[ms * G + t] = av[t];
+        for (int T = 0; T < 4; ++T) {
+#pragma unroll
+          for (int v2 = 0; v2 < 4; ++v2) acc[T][v2] = X[(size_t)(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr];
         }
-        __syncthreads();
+        __syncthreads();                    // every wave holds its old values before any wave stores
 #pragma unroll
-        for (int m = 0; m < B; ++m) {
+        for (int s4 = 0; s4 < B / 4; ++s4) {
 #pragma unroll
-          for (int t = 0; t < G; ++t) av[t] = fma(row[m], xb[m * G + t], av[t]);
+          for (int T = 0; T < 4; ++T) acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(xop[s4], uop[T][s4], acc[T], 0, 0, 0);
         }
 #pragma unroll
-        for (int t = 0; t < G; ++t) X[(size_t)(cg + t) * N + r] = av[t];
-        buf ^= 1;
+        for (int T = 0; T < 4; ++T) {
+#pragma unroll
+          for (int v2 = 0; v2 < 4; ++v2) X[(size_t)(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr] = acc[T][v2];
+        }
       }
+      __syncthreads();                      // the updated columns are visible before the next panel
     }
     __syncthreads();                        // sperm and sscl complete
     for (int m = 0; m < N; ++m) {
