@@ -277,7 +277,8 @@ pmg_status esdirk_stage_solve(const pmg_solve_opts* opts, double omega, double d
  * and the implicit stages solved by esdirk_stage_solve (the schemes are stiffly accurate, so
  * q^{n+1} is the last stage value).
  *   scheme  2: ESDIRK2, three stages (Kennedy & Carpenter), 3: ESDIRK3, four stages
- *           (ESDIRK3(2)4L[2]SA), the schemes cited in Sec. 2.4.
+ *           (ESDIRK3(2)4L[2]SA), 4: ESDIRK4, six stages (ESDIRK4(3)6L[2]SA), the schemes cited
+ *           in Sec. 2.4.
  *   q       device state, in q^n, out q^{n+1}.
  *   work    device, (number of stages) consecutive state arrays: q_c^n and the stage residuals.
  *   stats   host array of n_stats entries or NULL: one per implicit stage.
@@ -288,7 +289,7 @@ pmg_status esdirk_stage_solve(const pmg_solve_opts* opts, double omega, double d
 pmg_status esdirk_step(const pmg_solve_opts* opts, int32_t scheme, double dt, double* q, double* work,
                        pmg_solve_stats* stats, int32_t n_stats, void* stream);
 
-/* Number of stages of an ESDIRK scheme id (3 or 4), or 0 for an unknown id. */
+/* Number of stages of an ESDIRK scheme id (3, 4 or 6), or 0 for an unknown id. */
 int32_t esdirk_stages(int32_t scheme);
 
 /*

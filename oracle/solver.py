@@ -39,6 +39,9 @@ def esdirk_tableau(name: str) -> np.ndarray:
     gamma = 1 - sqrt(2)/2, c = (0, 2 gamma, 1) (Kennedy & Carpenter, as cited in Sec. 2.4).
     ESDIRK3: the four-stage ESDIRK3(2)4L[2]SA scheme of Kennedy & Carpenter (the
     implicit part of ARK3(2)4L[2]SA), the third-order scheme the paper cites.
+    ESDIRK4: the six-stage ESDIRK4(3)6L[2]SA scheme of Kennedy & Carpenter (the implicit part
+    of ARK4(3)6L[2]SA), gamma = 1/4, c = (0, 1/2, 83/250, 31/50, 17/20, 1), the fourth-order
+    scheme of Sec. 2.4.
     """
     if name == "esdirk2":
         g = 1.0 - math.sqrt(2.0) / 2.0
@@ -52,6 +55,16 @@ def esdirk_tableau(name: str) -> np.ndarray:
              11266239266428.0 / 11593286722821.0, g]
         return np.array([[0.0, 0.0, 0.0, 0.0], [g, g, 0.0, 0.0],
                          [a31, a32, g, 0.0], b])
+    if name == "esdirk4":
+        g = 0.25
+        A = np.zeros((6, 6))
+        A[1, :2] = [g, g]
+        A[2, :3] = [8611 / 62500, -1743 / 31250, g]
+        A[3, :4] = [5012029 / 34652500, -654441 / 2922500, 174375 / 388108, g]
+        A[4, :5] = [15267082809 / 155376265600, -71443401 / 120774400, 730878875 / 902184768,
+                    2285395 / 8070912, g]
+        A[5, :] = [82889 / 524892, 0.0, 15625 / 83664, 69875 / 102672, -2260 / 8211, g]
+        return A
     raise ValueError(name)
 
 

@@ -1060,6 +1060,18 @@ int esdirk_tableau(int scheme, double* A) {
     std::memcpy(A, t, sizeof(t));
     return 4;
   }
+  if (scheme == 4) {            // ESDIRK4(3)6L[2]SA, gamma = 1/4, c = (0, 1/2, 83/250, 31/50, 17/20, 1)
+    const double g = 0.25;
+    const double t[36] = {0, 0, 0, 0, 0, 0,
+                          g, g, 0, 0, 0, 0,
+                          8611.0 / 62500.0, -1743.0 / 31250.0, g, 0, 0, 0,
+                          5012029.0 / 34652500.0, -654441.0 / 2922500.0, 174375.0 / 388108.0, g, 0, 0,
+                          15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0, 730878875.0 / 902184768.0,
+                          2285395.0 / 8070912.0, g, 0,
+                          82889.0 / 524892.0, 0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, g};
+    std::memcpy(A, t, sizeof(t));
+    return 6;
+  }
   return 0;
 }
 

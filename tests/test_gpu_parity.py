@@ -246,9 +246,10 @@ def test_stage_solve_parity(case):
         assert np.all(h_err <= max(1e-11, 10.0 * h_floor32))
 
 
-def test_esdirk_step_parity():
-    """One ESDIRK2 time step (eq. (24)) through the C ABI against the oracle's driver, stages
-    converged to a 1e-4 relative drop."""
+@pytest.mark.parametrize("scheme,name", [(2, "esdirk2"), (3, "esdirk3"), (4, "esdirk4")])
+def test_esdirk_step_parity(scheme, name):
+    """One ESDIRK2, ESDIRK3 or ESDIRK4 time step (eq. (24)) through the C ABI against the oracle's
+    driver, stages converged to a 1e-4 relative drop."""
     from gpu_helpers import gas_for
     mesh = MESHES["cfg1_8x8"]()
     plev, nsm = (2, 1, 0), (5, 10, 20)
@@ -256,19 +257,21 @@ def test_esdirk_step_parity():
     opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, tol=1e-4, max_vcycles=60)
     osol = OS.PMGSolver(mesh, gas, opts, q_inf=VS.freestream())
     q0 = vortex_on(osol.levels[0], VS)
-    q_ref, st_ref = osol.esdirk_step(q0, 0.05, OS.esdirk_tableau("esdirk2"))
+    tab = OS.esdirk_tableau(name)
+    q_ref, st_ref = osol.esdirk_step(q0, 0.05, tab)
     qinf = VS.freestream()
     glevels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf,
                          q_ref=REF) for P in plev]
     facs = [api.Factors(lv, 64) for lv in glevels]
     solver = api.StageSolver(glevels, facs, nsm, tol_rel=1e-4, max_vcycles=60)
     q = to_dev(q0 - REF)
-    work = torch.zeros((3,) + glevels[0].shape, dtype=torch.float64, device="cuda")
-    stats = api.esdirk_step(solver, 2, 0.05, q, work)
+    assert api.esdirk_stages(scheme) == tab.shape[0]
+    work = torch.zeros((tab.shape[0],) + glevels[0].shape, dtype=torch.float64, device="cuda")
+    stats = api.esdirk_step(solver, scheme, 0.05, q, work)
     torch.cuda.synchronize()
     assert [s["n_vcycles"] for s in stats] == [s.n_vcycles for s in st_ref]
     err = rel_err_per_var(from_dev(q), q_ref - qinf)
-    print("esdirk step err", err, [s["n_vcycles"] for s in stats])
+    print(name, "step err", err, [s["n_vcycles"] for s in stats])
     assert np.all(err < 1e-8), err
 
 

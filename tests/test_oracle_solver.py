@@ -94,7 +94,7 @@ def test_vcycle_reduces_stage_residual():
     assert st.refreshes == [0]
 
 
-@pytest.mark.parametrize("name,order", [("esdirk2", 2), ("esdirk3", 3)])
+@pytest.mark.parametrize("name,order", [("esdirk2", 2), ("esdirk3", 3), ("esdirk4", 4)])
 def test_esdirk_tableau_order_and_l_stability(name, order):
     A = S.esdirk_tableau(name)
     b, c = A[-1], A.sum(axis=1)
@@ -104,6 +104,12 @@ def test_esdirk_tableau_order_and_l_stability(name, order):
         assert abs(b @ c ** 2 - 1 / 3) < 1e-14 and abs(b @ (A @ c) - 1 / 6) < 1e-14
     else:
         assert abs(b @ c ** 2 - 1 / 3) > 1e-3
+    # the four fourth-order conditions (Butcher trees of order 4)
+    o4 = [b @ c ** 3 - 1 / 4, b @ (c * (A @ c)) - 1 / 8, b @ (A @ c ** 2) - 1 / 12, b @ (A @ (A @ c)) - 1 / 24]
+    if order >= 4:
+        assert np.max(np.abs(o4)) < 1e-14, o4
+    else:
+        assert np.max(np.abs(o4)) > 1e-4
     # stability function R(z) = 1 + z b^T (I - zA)^{-1} 1 -> 0 as z -> -inf (L-stable, stiffly accurate)
     z = -1e8
     Rz = 1 + z * b @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b)))
@@ -127,7 +133,7 @@ def _newton_stage(lev, q, c_mass, src, tol=1e-12):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name,order", [("esdirk2", 2), ("esdirk3", 3)])
+@pytest.mark.parametrize("name,order", [("esdirk2", 2), ("esdirk3", 3), ("esdirk4", 4)])
 def test_esdirk_driver_temporal_order(name, order):
     """Self-convergence in dt of the ESDIRK source construction (eq. (26)) with exact stage solves."""
     mesh = W.periodic_quad_mesh(2, 10.0)
@@ -154,4 +160,6 @@ def test_esdirk_driver_temporal_order(name, order):
     e1 = np.linalg.norm(sols[0] - sols[1])
     e2 = np.linalg.norm(sols[1] - sols[2])
     rate = math.log2(e1 / e2)
-    assert abs(rate - order) < 0.2, rate
+    # steps of T/4 .. T/16 are pre-asymptotic for the fourth-order scheme (measured 4.34); the band
+    # still separates it from third and fifth order
+    assert abs(rate - order) < (0.4 if order == 4 else 0.2), rate
