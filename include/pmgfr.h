@@ -70,7 +70,7 @@ int32_t pmg_abi_version(void);
  * the call.
  *   dim          2 (quadrilaterals) or 3 (hexahedra: inviscid, P <= 3, slip wall and far field,
  *                primitive variables (p, u, v, w, T), Nv = 5).
- *   P            solution degree, 0..6 in 2-D (element blocks need P <= 4), 0..3 in 3-D.
+ *   P            solution degree, 0..6 in 2-D (element blocks need P <= 5), 0..3 in 3-D.
  *   geom_order   1 (bilinear / trilinear) or 2 (9-node / 27-node quadratic).
  *   nodes        2-D [Ne][(g+1)^2][2], 3-D [Ne][(g+1)^3][3] geometry nodes in tensor order, xi
  *                fastest, at reference coordinates (-1 + 2a/g, -1 + 2b/g[, -1 + 2c/g]).

@@ -615,7 +615,7 @@ pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) 
   if (pmg_status s = check_level(L)) return s;
   if (!out) return fail(PMG_E_ARG, "null output");
   if (precision != 32 && precision != 64) return fail(PMG_E_ARG, "precision must be 32 or 64");
-  if (L->P > 4) return fail(PMG_E_ARG, "element blocks are supported for P <= 4");
+  if (L->P > 5) return fail(PMG_E_ARG, "element blocks are supported for P <= 5");
   if (L->dim == 3 && L->P > 3) return fail(PMG_E_ARG, "3-D element blocks are supported for P <= 3");
   DeviceGuard guard(L->device);
   pmg_factors_s* F = new pmg_factors_s();

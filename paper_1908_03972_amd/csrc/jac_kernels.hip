@@ -135,9 +135,9 @@ __device__ __forceinline__ void face_jacobian(const JacArgs& a, int e, const dou
   for (int v = 0; v < NV; ++v) sB[((f * N1 + k) * NV + v) * NV + w] = fh[v].d[0];
 }
 
-// Same blocks for any P <= 4 with each row of D_e held in registers by S threads (S = 1, or 2
-// for n >= 64: thread 2r holds columns [0, n/2) of row r, thread 2r+1 columns [n/2, n)), in
-// ceil(S n / 64) wavefronts per element. The elimination is Gauss-Jordan with implicit partial
+// Same blocks for any P <= 5 with each row of D_e held in registers by S threads (S = 1; 2 for
+// n = 100, thread 2r holding columns [0, n/2) of row r and thread 2r+1 columns [n/2, n); 4 for
+// n = 144, a quarter of the row each), in ceil(S n / 64) wavefronts per element. The elimination is Gauss-Jordan with implicit partial
 // pivoting (the pivot row is chosen among rows not yet used; no rows move) in the
 // column-cycling form: step k always eliminates with the first stored column, every row shifts
 // left by one and the new column of the inverse enters at the right end, so that after n steps
@@ -150,8 +150,12 @@ struct RowsCfg {
   static constexpr int H = N / S;                 // columns per thread
   static constexpr int NW = (S * N + 63) / 64;
   static constexpr int NT = 64 * NW;
-  static_assert(N % S == 0 && (S == 1 || S == 2), "one or two threads per row");
-  static_assert(S * N <= 254, "pivot keys carry the thread index in 8 bits");
+  static_assert(N % S == 0 && (S == 1 || S == 2 || S == 4), "one, two or four threads per row");
+  static_assert(S * N <= 1023, "pivot keys carry the thread index in 10 bits");
+  // DPP quad permutations: every lane of a row's group takes the group's first lane (the row's
+  // entry in the current column), or the next lane of the group (its first stored column)
+  static constexpr int kFirst = S == 2 ? 0xA0 : 0x00;   // [0,0,2,2] or [0,0,0,0]
+  static constexpr int kNext = S == 2 ? 0xF5 : 0xF9;    // [1,1,3,3] or [1,2,3,3]
 };
 
 // Maximum of an unsigned value over the 64 lanes of a wavefront, returned to every lane: DPP
@@ -166,15 +170,13 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   return max(max(a, b), max(c, d));
 }
 
-// A double from a fixed lane of each pair (lane 2m or 2m+1) with a DPP quad permutation.
+// A double from another lane of the same quad, selected by a DPP quad permutation.
 template <int CTRL>
 __device__ __forceinline__ double pair_dpp(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
-constexpr int kQuadEven = 0xA0;   // quad_perm [0,0,2,2]: the even lane of each pair
-constexpr int kQuadOdd = 0xF5;    // quad_perm [1,1,3,3]: the odd lane of each pair
 
 template <int P, int S>
 __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
 
   const bool has_row = tid < S * N;
   const int r = has_row ? tid / S : 0;
-  const int h = (S == 2) ? (tid & 1) : 0;         // which half of the row this thread holds
+  const int h = (S > 1) ? (tid % S) : 0;          // which part of the row this thread holds
   const int pp = r / NV, v = r % NV, i = pp % N1, jj = pp / N1;
   const double ijac = a.lv.met[4 * sstride + (size_t)pp * ne + e];
   double row[H];
@@ -237,7 +239,8 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
   double mx = 0.0;                        // row equilibration by a power of two
 #pragma unroll
   for (int j = 0; j < H; ++j) mx = fmax(mx, fabs(row[j]));
-  if (S == 2) mx = fmax(mx, __shfl_xor(mx, 1, 64));
+  if (S >= 2) mx = fmax(mx, __shfl_xor(mx, 1, 64));
+  if (S == 4) mx = fmax(mx, __shfl_xor(mx, 2, 64));
   int ex = 0;
   frexp(mx, &ex);
   const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
@@ -251,21 +254,21 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
   // fused multiply-add per column per step with no divergent branch.
   //
   // Pivot choice: a 32-bit key per row (on the thread holding its first column), the upper word
-  // of |f| (sign 0, exponent, 20 mantissa bits) with its low 8 bits replaced by 255 - thread,
+  // of |f| (sign 0, exponent, 20 mantissa bits) with its low 10 bits replaced by 1023 - thread,
   // and 0 for rows already used; the largest key wins. The pivot is therefore within a factor
-  // 1 + 2^-12 of the largest candidate, and ties go to the lowest row.
+  // 1 + 2^-10 of the largest candidate, and ties go to the lowest row.
   bool used = !has_row;
   int my_step = 0;
   double my_inv = 1.0;
   bool bad = false;
   for (int k = 0; k < N; ++k) {
     const int par = k & 1;
-    const double f = (S == 2) ? pair_dpp<kQuadEven>(row[0]) : row[0];   // this row's entry in column k
+    const double f = (S > 1) ? pair_dpp<C::kFirst>(row[0]) : row[0];   // this row's entry in column k
     const unsigned key = (used || h != 0) ? 0u
-                         : ((((unsigned)__double2hiint(fabs(f))) & ~0xFFu) | (unsigned)(255 - tid));
+                         : ((((unsigned)__double2hiint(fabs(f))) & ~0x3FFu) | (unsigned)(1023 - tid));
     const unsigned wkey = wave_max_u32(key);
-    const int wtid = 255 - (int)(wkey & 0xFFu);
-    if (wkey != 0u && (tid == wtid || (S == 2 && tid == wtid + 1))) {   // publish the candidate row
+    const int wtid = 1023 - (int)(wkey & 0x3FFu);
+    if (wkey != 0u && tid >= wtid && tid < wtid + S) {   // publish the candidate row
 #pragma unroll
       for (int j = 0; j < H; ++j) slot[par][wv][h * H + j] = row[j];
     }
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
       win = (k2 > bk) ? w2 : win;
       bk = (k2 > bk) ? k2 : bk;
     }
-    int p = (255 - (int)(bk & 0xFFu)) / S;
+    int p = (1023 - (int)(bk & 0x3FFu)) / S;
     if (bk == 0u || p >= N) {             // no unused row left: only reachable with non-finite entries
       bad = true;
       p = (p < N && p >= 0) ? p : N - 1;
@@ -299,7 +302,7 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
       my_step = k;
       my_inv = ip;
     }
-    const double nb = (S == 2) ? pair_dpp<kQuadOdd>(row[0]) : 0.0;   // first column of the second half
+    const double nb = (S > 1) ? pair_dpp<C::kNext>(row[0]) : 0.0;   // first column of the next part
     const double* prh = pr + h * H;
     // pivot-row values in batches, so that a batch of LDS reads is in flight at once
     constexpr int B = 16;
@@ -313,8 +316,8 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
       for (int j = 0; j < B; ++j)
         if (j0 + j < H - 1) row[j0 + j] = fma(-g, buf[j], row[j0 + j + 1]);
     }
-    if (S == 2 && h == 0)
-      row[H - 1] = fma(-g, pr[H], nb);
+    if (S > 1 && h < S - 1)
+      row[H - 1] = fma(-g, pr[(h + 1) * H], nb);
     else
       row[H - 1] = is_p ? 1.0 : -g;
   }
@@ -577,6 +580,7 @@ hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, d
     case 2: return launch_jac_rows<2, 1>(a, L.ne, st);
     case 3: return launch_jac_rows<3, 1>(a, L.ne, st);
     case 4: return launch_jac_rows<4, 2>(a, L.ne, st);
+    case 5: return launch_jac_rows<5, 4>(a, L.ne, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -51,7 +51,8 @@ def test_solution_points_match(mesh_name, P):
 
 @pytest.mark.parametrize("mesh_name,P", [("cfg1_8x8", 2), ("cfg1_8x8", 1), ("cfg1_8x8", 0),
                                          ("ragged_13x11", 0), ("ragged_13x11", 1), ("ragged_13x11", 2),
-                                         ("ragged_13x11", 3), ("ragged_13x11", 4), ("cfg2_64x64", 3)])
+                                         ("ragged_13x11", 3), ("ragged_13x11", 4), ("ragged_13x11", 5),
+                                         ("ragged_13x11", 6), ("cfg2_64x64", 3)])
 def test_residual_parity(mesh_name, P):
     mesh = MESHES[mesh_name]()
     olev, glev = make_levels(mesh, P, VS)
@@ -94,7 +95,7 @@ def test_residual_freestream_on_gpu():
     assert np.max(np.abs(got[..., 3])) / (h_inf * speed * inv_h) < 1e-13 / VS.ma_inf ** 2
 
 
-@pytest.mark.parametrize("Pf,Pc", [(2, 1), (1, 0), (3, 2), (3, 1), (4, 2)])
+@pytest.mark.parametrize("Pf,Pc", [(2, 1), (1, 0), (3, 2), (3, 1), (4, 2), (5, 3), (6, 3)])
 def test_transfer_parity(Pf, Pc):
     mesh = MESHES["ragged_13x11"]()
     of, gf = make_levels(mesh, Pf, VS)
@@ -113,7 +114,7 @@ def test_transfer_parity(Pf, Pc):
 
 
 @pytest.mark.parametrize("mesh_name,P", [("cfg1_8x8", 2), ("ragged_13x11", 1), ("ragged_13x11", 3),
-                                         ("cfg1_8x8", 4)])
+                                         ("cfg1_8x8", 4), ("cfg1_8x8", 5)])
 def test_element_blocks_parity(mesh_name, P):
     mesh = MESHES[mesh_name]()
     olev, glev = make_levels(mesh, P, VS)
@@ -132,7 +133,8 @@ def test_element_blocks_parity(mesh_name, P):
 
 
 @pytest.mark.parametrize("mesh_name,P,prec", [("cfg1_8x8", 2, 64), ("ragged_13x11", 3, 64),
-                                              ("ragged_13x11", 1, 64), ("cfg1_8x8", 2, 32)])
+                                              ("ragged_13x11", 1, 64), ("cfg1_8x8", 2, 32),
+                                              ("cfg1_8x8", 5, 64), ("cfg1_8x8", 5, 32)])
 def test_sweep_parity(mesh_name, P, prec):
     mesh = MESHES[mesh_name]()
     olev, glev = make_levels(mesh, P, VS)
@@ -187,10 +189,14 @@ def _stage_case(case):
         return MESHES["ragged_13x11"](), (3, 1), (3, 6), 64
     if case == "cfg1_P210_fp32":
         return MESHES["cfg1_8x8"](), (2, 1, 0), (5, 10, 20), 32
+    if case == "cfg1_P531":            # the hierarchy of the time-refinement study (Sec. 4.1)
+        return MESHES["cfg1_8x8"](), (5, 3, 1), (5, 5, 10), 64
+    if case == "cfg1_P531_fp32":
+        return MESHES["cfg1_8x8"](), (5, 3, 1), (5, 5, 10), 32
     raise ValueError(case)
 
 
-@pytest.mark.parametrize("case", ["cfg1_P210", "ragged_P31", "cfg1_P210_fp32"])
+@pytest.mark.parametrize("case", ["cfg1_P210", "ragged_P31", "cfg1_P210_fp32", "cfg1_P531", "cfg1_P531_fp32"])
 def test_stage_solve_parity(case):
     """V-cycles of the ESDIRK2 second-stage solve (eqs. (26)-(31), Sec. 3): the state after each
     V-cycle count and the residual history against the oracle."""
