@@ -362,6 +362,14 @@ def measured_traffic(path=PROFILE_PMC, files=KERNEL_SOURCES_2D):
     return float(vals["traffic_bytes_per_launch"])
 
 
+_T0 = time.perf_counter()
+
+
+def progress(what):
+    """One line on stderr per finished block of the run (the JSON line goes to stdout)."""
+    print(f"bench: {what} done at {time.perf_counter() - _T0:.1f} s", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,6 +455,7 @@ def main():
         }
         finals[form] = q.detach().cpu().numpy()
         del facs, solver
+        progress(f"vortex 64x64 P{{3-2-1}} {form}")
 
     head = "mixed" if "mixed" in results else next(iter(results))
     r = results[head]
@@ -506,21 +515,27 @@ def main():
             small["speedup_time_to_1e-8_mixed_over_fp64"] = (small["fp64"]["time_to_1e-8_s_total"]
                                                              / small["mixed"]["time_to_1e-8_s_total"])
         line["time_to_1e-8_8x8_P210_esdirk2"] = small
+        progress("8x8 time to 1e-8")
     if not args.no_airfoil:
         line["airfoil_128x64_P4_steady"] = airfoil_block(api, torch, args.forms.split(","), args.airfoil_vcycles,
                                                          args.kernel_reps)
+        progress("airfoil steady solves")
     if not args.no_viscous:
         line["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
+        progress("viscous batch")
     if not args.no_sphere:
         if not args.no_sphere_p2:
             line["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, args.forms.split(","),
                                                                     args.sphere_vcycles, args.kernel_reps)
+            progress("sphere P{2-1-0}")
         if not args.no_sphere_p3:
             line["sphere_cubed_16x16x24_P3_steady"] = sphere_block(
                 api, torch, args.forms.split(","), args.sphere_vcycles, args.kernel_reps, plev=(3, 2, 1, 0),
                 nsm=(5, 10, 20, 20), profile_pmc=PROFILE_PMC_SPHERE3, cfl_init=30.0)
+            progress("sphere P{3-2-1-0}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
+        progress("cpu baseline")
     print(json.dumps(line), flush=True)
 
 
