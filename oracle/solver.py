@@ -233,6 +233,110 @@ class PMGSolver:
             r_prev = r
         return q, st
 
+    # ---- Newton-Krylov stage solve with the V-cycle as preconditioner ---------------------
+    def nk_stage_solve(self, q, c_mass=0.0, src=None, krylov_dim=10, eta=1e-2, max_newton=None,
+                       fd_rel=1e-7, pc_rel=1e-7, precondition=True):
+        """Pseudo-transient Newton on F(q) = 0 with the whole Jacobian (the linearisation of
+        eqs. (27)-(28) without the element-Jacobi splitting of eq. (29)): at step m,
+
+            (Gamma(q_m)/dtau_m - dF/dq) delta = F(q_m),   q_{m+1} = q_m + delta,
+
+        solved by one cycle of flexible GMRES from delta = 0 with at most krylov_dim directions,
+        stopped once the least-squares residual is <= eta ||F(q_m)||. Products with dF/dq are
+        forward differences (F(q_m + h z) - F(q_m))/h with h ||z|| = fd_rel sqrt(N) (N entries of
+        the state). The right preconditioner is one FAS V-cycle of Sec. 3 started at q_m on
+        F(q) - S_0 = 0 with S_0 = F(q_m) - e v, whose first sweep moves q_m by e D^{-1} v:
+        M^{-1} v = (V(q_m) - q_m)/e with e ||v|| = pc_rel sqrt(N). Orthogonalisation: classical
+        Gram-Schmidt applied twice. dtau follows the SER law of eq. (31) and the blocks are rebuilt
+        as in stage_solve (the coarse ones in the first preconditioner V-cycle of a refresh step).
+        The history holds ||F|| per Newton step; st.krylov counts the directions taken."""
+        o = self.opts
+        self.c_mass = c_mass
+        self.src = src
+        st = StageStats()
+        st.krylov = 0
+        nmax = o.max_vcycles if max_newton is None else max_newton
+        self.dtau_last_refresh = None
+        r_prev = None
+        if o.use_cfl:
+            scale = self.dtau_min(q)
+            dtau_init, dtau_max = o.cfl_init * scale, o.cfl_max * scale
+        else:
+            dtau_init, dtau_max = o.dtau_init, o.dtau_max
+        sqn = math.sqrt(q.size)
+        for m in range(nmax + 1):
+            F0 = self.F(0, q)
+            r = float(np.sqrt(np.sum(F0 ** 2)))
+            st.history.append(r)
+            if m == 0:
+                st.r0 = r
+                self.dtau = dtau_init
+            else:
+                self.dtau = min(self.dtau * (r_prev / r) ** o.ser_exp, dtau_max)
+            st.r_final = r
+            if r == 0.0 or r / st.r0 <= o.tol:
+                st.converged = True
+                break
+            if m == nmax:
+                break
+            st.dtau_history.append(self.dtau)
+            frozen = (o.freeze_at_max and self.dtau_last_refresh is not None
+                      and self.dtau_last_refresh >= dtau_max)
+            refresh_coarse = False
+            if m == 0 or (m % o.refresh_every == 0 and not frozen):
+                self.build_D(0, q)
+                self.dtau_last_refresh = self.dtau
+                st.refreshes.append(m)
+                refresh_coarse = True
+            gam = G.preconditioner(q, self.gas)
+            k = krylov_dim
+            V = [F0 / r]
+            Z = []
+            H = np.zeros((k + 1, k))
+            cs, sn = np.zeros(k), np.zeros(k)
+            g = np.zeros(k + 1)
+            g[0] = r
+            jj = 0
+            for j in range(k):
+                v = V[j]
+                if precondition:
+                    e = pc_rel * sqn / float(np.sqrt(np.sum(v ** 2)))
+                    self.refresh_now = refresh_coarse
+                    refresh_coarse = False
+                    z = (self.vcycle(0, q.copy(), F0 - e * v) - q) / e
+                    self.refresh_now = False
+                else:
+                    z = v
+                Z.append(z)
+                h = fd_rel * sqn / float(np.sqrt(np.sum(z ** 2)))
+                w = np.einsum("...ij,...j->...i", gam, z) / self.dtau - (self.F(0, q + h * z) - F0) / h
+                for _ in range(2):                          # classical Gram-Schmidt, twice
+                    c = np.array([float(np.sum(Vi * w)) for Vi in V])
+                    w = w - sum(ci * Vi for ci, Vi in zip(c, V))
+                    H[:j + 1, j] += c
+                H[j + 1, j] = float(np.sqrt(np.sum(w ** 2)))
+                for i in range(j):                          # earlier rotations, then a new one
+                    a, b = H[i, j], H[i + 1, j]
+                    H[i, j], H[i + 1, j] = cs[i] * a + sn[i] * b, -sn[i] * a + cs[i] * b
+                den = math.hypot(H[j, j], H[j + 1, j])
+                cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+                hn = H[j + 1, j]
+                H[j, j], H[j + 1, j] = den, 0.0
+                g[j + 1] = -sn[j] * g[j]
+                g[j] = cs[j] * g[j]
+                jj = j + 1
+                if abs(g[j + 1]) <= eta * r or hn == 0.0:
+                    break
+                V.append(w / hn)
+            y = np.zeros(jj)
+            for i in range(jj - 1, -1, -1):
+                y[i] = (g[i] - H[i, i + 1:jj] @ y[i + 1:jj]) / H[i, i]
+            q = q + sum(yi * zi for yi, zi in zip(y, Z))
+            st.krylov += jj
+            st.n_vcycles = m + 1
+            r_prev = r
+        return q, st
+
     # ---- ESDIRK step (eqs. (24)-(26)) -----------------------------------------------
     def esdirk_step(self, q_n, dt, tableau: np.ndarray):
         lev0 = self.levels[0]
