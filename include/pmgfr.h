@@ -61,7 +61,7 @@ typedef struct pmg_batch_s* pmg_batch;
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 105
+#define PMG_ABI_VERSION 106
 int32_t pmg_abi_version(void);
 
 /*
@@ -288,6 +288,44 @@ pmg_status esdirk_stage_solve(const pmg_solve_opts* opts, double omega, double d
  */
 pmg_status esdirk_step(const pmg_solve_opts* opts, int32_t scheme, double dt, double* q, double* work,
                        pmg_solve_stats* stats, int32_t n_stats, void* stream);
+
+/*
+ * nk_stage_solve — the stage equation F(q) = 0 of eq. (26) by pseudo-transient Newton with the
+ * whole Jacobian and the V-cycle as preconditioner (the paper names this combination as its next
+ * step for lower Mach numbers; Sec. 5). Newton step m solves
+ *   (Gamma(q_m)/dtau_m - dF/dq) delta = F(q_m),   q_{m+1} = q_m + delta
+ * (the linearisation of eqs. (27)-(28) without the element-Jacobi splitting of eq. (29)) by one
+ * cycle of flexible GMRES from delta = 0: at most krylov_dim directions, stopped once the
+ * least-squares residual is <= eta ||F(q_m)||; classical Gram-Schmidt applied twice. Products with
+ * dF/dq are forward differences (F(q_m + h z) - F(q_m))/h with h ||z|| = fd_rel sqrt(N), N the
+ * entries of a finest-level state: fd_rel is the RMS perturbation per entry, of the order of
+ * sqrt(machine epsilon) times the absolute state (about 1e-3 for pressures near 6e4). With precondition = 1 each direction v is preconditioned by
+ * one FAS V-cycle of Sec. 3 (the opts' levels, factors and smoothing counts) started at q_m on
+ * F(q) - S_0 = 0 with S_0 = F(q_m) - e v: M^{-1} v = (V(q_m) - q_m)/e with e ||v|| = pc_rel sqrt(N).
+ * dtau_m follows eq. (31) from ||F(q_m)|| as in esdirk_stage_solve (dtau or CFL form), and the
+ * blocks are rebuilt with the same rule (the coarse ones inside the first preconditioner V-cycle
+ * of a refresh step). Arguments as esdirk_stage_solve, plus:
+ *   nk        host options.
+ *   work      device, at least nk_work_elems(levels[0], krylov_dim) doubles, caller-owned.
+ *   stats     as esdirk_stage_solve, with n_vcycles = Newton steps and history[m] = ||F(q_m)||.
+ *   n_krylov  host int32 or NULL: Krylov directions over all Newton steps (= preconditioner
+ *             V-cycles and Jacobian products).
+ * Synchronises the stream several times per direction (host dot products). Returns
+ * PMG_E_NOT_CONVERGED after max_newton steps without r_m / r_0 <= tol_rel.
+ */
+typedef struct pmg_nk_opts {
+  int32_t krylov_dim;    /* 1..32 */
+  int32_t max_newton;    /* >= 0 */
+  double eta;            /* >= 0 */
+  double fd_rel;         /* > 0, e.g. 1e-3 at Ma 0.005 */
+  double pc_rel;         /* > 0, e.g. 1e-3 */
+  int32_t precondition;  /* 0 or 1 */
+} pmg_nk_opts;
+
+int64_t nk_work_elems(pmg_level L0, int32_t krylov_dim);   /* -1 for bad arguments */
+pmg_status nk_stage_solve(const pmg_solve_opts* opts, const pmg_nk_opts* nk, double omega, double dt,
+                          const double* qc_n, const double* const* R_prev, const double* a_row, int32_t n_prev,
+                          double* q, double* work, pmg_solve_stats* stats, int32_t* n_krylov, void* stream);
 
 /* Number of stages of an ESDIRK scheme id (3, 4 or 6), or 0 for an unknown id. */
 int32_t esdirk_stages(int32_t scheme);

@@ -235,7 +235,7 @@ class PMGSolver:
 
     # ---- Newton-Krylov stage solve with the V-cycle as preconditioner ---------------------
     def nk_stage_solve(self, q, c_mass=0.0, src=None, krylov_dim=10, eta=1e-2, max_newton=None,
-                       fd_rel=1e-7, pc_rel=1e-7, precondition=True):
+                       fd_rel=1e-3, pc_rel=1e-3, precondition=True):
         """Pseudo-transient Newton on F(q) = 0 with the whole Jacobian (the linearisation of
         eqs. (27)-(28) without the element-Jacobi splitting of eq. (29)): at step m,
 
@@ -244,7 +244,8 @@ class PMGSolver:
         solved by one cycle of flexible GMRES from delta = 0 with at most krylov_dim directions,
         stopped once the least-squares residual is <= eta ||F(q_m)||. Products with dF/dq are
         forward differences (F(q_m + h z) - F(q_m))/h with h ||z|| = fd_rel sqrt(N) (N entries of
-        the state). The right preconditioner is one FAS V-cycle of Sec. 3 started at q_m on
+        the state): fd_rel is the RMS size of the perturbation per entry, of the order of
+        sqrt(machine epsilon) times the absolute state (1e-3 for pressures near 6e4 at Ma 0.005). The right preconditioner is one FAS V-cycle of Sec. 3 started at q_m on
         F(q) - S_0 = 0 with S_0 = F(q_m) - e v, whose first sweep moves q_m by e D^{-1} v:
         M^{-1} v = (V(q_m) - q_m)/e with e ||v|| = pc_rel sqrt(N). Orthogonalisation: classical
         Gram-Schmidt applied twice. dtau follows the SER law of eq. (31) and the blocks are rebuilt

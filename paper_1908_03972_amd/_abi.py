@@ -58,6 +58,13 @@ class SolveStats(C.Structure):
     ]
 
 
+class NkOpts(C.Structure):
+    _fields_ = [
+        ("krylov_dim", C.c_int32), ("max_newton", C.c_int32), ("eta", C.c_double), ("fd_rel", C.c_double),
+        ("pc_rel", C.c_double), ("precondition", C.c_int32),
+    ]
+
+
 DP = C.c_void_p   # device pointers travel as plain addresses
 
 SIGNATURES = {
@@ -85,6 +92,10 @@ SIGNATURES = {
     "esdirk_step": (pmg_status, [C.POINTER(SolveOpts), C.c_int32, C.c_double, DP, DP, C.POINTER(SolveStats),
                                  C.c_int32, C.c_void_p]),
     "esdirk_stages": (C.c_int32, [C.c_int32]),
+    "nk_work_elems": (C.c_int64, [pmg_level, C.c_int32]),
+    "nk_stage_solve": (pmg_status, [C.POINTER(SolveOpts), C.POINTER(NkOpts), C.c_double, C.c_double, DP,
+                                    C.POINTER(DP), C.POINTER(C.c_double), C.c_int32, DP, DP, C.POINTER(SolveStats),
+                                    C.POINTER(C.c_int32), C.c_void_p]),
     "pmg_batch_create": (pmg_status, [C.POINTER(SolveOpts), C.c_int32, C.POINTER(pmg_batch)]),
     "pmg_batch_destroy": (pmg_status, [pmg_batch]),
     "pmg_batch_size": (C.c_int32, [pmg_batch]),

@@ -214,6 +214,44 @@ class StageSolver:
         return out
 
 
+def nk_stage_solve(solver: StageSolver, q, *, krylov_dim=10, eta=1e-2, max_newton=50, fd_rel=1e-3, pc_rel=1e-3,
+                   precondition=True, omega=0.0, dt=0.0, qc_n=None, R_prev=(), a_row=(), work=None, stream=None,
+                   raise_on_error=True):
+    """``nk_stage_solve``: Newton-Krylov stage solve with the solver's V-cycle as preconditioner
+    (levels, factors, smoothing counts, dtau/CFL range, SER and refresh rule from ``solver``;
+    ``tol_rel`` from it too). ``fd_rel`` and ``pc_rel`` are RMS perturbations per state entry
+    (about sqrt(machine epsilon) times the absolute state: the defaults suit pressures near 1e4-1e5).
+    ``work``: a float64 device tensor of at least ``nk_work_elems`` entries (allocated here when
+    None). Returns the stats dict with ``n_newton`` and ``n_krylov``."""
+    L0 = solver.levels[0]
+    need = int(A.lib().nk_work_elems(L0.handle, krylov_dim))
+    if need < 0:
+        raise ValueError("krylov_dim must be in 1..32")
+    if work is None:
+        work = torch.empty(need, dtype=torch.float64, device=L0.torch_device)
+    if work.dtype != torch.float64 or not work.is_contiguous() or work.numel() < need or work.device != L0.torch_device:
+        raise ValueError(f"work must be a contiguous float64 tensor of at least {need} entries on the level's device")
+    nk = A.NkOpts(krylov_dim, max_newton, eta, fd_rel, pc_rel, 1 if precondition else 0)
+    nprev = len(R_prev)
+    rp = (C.c_void_p * max(nprev, 1))(*[L0.check_state(r, "R_prev", False) for r in R_prev])
+    ar = (C.c_double * max(nprev, 1))(*a_row)
+    cap = max_newton + 1
+    hist = (C.c_double * cap)()
+    st = A.SolveStats()
+    st.history = C.cast(hist, C.POINTER(C.c_double))
+    st.history_capacity = cap
+    nkry = C.c_int32(0)
+    status = A.lib().nk_stage_solve(C.byref(solver.opts), C.byref(nk), omega, dt, L0.check_state(qc_n, "qc_n"), rp,
+                                    ar, nprev, L0.check_state(q, "q", False), C.c_void_p(work.data_ptr()), C.byref(st),
+                                    C.byref(nkry), _stream(stream))
+    out = {"status": status, "n_newton": st.n_vcycles, "n_krylov": nkry.value, "n_refresh": st.n_refresh,
+           "r0": st.r0, "r_final": st.r_final, "seconds": st.seconds, "dtau_min": st.dtau_min,
+           "history": list(hist[:min(st.n_vcycles + 1, cap)])}
+    if raise_on_error:
+        A.check(status, "nk_stage_solve")
+    return out
+
+
 def dtau_min(level: Level, q, stream=None) -> float:
     """``pmg_dtau_min``: the pseudo-time scale of eq. (33) at state q (synchronises)."""
     out = C.c_double(0.0)

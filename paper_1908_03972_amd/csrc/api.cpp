@@ -14,6 +14,7 @@
 
 #include "../../include/pmgfr.h"
 #include "internal.hpp"
+#include "krylov.hpp"
 
 using pmg::Ops1D;
 
@@ -1037,6 +1038,215 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
     if (pmg_status e = stage_advance(R)) return e;
   }
   return stage_finish(R);
+}
+
+// ---- Newton-Krylov stage solve (the V-cycle as a preconditioner) ------------------------------------
+// Pseudo-transient Newton on the stage equation with the whole Jacobian: per Newton step one cycle
+// of flexible GMRES on (Gamma(q_m)/dtau_m - dF/dq) delta = F(q_m), right-preconditioned by one FAS
+// V-cycle from q_m with the finest forcing F(q_m) - e v, Jacobian products by forward differences
+// of the residual kernel. The Hessenberg matrix and its Givens rotations live on the host; every
+// vector operation runs on the device.
+namespace {
+
+struct NkWork {
+  size_t N;
+  int k;
+  double* base;
+  double* V(int j) const { return base + (size_t)j * N; }
+  double* Z(int j) const { return base + (size_t)(k + 1 + j) * N; }
+  double* F0() const { return base + (size_t)(2 * k + 1) * N; }
+  double* W1() const { return base + (size_t)(2 * k + 2) * N; }
+  double* W2() const { return base + (size_t)(2 * k + 3) * N; }
+  double* part() const { return base + (size_t)(2 * k + 4) * N; }
+  double* dots() const { return part() + (size_t)pmg::kNkMaxTerms * pmg::kNkDotBlocks; }
+};
+
+// host[i] = <x[i], v> for i < nx (synchronises the stream)
+pmg_status nk_dots(const NkWork& w, const double* const* x, int nx, const double* v, double* host, hipStream_t st) {
+  PMG_HIP(pmg::launch_multidot(w.N, nx, x, v, w.part(), w.dots(), st));
+  PMG_HIP(hipMemcpyAsync(host, w.dots(), (size_t)nx * sizeof(double), hipMemcpyDeviceToHost, st));
+  PMG_HIP(hipStreamSynchronize(st));
+  return PMG_OK;
+}
+
+pmg_status nk_lincomb(const NkWork& w, int nt, const double* const* x, const double* c, double beta, double* y,
+                      hipStream_t st) {
+  PMG_HIP(pmg::launch_lincomb(w.N, nt, x, c, beta, y, st));
+  return PMG_OK;
+}
+
+}  // namespace
+
+extern "C" int64_t nk_work_elems(pmg_level L0, int32_t krylov_dim) {
+  if (!L0 || krylov_dim < 1 || krylov_dim > pmg::kNkMaxDim) return -1;
+  return (int64_t)(2 * krylov_dim + 4) * (int64_t)L0->state_elems() +
+         (int64_t)pmg::kNkMaxTerms * (pmg::kNkDotBlocks + 1);
+}
+
+extern "C" pmg_status nk_stage_solve(const pmg_solve_opts* o, const pmg_nk_opts* nk, double omega, double dt,
+                                     const double* qc_n, const double* const* R_prev, const double* a_row,
+                                     int32_t n_prev, double* q, double* work, pmg_solve_stats* stats,
+                                     int32_t* n_krylov, void* stream) {
+  if (pmg_status e = check_opts(o)) return e;
+  if (!nk || !work || !q) return fail(PMG_E_ARG, "null Newton-Krylov options, work array or state");
+  const int k = nk->krylov_dim;
+  if (k < 1 || k > pmg::kNkMaxDim) return fail(PMG_E_ARG, "krylov_dim must be in 1..32");
+  if (nk->max_newton < 0 || !(nk->eta >= 0.0) || !(nk->fd_rel > 0.0) || !(nk->pc_rel > 0.0) ||
+      (nk->precondition != 0 && nk->precondition != 1))
+    return fail(PMG_E_ARG, "bad Newton-Krylov options");
+  pmg_level L0 = o->levels[0];
+  DeviceGuard guard(L0->device);
+  const hipStream_t st = as_stream(stream);
+  StageRun R;
+  double hn[8];
+  R.host_norms = hn;
+  if (pmg_status e = stage_begin(R, o, omega, dt, qc_n, R_prev, a_row, n_prev, q, nullptr, stats, st)) return e;
+  Solve& s = R.s;
+  const NkWork w{L0->state_elems(), k, work};
+  const size_t N = w.N;
+  const double sqn = std::sqrt((double)N);
+  int krylov = 0, newton = 0;
+  double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
+  pmg_status result = PMG_E_NOT_CONVERGED;
+  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1), y(k), c(k + 1);
+  std::vector<const double*> xs(k + 1);
+  for (int m = 0;; ++m) {
+    if (m > 0) {   // F(q_m) and its norm (stage_begin enqueued those of q_0)
+      PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, st));
+      PMG_HIP(pmg::launch_norm_finalize(*L0, st));
+      PMG_HIP(hipMemcpyAsync(hn, L0->norms, (L0->nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    PMG_HIP(pmg::launch_copy(N, L0->wF, w.F0(), st));
+    PMG_HIP(hipStreamSynchronize(st));
+    r = hn[L0->nv];
+    if (stats && stats->history && m < stats->history_capacity) stats->history[m] = r;
+    if (!std::isfinite(r)) {
+      result = fail(PMG_E_NONFINITE, "non-finite residual norm");
+      break;
+    }
+    if (m == 0)
+      r0 = r;
+    else
+      s.dtau = std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), R.dtau_max);   // eq. (31)
+    if (r == 0.0 || r / r0 <= o->tol_rel) {
+      result = PMG_OK;
+      break;
+    }
+    if (m >= nk->max_newton) {
+      result = fail(PMG_E_NOT_CONVERGED, "Newton-Krylov stage solve reached max_newton");
+      break;
+    }
+    const bool frozen = o->freeze_at_max && dtau_last_refresh >= R.dtau_max;
+    bool refresh_coarse = false;
+    if (m == 0 || (m % o->refresh_every == 0 && !frozen)) {
+      PMG_HIP(pmg::launch_jacobian(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], st));
+      ++s.n_refresh;
+      dtau_last_refresh = s.dtau;
+      refresh_coarse = true;
+    }
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = r;
+    {
+      const double* x0 = w.F0();
+      const double c0 = 1.0 / r;
+      if (pmg_status e = nk_lincomb(w, 1, &x0, &c0, 0.0, w.V(0), st)) return e;
+    }
+    int jj = 0;
+    for (int j = 0; j < k; ++j) {
+      double* v = w.V(j);
+      double* z = w.Z(j);
+      if (nk->precondition) {   // z = (V(q_m; S_0 = F(q_m) - e v) - q_m) / e
+        double vv = 0.0;
+        const double* xv = v;
+        if (pmg_status e = nk_dots(w, &xv, 1, v, &vv, st)) return e;
+        const double e = nk->pc_rel * sqn / std::sqrt(vv);
+        PMG_HIP(pmg::launch_copy(N, q, w.W1(), st));
+        const double* x2[2] = {w.F0(), v};
+        const double c2[2] = {1.0, -e};
+        if (pmg_status er = nk_lincomb(w, 2, x2, c2, 0.0, w.W2(), st)) return er;
+        s.refresh = refresh_coarse;
+        refresh_coarse = false;
+        const pmg_status ve = vcycle(s, 0, w.W1(), w.W2());
+        s.refresh = false;
+        if (ve != PMG_OK) return ve;
+        const double* x3[2] = {w.W1(), q};
+        const double c3[2] = {1.0 / e, -1.0 / e};
+        if (pmg_status er = nk_lincomb(w, 2, x3, c3, 0.0, z, st)) return er;
+      } else {
+        PMG_HIP(pmg::launch_copy(N, v, z, st));
+      }
+      double zz = 0.0;
+      const double* xz = z;
+      if (pmg_status e = nk_dots(w, &xz, 1, z, &zz, st)) return e;
+      const double h = nk->fd_rel * sqn / std::sqrt(zz);
+      const double* x4[2] = {q, z};
+      const double c4[2] = {1.0, h};
+      if (pmg_status e = nk_lincomb(w, 2, x4, c4, 0.0, w.W1(), st)) return e;
+      PMG_HIP(pmg::launch_residual(*L0, w.W1(), s.src, nullptr, s.c_mass, w.W2(), false, st));
+      double* wn = w.V(j + 1);
+      PMG_HIP(pmg::launch_newton_op(*L0, q, z, w.W2(), w.F0(), 1.0 / s.dtau, 1.0 / h, wn, st));
+      for (int i = 0; i <= j; ++i) xs[i] = w.V(i);
+      for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
+        if (pmg_status e = nk_dots(w, xs.data(), j + 1, wn, c.data(), st)) return e;
+        for (int i = 0; i <= j; ++i) {
+          H[(size_t)i * k + j] += c[i];
+          c[i] = -c[i];
+        }
+        if (pmg_status e = nk_lincomb(w, j + 1, xs.data(), c.data(), 1.0, wn, st)) return e;
+      }
+      double ww = 0.0;
+      const double* xw = wn;
+      if (pmg_status e = nk_dots(w, &xw, 1, wn, &ww, st)) return e;
+      const double hnorm = std::sqrt(ww);
+      H[(size_t)(j + 1) * k + j] = hnorm;
+      for (int i = 0; i < j; ++i) {   // earlier rotations, then a new one
+        const double a = H[(size_t)i * k + j], b = H[(size_t)(i + 1) * k + j];
+        H[(size_t)i * k + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * k + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double den = std::hypot(H[(size_t)j * k + j], H[(size_t)(j + 1) * k + j]);
+      cs[j] = H[(size_t)j * k + j] / den;
+      sn[j] = H[(size_t)(j + 1) * k + j] / den;
+      H[(size_t)j * k + j] = den;
+      H[(size_t)(j + 1) * k + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      jj = j + 1;
+      if (std::fabs(g[j + 1]) <= nk->eta * r || hnorm == 0.0) break;
+      if (pmg_status e = nk_lincomb(w, 0, nullptr, nullptr, 1.0 / hnorm, wn, st)) return e;
+    }
+    for (int i = jj - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int l = i + 1; l < jj; ++l) t -= H[(size_t)i * k + l] * y[l];
+      y[i] = t / H[(size_t)i * k + i];
+    }
+    for (int i = 0; i < jj; ++i) xs[i] = w.Z(i);
+    if (pmg_status e = nk_lincomb(w, jj, xs.data(), y.data(), 1.0, q, st)) return e;
+    krylov += jj;
+    newton = m + 1;
+    r_prev = r;
+  }
+  if (result != PMG_E_NONFINITE) {
+    int any = 0;
+    for (int l = 0; l < o->n_levels; ++l) {
+      int fl = 0;
+      PMG_HIP(hipMemcpyAsync(&fl, o->levels[l]->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      PMG_HIP(hipStreamSynchronize(st));
+      any |= fl;
+    }
+    if (any & 1) result = fail(PMG_E_SINGULAR, "zero or non-finite pivot in an element block");
+  }
+  if (stats) {
+    stats->n_vcycles = newton;
+    stats->n_refresh = s.n_refresh;
+    stats->r0 = r0;
+    stats->r_final = r;
+    stats->status = result;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t_start).count();
+  }
+  if (n_krylov) *n_krylov = krylov;
+  return result;
 }
 
 // ---- ESDIRK time step ----------------------------------------------------------------------------

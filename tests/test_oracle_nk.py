@@ -50,15 +50,16 @@ def test_one_newton_step_is_the_dense_solve(precondition):
     src = OG.conservative(q, GAS) * c_mass * 1.001        # a source that makes F(q) != 0 everywhere
     ref = _dense_newton_step(sol, lev, q, c_mass, src, dtau)
     q1, st = sol.nk_stage_solve(q, c_mass, src, krylov_dim=q.size, eta=1e-13, max_newton=1,
-                                precondition=precondition)
+                                precondition=precondition, fd_rel=1e-7, pc_rel=1e-7)
     delta = q1 - q
     err = np.max(np.abs(delta - ref), axis=(0, 1)) / np.max(np.abs(ref), axis=(0, 1))
     assert st.n_vcycles == 1 and st.krylov <= q.size
     assert np.all(err < 2e-5), err
     if precondition:                  # the V-cycle preconditioner needs far fewer directions
-        _, st2 = sol.nk_stage_solve(q, c_mass, src, krylov_dim=q.size, eta=1e-6, max_newton=1)
+        _, st2 = sol.nk_stage_solve(q, c_mass, src, krylov_dim=q.size, eta=1e-6, max_newton=1,
+                                    fd_rel=1e-7, pc_rel=1e-7)
         _, st3 = sol.nk_stage_solve(q, c_mass, src, krylov_dim=q.size, eta=1e-6, max_newton=1,
-                                    precondition=False)
+                                    precondition=False, fd_rel=1e-7, pc_rel=1e-7)
         assert st2.krylov < st3.krylov, (st2.krylov, st3.krylov)
 
 
@@ -69,6 +70,7 @@ def test_newton_krylov_converges_fast_at_large_dtau():
     A = OS.esdirk_tableau("esdirk2")
     dt, om = 0.05, A[1, 1]
     src = (OG.conservative(q, GAS) + dt * A[1, 0] * lev.residual(q)) / (om * dt)
-    q1, st = sol.nk_stage_solve(q, 1.0 / (om * dt), src, krylov_dim=q.size, eta=1e-12, max_newton=3)
+    q1, st = sol.nk_stage_solve(q, 1.0 / (om * dt), src, krylov_dim=q.size, eta=1e-12, max_newton=3,
+                                fd_rel=1e-7, pc_rel=1e-7)
     h = np.array(st.history) / st.history[0]
     assert h[1] < 1e-2 and h[2] < 10.0 * h[1] ** 2 and h[3] < 10.0 * h[2] ** 2 + 1e-13, h
