@@ -258,6 +258,48 @@ def sphere_block(api, torch, forms, max_vcycles, kernel_reps, plev=(2, 1, 0), ns
     return out
 
 
+def newton_krylov_block(api, torch, levels, q0, forms):
+    """The first implicit ESDIRK3 stage of the 64x64 vortex solved to a 1e-8 drop two ways: the FAS
+    pseudo-transient solve of the main measurement (dtau 0.01 -> 10, at most 400 V-cycles) and the
+    Newton-Krylov solve with that V-cycle as preconditioner of flexible GMRES (10 directions per
+    Newton step, GMRES tolerance 0.05, dtau 10 -> 1e4, finite-difference scales 1e-3)."""
+    g = 1767732205903.0 / 4055673282236.0
+    L0 = levels[0]
+    qc = torch.empty_like(q0)
+    api.fr_conservative(L0, q0, qc)
+    R1 = torch.empty_like(q0)
+    api.fr_residual(L0, q0, R1)
+    stage = dict(omega=g, dt=DT, qc_n=qc, R_prev=[R1], a_row=[g])
+    out = {"workload": "first implicit ESDIRK3 stage (dt 0.05) of the 64x64 jittered vortex, P{3-2-1}, "
+                       "I{5-10-20}, stop at r/r0 <= 1e-8"}
+    for form in forms:
+        prec, graph = FORMS[form]
+        facs = [api.Factors(lv, prec) for lv in levels]
+        res = {}
+        for name, dtau, nk in (("fas", (0.01, 10.0), None), ("newton_krylov", (10.0, 1e4), True)):
+            solver = api.StageSolver(levels, facs, N_SMOOTH, dtau_init=dtau[0], dtau_max=dtau[1], tol_rel=1e-8,
+                                     max_vcycles=400, use_graph=graph)
+            for rep in range(2):                              # the first run captures the graph
+                q = q0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if nk:
+                    st = api.nk_stage_solve(solver, q, krylov_dim=10, eta=0.05, max_newton=60, raise_on_error=False,
+                                            **stage)
+                else:
+                    st = solver.solve(q, raise_on_error=False, **stage)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+            h = np.asarray(st["history"]) / st["history"][0]
+            res[name] = {"status": st["status"], "seconds": el, "final_rel_residual": float(h[-1]),
+                         "vcycles": st["n_krylov"] if nk else st["n_vcycles"], "dtau_range": list(dtau)}
+            if nk:
+                res[name]["newton_steps"] = st["n_newton"]
+        out[form] = res
+        del facs
+    return out
+
+
 def viscous_batch_block(api, torch, vcycles_per_stage, steps=1):
     """Eight independent viscous cases (Re 5000, Ma 0.001, no-slip adiabatic wall, 256 x 96
     O-mesh, seeded incidence and P in {2, 3, 4}), one ESDIRK3 step of dt = 0.05 from a free stream
@@ -386,6 +428,8 @@ def main():
     ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere steady solves")
     ap.add_argument("--no-sphere-p3", action="store_true", help="skip the 3-D sphere P{3-2-1-0} steady solves")
     ap.add_argument("--no-sphere-p2", action="store_true", help="skip the 3-D sphere P{2-1-0} steady solves")
+    ap.add_argument("--no-newton-krylov", action="store_true",
+                    help="skip the Newton-Krylov against FAS comparison on the 64x64 vortex stage")
     ap.add_argument("--sphere-vcycles", type=int, default=200)
     ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
     args = ap.parse_args()
@@ -497,6 +541,10 @@ def main():
                                          / np.linalg.norm(d.reshape(4, -1), axis=1)).tolist()
         t_m, t_f = mean_time(results["mixed"], "1e-04"), mean_time(results["fp64"], "1e-04")
         line["speedup_time_to_1e-4_mixed_over_fp64"] = (t_f / t_m) if (t_m and t_f) else None
+    if not args.no_newton_krylov:
+        line["newton_krylov_vs_fas_64x64_P321_stage"] = newton_krylov_block(api, torch, levels, q0,
+                                                                            args.forms.split(","))
+        progress("Newton-Krylov against FAS")
     if not args.no_small:
         # time to the 1e-8 drop where it is reachable: the 8x8 P{2-1-0} ESDIRK2 vortex
         m1, v1 = W.vortex_config1()
