@@ -99,3 +99,38 @@ def test_newton_krylov_solves_the_stage(prec):
     print("NK", prec, "to 1e-8:", out["n_newton"], "Newton steps,", out["n_krylov"], "directions, oracle r/r0", r / r0,
           "history", [h / out["history"][0] for h in out["history"]])
     assert r / r0 < 1.5e-8
+
+
+def test_newton_krylov_parity_3d():
+    """Hexahedra (five variables): two steady Newton steps of six directions on the rotated
+    3 x 3 x 2 cubed sphere, P{2-1-0}, Ma 0.01, slip wall, against the oracle."""
+    from oracle.fr3 import FRLevel3
+    from test_gpu_3d import GAS as GAS3, QINF as QINF3, FS as FS3, disturbed, glevel
+    from test_oracle_3d import small_sphere
+    mesh = small_sphere(inner=W.BC_SLIP_WALL)
+    plev, nsm = (2, 1, 0), (2, 4, 6)
+    dt3 = dict(dtau_init=1.0, dtau_max=1e3)
+    q0 = disturbed(FRLevel3(mesh, plev[0], GAS3, q_inf=QINF3), QINF3, 8)
+    kw = dict(krylov_dim=6, eta=0.0, max_newton=2, fd_rel=1e-4, pc_rel=1e-4)
+
+    def run_oracle(q):
+        sol = OS.PMGSolver(mesh, GAS3, OS.PMGOptions(p_levels=plev, n_smooth=nsm, tol=1e-30, **dt3), q_inf=QINF3)
+        return sol.nk_stage_solve(q, 0.0, None, **kw)
+
+    q_ref, st = run_oracle(q0)
+    rng = np.random.default_rng(6)
+    q_pert, st_p = run_oracle(q0 * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q0.shape)))
+    floor = rel_err_per_var(q_pert - QINF3, q_ref - QINF3)
+    levels = [glevel(mesh, P, FS3) for P in plev]
+    facs = [api.Factors(lv, 64) for lv in levels]
+    solver = api.StageSolver(levels, facs, nsm, tol_rel=1e-30, max_vcycles=50, **dt3)
+    q = to_dev(q0 - QINF3)
+    out = api.nk_stage_solve(solver, q, raise_on_error=False, **kw)
+    torch.cuda.synchronize()
+    assert levels[0].status() == 0
+    assert out["n_newton"] == 2 and out["n_krylov"] == 12 == st.krylov
+    err = rel_err_per_var(from_dev(q), q_ref - QINF3)
+    h_err = np.abs(np.array(out["history"]) - np.array(st.history)) / np.array(st.history)
+    print("NK 3-D state err", err, "floor", floor, "history", out["history"], "err", h_err)
+    assert np.all(err <= np.maximum(1e-10, 10.0 * floor)), (err, floor)
+    assert np.all(h_err <= max(1e-10, 10.0 * floor.max()))
