@@ -14,6 +14,7 @@
 
 #include "../../include/pmgfr.h"
 #include "internal.hpp"
+#include "jac3.hpp"
 #include "krylov.hpp"
 
 using pmg::Ops1D;
@@ -637,7 +638,9 @@ pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) 
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, L->device) != hipSuccess || cus <= 0)
       cus = 256;
     F->ws_slots = 2 * cus < L->ne ? 2 * cus : L->ne;
-    if (hipMalloc(&F->ws, (size_t)F->ws_slots * L->n * L->n * sizeof(double)) != hipSuccess) {
+    // the slots, then every element's pointwise derivatives
+    const size_t elems = (size_t)F->ws_slots * L->n * L->n + (size_t)L->ne * pmg::jac3_point_elems(L->P);
+    if (hipMalloc(&F->ws, elems * sizeof(double)) != hipSuccess) {
       (void)hipFree(F->W);
       delete F;
       return fail(PMG_E_NOMEM, "hipMalloc failed for the elimination work array");

@@ -7,6 +7,7 @@
 // npad = 4 ceil(n/4).
 #include "hex_points.hpp"
 #include "internal.hpp"
+#include "jac3.hpp"
 #include "physics3.hpp"
 
 namespace pmg {
@@ -351,10 +352,24 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
   }
 }
 
+// The pointwise derivatives of every element into global memory (jac3_point_elems(P) doubles per
+// element: sA, sDg, sB of element_point_jacobians3 one after the other), for the large-block
+// elimination, which then needs none of the dual-number arithmetic and its registers.
+template <int P>
+__global__ void __launch_bounds__(256) k_point_jac3(JacArgs3 a, double* __restrict__ pj) {
+  constexpr int NP = (P + 1) * (P + 1) * (P + 1), NV = 5;
+  __shared__ double sq[NV * NP];
+  const int e = blockIdx.x;
+  double* base = pj + (size_t)e * jac3_point_elems(P);
+  element_point_jacobians3<P, 256>(a, e, sq, base, base + 3 * NP * NV * NV, base + 4 * NP * NV * NV);
+}
+
 // Large element blocks (n = 320 at P = 3): the FP64 block is larger than a compute unit's LDS and
 // registers together, so each workgroup owns a slot of a global work array (n x n column-major,
-// X[c n + r]) and takes elements in turn, one thread per row. Gauss-Jordan elimination with partial
-// pivoting on the row-scaled block, in panels of B columns:
+// X[c n + r]) and takes elements in turn, one thread per row. The element's pointwise derivatives
+// come from k_point_jac3 (global memory, copied to LDS), the block is assembled row by row into
+// the slot and inverted by Gauss-Jordan elimination with partial pivoting on the row-scaled block,
+// in panels of B columns:
 //   * the panel's B steps run on each row's B panel entries held in registers; the pivot search and
 //     the broadcast of the pivot row go through LDS as in the register kernel. Eliminating in place
 //     (the pivot column's slot receives the transformed unit vector) leaves in the panel the columns
@@ -382,7 +397,8 @@ struct Big3 {
 };
 
 template <int P>
-__global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __restrict__ ws) {
+__global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __restrict__ ws,
+                                                         const double* __restrict__ pj) {
   using C = Big3<P>;
   constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, B = C::B, G = C::G, NW = C::NW,
                 NT = C::NT;
@@ -407,7 +423,10 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
 
   for (int e = blockIdx.x; e < ne; e += gridDim.x) {
     __syncthreads();                        // the previous element is done with the pool and sperm
-    element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
+    {                                       // sA, sDg, sB are contiguous in the pool
+      const double* src = pj + (size_t)e * jac3_point_elems(P);
+      for (int t = r; t < (int)jac3_point_elems(P); t += NT) sA[t] = src[t];
+    }
     __syncthreads();
 
     // row r of D_e: the largest entry lies on the row point's three tensor lines
@@ -502,7 +521,7 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
 #pragma unroll
         for (int s4 = 0; s4 < B / 4; ++s4) {
           const int row_ = 64 * wv + 16 * T + lr, m = 4 * s4 + lk;
-          const double u = X[(size_t)(k0 + m) * N + row_];
+          const double u = X[(k0 + m) * N + row_];
           uop[T][s4] = (sperm[k0 + m] == row_) ? u - 1.0 : u;
         }
       }
@@ -510,12 +529,12 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
         if (cg >= k0 && cg < k0 + B) continue;
         double xop[B / 4];
 #pragma unroll
-        for (int s4 = 0; s4 < B / 4; ++s4) xop[s4] = X[(size_t)(cg + lr) * N + sperm[k0 + 4 * s4 + lk]];
+        for (int s4 = 0; s4 < B / 4; ++s4) xop[s4] = X[(cg + lr) * N + sperm[k0 + 4 * s4 + lk]];
         dbl4 acc[4];
 #pragma unroll
         for (int T = 0; T < 4; ++T) {
 #pragma unroll
-          for (int v2 = 0; v2 < 4; ++v2) acc[T][v2] = X[(size_t)(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr];
+          for (int v2 = 0; v2 < 4; ++v2) acc[T][v2] = X[(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr];
         }
         __syncthreads();                    // every wave holds its old values before any wave stores
 #pragma unroll
@@ -526,7 +545,7 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
 #pragma unroll
         for (int T = 0; T < 4; ++T) {
 #pragma unroll
-          for (int v2 = 0; v2 < 4; ++v2) X[(size_t)(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr] = acc[T][v2];
+          for (int v2 = 0; v2 < 4; ++v2) X[(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr] = acc[T][v2];
         }
       }
       __syncthreads();                      // the updated columns are visible before the next panel
@@ -573,7 +592,9 @@ hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, 
     case 3: {
       if (!fac.ws || fac.ws_slots <= 0) return hipErrorInvalidValue;
       const int grid = fac.ws_slots < L.ne ? fac.ws_slots : L.ne;
-      hipLaunchKernelGGL(k_jac3_big<3>, dim3(grid), dim3(Big3<3>::NT), 0, st, a, fac.ws);
+      double* pj = fac.ws + (size_t)fac.ws_slots * L.n * L.n;   // after the work slots
+      hipLaunchKernelGGL(k_point_jac3<3>, dim3(L.ne), dim3(256), 0, st, a, pj);
+      hipLaunchKernelGGL(k_jac3_big<3>, dim3(grid), dim3(Big3<3>::NT), 0, st, a, fac.ws, (const double*)pj);
       return hipGetLastError();
     }
     default: return hipErrorInvalidValue;
