@@ -50,11 +50,12 @@ __device__ __forceinline__ void block_sync() {
 // Elements per workgroup. Lanes are (point, element) with the element fastest, so a load of one
 // (variable, point) of the [Nv][Np][Ne] state by a wave covers EPW consecutive elements: 16-32
 // elements fill whole cache lines, where 4-5 used a third of each (measured: P3 and P4 sweeps
-// 10-25% faster at 16 and 20 than at 4 and 5). Each element gets max((P+1)^2, 4(P+1)) lanes, so
+// 10-25% faster at 16 and 20 than at 4 and 5; at P2 and P4, 16 beats 20 by 6-9%: 256 rather than
+// 205 workgroups on a 4096-element level). Each element gets max((P+1)^2, 4(P+1)) lanes, so
 // that every flux point of its four faces has a lane of its own (at P <= 2 the faces have more
 // flux points than the element has solution points).
 constexpr int epw_for(int P) {
-  return P == 0 ? 32 : P == 1 ? 8 : P == 2 ? 20 : P == 3 ? 16 : P == 4 ? 20 : P == 5 ? 3 : 5;
+  return P == 0 ? 32 : P == 1 ? 8 : P == 2 ? 16 : P == 3 ? 16 : P == 4 ? 16 : P == 5 ? 3 : 5;
 }
 constexpr int lanes_per_element(int P) { return (P + 1) * (P + 1) > 4 * (P + 1) ? (P + 1) * (P + 1) : 4 * (P + 1); }
 
