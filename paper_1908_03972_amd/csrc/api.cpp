@@ -16,6 +16,7 @@
 #include "internal.hpp"
 #include "jac3.hpp"
 #include "krylov.hpp"
+#include "transfer.hpp"
 
 using pmg::Ops1D;
 
@@ -775,10 +776,9 @@ pmg_status vcycle(Solve& s, int l, double* q, const double* S) {
     return r;
   if (last) return PMG_OK;
   pmg_level Lc = o->levels[l + 1];
-  // q^b_{l+1} = P q^a_l (eqs. (39), (42)), written also to the coarse working state
-  PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), q, Lc->wqb, Lc->nv, s.st, Lc->wql));
+  // q^b_{l+1} = P q^a_l (eqs. (39), (42)), written also to the coarse working state, and
   // S_{l+1} = F_{l+1}(q^b) + P d_l = F_{l+1}(q^b) - P (F_l(q^a) - S_l)  (eqs. (40), (43))
-  PMG_HIP(pmg::launch_restrict(*L, *Lc, s.R1[l].data(), L->wF, Lc->wS, Lc->nv, s.st));
+  PMG_HIP(pmg::launch_restrict_pair(*L, *Lc, s.R1[l].data(), q, Lc->wqb, Lc->wql, L->wF, Lc->wS, Lc->nv, s.st));
   PMG_HIP(pmg::launch_residual(*Lc, Lc->wqb, nullptr, Lc->wS, s.c_mass, Lc->wS, false, s.st));
   if (pmg_status r = vcycle(s, l + 1, Lc->wql, Lc->wS)) return r;
   // q^{c,b}_l = q^a_l + I (q^{(c,)a}_{l+1} - q^b_{l+1}) (eqs. (44), (45)), then post-smoothing

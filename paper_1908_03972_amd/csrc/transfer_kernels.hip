@@ -5,6 +5,7 @@
 // load and store is coalesced. They are bandwidth-bound: one read of the input level and one
 // write of the output level per call.
 #include "internal.hpp"
+#include "transfer.hpp"
 
 namespace pmg {
 
@@ -34,6 +35,38 @@ __global__ void __launch_bounds__(256) k_restrict(int ne, int nvar, int nf1, int
   }
   xc[idx] = acc;
   if (xc2) xc2[idx] = acc;
+}
+
+// Both restrictions of a V-cycle level transition in one pass (eqs. (39), (42) and (40), (43)):
+// xc = xc2 = R xf (the state) and xd = R xg (the defect), the same index map as k_restrict.
+__global__ void __launch_bounds__(256) k_restrict_pair(int ne, int nvar, int nf1, int nc1, Mat1D R,
+                                                       const double* __restrict__ xf, double* __restrict__ xc,
+                                                       double* __restrict__ xc2, const double* __restrict__ xg,
+                                                       double* __restrict__ xd) {
+  const size_t npc = (size_t)nc1 * nc1, npf = (size_t)nf1 * nf1;
+  const size_t total = (size_t)nvar * npc * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int pc = (int)(rest % npc);
+  const int v = (int)(rest / npc);
+  const int a = pc % nc1, b = pc / nc1;
+  const size_t off = (size_t)v * npf * ne + e;
+  double acc = 0.0, accd = 0.0;
+  for (int j = 0; j < nf1; ++j) {
+    double row = 0.0, rowd = 0.0;
+    for (int i = 0; i < nf1; ++i) {
+      const size_t o = off + (size_t)(i + nf1 * j) * ne;
+      row += R.m[a * nf1 + i] * xf[o];
+      rowd += R.m[a * nf1 + i] * xg[o];
+    }
+    acc += R.m[b * nf1 + j] * row;
+    accd += R.m[b * nf1 + j] * rowd;
+  }
+  xc[idx] = acc;
+  xc2[idx] = acc;
+  xd[idx] = accd;
 }
 
 __global__ void __launch_bounds__(256) k_copy(size_t n, const double* __restrict__ src, double* __restrict__ dst) {
@@ -179,6 +212,21 @@ hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const d
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_restrict, dim3(blocks_for(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf, xc,
                      xc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_pair(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
+                                double* xc, double* xc2, const double* xg, double* xd, int nvar, hipStream_t st) {
+  if (Lf.dim == 3) {
+    const hipError_t e = launch_restrict3(Lf, Lc, R1, xf, xc, nvar, st, xc2);
+    return e != hipSuccess ? e : launch_restrict3(Lf, Lc, R1, xg, xd, nvar, st, nullptr);
+  }
+  Mat1D R{};
+  for (int k = 0; k < Lc.n1 * Lf.n1; ++k) R.m[k] = R1[k];
+  const size_t total = (size_t)nvar * Lc.np * Lc.ne;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restrict_pair, dim3(blocks_for(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf,
+                     xc, xc2, xg, xd);
   return hipGetLastError();
 }
 
