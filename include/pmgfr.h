@@ -330,6 +330,9 @@ pmg_status nk_stage_solve(const pmg_solve_opts* opts, const pmg_nk_opts* nk, dou
 
 /* Number of stages of an ESDIRK scheme id (3, 4 or 6), or 0 for an unknown id. */
 int32_t esdirk_stages(int32_t scheme);
+/* The Butcher matrix of an ESDIRK scheme id, row-major s x s into host A_out (s*s doubles; NULL
+ * only queries s); returns s, or 0 for an unknown id. */
+int32_t esdirk_butcher(int32_t scheme, double* A_out);
 
 /*
  * Batches of independent cases (several meshes, degrees or flow conditions advanced together).

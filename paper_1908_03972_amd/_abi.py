@@ -92,6 +92,7 @@ SIGNATURES = {
     "esdirk_step": (pmg_status, [C.POINTER(SolveOpts), C.c_int32, C.c_double, DP, DP, C.POINTER(SolveStats),
                                  C.c_int32, C.c_void_p]),
     "esdirk_stages": (C.c_int32, [C.c_int32]),
+    "esdirk_butcher": (C.c_int32, [C.c_int32, C.POINTER(C.c_double)]),
     "nk_work_elems": (C.c_int64, [pmg_level, C.c_int32]),
     "nk_stage_solve": (pmg_status, [C.POINTER(SolveOpts), C.POINTER(NkOpts), C.c_double, C.c_double, DP,
                                     C.POINTER(DP), C.POINTER(C.c_double), C.c_int32, DP, DP, C.POINTER(SolveStats),

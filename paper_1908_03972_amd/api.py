@@ -264,6 +264,17 @@ def esdirk_stages(scheme: int) -> int:
     return int(A.lib().esdirk_stages(scheme))
 
 
+def esdirk_butcher(scheme: int):
+    """The library's Butcher matrix of an ESDIRK scheme id (s x s numpy array)."""
+    import numpy as np
+    s = esdirk_stages(scheme)
+    if s == 0:
+        raise ValueError(f"unknown ESDIRK scheme {scheme}")
+    buf = (C.c_double * (s * s))()
+    A.lib().esdirk_butcher(scheme, buf)
+    return np.array(buf[:], dtype=float).reshape(s, s)
+
+
 def esdirk_step(solver: StageSolver, scheme: int, dt: float, q, work, stream=None, raise_on_error=True):
     """One time step of ``esdirk_step``; ``work`` is a float64 device tensor of shape
     (stages, Nv, Np, Ne). Returns one stats dict per implicit stage (with its residual history)."""

@@ -1295,6 +1295,13 @@ extern "C" int32_t esdirk_stages(int32_t scheme) {
   return esdirk_tableau(scheme, A);
 }
 
+extern "C" int32_t esdirk_butcher(int32_t scheme, double* A_out) {
+  double A[64];
+  const int s = esdirk_tableau(scheme, A);
+  if (A_out) std::memcpy(A_out, A, (size_t)s * s * sizeof(double));
+  return s;
+}
+
 extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, double dt, double* q, double* work,
                                   pmg_solve_stats* stats, int32_t n_stats, void* stream) {
   double A[64];

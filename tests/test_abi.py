@@ -52,3 +52,22 @@ def test_argument_errors_are_reported_without_a_gpu():
     assert lib.pmg_level_create(ctypes.byref(d), ctypes.byref(h)) == A.PMG_E_ARG
     assert lib.fr_residual(None, None, None, None, 0.0, None, None, None) == A.PMG_E_ARG
     assert lib.esdirk_stage_solve(None, 0.0, 0.0, None, None, None, 0, None, None, None, None) == A.PMG_E_ARG
+
+
+def test_esdirk_tableaux_match_the_oracle():
+    """The library's Butcher matrices (a host call, no GPU) equal the oracle's, which the oracle pins
+    by the order conditions and L-stability; the two are typed independently from the published
+    coefficients."""
+    import ctypes as C
+
+    import numpy as np
+
+    from oracle import solver as OS
+    from paper_1908_03972_amd import _abi as A
+    for scheme, name in ((2, "esdirk2"), (3, "esdirk3"), (4, "esdirk4")):
+        ref = OS.esdirk_tableau(name)
+        s = ref.shape[0]
+        buf = (C.c_double * (s * s))()
+        assert A.lib().esdirk_butcher(scheme, buf) == s
+        assert np.max(np.abs(np.array(buf[:]).reshape(s, s) - ref)) < 1e-15
+    assert A.lib().esdirk_butcher(5, None) == 0
