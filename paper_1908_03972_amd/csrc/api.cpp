@@ -16,7 +16,7 @@
 #include "internal.hpp"
 #include "jac3.hpp"
 #include "krylov.hpp"
-#include "transfer.hpp"
+#include "vcycle.hpp"
 
 using pmg::Ops1D;
 
@@ -263,13 +263,19 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // n synchronous element-Jacobi sweeps ping-ponging between q and the level's workspace (kernels
 // only, so the sequence can be captured in a graph); optional norms of the first sweep's F and
 // F_after = F(q) - S at the final state.
+// n sweeps; with form_S (a coarse level at its restricted state, S holding P w) the first sweep
+// also turns S into the level's forcing (n must then be >= 1)
 pmg_status run_sweeps(pmg_level_s& L, const pmg_factors_s& fac, double* q, const double* src, const double* S,
-                      double c_mass, int n, double alpha, double* F_after, bool norms, hipStream_t st) {
+                      double c_mass, int n, double alpha, double* F_after, bool norms, hipStream_t st,
+                      double* form_S = nullptr) {
   double* in = q;
   double* out = L.wq;
   for (int k = 0; k < n; ++k) {
     const bool nrm = norms && k == 0;
-    PMG_HIP(pmg::launch_sweep(L, fac, in, out, src, S, c_mass, alpha, nrm, st));
+    if (k == 0 && form_S)
+      PMG_HIP(pmg::launch_sweep_forming_S(L, fac, in, out, form_S, c_mass, alpha, st));
+    else
+      PMG_HIP(pmg::launch_sweep(L, fac, in, out, src, S, c_mass, alpha, nrm, st));
     if (nrm) PMG_HIP(pmg::launch_norm_finalize(L, st));
     std::swap(in, out);
   }
@@ -760,7 +766,10 @@ struct Solve {
   std::vector<std::vector<double>> R1, I1;   // per level l: matrices between l and l+1
 };
 
-pmg_status vcycle(Solve& s, int l, double* q, const double* S) {
+// One V-cycle from level l. With S_pending (coarse levels) S holds the restricted fine residual
+// P w = P (F_l(q^a) - S_l) and q the restricted state q^b: the forcing S_{l+1} = F_{l+1}(q^b) - P w
+// of eqs. (40), (43) is formed by the first pre-smoothing sweep, whose defect at q^b is P w.
+pmg_status vcycle(Solve& s, int l, double* q, double* S, bool S_pending = false) {
   const pmg_solve_opts* o = s.o;
   pmg_level L = o->levels[l];
   pmg_factors fac = o->factors[l];
@@ -770,17 +779,20 @@ pmg_status vcycle(Solve& s, int l, double* q, const double* S) {
     PMG_HIP(pmg::launch_jacobian(*L, q, s.dtau, s.c_mass, nullptr, *fac, s.st));
     ++s.n_refresh;
   }
+  if (S_pending && o->n_smooth[l] == 0) {   // no sweep to form it in
+    PMG_HIP(pmg::launch_residual(*L, q, nullptr, S, s.c_mass, S, false, s.st));
+    S_pending = false;
+  }
   // pre-smoothing; F_after = F_l(q^a) - S_l = -d_l
   if (pmg_status r = run_sweeps(*L, *fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r, last ? nullptr : L->wF,
-                                false, s.st))
+                                false, s.st, S_pending ? S : nullptr))
     return r;
   if (last) return PMG_OK;
   pmg_level Lc = o->levels[l + 1];
   // q^b_{l+1} = P q^a_l (eqs. (39), (42)), written also to the coarse working state, and
   // S_{l+1} = F_{l+1}(q^b) + P d_l = F_{l+1}(q^b) - P (F_l(q^a) - S_l)  (eqs. (40), (43))
   PMG_HIP(pmg::launch_restrict_pair(*L, *Lc, s.R1[l].data(), q, Lc->wqb, Lc->wql, L->wF, Lc->wS, Lc->nv, s.st));
-  PMG_HIP(pmg::launch_residual(*Lc, Lc->wqb, nullptr, Lc->wS, s.c_mass, Lc->wS, false, s.st));
-  if (pmg_status r = vcycle(s, l + 1, Lc->wql, Lc->wS)) return r;
+  if (pmg_status r = vcycle(s, l + 1, Lc->wql, Lc->wS, true)) return r;
   // q^{c,b}_l = q^a_l + I (q^{(c,)a}_{l+1} - q^b_{l+1}) (eqs. (44), (45)), then post-smoothing
   PMG_HIP(pmg::launch_prolong(*Lc, *L, s.I1[l].data(), Lc->wql, Lc->wqb, q, L->nv, s.st));
   return run_sweeps(*L, *fac, q, src, S, s.c_mass, o->n_smooth[l], o->alpha_r, nullptr, false, s.st);

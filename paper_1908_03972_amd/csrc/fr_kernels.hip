@@ -17,6 +17,7 @@
 // writes q + alpha D^{-1} F to a second buffer (synchronous Jacobi: neighbours are read from the
 // input buffer only).
 #include "internal.hpp"
+#include "vcycle.hpp"
 
 namespace pmg {
 
@@ -86,6 +87,7 @@ struct ResArgs {
   const void* W;
   double alpha;
   double* q_out;
+  double* S_out;   // non-null: S held P w, the defect is P w and S_out receives F(q) - P w
 };
 
 // MODE 0: residual only; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
@@ -453,7 +455,9 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
           d += o.gL[j] * SJ(2, i, v, el) + o.gR[j] * SJ(3, i, v, el);
         }
       }
-      const double fv = -d * ij - a.c_mass * qc[v] + srcv[v] - sv[v];
+      const double fraw = -d * ij - a.c_mass * qc[v] + srcv[v];
+      const double fv = a.S_out ? sv[v] : fraw - sv[v];
+      if (a.S_out && valid) a.S_out[v * sstride + gp] = fraw - sv[v];
       Fv[v] = valid ? fv : 0.0;
     }
   }
@@ -703,14 +707,14 @@ hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* 
   return launch_fr<0>(L.P, a, L.ne, L.visc != 0, st);
 }
 
-hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
-                        const double* src, const double* S, double c_mass, double alpha, bool want_norms,
-                        hipStream_t st) {
-  if (L.dim == 3) return launch_sweep3(L, fac, q_in, q_out, src, S, c_mass, alpha, want_norms, st);
+static hipError_t launch_sweep2(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                                const double* src, const double* S, double* S_out, double c_mass, double alpha,
+                                bool want_norms, hipStream_t st) {
   ResArgs a = base_args(L);
   a.q = q_in;
   a.src = src;
   a.S = S;
+  a.S_out = S_out;
   a.c_mass = c_mass;
   a.part = want_norms ? L.part : nullptr;
   a.W = fac.W;
@@ -722,6 +726,23 @@ hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const do
   }
   if (fac.precision == 32) return launch_fr<2>(L.P, a, L.ne, L.visc != 0, st);
   return launch_fr<1>(L.P, a, L.ne, L.visc != 0, st);
+}
+
+hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                        const double* src, const double* S, double c_mass, double alpha, bool want_norms,
+                        hipStream_t st) {
+  if (L.dim == 3) return launch_sweep3(L, fac, q_in, q_out, src, S, c_mass, alpha, want_norms, st);
+  return launch_sweep2(L, fac, q_in, q_out, src, S, nullptr, c_mass, alpha, want_norms, st);
+}
+
+hipError_t launch_sweep_forming_S(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
+                                  double* S, double c_mass, double alpha, hipStream_t st) {
+  if (L.dim == 3) {
+    const hipError_t e = launch_residual3(L, q_in, nullptr, S, c_mass, S, false, st);
+    if (e != hipSuccess) return e;
+    return launch_sweep3(L, fac, q_in, q_out, nullptr, S, c_mass, alpha, false, st);
+  }
+  return launch_sweep2(L, fac, q_in, q_out, nullptr, S, S, c_mass, alpha, false, st);
 }
 
 }  // namespace pmg

@@ -5,7 +5,7 @@
 // load and store is coalesced. They are bandwidth-bound: one read of the input level and one
 // write of the output level per call.
 #include "internal.hpp"
-#include "transfer.hpp"
+#include "vcycle.hpp"
 
 namespace pmg {
 
