@@ -297,12 +297,14 @@ pmg_status esdirk_step(const pmg_solve_opts* opts, int32_t scheme, double dt, do
  *   (Gamma(q_m)/dtau_m - dF/dq) delta = F(q_m),   q_{m+1} = q_m + delta
  * (the linearisation of eqs. (27)-(28) without the element-Jacobi splitting of eq. (29)) by one
  * cycle of flexible GMRES from delta = 0: at most krylov_dim directions, stopped once the
- * least-squares residual is <= eta ||F(q_m)||; classical Gram-Schmidt applied twice. Products with
+ * least-squares residual is <= eta ||F(q_m)||; classical Gram-Schmidt applied twice (the new
+ * direction's norm from the second pass's dot products). Products with
  * dF/dq are forward differences (F(q_m + h z) - F(q_m))/h with h ||z|| = fd_rel sqrt(N), N the
  * entries of a finest-level state: fd_rel is the RMS perturbation per entry, of the order of
  * sqrt(machine epsilon) times the absolute state (about 1e-3 for pressures near 6e4). With precondition = 1 each direction v is preconditioned by
  * one FAS V-cycle of Sec. 3 (the opts' levels, factors and smoothing counts) started at q_m on
- * F(q) - S_0 = 0 with S_0 = F(q_m) - e v: M^{-1} v = (V(q_m) - q_m)/e with e ||v|| = pc_rel sqrt(N).
+ * F(q) - S_0 = 0 with S_0 = F(q_m) - e v: M^{-1} v = (V(q_m) - q_m)/e with e = pc_rel sqrt(N)
+ * (||v|| = 1).
  * dtau_m follows eq. (31) from ||F(q_m)|| as in esdirk_stage_solve (dtau or CFL form), and the
  * blocks are rebuilt with the same rule (the coarse ones inside the first preconditioner V-cycle
  * of a refresh step). Arguments as esdirk_stage_solve, plus:

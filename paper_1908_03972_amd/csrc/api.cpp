@@ -1124,7 +1124,7 @@ extern "C" pmg_status nk_stage_solve(const pmg_solve_opts* o, const pmg_nk_opts*
   double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
   pmg_status result = PMG_E_NOT_CONVERGED;
   std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1), y(k), c(k + 1);
-  std::vector<const double*> xs(k + 1);
+  std::vector<const double*> xs(k + 2);
   for (int m = 0;; ++m) {
     if (m > 0) {   // F(q_m) and its norm (stage_begin enqueued those of q_0)
       PMG_HIP(pmg::launch_residual(*L0, q, s.src, nullptr, s.c_mass, L0->wF, true, st));
@@ -1171,11 +1171,8 @@ extern "C" pmg_status nk_stage_solve(const pmg_solve_opts* o, const pmg_nk_opts*
     for (int j = 0; j < k; ++j) {
       double* v = w.V(j);
       double* z = w.Z(j);
-      if (nk->precondition) {   // z = (V(q_m; S_0 = F(q_m) - e v) - q_m) / e
-        double vv = 0.0;
-        const double* xv = v;
-        if (pmg_status e = nk_dots(w, &xv, 1, v, &vv, st)) return e;
-        const double e = nk->pc_rel * sqn / std::sqrt(vv);
+      if (nk->precondition) {   // z = (V(q_m; S_0 = F(q_m) - e v) - q_m) / e, ||v|| = 1
+        const double e = nk->pc_rel * sqn;
         PMG_HIP(pmg::launch_copy(N, q, w.W1(), st));
         const double* x2[2] = {w.F0(), v};
         const double c2[2] = {1.0, -e};
@@ -1201,19 +1198,22 @@ extern "C" pmg_status nk_stage_solve(const pmg_solve_opts* o, const pmg_nk_opts*
       PMG_HIP(pmg::launch_residual(*L0, w.W1(), s.src, nullptr, s.c_mass, w.W2(), false, st));
       double* wn = w.V(j + 1);
       PMG_HIP(pmg::launch_newton_op(*L0, q, z, w.W2(), w.F0(), 1.0 / s.dtau, 1.0 / h, wn, st));
+      // classical Gram-Schmidt applied twice; the second pass's block of dots also gives ||w||^2,
+      // and ||w - V c||^2 = ||w||^2 - ||c||^2 for orthonormal V
       for (int i = 0; i <= j; ++i) xs[i] = w.V(i);
-      for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
-        if (pmg_status e = nk_dots(w, xs.data(), j + 1, wn, c.data(), st)) return e;
+      xs[j + 1] = wn;
+      double ww = 0.0;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pmg_status e = nk_dots(w, xs.data(), j + 1 + pass, wn, c.data(), st)) return e;
+        if (pass == 1) ww = c[j + 1];
         for (int i = 0; i <= j; ++i) {
           H[(size_t)i * k + j] += c[i];
+          if (pass == 1) ww -= c[i] * c[i];
           c[i] = -c[i];
         }
         if (pmg_status e = nk_lincomb(w, j + 1, xs.data(), c.data(), 1.0, wn, st)) return e;
       }
-      double ww = 0.0;
-      const double* xw = wn;
-      if (pmg_status e = nk_dots(w, &xw, 1, wn, &ww, st)) return e;
-      const double hnorm = std::sqrt(ww);
+      const double hnorm = std::sqrt(std::max(ww, 0.0));
       H[(size_t)(j + 1) * k + j] = hnorm;
       for (int i = 0; i < j; ++i) {   // earlier rotations, then a new one
         const double a = H[(size_t)i * k + j], b = H[(size_t)(i + 1) * k + j];
