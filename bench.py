@@ -47,11 +47,10 @@ def dof_updates_per_vcycle(ne, p_levels, n_smooth, nv=4, dim=2):
     return tot
 
 
-def cpu_baseline(n_side=32):
-    """The CPU oracle on a bounded sample of the workload: one block rebuild on every level and
-    one V-cycle of the first implicit ESDIRK3 stage, on the same vortex with an n_side x n_side
-    jittered mesh. DOF-updates/s = DOF-updates of one V-cycle / (V-cycle time + rebuild/10), the
-    rebuild amortised as in the GPU metric."""
+def _cpu_sample(n_side, threads):
+    """Block rebuild on every level and one V-cycle of the first implicit ESDIRK3 stage by the CPU
+    oracle, with its BLAS/LAPACK limited to the given number of threads: (rebuild s, V-cycle s,
+    DOF-updates of the V-cycle, elements)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import gas as OG
@@ -59,7 +58,7 @@ def cpu_baseline(n_side=32):
     mesh = W.periodic_quad_mesh(n_side, 10.0, jitter=0.1, seed=W.JITTER_SEED)
     vs = W.VortexSpec(length=10.0)
     gas = OG.Gas(gamma=vs.gamma, rgas=vs.rgas, eps_mode="local")
-    with threadpool_limits(1):
+    with threadpool_limits(threads):
         opts = OS.PMGOptions(p_levels=P_LEVELS, n_smooth=N_SMOOTH)
         sol = OS.PMGSolver(mesh, gas, opts, q_inf=vs.freestream())
         lev = sol.levels[0]
@@ -80,12 +79,26 @@ def cpu_baseline(n_side=32):
         t0 = time.perf_counter()
         sol.vcycle(0, q, None)
         t_vc = time.perf_counter() - t0
-    per_vc = dof_updates_per_vcycle(mesh.n_elements, P_LEVELS, N_SMOOTH)
-    value = per_vc / (t_vc + t_build / 10.0)
-    return {"value": value, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+    return t_build, t_vc, dof_updates_per_vcycle(mesh.n_elements, P_LEVELS, N_SMOOTH), mesh.n_elements
+
+
+def cpu_baseline(n_side=32):
+    """The CPU oracle on a bounded sample of the workload: one block rebuild on every level and
+    one V-cycle of the first implicit ESDIRK3 stage, on the same vortex with an n_side x n_side
+    jittered mesh, on one thread and on all the host cores available to this process (at most 16).
+    DOF-updates/s = DOF-updates of one V-cycle / (V-cycle time + rebuild/10), the rebuild amortised
+    as in the GPU metric; the faster run is the baseline."""
+    runs = {}
+    for threads in sorted({1, max(1, min(16, len(os.sched_getaffinity(0))))}):
+        t_build, t_vc, per_vc, ne = _cpu_sample(n_side, threads)
+        runs[threads] = (per_vc / (t_vc + t_build / 10.0), t_build, t_vc)
+    best = max(runs, key=lambda t: runs[t][0])
+    value, t_build, t_vc = runs[best]
+    return {"value": value, "unit": "DOF-updates/s", "cores": best, "kind": "oracle",
             "sample": (f"block rebuild on all levels ({t_build:.1f} s) + one V-cycle ({t_vc:.1f} s) of the first "
                        f"ESDIRK3 stage on the same vortex with a {n_side}x{n_side} jittered mesh "
-                       f"({mesh.n_elements} elements, {per_vc} DOF-updates per V-cycle); rebuild amortised 1/10"),
+                       f"({ne} elements, {per_vc} DOF-updates per V-cycle); rebuild amortised 1/10"),
+            "value_per_thread_count": {str(t): v[0] for t, v in runs.items()},
             "cpu": platform.processor() or platform.machine()}
 
 
