@@ -119,18 +119,27 @@ class FRLevel:
         return br2.terms(q, own, out, out_grad, one_sided, m.face_nbr == BC_NOSLIP_WALL, m.face_nbr == BC_FAR_FIELD)
 
     # ---- residual ----------------------------------------------------------------
-    def residual(self, q, q_nbr=None):
+    def residual(self, q, q_nbr=None, nbr_faces=None):
         """R(q) = -div f at the solution points, [Ne, Np, Nv].
 
         ``q_nbr`` (default q) is the state the neighbours' face traces are taken from;
         the Jacobian module passes the unperturbed state there so that only the
-        element's own unknowns move.
+        element's own unknowns move. With ``nbr_faces`` (a tuple of face indices) only
+        those faces of every element see q_nbr; the others see the neighbours' traces of q
+        (inviscid only), so that the response of element e measures its coupling to the one
+        neighbour across each listed face.
         """
         o, g = self.ops, self.geo
         ne, n1, nv = self.ne, self.n1, self.nv
         own = self.traces(q)
         nbr_tr = own if q_nbr is None else self.traces(q_nbr)
         out = self.outside_states(own, nbr_tr)
+        if nbr_faces is not None:
+            if self.br2 is not None:
+                raise ValueError("per-face neighbour states are defined for inviscid levels only")
+            keep = np.zeros(4, bool)
+            keep[list(nbr_faces)] = True
+            out = np.where(keep[None, :, None, None], out, self.outside_states(own, own))
         fv = g.fvec
         fh = [G.common_flux(out[:, 0], own[:, 0], fv[:, 0], self.gas),
               G.common_flux(own[:, 1], out[:, 1], fv[:, 1], self.gas),

@@ -28,6 +28,7 @@ from .fr import FRLevel
 from .fr3 import FRLevel3
 from .geometry import element_dx
 from .geometry3d import element_dx3
+from .lines import line_blocks, line_sweeps
 from .jacobian import element_blocks
 
 
@@ -110,6 +111,9 @@ class PMGOptions:
     use_cfl: bool = False
     cfl_init: float = 1e2
     cfl_max: float = 1e5
+    # per level: None (element Jacobi) or a [n_lines, K] array of element lines on which that
+    # level smooths by element-line Jacobi (``oracle.lines``)
+    lines: tuple = ()
 
 
 @dataclass
@@ -144,12 +148,25 @@ class PMGSolver:
         """F_l(q) - S_l on level l (only level 0 carries the ESDIRK source)."""
         return self.levels[l].stage_residual(q, self.c_mass, self.src if l == 0 else None, S)
 
+    def level_lines(self, l):
+        lines = self.opts.lines
+        return lines[l] if l < len(lines) else None
+
     def build_D(self, l, q):
-        self.D[l] = element_blocks(self.levels[l], q, self.dtau, self.c_mass)
+        lines = self.level_lines(l)
+        if lines is None:
+            self.D[l] = element_blocks(self.levels[l], q, self.dtau, self.c_mass)
+        else:
+            self.D[l] = line_blocks(self.levels[l], q, self.dtau, self.c_mass, lines)
 
     def smooth(self, l, q, S, nsweep):
-        """Element Jacobi, eq. (30): q <- q + alpha_r D^{-1} (F_l(q) - S_l), all elements at once."""
+        """Element Jacobi, eq. (30): q <- q + alpha_r D^{-1} (F_l(q) - S_l), all elements at once
+        (or element-line Jacobi where the level has lines, ``oracle.lines``)."""
         lev = self.levels[l]
+        lines = self.level_lines(l)
+        if lines is not None:
+            return line_sweeps(lev, q, self.D[l], lines, nsweep, self.c_mass,
+                               self.src if l == 0 else None, S, self.opts.alpha_r)
         for _ in range(nsweep):
             Fq = self.F(l, q, S).reshape(lev.ne, lev.n, 1)
             dq = np.linalg.solve(self.D[l], Fq)
