@@ -61,7 +61,7 @@ typedef struct pmg_batch_s* pmg_batch;
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 106
+#define PMG_ABI_VERSION 107
 int32_t pmg_abi_version(void);
 
 /*
@@ -158,6 +158,39 @@ pmg_status pmg_level_status(pmg_level L, int32_t* flags);
  * element (2.6 GB for 36 864 elements), held until pmg_factors_destroy. */
 pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out);
 pmg_status pmg_factors_destroy(pmg_factors F);
+
+/*
+ * pmg_line_factors_create — blocks for element-line Jacobi instead of element Jacobi. This is the
+ * smoother for strongly stretched meshes that the introduction cites from earlier implicit
+ * high-order solvers. Along each line of face-connected elements it keeps, besides D_e of
+ * eqs. (28)-(30), the blocks A_{e,e'} = -dR_e/dq_{e'} coupling an element to its predecessor and
+ * successor. It solves each line's block-tridiagonal system exactly; the lines are independent
+ * (Jacobi across lines).
+ *   line_elems  host int32[n_lines][line_len], element indices in line order, copied. Every element
+ *               appears exactly once (n_lines * line_len == Ne), and consecutive elements of a line
+ *               share exactly one face; else PMG_E_SHAPE.
+ *   precision   64 or 32: storage of the block-Thomas inverses W_k = D'_k^{-1}. The elimination
+ *               itself runs in FP64.
+ * The handle is a pmg_factors and takes the place of element blocks everywhere:
+ *   - fr_element_jacobian builds D_e and factors every line (D_out as documented there);
+ *   - ejacobi_sweep runs line sweeps q <- q + alpha_r A_line^{-1} (F(q) - S);
+ *   - a stage solve smooths by lines on every level whose factors are line factors.
+ * Limits: quadrilateral, inviscid levels with P <= 4; otherwise PMG_E_ARG.
+ * Footprint per element: n*n*8 (D_e) + n*n*precision/8 (W) + 256 (P+1) bytes, plus one state-sized
+ * FP64 array; released by pmg_factors_destroy.
+ */
+pmg_status pmg_line_factors_create(pmg_level L, int32_t precision, const int32_t* line_elems, int32_t n_lines,
+                                   int32_t line_len, pmg_factors* out);
+
+/* pmg_line_blocks — refactors line factors F at state q, as fr_element_jacobian does. It also writes
+ * the blocks out, for tests; each output is device double[Ne][n][n], row-major, row index p*Nv + v,
+ * or NULL:
+ *   D_out   D_e;
+ *   Am_out  A_{e, previous element of its line}; zero for a line's first element;
+ *   Ap_out  A_{e, next element of its line}; zero for a line's last element.
+ * Errors: PMG_E_ARG (not a line-factor handle, null q, dtau <= 0), PMG_E_HIP. */
+pmg_status pmg_line_blocks(pmg_factors F, const double* q, double dtau, double c_mass, double* D_out,
+                           double* Am_out, double* Ap_out, void* stream);
 
 /*
  * fr_residual — stage residual of eq. (26) with the FAS forcing of eqs. (34)-(36):

@@ -79,6 +79,9 @@ SIGNATURES = {
     "pmg_dtau_min": (pmg_status, [pmg_level, DP, C.POINTER(C.c_double), C.c_void_p]),
     "pmg_factors_create": (pmg_status, [pmg_level, C.c_int32, C.POINTER(pmg_factors)]),
     "pmg_factors_destroy": (pmg_status, [pmg_factors]),
+    "pmg_line_factors_create": (pmg_status, [pmg_level, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                             C.POINTER(pmg_factors)]),
+    "pmg_line_blocks": (pmg_status, [pmg_factors, DP, C.c_double, C.c_double, DP, DP, DP, C.c_void_p]),
     "fr_residual": (pmg_status, [pmg_level, DP, DP, DP, C.c_double, DP, DP, C.c_void_p]),
     "fr_conservative": (pmg_status, [pmg_level, DP, DP, C.c_void_p]),
     "fr_element_jacobian": (pmg_status, [pmg_level, DP, C.c_double, C.c_double, DP, pmg_factors, C.c_void_p]),

@@ -120,6 +120,38 @@ class Factors:
             pass
 
 
+class LineFactors(Factors):
+    """Element-line Jacobi blocks of one level (a ``pmg_factors`` handle made by
+    ``pmg_line_factors_create``); ``lines`` is an [n_lines, K] integer array of element indices in
+    line order covering every element once."""
+
+    def __init__(self, level: Level, lines, precision: int = 64):
+        import numpy as np
+        arr = np.ascontiguousarray(np.asarray(lines), dtype=np.int32)
+        if arr.ndim != 2:
+            raise ValueError("lines must be a 2-D array [n_lines, K]")
+        h = A.pmg_factors()
+        A.check(A.lib().pmg_line_factors_create(level.handle, precision, arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                 arr.shape[0], arr.shape[1], C.byref(h)), "pmg_line_factors_create")
+        self.handle = h
+        self.level = level
+        self.precision = precision
+        self.lines = arr
+
+
+def line_blocks(fac: LineFactors, q, dtau: float, c_mass: float = 0.0, stream=None):
+    """Refactor the line factors at state q and return (D, Am, Ap), each [Ne, n, n] float64 on the
+    level's device (row index p*Nv + v; Am/Ap the blocks towards the previous/next element of the
+    line, zero at the line's ends)."""
+    lev = fac.level
+    shape = (lev.ne, lev.n, lev.n)
+    D, Am, Ap = (torch.empty(shape, dtype=torch.float64, device=lev.torch_device) for _ in range(3))
+    A.check(A.lib().pmg_line_blocks(fac.handle, lev.check_state(q, "q", False), dtau, c_mass,
+                                    C.c_void_p(D.data_ptr()), C.c_void_p(Am.data_ptr()), C.c_void_p(Ap.data_ptr()),
+                                    _stream(stream)), "pmg_line_blocks")
+    return D, Am, Ap
+
+
 def _norms_ptr(level: Level, norms):
     if norms is None:
         return None

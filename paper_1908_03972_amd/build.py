@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmgfr.so")
 ARCH = os.environ.get("PMGFR_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "hex_geometry.cpp", "fr_kernels.hip", "fr3_kernels.hip", "jac3_kernels.hip", "jac_kernels.hip", "transfer_kernels.hip", "krylov_kernels.hip"]
+SOURCES = ["api.cpp", "hex_geometry.cpp", "fr_kernels.hip", "fr3_kernels.hip", "jac3_kernels.hip", "jac_kernels.hip", "transfer_kernels.hip", "krylov_kernels.hip",
+           "line_kernels.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",

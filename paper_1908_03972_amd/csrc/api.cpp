@@ -16,6 +16,7 @@
 #include "internal.hpp"
 #include "jac3.hpp"
 #include "krylov.hpp"
+#include "lines.hpp"
 #include "vcycle.hpp"
 
 using pmg::Ops1D;
@@ -260,14 +261,39 @@ void free_level(pmg_level_s* L) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The smoother's blocks at state q: element inverses, or the block-Thomas factors of line factors.
+hipError_t build_blocks(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
+                        pmg_factors_s& fac, hipStream_t st) {
+  if (fac.lines) return pmg::launch_line_factor(L, q, dtau, c_mass, D_out, fac, st);
+  return pmg::launch_jacobian(L, q, dtau, c_mass, D_out, fac, st);
+}
+
 // n synchronous element-Jacobi sweeps ping-ponging between q and the level's workspace (kernels
 // only, so the sequence can be captured in a graph); optional norms of the first sweep's F and
-// F_after = F(q) - S at the final state.
+// F_after = F(q) - S at the final state. Line factors sweep in place instead (a residual, then
+// the line solves).
 // n sweeps; with form_S (a coarse level at its restricted state, S holding P w) the first sweep
 // also turns S into the level's forcing (n must then be >= 1)
 pmg_status run_sweeps(pmg_level_s& L, const pmg_factors_s& fac, double* q, const double* src, const double* S,
                       double c_mass, int n, double alpha, double* F_after, bool norms, hipStream_t st,
                       double* form_S = nullptr) {
+  if (fac.lines) {
+    if (form_S) {                         // S_{l+1} = F(q^b) - P w first, then ordinary sweeps
+      PMG_HIP(pmg::launch_residual(L, q, nullptr, form_S, c_mass, form_S, false, st));
+      S = form_S;
+    }
+    for (int k = 0; k < n; ++k) {
+      const bool nrm = norms && k == 0;
+      PMG_HIP(pmg::launch_line_sweep(L, fac, q, src, S, c_mass, alpha, nrm, st));
+      if (nrm) PMG_HIP(pmg::launch_norm_finalize(L, st));
+    }
+    if (F_after) {
+      const bool nrm = norms && n == 0;
+      PMG_HIP(pmg::launch_residual(L, q, src, S, c_mass, F_after, nrm, st));
+      if (nrm) PMG_HIP(pmg::launch_norm_finalize(L, st));
+    }
+    return PMG_OK;
+  }
   double* in = q;
   double* out = L.wq;
   for (int k = 0; k < n; ++k) {
@@ -662,7 +688,83 @@ pmg_status pmg_factors_destroy(pmg_factors F) {
   DeviceGuard guard(F->L->device);
   if (F->W) (void)hipFree(F->W);
   if (F->ws) (void)hipFree(F->ws);
+  if (pmg::LineFactors* lf = F->lines) {
+    void* ptrs[] = {lf->elems, lf->fside, lf->D, lf->Winv, lf->Kc, lf->r};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    delete lf;
+  }
   delete F;
+  return PMG_OK;
+}
+
+pmg_status pmg_line_factors_create(pmg_level L, int32_t precision, const int32_t* line_elems, int32_t n_lines,
+                                   int32_t line_len, pmg_factors* out) {
+  if (pmg_status s = check_level(L)) return s;
+  if (!out || !line_elems) return fail(PMG_E_ARG, "null output or line list");
+  if (precision != 32 && precision != 64) return fail(PMG_E_ARG, "precision must be 32 or 64");
+  if (L->dim != 2) return fail(PMG_E_ARG, "element-line Jacobi is implemented for quadrilateral levels");
+  if (L->P > pmg::kLineMaxP) return fail(PMG_E_ARG, "element-line Jacobi is implemented for P <= 4");
+  if (L->visc) return fail(PMG_E_ARG, "element-line Jacobi is implemented for inviscid levels");
+  if (n_lines < 1 || line_len < 1 || (int64_t)n_lines * line_len != L->ne)
+    return fail(PMG_E_SHAPE, "the lines must hold every element exactly once (n_lines * line_len == Ne)");
+  DeviceGuard guard(L->device);
+  const int ne = L->ne;
+  std::vector<int> nbr((size_t)4 * ne);
+  PMG_HIP(hipMemcpy(nbr.data(), L->nbr, nbr.size() * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<int> seen(ne, 0), fside((size_t)2 * ne, -1);
+  for (int64_t i = 0; i < (int64_t)n_lines * line_len; ++i) {
+    const int e = line_elems[i];
+    if (e < 0 || e >= ne || seen[e]++) return fail(PMG_E_SHAPE, "an element is missing from the lines or repeated");
+  }
+  for (int l = 0; l < n_lines; ++l) {
+    for (int k = 0; k + 1 < line_len; ++k) {
+      const int e = line_elems[(size_t)l * line_len + k], e2 = line_elems[(size_t)l * line_len + k + 1];
+      int f12 = -1, f21 = -1, n12 = 0, n21 = 0;
+      for (int f = 0; f < 4; ++f) {
+        if (nbr[(size_t)f * ne + e] == e2) f12 = f, ++n12;
+        if (nbr[(size_t)f * ne + e2] == e) f21 = f, ++n21;
+      }
+      if (n12 != 1 || n21 != 1) return fail(PMG_E_SHAPE, "consecutive elements of a line must share exactly one face");
+      fside[(size_t)ne + e] = f12;        // towards the next element
+      fside[e2] = f21;                    // towards the previous element
+    }
+  }
+  pmg_factors_s* F = new pmg_factors_s();
+  F->L = L;
+  F->precision = precision;
+  F->lines = new pmg::LineFactors();
+  pmg::LineFactors& lf = *F->lines;
+  lf.n_lines = n_lines;
+  lf.K = line_len;
+  const size_t nn = (size_t)ne * L->n * L->n;
+  F->bytes = nn * (precision / 8);
+  std::vector<int> elems(line_elems, line_elems + (size_t)n_lines * line_len);
+  bool ok = upload(&lf.elems, elems) == PMG_OK && upload(&lf.fside, fside) == PMG_OK &&
+            hipMalloc(&lf.D, nn * sizeof(double)) == hipSuccess && hipMalloc(&lf.Winv, F->bytes) == hipSuccess &&
+            hipMalloc(&lf.Kc, (size_t)2 * ne * 16 * L->n1 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&lf.r, L->state_elems() * sizeof(double)) == hipSuccess;
+  // a sweep before the first factorisation leaves q unchanged
+  ok = ok && hipMemset(lf.Winv, 0, F->bytes) == hipSuccess &&
+       hipMemset(lf.Kc, 0, (size_t)2 * ne * 16 * L->n1 * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    (void)pmg_factors_destroy(F);
+    return fail(PMG_E_NOMEM, "device allocation failed for the line factors");
+  }
+  *out = F;
+  return PMG_OK;
+}
+
+pmg_status pmg_line_blocks(pmg_factors F, const double* q, double dtau, double c_mass, double* D_out,
+                           double* Am_out, double* Ap_out, void* stream) {
+  if (!F || !F->lines) return fail(PMG_E_ARG, "not a line-factor handle");
+  if (!q) return fail(PMG_E_ARG, "null q");
+  if (!(dtau > 0.0)) return fail(PMG_E_ARG, "dtau must be positive");
+  pmg_level L = F->L;
+  DeviceGuard guard(L->device);
+  hipStream_t st = as_stream(stream);
+  PMG_HIP(pmg::launch_line_factor(*L, q, dtau, c_mass, D_out, *F, st));
+  if (Am_out || Ap_out) PMG_HIP(pmg::launch_line_dense(*L, *F, Am_out, Ap_out, st));
   return PMG_OK;
 }
 
@@ -697,7 +799,7 @@ pmg_status fr_element_jacobian(pmg_level L, const double* q, double dtau, double
   if (fac->L != L) return fail(PMG_E_SHAPE, "factors belong to another level");
   if (!(dtau > 0.0)) return fail(PMG_E_ARG, "dtau must be positive");
   DeviceGuard guard(L->device);
-  PMG_HIP(pmg::launch_jacobian(*L, q, dtau, c_mass, D_out, *fac, as_stream(stream)));
+  PMG_HIP(build_blocks(*L, q, dtau, c_mass, D_out, *fac, as_stream(stream)));
   return PMG_OK;
 }
 
@@ -776,7 +878,7 @@ pmg_status vcycle(Solve& s, int l, double* q, double* S, bool S_pending = false)
   const bool last = (l == o->n_levels - 1);
   const double* src = (l == 0) ? s.src : nullptr;
   if (s.refresh && l > 0) {
-    PMG_HIP(pmg::launch_jacobian(*L, q, s.dtau, s.c_mass, nullptr, *fac, s.st));
+    PMG_HIP(build_blocks(*L, q, s.dtau, s.c_mass, nullptr, *fac, s.st));
     ++s.n_refresh;
   }
   if (S_pending && o->n_smooth[l] == 0) {   // no sweep to form it in
@@ -992,7 +1094,7 @@ pmg_status stage_advance(StageRun& R) {
   const bool frozen = o->freeze_at_max && R.dtau_last_refresh >= R.dtau_max;
   s.refresh = (m == 0) || (m % o->refresh_every == 0 && !frozen);
   if (s.refresh) {
-    PMG_HIP(pmg::launch_jacobian(*L0, R.q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
+    PMG_HIP(build_blocks(*L0, R.q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
     ++s.n_refresh;
     R.dtau_last_refresh = s.dtau;
     if (pmg_status e = vcycle_and_norm(s, R.q)) return e;
@@ -1154,7 +1256,7 @@ extern "C" pmg_status nk_stage_solve(const pmg_solve_opts* o, const pmg_nk_opts*
     const bool frozen = o->freeze_at_max && dtau_last_refresh >= R.dtau_max;
     bool refresh_coarse = false;
     if (m == 0 || (m % o->refresh_every == 0 && !frozen)) {
-      PMG_HIP(pmg::launch_jacobian(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], st));
+      PMG_HIP(build_blocks(*L0, q, s.dtau, s.c_mass, nullptr, *o->factors[0], st));
       ++s.n_refresh;
       dtau_last_refresh = s.dtau;
       refresh_coarse = true;

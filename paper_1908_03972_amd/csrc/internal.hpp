@@ -104,6 +104,10 @@ struct pmg_level_s {
   }
 };
 
+namespace pmg {
+struct LineFactors;
+}
+
 struct pmg_factors_s {
   pmg_level_s* L = nullptr;
   int precision = 64;     // 64: FP64 inverse blocks; 32: FP32 inverse blocks
@@ -111,6 +115,7 @@ struct pmg_factors_s {
   size_t bytes = 0;
   double* ws = nullptr;   // work array of the large-block elimination: ws_slots x n x n FP64 (3-D P = 3)
   int ws_slots = 0;
+  pmg::LineFactors* lines = nullptr;   // element-line Jacobi instead of element Jacobi (lines.hpp)
 };
 
 namespace pmg {

@@ -236,6 +236,7 @@ __global__ void __launch_bounds__((RowsCfg<P, S>::NT)) k_jac_rows(JacArgs a) {
 #pragma unroll
     for (int j = 0; j < H; ++j) a.D_out[((size_t)e * N + r) * N + h * H + j] = row[j];
   }
+  if (!a.W) return;                       // blocks only (the line smoother factors them itself)
   double mx = 0.0;                        // row equilibration by a power of two
 #pragma unroll
   for (int j = 0; j < H; ++j) mx = fmax(mx, fabs(row[j]));

@@ -1,0 +1,35 @@
+// Element-line Jacobi on quadrilateral levels: the state a line-smoother factor set keeps and its
+// kernel launchers (line_kernels.hip).
+#pragma once
+
+#include "internal.hpp"
+
+namespace pmg {
+
+constexpr int kLineMaxP = 4;   // a line workgroup holds one n x n block in LDS (n = 100 at P = 4)
+
+struct LineFactors {
+  int n_lines = 0, K = 0;      // lines of K elements each; n_lines * K = Ne
+  int* elems = nullptr;        // device [n_lines][K] element indices in line order
+  int* fside = nullptr;        // device [2][Ne]: face of e towards the previous / next element of its
+                               // line, -1 at the line's ends
+  double* D = nullptr;         // device [Ne][n][n] row-major FP64: element blocks of the last factorisation
+  void* Winv = nullptr;        // device [Ne][n][n] at the factor precision, column-major per element
+                               // ([e][c][r]): W_k = D'_k^{-1} of the block-Thomas elimination
+  double* Kc = nullptr;        // device [2][Ne][n1][4][4]: derivative of |S| f_com at each flux point of the
+                               // face towards the previous / next element with respect to that
+                               // neighbour's trace
+  double* r = nullptr;         // device state-sized work array: F - S, then the forward sweep's y
+};
+
+// D_e (and D_out, if given), the coupling derivatives and the block-Thomas inverses of every line
+hipError_t launch_line_factor(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
+                              pmg_factors_s& fac, hipStream_t st);
+// one line-Jacobi sweep in place: q += alpha A_line^{-1} (F(q) - S), with the norms of F(q) - S
+hipError_t launch_line_sweep(const pmg_level_s& L, const pmg_factors_s& fac, double* q, const double* src,
+                             const double* S, double c_mass, double alpha, bool want_norms, hipStream_t st);
+// the coupling blocks of the last factorisation written out dense, [Ne][n][n] row-major (null skips)
+hipError_t launch_line_dense(const pmg_level_s& L, const pmg_factors_s& fac, double* Am, double* Ap,
+                             hipStream_t st);
+
+}  // namespace pmg
