@@ -203,6 +203,67 @@ def airfoil_block(api, torch, forms, max_vcycles, kernel_reps):
     return out
 
 
+def airfoil_lines_block(api, torch, max_vcycles, kernel_reps, plev=(4, 2, 1), nsm=(5, 10, 20)):
+    """The same steady airfoil solve with FP32 blocks and graph replay, smoothed by element Jacobi
+    and by element-line Jacobi along the O-mesh's radial lines (128 lines of 64 elements, the
+    direction in which the cells are stretched) on every level: V-cycles, time to each tolerance,
+    and the live duration of the fine-level line sweep (residual + forward and backward block
+    substitution) against its algorithmic bytes."""
+    mesh, fs = W.airfoil_config3()
+    qinf = fs.freestream()
+    nw, nr = 128, 64                                     # element e = i + 128 j (i round, j outwards)
+    radial = np.arange(nw)[:, None] + nw * np.arange(nr)[None, :]
+    levels = [api.Level(mesh, P, gamma=fs.gamma, rgas=fs.rgas, eps_mode=1, ma_inf=fs.ma_inf, kappa=1.0,
+                        q_inf=qinf, q_ref=qinf) for P in plev]
+    per_vc = dof_updates_per_vcycle(levels[0].ne, plev, nsm)
+    out = {"workload": f"airfoil O-mesh {nw}x{nr}, P{{{'-'.join(map(str, plev))}}} I{{{'-'.join(map(str, nsm))}}}, "
+                       "FP32 blocks, graph replay, steady, CFL 1e2 -> 1e5",
+           "lines": f"{nw} radial lines of {nr} elements", "dof_updates_per_vcycle": per_vc}
+    kw = dict(tol_rel=1e-8, use_graph=True, use_cfl=True, cfl_init=1e2, cfl_max=1e5, freeze_at_max=False)
+    for smoother in ("element", "line"):
+        if smoother == "line":
+            facs = [api.LineFactors(lv, radial, 32) for lv in levels]
+        else:
+            facs = [api.Factors(lv, 32) for lv in levels]
+        q = levels[0].new_state()
+        api.StageSolver(levels, facs, nsm, max_vcycles=12, **kw).solve(q, raise_on_error=False)   # warm-up
+        q.zero_()
+        solver = api.StageSolver(levels, facs, nsm, max_vcycles=max_vcycles, **kw)
+        torch.cuda.synchronize()
+        st = solver.solve(q, raise_on_error=False)
+        h = np.asarray(st["history"]) / st["history"][0]
+        per = st["seconds"] / max(st["n_vcycles"], 1)
+        ttt = {}
+        for t in TOLS:
+            hit = np.nonzero(h <= t)[0]
+            ttt[f"{t:.0e}"] = float(hit[0] * per) if hit.size else None
+        fin = np.isfinite(h)
+        qk = q.clone()
+        api.ejacobi_sweep(levels[0], facs[0], qk, 2, alpha_r=0.0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        api.ejacobi_sweep(levels[0], facs[0], qk, kernel_reps, alpha_r=0.0)
+        ev1.record()
+        torch.cuda.synchronize()
+        k_ms = ev0.elapsed_time(ev1) / kernel_reps
+        n = levels[0].n
+        # element: one pass over the FP32 inverses + 24 B/DOF of state; line: the inverses twice
+        # (forward and backward substitution) + 24 B/DOF for the residual kernel and 40 B/DOF for
+        # the substitutions' right-hand side, intermediate and state traffic
+        bpd = 4 * n + 24 if smoother == "element" else 8 * n + 64
+        kbytes = levels[0].ne * n * bpd
+        out[smoother] = {"status": st["status"], "vcycles": st["n_vcycles"], "block_rebuilds": st["n_refresh"],
+                         "seconds": st["seconds"], "ms_per_vcycle": 1e3 * per,
+                         "dof_updates_per_s": per_vc * st["n_vcycles"] / st["seconds"],
+                         "time_to_tol_s": ttt, "min_rel_residual": float(np.min(h[fin])),
+                         "final_rel_residual": float(h[fin][-1]),
+                         "history_every_25": [float(x) for x in h[::25]],
+                         "fine_sweep_ms": k_ms, "fine_sweep_bytes": kbytes,
+                         "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del facs, solver
+    return out
+
+
 def sphere_block(api, torch, forms, max_vcycles, kernel_reps, plev=(2, 1, 0), nsm=(5, 10, 20),
                  profile_pmc=None, cfl_init=1e2):
     """Steady inviscid flow at Ma 0.001 past the unit sphere on the 6 x 16 x 16 x 24 cubed sphere of
@@ -464,6 +525,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
+    ap.add_argument("--no-lines", action="store_true",
+                    help="skip the airfoil comparison of element and radial element-line Jacobi")
     ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
     ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere steady solves")
     ap.add_argument("--no-sphere-p3", action="store_true", help="skip the 3-D sphere P{3-2-1-0} steady solves")
@@ -608,6 +671,10 @@ def main():
         line["airfoil_128x64_P4_steady"] = airfoil_block(api, torch, args.forms.split(","), args.airfoil_vcycles,
                                                          args.kernel_reps)
         progress("airfoil steady solves")
+    if not args.no_lines:
+        line["airfoil_128x64_P421_element_vs_line_jacobi"] = airfoil_lines_block(api, torch, args.airfoil_vcycles,
+                                                                                args.kernel_reps)
+        progress("airfoil element against line Jacobi")
     if not args.no_viscous:
         line["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
         progress("viscous batch")
