@@ -247,10 +247,11 @@ def airfoil_lines_block(api, torch, max_vcycles, kernel_reps, plev=(4, 2, 1), ns
         torch.cuda.synchronize()
         k_ms = ev0.elapsed_time(ev1) / kernel_reps
         n = levels[0].n
-        # element: one pass over the FP32 inverses + 24 B/DOF of state; line: the inverses twice
-        # (forward and backward substitution) + 24 B/DOF for the residual kernel and 40 B/DOF for
-        # the substitutions' right-hand side, intermediate and state traffic
-        bpd = 4 * n + 24 if smoother == "element" else 8 * n + 64
+        # element: one pass over the FP32 inverses + 24 B/DOF of state; line: the inverses once and
+        # C_k, B_k (4(P+1) FP32 columns each) once, 24 B/DOF for the residual kernel and 56 B/DOF
+        # for the substitutions' right-hand side, intermediates and state
+        nj = 4 * (plev[0] + 1)
+        bpd = 4 * n + 24 if smoother == "element" else 4 * n + 8 * nj + 80
         kbytes = levels[0].ne * n * bpd
         out[smoother] = {"status": st["status"], "vcycles": st["n_vcycles"], "block_rebuilds": st["n_refresh"],
                          "seconds": st["seconds"], "ms_per_vcycle": 1e3 * per,

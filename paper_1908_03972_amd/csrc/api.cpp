@@ -689,7 +689,7 @@ pmg_status pmg_factors_destroy(pmg_factors F) {
   if (F->W) (void)hipFree(F->W);
   if (F->ws) (void)hipFree(F->ws);
   if (pmg::LineFactors* lf = F->lines) {
-    void* ptrs[] = {lf->elems, lf->fside, lf->D, lf->Winv, lf->Kc, lf->r};
+    void* ptrs[] = {lf->elems, lf->fside, lf->D, lf->Winv, lf->Kc, lf->r, lf->C, lf->B, lf->M, lf->N, lf->z, lf->tr};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     delete lf;
@@ -744,9 +744,17 @@ pmg_status pmg_line_factors_create(pmg_level L, int32_t precision, const int32_t
             hipMalloc(&lf.D, nn * sizeof(double)) == hipSuccess && hipMalloc(&lf.Winv, F->bytes) == hipSuccess &&
             hipMalloc(&lf.Kc, (size_t)2 * ne * 16 * L->n1 * sizeof(double)) == hipSuccess &&
             hipMalloc(&lf.r, L->state_elems() * sizeof(double)) == hipSuccess;
-  // a sweep before the first factorisation leaves q unchanged
+  const size_t nj = (size_t)pmg::line_rank(L->P), cb = (size_t)ne * nj * L->n * (precision / 8),
+               mn = (size_t)ne * nj * nj * sizeof(double);
+  ok = ok && hipMalloc(&lf.C, cb) == hipSuccess && hipMalloc(&lf.B, cb) == hipSuccess &&
+       hipMalloc(&lf.M, mn) == hipSuccess && hipMalloc(&lf.N, mn) == hipSuccess &&
+       hipMalloc(&lf.z, (size_t)ne * L->n * sizeof(double)) == hipSuccess &&
+       hipMalloc(&lf.tr, (size_t)4 * ne * nj * sizeof(double)) == hipSuccess;
+  // a sweep before the first factorisation leaves q unchanged; M and N stay zero at the line ends
   ok = ok && hipMemset(lf.Winv, 0, F->bytes) == hipSuccess &&
-       hipMemset(lf.Kc, 0, (size_t)2 * ne * 16 * L->n1 * sizeof(double)) == hipSuccess;
+       hipMemset(lf.Kc, 0, (size_t)2 * ne * 16 * L->n1 * sizeof(double)) == hipSuccess &&
+       hipMemset(lf.C, 0, cb) == hipSuccess && hipMemset(lf.B, 0, cb) == hipSuccess &&
+       hipMemset(lf.M, 0, mn) == hipSuccess && hipMemset(lf.N, 0, mn) == hipSuccess;
   if (!ok) {
     (void)pmg_factors_destroy(F);
     return fail(PMG_E_NOMEM, "device allocation failed for the line factors");

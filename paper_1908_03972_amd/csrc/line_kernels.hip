@@ -20,8 +20,17 @@
 //                    4(P+1). It is formed from H = W_{k-1} P K (n x 4(P+1), kept in LDS between steps),
 //                    its face trace T = E H and Z = K T. D'_k is inverted by Gauss-Jordan with partial
 //                    pivoting in LDS.
-//   k_line_sweep     One workgroup per line. Forward: y_k = W_k (r_k - A_{k,k-1} y_{k-1}). Backward:
-//                    x_k = y_k - W_k A_{k,k+1} x_{k+1}, then q += alpha x.
+//                    It also stores, for the substitutions, C_k = W_k P_m K_m and B_k = W_k P_p K_p
+//                    (n x 4(P+1) each) and their face traces M_k = E_{k+1} C_k, N_k = E_{k-1} B_k.
+//   line sweep       The block-tridiagonal solve y_k = W_k (r_k - A_{k,k-1} y_{k-1}),
+//                    x_k = y_k - W_k A_{k,k+1} x_{k+1}. A coupling block reads its neighbour only
+//                    through the 4(P+1) trace values on the shared face, so only those travel along
+//                    the line: with z_k = W_k r_k, y_k = z_k - C_k t_k where t_k = E_k y_{k-1} obeys
+//                    t_{k+1} = E_{k+1} z_k - M_k t_k; likewise x_k = y_k - B_k s_k with
+//                    s_{k-1} = E_{k-1} y_k - N_k s_k. Three element-parallel kernels (k_line_zu,
+//                    k_line_yv, k_line_x: the n x n and the two n x 4(P+1) matrix-vector products) and
+//                    two line-sequential ones (k_line_rec: 4(P+1)-square products per step) replace
+//                    a chain of K dependent n x n products per line.
 //   k_line_dense     The coupling blocks written out dense (for tests).
 #include "lines.hpp"
 
@@ -36,6 +45,10 @@ struct LineArgs {
   const int* fside;      // [2][Ne]
   int K;
   double* Kc;            // [2][Ne][n1][4][4]
+  void* C;               // [Ne][NJ][n] at the factor precision
+  void* B;               // [Ne][NJ][n] at the factor precision
+  double* M;             // [Ne][NJ][NJ]
+  double* N;             // [Ne][NJ][NJ]
 };
 
 template <int P>
@@ -152,7 +165,8 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
   using C = LineCfg<P>;
   constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, LD = C::LD, NT = C::NT;
   __shared__ double sM[N * LD];          // D'_k, inverted in place
-  __shared__ double sH[N * NJ];          // H = W_{k-1} P K of the previous element
+  __shared__ double sH[NJ * N];          // B_{k-1} = W_{k-1} P_p K_p of the previous element, [j][r]
+  __shared__ double sC[NJ * N];          // C_k = W_k P_m K_m, [j][r]
   __shared__ double sT[NJ * NJ], sZ[NJ * NJ];
   __shared__ double sf[N];               // column k of the eliminated matrix (0 at the pivot row)
   __shared__ int sperm[N];               // row exchanged with row k at step k
@@ -178,7 +192,7 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
         const int i = t / NJ, j = t % NJ, kf = i / NV, w = i % NV;
         const int kk = om ? N1 - 1 - kf : kf;
         double s = 0.0;
-        for (int m = 0; m < N1; ++m) s += wnm[m] * sH[(face_line_point(nfm, kk, m, N1) * NV + w) * NJ + j];
+        for (int m = 0; m < N1; ++m) s += wnm[m] * sH[j * N + face_line_point(nfm, kk, m, N1) * NV + w];
         sT[t] = s;
       }
       __syncthreads();
@@ -268,21 +282,46 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
     __syncthreads();
     T* We = Winv + (size_t)e * N * N;
     for (int t = tid; t < N * N; t += NT) We[t] = (T)sM[(t % N) * LD + t / N];
-    if (k + 1 < a.K) {
-      // H[r][kf, w] = sum over the points pp on line kf of the face towards the next element and
-      // over v of W[r][pp, v] (1/|J|)(pp) g'(pp) K_p[kf][v][w]
-      const int fpf = a.fside[ne + e];
-      const double* Kp = a.Kc + ((size_t)ne + e) * (NJ * NV);
+    // B_k = W_k P_p K_p (towards the next element) and C_k = W_k P_m K_m (towards the previous one):
+    // X[r][kf, w] = sum over the points pp on line kf of the face and over v of
+    // W[r][pp, v] (1/|J|)(pp) g'(pp) K[kf][v][w]. B_k stays in LDS for the next step's update.
+    for (int side = 1; side >= 0; --side) {
+      if (side == 1 ? k + 1 >= a.K : k == 0) continue;
+      const int fs = a.fside[side * ne + e];
+      const double* Ks = a.Kc + ((size_t)side * ne + e) * (NJ * NV);
+      double* sX = side ? sH : sC;
+      T* gX = static_cast<T*>(side ? a.B : a.C) + (size_t)e * NJ * N;
       for (int t = tid; t < N * NJ; t += NT) {
-        const int r = t / NJ, j = t % NJ, kf = j / NV, w = j % NV;
+        const int j = t / N, r = t % N, kf = j / NV, w = j % NV;
         double s = 0.0;
         for (int m = 0; m < N1; ++m) {
-          const int pp = face_line_point(fpf, kf, m, N1);
-          const double cm = ijac[(size_t)pp * ne + e] * corr_deriv(o, fpf, m);
+          const int pp = face_line_point(fs, kf, m, N1);
+          const double cm = ijac[(size_t)pp * ne + e] * corr_deriv(o, fs, m);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) s += sM[r * LD + pp * NV + v] * cm * Kp[(kf * NV + v) * NV + w];
+          for (int v = 0; v < NV; ++v) s += sM[r * LD + pp * NV + v] * cm * Ks[(kf * NV + v) * NV + w];
         }
-        sH[t] = s;
+        sX[t] = s;
+        gX[t] = (T)s;
+      }
+    }
+    __syncthreads();
+    if (k > 0 && k + 1 < a.K) {
+      // M_k = E_{k+1} C_k and N_k = E_{k-1} B_k: the columns' traces on the faces shared with the
+      // next and the previous element, in that element's flux-point order
+      for (int side = 0; side < 2; ++side) {
+        const int en = a.elems[(size_t)line * a.K + (side ? k - 1 : k + 1)];
+        const int fn = a.fside[(side ? ne : 0) + en];            // the neighbour's face towards e
+        const int fe = a.lv.nbf[fn * ne + en], on = a.lv.ori[fn * ne + en];
+        const double* we = trace_weights(o, fe);
+        const double* sX = side ? sH : sC;
+        double* gX = (side ? a.N : a.M) + (size_t)e * NJ * NJ;
+        for (int t = tid; t < NJ * NJ; t += NT) {
+          const int jc = t / NJ, i = t % NJ, kf = i / NV, w = i % NV;
+          const int kk = on ? N1 - 1 - kf : kf;
+          double s = 0.0;
+          for (int m = 0; m < N1; ++m) s += we[m] * sX[jc * N + face_line_point(fe, kk, m, N1) * NV + w];
+          gX[t] = s;
+        }
       }
     }
     __syncthreads();
@@ -290,98 +329,210 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
   if (bad) *flag = 1;
 }
 
-// out = A_side x_nb (assign) or out -= A_side x_nb, for element e and its neighbour on side `side`
-// (x_nb in LDS, n values). Every thread of the block must call it.
-template <int P>
-__device__ __forceinline__ void apply_coupling(const LineArgs& a, int e, int side, const double* x_nb, double* st,
-                                               double* su, double* out, bool subtract) {
-  using C = LineCfg<P>;
-  constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
-  const int ne = a.lv.ne, tid = threadIdx.x;
-  const Ops1D& o = a.ops;
-  const int f = a.fside[side * ne + e];
-  const int nf = a.lv.nbf[f * ne + e], ori = a.lv.ori[f * ne + e];
-  const double* wn = trace_weights(o, nf);
-  for (int t = tid; t < NJ; t += NT) {
-    const int kf = t / NV, w = t % NV;
-    const int kk = ori ? N1 - 1 - kf : kf;
-    double s = 0.0;
-    for (int m = 0; m < N1; ++m) s += wn[m] * x_nb[face_line_point(nf, kk, m, N1) * NV + w];
-    st[t] = s;
-  }
-  __syncthreads();
-  const double* Kf = a.Kc + ((size_t)side * ne + e) * (NJ * NV);
-  for (int t = tid; t < NJ; t += NT) {
-    const int kf = t / NV, v = t % NV;
-    double s = 0.0;
+// Sixteen bytes of a column at a time: four FP32 or two FP64 rows per thread.
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+
+// part[g][r] = sum over the columns c = g, g + G, ... of X[c][r] x[c] for an NR x NC matrix stored
+// column-major (a column's NR rows contiguous and 16-byte aligned); the caller sums over g < G.
+template <int NR, int NC, class T, int NT>
+struct ColMatvec {
+  static constexpr int RV = Vec16<T>::n, RT = NR / RV, G0 = NT / RT, G = G0 < NC ? G0 : NC;
+  static_assert(NR % RV == 0, "rows come in whole vectors");
+  __device__ static void run(const T* __restrict__ X, const double* x, double* part) {
+    using V = typename Vec16<T>::type;
+    const int rt = threadIdx.x % RT, g = threadIdx.x / RT;
+    if (g >= G) return;
+    double acc[RV];
 #pragma unroll
-    for (int w = 0; w < NV; ++w) s += Kf[(kf * NV + v) * NV + w] * st[kf * NV + w];
-    su[t] = s;
+    for (int i = 0; i < RV; ++i) acc[i] = 0.0;
+#pragma unroll 4
+    for (int c = g; c < NC; c += G) {
+      V v = *reinterpret_cast<const V*>(X + (size_t)c * NR + rt * RV);
+      T vv[RV];
+      __builtin_memcpy(vv, &v, sizeof(V));
+      const double xc = x[c];
+#pragma unroll
+      for (int i = 0; i < RV; ++i) acc[i] += (double)vv[i] * xc;
+    }
+#pragma unroll
+    for (int i = 0; i < RV; ++i) part[g * NR + rt * RV + i] = acc[i];
+  }
+};
+
+// The trace of an element's values x ([pp * NV + v]) on its face fe, at flux point kf of the
+// neighbour across it (whose view of the face has orientation flag on), variable w.
+template <int P>
+__device__ __forceinline__ double face_trace(const Ops1D& o, int fe, int on, const double* x, int kf, int w) {
+  constexpr int N1 = P + 1, NV = 4;
+  const int kk = on ? N1 - 1 - kf : kf;
+  const double* we = trace_weights(o, fe);
+  double s = 0.0;
+  for (int m = 0; m < N1; ++m) s += we[m] * x[face_line_point(fe, kk, m, N1) * NV + w];
+  return s;
+}
+
+// The neighbour across element e's face towards side `side` of its line (-1 at a line end) and
+// that neighbour's orientation flag for the shared face.
+__device__ __forceinline__ int line_nbr(const LineArgs& a, int e, int side, int& fe, int& on) {
+  const int ne = a.lv.ne;
+  fe = a.fside[side * ne + e];
+  if (fe < 0) return -1;
+  const int en = a.lv.nbr[fe * ne + e];
+  on = a.lv.ori[a.lv.nbf[fe * ne + e] * ne + en];
+  return en;
+}
+
+// Substitution pass 1, one workgroup per element: z_k = W_k r_k, and u_k = E_{k+1} z_k, the trace of
+// z_k on the face shared with the next element of the line in that element's flux-point order.
+template <int P, class T>
+__global__ void __launch_bounds__(256) k_line_zu(LineArgs a, const T* __restrict__ W, const double* __restrict__ r,
+                                                 double* __restrict__ z, double* __restrict__ u) {
+  using C = LineCfg<P>;
+  constexpr int NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
+  using MV = ColMatvec<N, N, T, NT>;
+  __shared__ double sx[N], sz[N];
+  __shared__ double part[MV::G * N];
+  const int ne = a.lv.ne, e = blockIdx.x, tid = threadIdx.x;
+  for (int t = tid; t < N; t += NT) sx[t] = r[((size_t)(t % NV) * NP + t / NV) * ne + e];
+  __syncthreads();
+  MV::run(W + (size_t)e * N * N, sx, part);
+  __syncthreads();
+  for (int t = tid; t < N; t += NT) {
+    double v = 0.0;
+#pragma unroll
+    for (int g = 0; g < MV::G; ++g) v += part[g * N + t];
+    sz[t] = v;
+    z[(size_t)e * N + t] = v;
+  }
+  int fe, on;
+  if (line_nbr(a, e, 1, fe, on) < 0) return;
+  __syncthreads();
+  for (int t = tid; t < NJ; t += NT) u[(size_t)e * NJ + t] = face_trace<P>(a.ops, fe, on, sz, t / NV, t % NV);
+}
+
+// Substitution pass 3: y_k = z_k - C_k t_k (in place of z), and v_k = E_{k-1} y_k, the trace of y_k on
+// the face shared with the previous element in that element's order.
+template <int P, class T>
+__global__ void __launch_bounds__(256) k_line_yv(LineArgs a, double* __restrict__ z, const double* __restrict__ tt,
+                                                 double* __restrict__ v) {
+  using C = LineCfg<P>;
+  constexpr int NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
+  using MV = ColMatvec<N, NJ, T, NT>;
+  __shared__ double sx[NJ], sy[N];
+  __shared__ double part[MV::G * N];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  int fe, on;
+  if (line_nbr(a, e, 0, fe, on) < 0) return;            // a line's first element: y = z, no trace needed
+  for (int t = tid; t < NJ; t += NT) sx[t] = tt[(size_t)e * NJ + t];
+  __syncthreads();
+  MV::run(static_cast<const T*>(a.C) + (size_t)e * NJ * N, sx, part);
+  __syncthreads();
+  for (int t = tid; t < N; t += NT) {
+    double y = z[(size_t)e * N + t];
+#pragma unroll
+    for (int g = 0; g < MV::G; ++g) y -= part[g * N + t];
+    sy[t] = y;
+    z[(size_t)e * N + t] = y;
   }
   __syncthreads();
-  const double* ijac = a.lv.met + 4 * (size_t)NP * ne;
+  for (int t = tid; t < NJ; t += NT) v[(size_t)e * NJ + t] = face_trace<P>(a.ops, fe, on, sy, t / NV, t % NV);
+}
+
+// Substitution pass 5: x_k = y_k - B_k s_k, q += alpha x_k.
+template <int P, class T>
+__global__ void __launch_bounds__(256) k_line_x(LineArgs a, const double* __restrict__ y, const double* __restrict__ ss,
+                                                double* __restrict__ q, double alpha) {
+  using C = LineCfg<P>;
+  constexpr int NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
+  using MV = ColMatvec<N, NJ, T, NT>;
+  __shared__ double sx[NJ];
+  __shared__ double part[MV::G * N];
+  const int ne = a.lv.ne, e = blockIdx.x, tid = threadIdx.x;
+  const bool last = a.fside[ne + e] < 0;
+  if (!last) {
+    for (int t = tid; t < NJ; t += NT) sx[t] = ss[(size_t)e * NJ + t];
+    __syncthreads();
+    MV::run(static_cast<const T*>(a.B) + (size_t)e * NJ * N, sx, part);
+    __syncthreads();
+  }
   for (int t = tid; t < N; t += NT) {
-    const int pp = t / NV, v = t % NV;
-    const int kf = point_line(f, pp, N1), ni = point_normal(f, pp, N1);
-    const double val = ijac[(size_t)pp * ne + e] * corr_deriv(o, f, ni) * su[kf * NV + v];
-    out[t] = subtract ? out[t] - val : val;
-  }
-}
-
-// y = W_e b with two threads per row (each half of the columns), the halves summed by the caller
-// from part[0][r] + part[1][r]; W_e column-major, so a column's rows are contiguous.
-template <int P, class T>
-__device__ __forceinline__ void line_matvec(const T* We, const double* b, double (*part)[LineCfg<P>::NT / 2]) {
-  using C = LineCfg<P>;
-  constexpr int N = C::N, HALF = C::NT / 2;
-  const int h = threadIdx.x / HALF, rr = threadIdx.x % HALF;
-  double acc = 0.0;
-  if (rr < N) {
-    const int c0 = h ? N / 2 : 0, c1 = h ? N : N / 2;
-    for (int c = c0; c < c1; ++c) acc += (double)We[(size_t)c * N + rr] * b[c];
-  }
-  part[h][rr] = acc;
-}
-
-template <int P, class T>
-__global__ void __launch_bounds__(256) k_line_sweep(LineArgs a, const T* Winv, double* r, double* q, double alpha) {
-  using C = LineCfg<P>;
-  constexpr int NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT, HALF = NT / 2;
-  __shared__ double sb[N], sx[N], st[NJ], su[NJ];
-  __shared__ double part[2][HALF];
-  const int ne = a.lv.ne, line = blockIdx.x, tid = threadIdx.x, K = a.K;
-  const int* el = a.elems + (size_t)line * K;
-  // forward: y_k = W_k (r_k - A_{k,k-1} y_{k-1}); y_k replaces r_k and stays in sx for the next step
-  for (int k = 0; k < K; ++k) {
-    const int e = el[k];
-    for (int t = tid; t < N; t += NT) sb[t] = r[((size_t)(t % NV) * NP + t / NV) * ne + e];
-    if (k > 0) apply_coupling<P>(a, e, 0, sx, st, su, sb, true);
-    __syncthreads();
-    line_matvec<P, T>(Winv + (size_t)e * N * N, sb, part);
-    __syncthreads();
-    for (int t = tid; t < N; t += NT) {
-      const double y = part[0][t] + part[1][t];
-      sx[t] = y;
-      r[((size_t)(t % NV) * NP + t / NV) * ne + e] = y;
+    double x = y[(size_t)e * N + t];
+    if (!last) {
+#pragma unroll
+      for (int g = 0; g < MV::G; ++g) x -= part[g * N + t];
     }
-    __syncthreads();
+    q[((size_t)(t % NV) * NP + t / NV) * ne + e] += alpha * x;
   }
-  // backward: x_{K-1} = y_{K-1}; x_k = y_k - W_k A_{k,k+1} x_{k+1}; q += alpha x
-  {
-    const int e = el[K - 1];
-    for (int t = tid; t < N; t += NT) q[((size_t)(t % NV) * NP + t / NV) * ne + e] += alpha * sx[t];
-  }
-  for (int k = K - 2; k >= 0; --k) {
-    const int e = el[k];
-    apply_coupling<P>(a, e, 1, sx, st, su, sb, false);
-    __syncthreads();
-    line_matvec<P, T>(Winv + (size_t)e * N * N, sb, part);
-    __syncthreads();
-    for (int t = tid; t < N; t += NT) {
-      const size_t gi = ((size_t)(t % NV) * NP + t / NV) * ne + e;
-      const double x = r[gi] - (part[0][t] + part[1][t]);
-      sx[t] = x;
-      q[gi] += alpha * x;
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Substitution passes 2 and 4, one workgroup per line: the trace recursion
+//   forward  t_0 = 0,     t_{k+1} = u_k - M_k t_k      (k = 0 .. K-2)
+//   backward s_{K-1} = 0, s_{k-1} = v_k - N_k s_k      (k = K-1 .. 1)
+// The first wave runs the recursion, lane i holding entry i, from LDS; the other waves stage the next
+// chunk of CH steps (matrices, vectors, element indices) meanwhile.
+template <int P>
+__global__ void __launch_bounds__(256) k_line_rec(LineArgs a, const double* __restrict__ Mat,
+                                                  const double* __restrict__ vec, double* __restrict__ out,
+                                                  int backward) {
+  using C = LineCfg<P>;
+  constexpr int NJ = C::NJ, NT = C::NT, CH = 16, MM = NJ * NJ;
+  static_assert(NJ <= 64, "one lane per trace entry");
+  __shared__ double sMat[2][CH * MM];
+  __shared__ double sVec[2][CH * NJ];
+  __shared__ int sDst[2][CH];
+  const int line = blockIdx.x, tid = threadIdx.x, K = a.K;
+  const int* el = a.elems + (size_t)line * K;
+  const int nsteps = K - 1, nchunks = (nsteps + CH - 1) / CH;
+  auto src_pos = [&](int j) { return backward ? K - 1 - j : j; };
+  // stage chunk c into buffer b with threads t0, t0 + stride, ...
+  auto stage = [&](int c, int b, int t0, int stride) {
+    const int j0 = c * CH, ns = min(CH, nsteps - j0);
+    for (int t = t0; t < ns * MM; t += stride) {
+      const int sidx = t / MM, o = t % MM;
+      sMat[b][t] = Mat[(size_t)el[src_pos(j0 + sidx)] * MM + o];
+    }
+    for (int t = t0; t < ns * NJ; t += stride) {
+      const int sidx = t / NJ, o = t % NJ;
+      sVec[b][t] = vec[(size_t)el[src_pos(j0 + sidx)] * NJ + o];
+    }
+    for (int t = t0; t < ns; t += stride) sDst[b][t] = el[backward ? K - 2 - (j0 + t) : j0 + t + 1];
+  };
+  const int lane = tid, il = lane < NJ ? lane : NJ - 1;
+  double cur = 0.0;
+  if (tid < NJ) out[(size_t)el[backward ? K - 1 : 0] * NJ + tid] = 0.0;
+  if (nchunks > 0) stage(0, 0, tid, NT);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int b = c & 1;
+    if (tid >= 64) {
+      if (c + 1 < nchunks) stage(c + 1, b ^ 1, tid - 64, NT - 64);
+    } else {
+      const int ns = min(CH, nsteps - c * CH);
+      for (int sidx = 0; sidx < ns; ++sidx) {
+        const double* Ms = sMat[b] + sidx * MM;
+        double acc = sVec[b][sidx * NJ + il];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) acc -= Ms[jj * NJ + il] * readlane_f64(cur, jj);
+        cur = acc;
+        if (lane < NJ) out[(size_t)sDst[b][sidx] * NJ + lane] = cur;
+      }
     }
     __syncthreads();
   }
@@ -396,6 +547,10 @@ LineArgs make_args(const pmg_level_s& L, const LineFactors& lf) {
   a.fside = lf.fside;
   a.K = lf.K;
   a.Kc = lf.Kc;
+  a.C = lf.C;
+  a.B = lf.B;
+  a.M = lf.M;
+  a.N = lf.N;
   return a;
 }
 
@@ -412,16 +567,23 @@ hipError_t line_factor_p(const pmg_level_s& L, const LineArgs& a, const double* 
   return hipGetLastError();
 }
 
+template <int P, class T>
+hipError_t line_sweep_pt(const LineArgs& a, const LineFactors& lf, double* q, double alpha, hipStream_t st) {
+  const int ne = a.lv.ne, NJ = LineCfg<P>::NJ, NT = LineCfg<P>::NT;
+  double *u = lf.tr, *t = lf.tr + (size_t)ne * NJ, *v = lf.tr + (size_t)2 * ne * NJ, *s = lf.tr + (size_t)3 * ne * NJ;
+  hipLaunchKernelGGL((k_line_zu<P, T>), dim3(ne), dim3(NT), 0, st, a, (const T*)lf.Winv, (const double*)lf.r, lf.z, u);
+  hipLaunchKernelGGL(k_line_rec<P>, dim3(lf.n_lines), dim3(NT), 0, st, a, (const double*)lf.M, (const double*)u, t, 0);
+  hipLaunchKernelGGL((k_line_yv<P, T>), dim3(ne), dim3(NT), 0, st, a, lf.z, (const double*)t, v);
+  hipLaunchKernelGGL(k_line_rec<P>, dim3(lf.n_lines), dim3(NT), 0, st, a, (const double*)lf.N, (const double*)v, s, 1);
+  hipLaunchKernelGGL((k_line_x<P, T>), dim3(ne), dim3(NT), 0, st, a, (const double*)lf.z, (const double*)s, q, alpha);
+  return hipGetLastError();
+}
+
 template <int P>
 hipError_t line_sweep_p(const LineArgs& a, const pmg_factors_s& fac, double* q, double alpha, hipStream_t st) {
   const LineFactors& lf = *fac.lines;
-  if (fac.precision == 32)
-    hipLaunchKernelGGL((k_line_sweep<P, float>), dim3(lf.n_lines), dim3(LineCfg<P>::NT), 0, st, a,
-                       (const float*)lf.Winv, lf.r, q, alpha);
-  else
-    hipLaunchKernelGGL((k_line_sweep<P, double>), dim3(lf.n_lines), dim3(LineCfg<P>::NT), 0, st, a,
-                       (const double*)lf.Winv, lf.r, q, alpha);
-  return hipGetLastError();
+  if (fac.precision == 32) return line_sweep_pt<P, float>(a, lf, q, alpha, st);
+  return line_sweep_pt<P, double>(a, lf, q, alpha, st);
 }
 
 template <int P>

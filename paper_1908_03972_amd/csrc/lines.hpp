@@ -19,8 +19,18 @@ struct LineFactors {
   double* Kc = nullptr;        // device [2][Ne][n1][4][4]: derivative of |S| f_com at each flux point of the
                                // face towards the previous / next element with respect to that
                                // neighbour's trace
-  double* r = nullptr;         // device state-sized work array: F - S, then the forward sweep's y
+  double* r = nullptr;         // device state-sized work array: F - S
+  // The substitutions pass only face traces along a line (see line_kernels.hip):
+  void* C = nullptr;           // device [Ne][NJ][n] at the factor precision: C_k = W_k P_m K_m (column-major)
+  void* B = nullptr;           // device [Ne][NJ][n] at the factor precision: B_k = W_k P_p K_p
+  double* M = nullptr;         // device [Ne][NJ][NJ]: M_k = E_{k+1} C_k (column-major), zero at the line ends
+  double* N = nullptr;         // device [Ne][NJ][NJ]: N_k = E_{k-1} B_k, zero at the line ends
+  double* z = nullptr;         // device [Ne][n] element-major: W_k r_k, then y_k
+  double* tr = nullptr;        // device [4][Ne][NJ]: u, t, v, s traces of the substitutions
 };
+
+// NJ = 4 (P + 1): the rank of a coupling block (4 variables at the P + 1 flux points of a face)
+inline int line_rank(int P) { return 4 * (P + 1); }
 
 // D_e (and D_out, if given), the coupling derivatives and the block-Thomas inverses of every line
 hipError_t launch_line_factor(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
