@@ -689,7 +689,7 @@ pmg_status pmg_factors_destroy(pmg_factors F) {
   if (F->W) (void)hipFree(F->W);
   if (F->ws) (void)hipFree(F->ws);
   if (pmg::LineFactors* lf = F->lines) {
-    void* ptrs[] = {lf->elems, lf->fside, lf->D, lf->Winv, lf->Kc, lf->r, lf->C, lf->B, lf->M, lf->N, lf->z, lf->tr};
+    void* ptrs[] = {lf->elems, lf->pos, lf->fside, lf->D, lf->Winv, lf->Kc, lf->r, lf->C, lf->B, lf->M, lf->N, lf->z, lf->tr};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     delete lf;
@@ -739,8 +739,10 @@ pmg_status pmg_line_factors_create(pmg_level L, int32_t precision, const int32_t
   lf.K = line_len;
   const size_t nn = (size_t)ne * L->n * L->n;
   F->bytes = nn * (precision / 8);
-  std::vector<int> elems(line_elems, line_elems + (size_t)n_lines * line_len);
-  bool ok = upload(&lf.elems, elems) == PMG_OK && upload(&lf.fside, fside) == PMG_OK &&
+  std::vector<int> elems(line_elems, line_elems + (size_t)n_lines * line_len), pos(ne);
+  for (size_t i = 0; i < elems.size(); ++i) pos[elems[i]] = (int)i;
+  bool ok = upload(&lf.elems, elems) == PMG_OK && upload(&lf.pos, pos) == PMG_OK &&
+            upload(&lf.fside, fside) == PMG_OK &&
             hipMalloc(&lf.D, nn * sizeof(double)) == hipSuccess && hipMalloc(&lf.Winv, F->bytes) == hipSuccess &&
             hipMalloc(&lf.Kc, (size_t)2 * ne * 16 * L->n1 * sizeof(double)) == hipSuccess &&
             hipMalloc(&lf.r, L->state_elems() * sizeof(double)) == hipSuccess;

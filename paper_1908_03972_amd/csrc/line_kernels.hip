@@ -43,6 +43,7 @@ struct LineArgs {
   GasParams gas;
   const int* elems;      // [n_lines][K]
   const int* fside;      // [2][Ne]
+  const int* pos;        // [Ne]: line * K + position of the element in its line
   int K;
   double* Kc;            // [2][Ne][n1][4][4]
   void* C;               // [Ne][NJ][n] at the factor precision
@@ -170,7 +171,10 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
   __shared__ double sT[NJ * NJ], sZ[NJ * NJ];
   __shared__ double sf[N];               // column k of the eliminated matrix (0 at the pivot row)
   __shared__ int sperm[N];               // row exchanged with row k at step k
+  __shared__ int scol[N];                // column of sM that holds column c of the inverse
   __shared__ double spiv;
+  __shared__ double sIJ[NP];             // 1/|J| at the element's points
+  __shared__ double sK[2][NJ * NV];      // its coupling derivatives towards the previous / next element
   const int ne = a.lv.ne, line = blockIdx.x, tid = threadIdx.x;
   const Ops1D& o = a.ops;
   const double* ijac = a.lv.met + 4 * (size_t)NP * ne;
@@ -179,6 +183,10 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
     const int e = a.elems[(size_t)line * a.K + k];
     const double* De = D + (size_t)e * N * N;
     for (int t = tid; t < N * N; t += NT) sM[(t / N) * LD + t % N] = De[t];
+    for (int t = tid; t < NP; t += NT) sIJ[t] = ijac[(size_t)t * ne + e];
+    for (int t = tid; t < 2 * NJ * NV; t += NT)
+      sK[t / (NJ * NV)][t % (NJ * NV)] = a.Kc[((size_t)(t / (NJ * NV)) * ne + e) * (NJ * NV) + t % (NJ * NV)];
+    __syncthreads();
     if (k > 0) {
       // D'_k = D_k - P_m K_m (E_m H) with E_m taking the previous element's trace at this
       // element's flux points, and H's columns expanded onto this element's points by E_p
@@ -196,7 +204,7 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
         sT[t] = s;
       }
       __syncthreads();
-      const double* Km = a.Kc + (size_t)e * (NJ * NV);
+      const double* Km = sK[0];
       for (int t = tid; t < NJ * NJ; t += NT) {
         const int i = t / NJ, j = t % NJ, kf = i / NV, v = i % NV;
         double s = 0.0;
@@ -212,7 +220,7 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
         const int kf = point_line(fm, pp, N1), ni = point_normal(fm, pp, N1);
         const int kkp = point_line(nfp, pn, N1), mm = point_normal(nfp, pn, N1);
         const int kfp = op ? N1 - 1 - kkp : kkp;
-        sM[r * LD + c] -= ijac[(size_t)pp * ne + e] * corr_deriv(o, fm, ni) *
+        sM[r * LD + c] -= sIJ[pp] * corr_deriv(o, fm, ni) *
                           sZ[(kf * NV + v) * NJ + kfp * NV + w] * wnp[mm];
       }
     }
@@ -261,34 +269,52 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
         sM[kk * LD + j] = (j == kk ? 1.0 : pv) * ip;
       }
       __syncthreads();
-      for (int t = tid; t < N * N; t += NT) {
-        const int i = t / N, j = t % N;
-        if (i == kk) continue;
-        const double cur = (j == kk) ? 0.0 : sM[i * LD + j];
-        sM[i * LD + j] = cur - sf[i] * sM[kk * LD + j];
+      {
+        // one column per thread, rows in RG interleaved groups; the row loop has a fixed trip count
+        // so that its LDS loads can be issued ahead of the stores
+        constexpr int CW = N <= 64 ? 64 : 128, RG = NT / CW;
+        static_assert(N <= CW && NT % CW == 0, "a thread column per matrix column");
+        constexpr int NR = (N + RG - 1) / RG;
+        const int j = tid % CW, rg = tid / CW;
+        if (j < N) {
+          const double pr = sM[kk * LD + j];
+          const bool colk = (j == kk);
+          double col[NR], fac[NR];        // the whole column first, then the updates
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            const int i = rg + q * RG;
+            col[q] = (i < N && !colk) ? sM[i * LD + j] : 0.0;
+            fac[q] = i < N ? sf[i] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            const int i = rg + q * RG;
+            if (i < N && i != kk) sM[i * LD + j] = col[q] - fac[q] * pr;
+          }
+        }
       }
       __syncthreads();
     }
-    for (int i = tid; i < N; i += NT) {
+    // the row exchanges act on the inverse's columns in reverse order; follow where each column
+    // ends up instead of moving the data: W[r][c] = sM[r][scol[c]]
+    for (int c = tid; c < N; c += NT) {
+      int pc = c;
       for (int kk = N - 1; kk >= 0; --kk) {
         const int p = sperm[kk];
-        if (p != kk) {
-          const double x = sM[i * LD + kk];
-          sM[i * LD + kk] = sM[i * LD + p];
-          sM[i * LD + p] = x;
-        }
+        pc = (pc == kk) ? p : (pc == p ? kk : pc);
       }
+      scol[pc] = c;
     }
     __syncthreads();
     T* We = Winv + (size_t)e * N * N;
-    for (int t = tid; t < N * N; t += NT) We[t] = (T)sM[(t % N) * LD + t / N];
+    for (int t = tid; t < N * N; t += NT) We[t] = (T)sM[(t % N) * LD + scol[t / N]];
     // B_k = W_k P_p K_p (towards the next element) and C_k = W_k P_m K_m (towards the previous one):
     // X[r][kf, w] = sum over the points pp on line kf of the face and over v of
     // W[r][pp, v] (1/|J|)(pp) g'(pp) K[kf][v][w]. B_k stays in LDS for the next step's update.
     for (int side = 1; side >= 0; --side) {
       if (side == 1 ? k + 1 >= a.K : k == 0) continue;
       const int fs = a.fside[side * ne + e];
-      const double* Ks = a.Kc + ((size_t)side * ne + e) * (NJ * NV);
+      const double* Ks = sK[side];
       double* sX = side ? sH : sC;
       T* gX = static_cast<T*>(side ? a.B : a.C) + (size_t)e * NJ * N;
       for (int t = tid; t < N * NJ; t += NT) {
@@ -296,9 +322,9 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
         double s = 0.0;
         for (int m = 0; m < N1; ++m) {
           const int pp = face_line_point(fs, kf, m, N1);
-          const double cm = ijac[(size_t)pp * ne + e] * corr_deriv(o, fs, m);
+          const double cm = sIJ[pp] * corr_deriv(o, fs, m);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) s += sM[r * LD + pp * NV + v] * cm * Ks[(kf * NV + v) * NV + w];
+          for (int v = 0; v < NV; ++v) s += sM[r * LD + scol[pp * NV + v]] * cm * Ks[(kf * NV + v) * NV + w];
         }
         sX[t] = s;
         gX[t] = (T)s;
@@ -314,7 +340,7 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
         const int fe = a.lv.nbf[fn * ne + en], on = a.lv.ori[fn * ne + en];
         const double* we = trace_weights(o, fe);
         const double* sX = side ? sH : sC;
-        double* gX = (side ? a.N : a.M) + (size_t)e * NJ * NJ;
+        double* gX = (side ? a.N : a.M) + ((size_t)line * a.K + k) * NJ * NJ;
         for (int t = tid; t < NJ * NJ; t += NT) {
           const int jc = t / NJ, i = t % NJ, kf = i / NV, w = i % NV;
           const int kk = on ? N1 - 1 - kf : kf;
@@ -418,7 +444,7 @@ __global__ void __launch_bounds__(256) k_line_zu(LineArgs a, const T* __restrict
   int fe, on;
   if (line_nbr(a, e, 1, fe, on) < 0) return;
   __syncthreads();
-  for (int t = tid; t < NJ; t += NT) u[(size_t)e * NJ + t] = face_trace<P>(a.ops, fe, on, sz, t / NV, t % NV);
+  for (int t = tid; t < NJ; t += NT) u[(size_t)a.pos[e] * NJ + t] = face_trace<P>(a.ops, fe, on, sz, t / NV, t % NV);
 }
 
 // Substitution pass 3: y_k = z_k - C_k t_k (in place of z), and v_k = E_{k-1} y_k, the trace of y_k on
@@ -434,7 +460,8 @@ __global__ void __launch_bounds__(256) k_line_yv(LineArgs a, double* __restrict_
   const int e = blockIdx.x, tid = threadIdx.x;
   int fe, on;
   if (line_nbr(a, e, 0, fe, on) < 0) return;            // a line's first element: y = z, no trace needed
-  for (int t = tid; t < NJ; t += NT) sx[t] = tt[(size_t)e * NJ + t];
+  const size_t pe = a.pos[e];
+  for (int t = tid; t < NJ; t += NT) sx[t] = tt[pe * NJ + t];
   __syncthreads();
   MV::run(static_cast<const T*>(a.C) + (size_t)e * NJ * N, sx, part);
   __syncthreads();
@@ -446,7 +473,7 @@ __global__ void __launch_bounds__(256) k_line_yv(LineArgs a, double* __restrict_
     z[(size_t)e * N + t] = y;
   }
   __syncthreads();
-  for (int t = tid; t < NJ; t += NT) v[(size_t)e * NJ + t] = face_trace<P>(a.ops, fe, on, sy, t / NV, t % NV);
+  for (int t = tid; t < NJ; t += NT) v[pe * NJ + t] = face_trace<P>(a.ops, fe, on, sy, t / NV, t % NV);
 }
 
 // Substitution pass 5: x_k = y_k - B_k s_k, q += alpha x_k.
@@ -461,7 +488,7 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, const double* __rest
   const int ne = a.lv.ne, e = blockIdx.x, tid = threadIdx.x;
   const bool last = a.fside[ne + e] < 0;
   if (!last) {
-    for (int t = tid; t < NJ; t += NT) sx[t] = ss[(size_t)e * NJ + t];
+    for (int t = tid; t < NJ; t += NT) sx[t] = ss[(size_t)a.pos[e] * NJ + t];
     __syncthreads();
     MV::run(static_cast<const T*>(a.B) + (size_t)e * NJ * N, sx, part);
     __syncthreads();
@@ -482,41 +509,44 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// Steps of the trace recursion staged in LDS at a time (two buffers of CH matrices, <= 112 KB).
+template <int P>
+struct RecChunk {
+  static constexpr int NJ = 4 * (P + 1), MM = NJ * NJ, C0 = 112 * 1024 / (2 * MM * 8);
+  static constexpr int CH = C0 < 64 ? C0 : 64;
+};
+
 // Substitution passes 2 and 4, one workgroup per line: the trace recursion
 //   forward  t_0 = 0,     t_{k+1} = u_k - M_k t_k      (k = 0 .. K-2)
 //   backward s_{K-1} = 0, s_{k-1} = v_k - N_k s_k      (k = K-1 .. 1)
-// The first wave runs the recursion, lane i holding entry i, from LDS; the other waves stage the next
-// chunk of CH steps (matrices, vectors, element indices) meanwhile.
+// Matrices, vectors and results are stored by line position, so a chunk of steps is one contiguous
+// range. The first wave runs the recursion, lane i holding entry i, from LDS; the other waves stage
+// the next chunk meanwhile.
 template <int P>
 __global__ void __launch_bounds__(256) k_line_rec(LineArgs a, const double* __restrict__ Mat,
                                                   const double* __restrict__ vec, double* __restrict__ out,
                                                   int backward) {
   using C = LineCfg<P>;
-  constexpr int NJ = C::NJ, NT = C::NT, CH = 16, MM = NJ * NJ;
-  static_assert(NJ <= 64, "one lane per trace entry");
+  constexpr int NJ = C::NJ, NT = C::NT, CH = RecChunk<P>::CH, MM = NJ * NJ;
+  static_assert(NJ <= 64 && NJ % 4 == 0, "one lane per trace entry, four partial sums");
   __shared__ double sMat[2][CH * MM];
   __shared__ double sVec[2][CH * NJ];
-  __shared__ int sDst[2][CH];
   const int line = blockIdx.x, tid = threadIdx.x, K = a.K;
-  const int* el = a.elems + (size_t)line * K;
+  const size_t base = (size_t)line * K;
   const int nsteps = K - 1, nchunks = (nsteps + CH - 1) / CH;
-  auto src_pos = [&](int j) { return backward ? K - 1 - j : j; };
-  // stage chunk c into buffer b with threads t0, t0 + stride, ...
+  // chunk c: steps j0 .. j0 + ns - 1, whose source positions j (forward) or K-1-j (backward) form
+  // the range lo .. lo + ns - 1
   auto stage = [&](int c, int b, int t0, int stride) {
-    const int j0 = c * CH, ns = min(CH, nsteps - j0);
-    for (int t = t0; t < ns * MM; t += stride) {
-      const int sidx = t / MM, o = t % MM;
-      sMat[b][t] = Mat[(size_t)el[src_pos(j0 + sidx)] * MM + o];
-    }
-    for (int t = t0; t < ns * NJ; t += stride) {
-      const int sidx = t / NJ, o = t % NJ;
-      sVec[b][t] = vec[(size_t)el[src_pos(j0 + sidx)] * NJ + o];
-    }
-    for (int t = t0; t < ns; t += stride) sDst[b][t] = el[backward ? K - 2 - (j0 + t) : j0 + t + 1];
+    const int j0 = c * CH, ns = min(CH, nsteps - j0), lo = backward ? K - j0 - ns : j0;
+    const double* gM = Mat + (base + lo) * MM;
+    const double* gv = vec + (base + lo) * NJ;
+#pragma unroll 8
+    for (int t = t0; t < ns * MM; t += stride) sMat[b][t] = gM[t];
+    for (int t = t0; t < ns * NJ; t += stride) sVec[b][t] = gv[t];
   };
   const int lane = tid, il = lane < NJ ? lane : NJ - 1;
   double cur = 0.0;
-  if (tid < NJ) out[(size_t)el[backward ? K - 1 : 0] * NJ + tid] = 0.0;
+  if (tid < NJ) out[(base + (backward ? K - 1 : 0)) * NJ + tid] = 0.0;
   if (nchunks > 0) stage(0, 0, tid, NT);
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
@@ -524,14 +554,16 @@ __global__ void __launch_bounds__(256) k_line_rec(LineArgs a, const double* __re
     if (tid >= 64) {
       if (c + 1 < nchunks) stage(c + 1, b ^ 1, tid - 64, NT - 64);
     } else {
-      const int ns = min(CH, nsteps - c * CH);
+      const int j0 = c * CH, ns = min(CH, nsteps - j0);
       for (int sidx = 0; sidx < ns; ++sidx) {
-        const double* Ms = sMat[b] + sidx * MM;
-        double acc = sVec[b][sidx * NJ + il];
+        const int off = backward ? ns - 1 - sidx : sidx;
+        const double* Ms = sMat[b] + off * MM;
+        double acc[4] = {sVec[b][off * NJ + il], 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) acc -= Ms[jj * NJ + il] * readlane_f64(cur, jj);
-        cur = acc;
-        if (lane < NJ) out[(size_t)sDst[b][sidx] * NJ + lane] = cur;
+        for (int jj = 0; jj < NJ; ++jj) acc[jj & 3] -= Ms[jj * NJ + il] * readlane_f64(cur, jj);
+        cur = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        const int j = j0 + sidx, dst = backward ? K - 2 - j : j + 1;
+        if (lane < NJ) out[(base + dst) * NJ + lane] = cur;
       }
     }
     __syncthreads();
@@ -545,6 +577,7 @@ LineArgs make_args(const pmg_level_s& L, const LineFactors& lf) {
   a.gas = L.gas;
   a.elems = lf.elems;
   a.fside = lf.fside;
+  a.pos = lf.pos;
   a.K = lf.K;
   a.Kc = lf.Kc;
   a.C = lf.C;

@@ -11,6 +11,7 @@ constexpr int kLineMaxP = 4;   // a line workgroup holds one n x n block in LDS 
 struct LineFactors {
   int n_lines = 0, K = 0;      // lines of K elements each; n_lines * K = Ne
   int* elems = nullptr;        // device [n_lines][K] element indices in line order
+  int* pos = nullptr;          // device [Ne]: line * K + position of the element in its line
   int* fside = nullptr;        // device [2][Ne]: face of e towards the previous / next element of its
                                // line, -1 at the line's ends
   double* D = nullptr;         // device [Ne][n][n] row-major FP64: element blocks of the last factorisation
@@ -23,10 +24,12 @@ struct LineFactors {
   // The substitutions pass only face traces along a line (see line_kernels.hip):
   void* C = nullptr;           // device [Ne][NJ][n] at the factor precision: C_k = W_k P_m K_m (column-major)
   void* B = nullptr;           // device [Ne][NJ][n] at the factor precision: B_k = W_k P_p K_p
-  double* M = nullptr;         // device [Ne][NJ][NJ]: M_k = E_{k+1} C_k (column-major), zero at the line ends
-  double* N = nullptr;         // device [Ne][NJ][NJ]: N_k = E_{k-1} B_k, zero at the line ends
+  double* M = nullptr;         // device [n_lines][K][NJ][NJ] by line position: M_k = E_{k+1} C_k
+                               // (column-major), zero at the line ends
+  double* N = nullptr;         // device [n_lines][K][NJ][NJ]: N_k = E_{k-1} B_k, zero at the line ends
   double* z = nullptr;         // device [Ne][n] element-major: W_k r_k, then y_k
-  double* tr = nullptr;        // device [4][Ne][NJ]: u, t, v, s traces of the substitutions
+  double* tr = nullptr;        // device [4][n_lines][K][NJ] by line position: u, t, v, s traces of the
+                               // substitutions
 };
 
 // NJ = 4 (P + 1): the rank of a coupling block (4 variables at the P + 1 flux points of a face)
