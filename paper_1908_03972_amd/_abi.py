@@ -76,6 +76,10 @@ SIGNATURES = {
     "pmg_level_points": (pmg_status, [pmg_level, C.POINTER(C.c_double)]),
     "pmg_level_status": (pmg_status, [pmg_level, C.POINTER(C.c_int32)]),
     "pmg_level_dx": (pmg_status, [pmg_level, C.POINTER(C.c_double)]),
+    "pmg_level_epw": (pmg_status, [pmg_level, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "pmg_level_set_epw": (pmg_status, [pmg_level, C.c_int32]),
+    "pmg_level_autotune": (pmg_status, [pmg_level, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double), C.c_void_p]),
     "pmg_dtau_min": (pmg_status, [pmg_level, DP, C.POINTER(C.c_double), C.c_void_p]),
     "pmg_factors_create": (pmg_status, [pmg_level, C.c_int32, C.POINTER(pmg_factors)]),
     "pmg_factors_destroy": (pmg_status, [pmg_factors]),

@@ -67,6 +67,27 @@ class Level:
         A.check(A.lib().pmg_level_dx(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))), "pmg_level_dx")
         return out
 
+    def epw(self):
+        """``pmg_level_epw``: (current elements per workgroup of the fused kernel, compiled candidates)."""
+        cur, n = C.c_int32(0), C.c_int32(0)
+        cand = (C.c_int32 * 4)()
+        A.check(A.lib().pmg_level_epw(self.handle, C.byref(cur), cand, C.byref(n)), "pmg_level_epw")
+        return cur.value, [cand[i] for i in range(n.value)]
+
+    def set_epw(self, epw: int) -> None:
+        """``pmg_level_set_epw`` (0: the default for P)."""
+        A.check(A.lib().pmg_level_set_epw(self.handle, int(epw)), "pmg_level_set_epw")
+
+    def autotune(self, precision: int = 32, reps: int = 10, stream=None) -> dict:
+        """``pmg_level_autotune``: time every candidate, keep the fastest; returns
+        {"epw": chosen, "us_per_residual_and_sweep": {candidate: microseconds}}."""
+        _, cand = self.epw()
+        us = (C.c_double * 4)()
+        best = C.c_int32(0)
+        A.check(A.lib().pmg_level_autotune(self.handle, precision, reps, C.byref(best), us, _stream(stream)),
+                "pmg_level_autotune")
+        return {"epw": best.value, "us_per_residual_and_sweep": {int(c): us[i] for i, c in enumerate(cand)}}
+
     def new_state(self) -> torch.Tensor:
         return torch.zeros(self.shape, dtype=torch.float64, device=self.torch_device)
 

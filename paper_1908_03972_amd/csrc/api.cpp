@@ -560,10 +560,14 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
     return s;
   }
   const size_t ns = L->state_elems();
+  L->epw = pmg::default_epw(L->P);
   L->part_blocks = pmg::residual_blocks(*L);
+  int cand[4], min_epw = L->epw;
+  for (int c = 0, nc = pmg::epw_candidates(*L, cand); c < nc; ++c) min_epw = std::min(min_epw, cand[c]);
+  const size_t part_max = (size_t)(L->ne + min_epw - 1) / min_epw;   // room for every tuner candidate
   if ((s = alloc_zero(&L->wq, ns)) || (s = alloc_zero(&L->wF, ns)) || (s = alloc_zero(&L->wS, ns)) ||
       (s = alloc_zero(&L->wqb, ns)) || (s = alloc_zero(&L->wql, ns)) || (s = alloc_zero(&L->wsrc, ns)) ||
-      (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
+      (s = alloc_zero(&L->part, part_max * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
       (s = alloc_zero(&L->dtpart, pmg::dtau_blocks(*L))) || (s = alloc_zero(&L->dtmin, 1))) {
     free_level(L);
     return s;
@@ -618,6 +622,100 @@ pmg_status pmg_level_dx(pmg_level L, double* dx_host) {
   if (!dx_host) return fail(PMG_E_ARG, "null output");
   std::memcpy(dx_host, L->dx_host.data(), L->dx_host.size() * sizeof(double));
   return PMG_OK;
+}
+
+pmg_status pmg_level_epw(pmg_level L, int32_t* epw, int32_t* cand, int32_t* n_cand) {
+  if (pmg_status e = check_level(L)) return e;
+  if (!epw) return fail(PMG_E_ARG, "null output");
+  *epw = L->dim == 2 ? L->epw : 0;
+  int c[4];
+  const int nc = pmg::epw_candidates(*L, c);
+  if (n_cand) *n_cand = nc;
+  if (cand)
+    for (int i = 0; i < nc; ++i) cand[i] = c[i];
+  return PMG_OK;
+}
+
+pmg_status pmg_level_set_epw(pmg_level L, int32_t epw) {
+  if (pmg_status e = check_level(L)) return e;
+  int c[4];
+  const int nc = pmg::epw_candidates(*L, c);
+  if (nc == 0) return fail(PMG_E_ARG, "elements per workgroup are tuned on quadrilateral levels only");
+  if (epw == 0) epw = c[0];
+  if (std::find(c, c + nc, (int)epw) == c + nc) return fail(PMG_E_ARG, "not a compiled elements-per-workgroup variant");
+  L->epw = epw;
+  L->part_blocks = pmg::residual_blocks(*L);
+  return PMG_OK;
+}
+
+pmg_status pmg_level_autotune(pmg_level L, int32_t precision, int32_t reps, int32_t* epw_out, double* us_out,
+                              void* stream) {
+  if (pmg_status e = check_level(L)) return e;
+  if (precision != 32 && precision != 64) return fail(PMG_E_ARG, "precision must be 32 or 64");
+  if (reps < 1) return fail(PMG_E_ARG, "reps must be >= 1");
+  int c[4];
+  const int nc = pmg::epw_candidates(*L, c);
+  if (nc == 0) return fail(PMG_E_ARG, "elements per workgroup are tuned on quadrilateral levels only");
+  DeviceGuard guard(L->device);
+  const hipStream_t st = as_stream(stream);
+  // the free stream (zero offsets) and zero inverse blocks: the kernels' work does not depend on
+  // the values, and alpha_r = 0 leaves the scratch state unchanged
+  const size_t ns = L->state_elems();
+  double *q = nullptr, *F = nullptr;
+  pmg_factors_s fac{};
+  fac.L = L;
+  fac.precision = precision;
+  fac.bytes = (size_t)L->n * L->npad * L->ne * (precision / 8);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto release = [&]() {
+    if (q) (void)hipFree(q);
+    if (F) (void)hipFree(F);
+    if (fac.W) (void)hipFree(fac.W);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (hipMalloc(&q, ns * sizeof(double)) != hipSuccess || hipMalloc(&F, ns * sizeof(double)) != hipSuccess ||
+      hipMalloc(&fac.W, fac.bytes) != hipSuccess || hipMemsetAsync(q, 0, ns * sizeof(double), st) != hipSuccess ||
+      hipMemsetAsync(fac.W, 0, fac.bytes, st) != hipSuccess || hipEventCreate(&ev[0]) != hipSuccess ||
+      hipEventCreate(&ev[1]) != hipSuccess) {
+    release();
+    return fail(PMG_E_NOMEM, "could not allocate the tuner's scratch arrays");
+  }
+  const int keep = L->epw;
+  int best = -1;
+  double best_us = 0.0;
+  pmg_status status = PMG_OK;
+  for (int i = 0; i < nc && status == PMG_OK; ++i) {
+    L->epw = c[i];
+    L->part_blocks = pmg::residual_blocks(*L);
+    float ms = 0.0f;
+    hipError_t err = hipSuccess;
+    for (int pass = 0; pass < 2 && err == hipSuccess; ++pass) {   // pass 0 warms up
+      err = hipEventRecord(ev[0], st);
+      for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        err = pmg::launch_residual(*L, q, nullptr, nullptr, 0.0, F, true, st);
+        if (err == hipSuccess) err = pmg::launch_sweep(*L, fac, q, L->wq, nullptr, nullptr, 0.0, 0.0, true, st);
+      }
+      if (err == hipSuccess) err = hipEventRecord(ev[1], st);
+      if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    }
+    if (err != hipSuccess) {
+      status = fail(PMG_E_HIP, hipGetErrorString(err));
+      break;
+    }
+    const double us = 1e3 * ms / reps;
+    if (us_out) us_out[i] = us;
+    if (best < 0 || us < best_us) {
+      best = i;
+      best_us = us;
+    }
+  }
+  release();
+  L->epw = (status == PMG_OK) ? c[best] : keep;
+  L->part_blocks = pmg::residual_blocks(*L);
+  if (status == PMG_OK && epw_out) *epw_out = L->epw;
+  return status;
 }
 
 pmg_status pmg_dtau_min(pmg_level L, const double* q, double* dtau_min, void* stream) {

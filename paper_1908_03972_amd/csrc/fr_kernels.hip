@@ -60,13 +60,21 @@ constexpr int epw_for(int P) {
 }
 constexpr int lanes_per_element(int P) { return (P + 1) * (P + 1) > 4 * (P + 1) ? (P + 1) * (P + 1) : 4 * (P + 1); }
 
-template <int P>
+// The tuner's candidates on inviscid levels (pmg_level_autotune): the default and the others whose
+// registers still fit the workgroup (P4 at 32 elements would spill). Viscous levels and P >= 5
+// keep the default.
+constexpr bool epw_candidate(int P, int epw) {
+  return epw == epw_for(P) || (P == 0 && (epw == 16 || epw == 64)) ||
+         (P >= 1 && P <= 3 && (epw == 8 || epw == 16 || epw == 32)) || (P == 4 && epw == 8);
+}
+
+template <int P, int EPW_ = epw_for(P)>
 struct Cfg {
   static constexpr int N1 = P + 1;
   static constexpr int NP = N1 * N1;
   static constexpr int NV = 4;
   static constexpr int N = NV * NP;
-  static constexpr int EPW = epw_for(P);
+  static constexpr int EPW = EPW_;
   static constexpr int LPE = lanes_per_element(P);
   static constexpr int NACT = EPW * LPE;   // lanes with an element slot
   static constexpr int NPT = EPW * NP;     // lanes that own a solution point
@@ -91,9 +99,9 @@ struct ResArgs {
 };
 
 // MODE 0: residual only; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
-template <int P, int MODE, bool VISC>
-__global__ void __launch_bounds__(Cfg<P>::NT) k_fr(ResArgs a) {
-  using C = Cfg<P>;
+template <int P, int MODE, bool VISC, int EPW_ = epw_for(P)>
+__global__ void __launch_bounds__((Cfg<P, EPW_>::NT)) k_fr(ResArgs a) {
+  using C = Cfg<P, EPW_>;
   constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, EPW = C::EPW;
   constexpr int VS = VISC ? 1 : 0;          // viscous LDS arrays exist only when used
   __shared__ double s_q[NV * NP * EPW];
@@ -630,27 +638,40 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_grad(LevelView lv, Ops1D o, cons
   }
 }
 
-template <int P, int MODE>
-static hipError_t launch_fr_p(const ResArgs& a, int ne, bool visc, hipStream_t st) {
-  using C = Cfg<P>;
-  const int blocks = (ne + C::EPW - 1) / C::EPW;
-  if (visc)
-    hipLaunchKernelGGL((k_fr<P, MODE, true>), dim3(blocks), dim3(C::NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_fr<P, MODE, false>), dim3(blocks), dim3(C::NT), 0, st, a);
+template <int P, int MODE, bool VISC, int EPW>
+static hipError_t launch_fr_e(const ResArgs& a, int ne, hipStream_t st) {
+  using C = Cfg<P, EPW>;
+  const int blocks = (ne + EPW - 1) / EPW;
+  hipLaunchKernelGGL((k_fr<P, MODE, VISC, EPW>), dim3(blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 
+template <int P, int MODE>
+static hipError_t launch_fr_p(const ResArgs& a, int ne, bool visc, int epw, hipStream_t st) {
+  constexpr int DEF = epw_for(P);
+  if (visc) return launch_fr_e<P, MODE, true, DEF>(a, ne, st);
+  if (epw <= 0 || epw == DEF) return launch_fr_e<P, MODE, false, DEF>(a, ne, st);
+  if constexpr (DEF != 8 && epw_candidate(P, 8))
+    if (epw == 8) return launch_fr_e<P, MODE, false, 8>(a, ne, st);
+  if constexpr (DEF != 16 && epw_candidate(P, 16))
+    if (epw == 16) return launch_fr_e<P, MODE, false, 16>(a, ne, st);
+  if constexpr (DEF != 32 && epw_candidate(P, 32))
+    if (epw == 32) return launch_fr_e<P, MODE, false, 32>(a, ne, st);
+  if constexpr (DEF != 64 && epw_candidate(P, 64))
+    if (epw == 64) return launch_fr_e<P, MODE, false, 64>(a, ne, st);
+  return hipErrorInvalidValue;
+}
+
 template <int MODE>
-static hipError_t launch_fr(int P, const ResArgs& a, int ne, bool visc, hipStream_t st) {
+static hipError_t launch_fr(int P, const ResArgs& a, int ne, bool visc, int epw, hipStream_t st) {
   switch (P) {
-    case 0: return launch_fr_p<0, MODE>(a, ne, visc, st);
-    case 1: return launch_fr_p<1, MODE>(a, ne, visc, st);
-    case 2: return launch_fr_p<2, MODE>(a, ne, visc, st);
-    case 3: return launch_fr_p<3, MODE>(a, ne, visc, st);
-    case 4: return launch_fr_p<4, MODE>(a, ne, visc, st);
-    case 5: return launch_fr_p<5, MODE>(a, ne, visc, st);
-    case 6: return launch_fr_p<6, MODE>(a, ne, visc, st);
+    case 0: return launch_fr_p<0, MODE>(a, ne, visc, epw, st);
+    case 1: return launch_fr_p<1, MODE>(a, ne, visc, epw, st);
+    case 2: return launch_fr_p<2, MODE>(a, ne, visc, epw, st);
+    case 3: return launch_fr_p<3, MODE>(a, ne, visc, epw, st);
+    case 4: return launch_fr_p<4, MODE>(a, ne, visc, epw, st);
+    case 5: return launch_fr_p<5, MODE>(a, ne, visc, epw, st);
+    case 6: return launch_fr_p<6, MODE>(a, ne, visc, epw, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -678,8 +699,21 @@ hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStre
 
 int residual_blocks(const pmg_level_s& L) {
   if (L.dim == 3) return residual_blocks3(L);
-  const int epw = epw_for(L.P);
+  const int epw = L.epw > 0 ? L.epw : epw_for(L.P);
   return (L.ne + epw - 1) / epw;
+}
+
+int default_epw(int P) { return epw_for(P); }
+
+int epw_candidates(const pmg_level_s& L, int* out) {
+  int n = 0;
+  if (L.dim != 2) return 0;
+  out[n++] = epw_for(L.P);
+  if (L.visc) return n;
+  const int all[4] = {8, 16, 32, 64};
+  for (int c : all)
+    if (c != epw_for(L.P) && epw_candidate(L.P, c)) out[n++] = c;
+  return n;
 }
 
 static ResArgs base_args(const pmg_level_s& L) {
@@ -704,7 +738,7 @@ hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* 
     const hipError_t e = launch_gradient_traces(L, q, st);
     if (e != hipSuccess) return e;
   }
-  return launch_fr<0>(L.P, a, L.ne, L.visc != 0, st);
+  return launch_fr<0>(L.P, a, L.ne, L.visc != 0, L.epw, st);
 }
 
 static hipError_t launch_sweep2(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
@@ -724,8 +758,8 @@ static hipError_t launch_sweep2(const pmg_level_s& L, const pmg_factors_s& fac, 
     const hipError_t e = launch_gradient_traces(L, q_in, st);
     if (e != hipSuccess) return e;
   }
-  if (fac.precision == 32) return launch_fr<2>(L.P, a, L.ne, L.visc != 0, st);
-  return launch_fr<1>(L.P, a, L.ne, L.visc != 0, st);
+  if (fac.precision == 32) return launch_fr<2>(L.P, a, L.ne, L.visc != 0, L.epw, st);
+  return launch_fr<1>(L.P, a, L.ne, L.visc != 0, L.epw, st);
 }
 
 hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,

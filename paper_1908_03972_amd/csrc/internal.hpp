@@ -72,7 +72,8 @@ struct pmg_level_s {
   double* part = nullptr;    // per-workgroup norm partials
   double* norms = nullptr;   // [Nv + 1]
   int* flag = nullptr;       // device error flags
-  int part_blocks = 0;
+  int part_blocks = 0;       // workgroups of the fused residual/sweep kernel (norm partials in use)
+  int epw = 0;               // 2-D: elements per workgroup of the fused kernel (0: the default for P)
   std::vector<double> dx_host;     // [Ne] element length scale of eqs. (32)-(33)
   double* hdx = nullptr;           // [Ne] device: dx_e / (P + 1)
   double* dtpart = nullptr;        // per-workgroup partial minima of the pseudo-time scale
@@ -138,6 +139,10 @@ hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc
 hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
                                int n_prev, double dt, double c_mass, double* src, hipStream_t st);
 int residual_blocks(const pmg_level_s& L);
+// 2-D fused kernel: the default elements per workgroup at degree P, and the tuner's candidates for
+// a level (the default first; at most 4; 0 on hexahedral levels)
+int default_epw(int P);
+int epw_candidates(const pmg_level_s& L, int* out);
 hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStream_t st);
 hipError_t launch_visc_jacobian(const pmg_level_s& L, const double* q, hipStream_t st);
 int dtau_blocks(const pmg_level_s& L);
