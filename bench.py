@@ -526,6 +526,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default elements per workgroup on the vortex levels")
     ap.add_argument("--no-lines", action="store_true",
                     help="skip the airfoil comparison of element and radial element-line Jacobi")
     ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
@@ -564,7 +566,15 @@ def main():
 
     results = {}
     finals = {}
+    tuned = {}
     for form in args.forms.split(","):
+        # elements per workgroup of the fused kernel, picked per level by the library's tuner for
+        # this form's block precision (setup, outside the timed region)
+        if args.no_autotune:
+            for lv in levels:
+                lv.set_epw(0)
+        else:
+            tuned[form] = [lv.autotune(precision=FORMS[form][0], reps=20) for lv in levels]
         facs, solver, q, stage_stats, elapsed = run_form(api, torch, levels, q0, form, SCHEME, DT, args.steps,
                                                          args.warmup, args.max_vcycles, work)
         nvc = sum(st["n_vcycles"] for st in stage_stats)
@@ -600,6 +610,10 @@ def main():
             "sweep_kernel_ms": k_ms,
             "sweep_bytes_per_launch": launch_bytes,
             "sweep_bytes_per_dof_update": bytes_per_dof,
+            "elements_per_workgroup": [lv.epw()[0] for lv in levels],
+            "autotune": [{"epw": t["epw"], "us_per_residual_and_sweep": {str(k): v for k, v in
+                                                                         t["us_per_residual_and_sweep"].items()}}
+                         for t in tuned.get(form, [])],
         }
         finals[form] = q.detach().cpu().numpy()
         del facs, solver
@@ -632,7 +646,10 @@ def main():
                    "form": head},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if FORMS[head][0] == 32 else None,
+                     # the counters were taken with the default grouping of the fine level
+                     "traffic": (measured_traffic() if FORMS[head][0] == 32
+                                 and r["elements_per_workgroup"][0] == L0.epw()[1][0] else None),
+                     "elements_per_workgroup": r["elements_per_workgroup"][0],
                      "kernel": f"k_fr<3,{2 if FORMS[head][0] == 32 else 1}> (fused residual + element-Jacobi sweep, P=3)",
                      "kernel_ms": r["sweep_kernel_ms"], "bytes_per_launch": r["sweep_bytes_per_launch"]},
         "time_to_1e-4_s": mean_time(r, "1e-04"),
