@@ -139,20 +139,20 @@ pmg_status pmg_level_points(pmg_level L, double* xy_host);
  * rule) to the six face planes (through the face's centre node, normal to its corner diagonals). */
 pmg_status pmg_level_dx(pmg_level L, double* dx_host);
 
-/* Elements per workgroup of the fused residual / element-Jacobi kernel on a quadrilateral level
- * (the kernel of eqs. (20), (21) and (30)). A workgroup owns that many elements, with the element
+/* Elements per workgroup of the fused residual / element-Jacobi kernel of a level (the kernel of
+ * eqs. (20), (21) and (30); quadrilaterals and hexahedra). A workgroup owns that many elements, with the element
  * fastest across lanes, so that a wave's load of one (variable, point) of the [Nv][Np][Ne] state
  * covers consecutive elements. Several values are compiled per P; results do not depend on the
  * choice beyond the summation order of the residual norms.
  *
- * pmg_level_epw — *epw the level's current value (0 on hexahedral levels); cand (nullable, room for
- *   4) and *n_cand (nullable) the compiled candidates, the default for P first (only the default on
- *   viscous levels and at P >= 5). Errors: PMG_E_ARG (null epw). */
+ * pmg_level_epw — *epw the level's current value; cand (nullable, room for 4) and *n_cand
+ *   (nullable) the compiled candidates, the default for P first (only the default on viscous levels
+ *   and at P >= 5). Errors: PMG_E_ARG (null epw). */
 pmg_status pmg_level_epw(pmg_level L, int32_t* epw, int32_t* cand, int32_t* n_cand);
 
 /* pmg_level_set_epw — use candidate epw (0: the default for P) from now on. Set it before capturing
  * a stage solve in a graph: a captured graph keeps the launches it recorded.
- * Errors: PMG_E_ARG (hexahedral level, or not a compiled candidate). */
+ * Errors: PMG_E_ARG (not a compiled candidate). */
 pmg_status pmg_level_set_epw(pmg_level L, int32_t epw);
 
 /* pmg_level_autotune — time every candidate on this level (reps residual evaluations plus reps
@@ -160,7 +160,7 @@ pmg_status pmg_level_set_epw(pmg_level L, int32_t epw);
  * pass of the same), keep the fastest and return it in *epw_out (nullable); us_out (nullable, room
  * for n_cand doubles, in candidate order) receives the microseconds per residual + sweep pair.
  * A setup call: it allocates and frees its own scratch state, overwrites the level's workspace,
- * and synchronises the stream. Errors: PMG_E_ARG (hexahedral level, precision, reps < 1),
+ * and synchronises the stream. Errors: PMG_E_ARG (precision, reps < 1),
  * PMG_E_NOMEM, PMG_E_HIP; on error the level keeps its previous value. */
 pmg_status pmg_level_autotune(pmg_level L, int32_t precision, int32_t reps, int32_t* epw_out, double* us_out,
                               void* stream);

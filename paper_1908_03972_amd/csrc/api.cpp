@@ -397,10 +397,14 @@ static pmg_status create_hex_level(const pmg_level_desc* d, pmg_level* out) {
     return s;
   }
   const size_t ns = L->state_elems();
+  L->epw = pmg::default_epw3(L->P);
   L->part_blocks = pmg::residual_blocks(*L);
+  int cand[4], min_epw = L->epw;
+  for (int c = 0, nc = pmg::epw_candidates(*L, cand); c < nc; ++c) min_epw = std::min(min_epw, cand[c]);
+  const size_t part_max = (size_t)(L->ne + min_epw - 1) / min_epw;   // room for every tuner candidate
   if ((s = alloc_zero(&L->wq, ns)) || (s = alloc_zero(&L->wF, ns)) || (s = alloc_zero(&L->wS, ns)) ||
       (s = alloc_zero(&L->wqb, ns)) || (s = alloc_zero(&L->wql, ns)) || (s = alloc_zero(&L->wsrc, ns)) ||
-      (s = alloc_zero(&L->part, (size_t)L->part_blocks * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
+      (s = alloc_zero(&L->part, part_max * L->nv)) || (s = alloc_zero(&L->norms, L->nv + 1)) ||
       (s = alloc_zero(&L->dtpart, pmg::dtau_blocks(*L))) || (s = alloc_zero(&L->dtmin, 1))) {
     free_level(L);
     return s;
@@ -627,7 +631,7 @@ pmg_status pmg_level_dx(pmg_level L, double* dx_host) {
 pmg_status pmg_level_epw(pmg_level L, int32_t* epw, int32_t* cand, int32_t* n_cand) {
   if (pmg_status e = check_level(L)) return e;
   if (!epw) return fail(PMG_E_ARG, "null output");
-  *epw = L->dim == 2 ? L->epw : 0;
+  *epw = L->epw;
   int c[4];
   const int nc = pmg::epw_candidates(*L, c);
   if (n_cand) *n_cand = nc;
@@ -640,7 +644,6 @@ pmg_status pmg_level_set_epw(pmg_level L, int32_t epw) {
   if (pmg_status e = check_level(L)) return e;
   int c[4];
   const int nc = pmg::epw_candidates(*L, c);
-  if (nc == 0) return fail(PMG_E_ARG, "elements per workgroup are tuned on quadrilateral levels only");
   if (epw == 0) epw = c[0];
   if (std::find(c, c + nc, (int)epw) == c + nc) return fail(PMG_E_ARG, "not a compiled elements-per-workgroup variant");
   L->epw = epw;
@@ -655,7 +658,6 @@ pmg_status pmg_level_autotune(pmg_level L, int32_t precision, int32_t reps, int3
   if (reps < 1) return fail(PMG_E_ARG, "reps must be >= 1");
   int c[4];
   const int nc = pmg::epw_candidates(*L, c);
-  if (nc == 0) return fail(PMG_E_ARG, "elements per workgroup are tuned on quadrilateral levels only");
   DeviceGuard guard(L->device);
   const hipStream_t st = as_stream(stream);
   // the free stream (zero offsets) and zero inverse blocks: the kernels' work does not depend on

@@ -27,11 +27,18 @@ constexpr int kPad3 = -100;   // neighbour tag of the padding elements of the la
 // elements: with one element per workgroup every such load would touch a cache line of its own.
 constexpr int epw3_for(int P) { return P == 0 ? 32 : P == 1 ? 8 : P == 2 ? 8 : 4; }
 
-template <int P>
+// The tuner's candidates (pmg_level_autotune): the default and the groupings whose registers still
+// fit the workgroup (twice the default would spill at P2 and P3).
+constexpr bool epw3_candidate(int P, int epw) {
+  return epw == epw3_for(P) || (P == 0 && (epw == 16 || epw == 64)) || (P == 1 && (epw == 4 || epw == 16)) ||
+         (P == 2 && epw == 4) || (P == 3 && epw == 2);
+}
+
+template <int P, int EPW_ = epw3_for(P)>
 struct Cfg3 {
   static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
   static constexpr int NPAD = (N + 3) / 4 * 4;
-  static constexpr int EPW = epw3_for(P);
+  static constexpr int EPW = EPW_;
   static constexpr int LPE = NP > 6 * NF ? NP : 6 * NF;   // lanes per element
   static constexpr int NACT = EPW * LPE;
   static constexpr int NT = ((NACT + 63) / 64) * 64;
@@ -66,9 +73,9 @@ __device__ __forceinline__ void sync3() {
 }
 
 // MODE 0: residual; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
-template <int P, int MODE>
-__global__ void __launch_bounds__(Cfg3<P>::NT) k_fr3(ResArgs3 a) {
-  using C = Cfg3<P>;
+template <int P, int MODE, int EPW_ = epw3_for(P)>
+__global__ void __launch_bounds__((Cfg3<P, EPW_>::NT)) k_fr3(ResArgs3 a) {
+  using C = Cfg3<P, EPW_>;
   constexpr int N1 = C::N1, NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, EPW = C::EPW;
   __shared__ double s_q[NV * NP * EPW];
   // F~, G~, H~ per point; after the divergence the matvec's F and D^{-1} F reuse it
@@ -467,25 +474,51 @@ __global__ void __launch_bounds__(256) k_dtau_partial3(int ne, int np, const dou
 static unsigned blocks3(size_t n) { return (unsigned)((n + 255) / 256); }
 
 int residual_blocks3(const pmg_level_s& L) {
-  const int epw = epw3_for(L.P);
+  const int epw = L.epw > 0 ? L.epw : epw3_for(L.P);
   return (L.ne + epw - 1) / epw;
 }
 
-template <int P, int MODE>
-static hipError_t launch_fr3_p(const ResArgs3& a, int ne, hipStream_t st) {
-  using C = Cfg3<P>;
-  const int blocks = (ne + C::EPW - 1) / C::EPW;
-  hipLaunchKernelGGL((k_fr3<P, MODE>), dim3(blocks), dim3(C::NT), 0, st, a);
+int default_epw3(int P) { return epw3_for(P); }
+
+int epw3_candidates(int P, int* out) {
+  int n = 0;
+  out[n++] = epw3_for(P);
+  const int all[6] = {2, 4, 8, 16, 32, 64};
+  for (int c : all)
+    if (c != epw3_for(P) && epw3_candidate(P, c)) out[n++] = c;
+  return n;
+}
+
+template <int P, int MODE, int EPW>
+static hipError_t launch_fr3_e(const ResArgs3& a, int ne, hipStream_t st) {
+  using C = Cfg3<P, EPW>;
+  const int blocks = (ne + EPW - 1) / EPW;
+  hipLaunchKernelGGL((k_fr3<P, MODE, EPW>), dim3(blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 
+template <int P, int MODE>
+static hipError_t launch_fr3_p(const ResArgs3& a, int ne, int epw, hipStream_t st) {
+  constexpr int DEF = epw3_for(P);
+  if (epw <= 0 || epw == DEF) return launch_fr3_e<P, MODE, DEF>(a, ne, st);
+  if constexpr (DEF != 2 && epw3_candidate(P, 2))
+    if (epw == 2) return launch_fr3_e<P, MODE, 2>(a, ne, st);
+  if constexpr (DEF != 4 && epw3_candidate(P, 4))
+    if (epw == 4) return launch_fr3_e<P, MODE, 4>(a, ne, st);
+  if constexpr (DEF != 16 && epw3_candidate(P, 16))
+    if (epw == 16) return launch_fr3_e<P, MODE, 16>(a, ne, st);
+  if constexpr (DEF != 64 && epw3_candidate(P, 64))
+    if (epw == 64) return launch_fr3_e<P, MODE, 64>(a, ne, st);
+  return hipErrorInvalidValue;
+}
+
 template <int MODE>
-static hipError_t launch_fr3(int P, const ResArgs3& a, int ne, hipStream_t st) {
+static hipError_t launch_fr3(int P, const ResArgs3& a, int ne, int epw, hipStream_t st) {
   switch (P) {
-    case 0: return launch_fr3_p<0, MODE>(a, ne, st);
-    case 1: return launch_fr3_p<1, MODE>(a, ne, st);
-    case 2: return launch_fr3_p<2, MODE>(a, ne, st);
-    case 3: return launch_fr3_p<3, MODE>(a, ne, st);
+    case 0: return launch_fr3_p<0, MODE>(a, ne, epw, st);
+    case 1: return launch_fr3_p<1, MODE>(a, ne, epw, st);
+    case 2: return launch_fr3_p<2, MODE>(a, ne, epw, st);
+    case 3: return launch_fr3_p<3, MODE>(a, ne, epw, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -507,7 +540,7 @@ hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double*
   a.c_mass = c_mass;
   a.F = F;
   a.part = want_norms ? L.part : nullptr;
-  return launch_fr3<0>(L.P, a, L.ne, st);
+  return launch_fr3<0>(L.P, a, L.ne, L.epw, st);
 }
 
 hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
@@ -522,8 +555,8 @@ hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const d
   a.W = fac.W;
   a.alpha = alpha;
   a.q_out = q_out;
-  if (fac.precision == 32) return launch_fr3<2>(L.P, a, L.ne, st);
-  return launch_fr3<1>(L.P, a, L.ne, st);
+  if (fac.precision == 32) return launch_fr3<2>(L.P, a, L.ne, L.epw, st);
+  return launch_fr3<1>(L.P, a, L.ne, L.epw, st);
 }
 
 hipError_t launch_restrict3(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,

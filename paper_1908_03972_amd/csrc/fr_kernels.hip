@@ -707,7 +707,7 @@ int default_epw(int P) { return epw_for(P); }
 
 int epw_candidates(const pmg_level_s& L, int* out) {
   int n = 0;
-  if (L.dim != 2) return 0;
+  if (L.dim == 3) return epw3_candidates(L.P, out);
   out[n++] = epw_for(L.P);
   if (L.visc) return n;
   const int all[4] = {8, 16, 32, 64};

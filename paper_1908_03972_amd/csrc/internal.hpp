@@ -73,7 +73,7 @@ struct pmg_level_s {
   double* norms = nullptr;   // [Nv + 1]
   int* flag = nullptr;       // device error flags
   int part_blocks = 0;       // workgroups of the fused residual/sweep kernel (norm partials in use)
-  int epw = 0;               // 2-D: elements per workgroup of the fused kernel (0: the default for P)
+  int epw = 0;               // elements per workgroup of the fused kernel (0: the default for P)
   std::vector<double> dx_host;     // [Ne] element length scale of eqs. (32)-(33)
   double* hdx = nullptr;           // [Ne] device: dx_e / (P + 1)
   double* dtpart = nullptr;        // per-workgroup partial minima of the pseudo-time scale
@@ -139,8 +139,8 @@ hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc
 hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
                                int n_prev, double dt, double c_mass, double* src, hipStream_t st);
 int residual_blocks(const pmg_level_s& L);
-// 2-D fused kernel: the default elements per workgroup at degree P, and the tuner's candidates for
-// a level (the default first; at most 4; 0 on hexahedral levels)
+// 2-D fused kernel: the default elements per workgroup at degree P; the tuner's candidates for a
+// level, 2-D or 3-D (the default first; at most 4)
 int default_epw(int P);
 int epw_candidates(const pmg_level_s& L, int* out);
 hipError_t launch_gradient_traces(const pmg_level_s& L, const double* q, hipStream_t st);
@@ -150,6 +150,8 @@ hipError_t launch_dtau_min(const pmg_level_s& L, const double* q, hipStream_t st
 
 // hexahedral levels (fr3_kernels.hip; element blocks in jac3_kernels.hip)
 int residual_blocks3(const pmg_level_s& L);
+int default_epw3(int P);
+int epw3_candidates(int P, int* out);
 hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double* src, const double* S,
                             double c_mass, double* F, bool want_norms, hipStream_t st);
 hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,

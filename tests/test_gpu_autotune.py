@@ -89,3 +89,39 @@ def test_set_epw_rejects_uncompiled_values():
         lev.set_epw(5)
     with pytest.raises(api.A.PmgError):
         lev.autotune(precision=16)
+
+
+# hexahedral levels: the rotated 3 x 3 x 2 cubed sphere (108 elements, every face orientation code)
+
+def setup3(P):
+    from test_gpu_3d import disturbed_at
+    from test_oracle_3d import small_sphere
+    fs = W.FreeStream3Spec(ma_inf=0.01)
+    qinf = fs.freestream()
+    lev = api.Level(small_sphere(inner=W.BC_SLIP_WALL), P, gamma=fs.gamma, rgas=fs.rgas, eps_mode=1,
+                    ma_inf=fs.ma_inf, kappa=1.0, q_inf=qinf, q_ref=qinf)
+    x = np.moveaxis(np.asarray(lev.points()), 0, -1)
+    q = torch.from_numpy(np.ascontiguousarray(np.moveaxis(disturbed_at(x, qinf) - qinf, -1, 0))).cuda()
+    return lev, q
+
+
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
+def test_every_3d_variant_matches_the_default(P):
+    lev, q = setup3(P)
+    cur, cand = lev.epw()
+    assert cur == cand[0] and len(cand) >= 2
+    fac = api.Factors(lev, 32)
+    dtau = 0.2 * api.dtau_min(lev, q)
+    api.fr_element_jacobian(lev, q, dtau, 0.0, fac)
+    ref = run(lev, q, fac, 0.0)
+    for epw in cand[1:]:
+        lev.set_epw(epw)
+        got = run(lev, q, fac, 0.0)
+        print("3-D P", P, "epw", epw)
+        for name, g, r in zip(("F", "norms", "q after sweeps", "sweep norms", "F after"), got, ref):
+            if "norms" in name:
+                np.testing.assert_allclose(g, r, rtol=1e-13, atol=0.0, err_msg=name)
+            else:
+                assert np.array_equal(g, r), (name, float(np.max(np.abs(g - r))))
+    res = lev.autotune(precision=32, reps=2)
+    assert res["epw"] in cand and lev.status() == 0
