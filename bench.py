@@ -287,6 +287,7 @@ def sphere_block(api, torch, forms, max_vcycles, kernel_reps, plev=(2, 1, 0), ns
            "n_smooth": list(nsm)}
     for form in forms:
         prec, graph = FORMS[form]
+        tuned = [lv.autotune(precision=prec, reps=5) for lv in levels]   # setup, before the solve
         facs = [api.Factors(lv, prec) for lv in levels]
         kw = dict(tol_rel=1e-8, use_graph=graph, use_cfl=True, cfl_init=cfl_init, cfl_max=1e5, freeze_at_max=False)
         q = levels[0].new_state()
@@ -325,8 +326,13 @@ def sphere_block(api, torch, forms, max_vcycles, kernel_reps, plev=(2, 1, 0), ns
                      "history_every_25": [float(x) for x in h[::25]],
                      "fine_sweep_kernel_ms": k_ms, "fine_sweep_bytes_per_launch": kbytes,
                      "fine_sweep_hbm_frac": kbytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     # the counters were taken with the default grouping of the fine level
                      "fine_sweep_traffic": (measured_traffic(profile_pmc, KERNEL_SOURCES_3D)
-                                            if prec == 32 else None),
+                                            if prec == 32 and levels[0].epw()[0] == levels[0].epw()[1][0]
+                                            else None),
+                     "elements_per_workgroup": [lv.epw()[0] for lv in levels],
+                     "autotune_us_per_residual_and_sweep": [{str(k): v for k, v in
+                                                             t["us_per_residual_and_sweep"].items()} for t in tuned],
                      "fine_block_rebuild_ms": jac_ms,
                      "fine_block_rebuild_gj_tflops": levels[0].ne * 2.0 * n ** 3 / (jac_ms * 1e-3) / 1e12}
         del facs, solver
