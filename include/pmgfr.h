@@ -157,7 +157,9 @@ pmg_status pmg_level_set_epw(pmg_level L, int32_t epw);
 
 /* pmg_level_autotune — time every candidate on this level (reps residual evaluations plus reps
  * element-Jacobi sweeps with inverse blocks of the given precision, 32 or 64, after one untimed
- * pass of the same), keep the fastest and return it in *epw_out (nullable); us_out (nullable, room
+ * pass of the same), keep the fastest — the default unless another candidate is more than 2%
+ * faster, so that timing noise does not flip the choice — and return it in *epw_out (nullable);
+ * us_out (nullable, room
  * for n_cand doubles, in candidate order) receives the microseconds per residual + sweep pair.
  * A setup call: it allocates and frees its own scratch state, overwrites the level's workspace,
  * and synchronises the stream. Errors: PMG_E_ARG (precision, reps < 1),

@@ -685,7 +685,8 @@ pmg_status pmg_level_autotune(pmg_level L, int32_t precision, int32_t reps, int3
   }
   const int keep = L->epw;
   int best = -1;
-  double best_us = 0.0;
+  double best_us = 0.0, us_def = 0.0;
+  constexpr double kTuneMargin = 0.98;   // a candidate must beat the default by more than 2%
   pmg_status status = PMG_OK;
   for (int i = 0; i < nc && status == PMG_OK; ++i) {
     L->epw = c[i];
@@ -708,12 +709,16 @@ pmg_status pmg_level_autotune(pmg_level L, int32_t precision, int32_t reps, int3
     }
     const double us = 1e3 * ms / reps;
     if (us_out) us_out[i] = us;
+    if (i == 0) us_def = us;
     if (best < 0 || us < best_us) {
       best = i;
       best_us = us;
     }
   }
   release();
+  // the default stays unless a candidate is clearly faster: timings within a few percent are noise
+  // and would only make the configuration flip between runs
+  if (status == PMG_OK && best != 0 && us_def * kTuneMargin <= best_us) best = 0;
   L->epw = (status == PMG_OK) ? c[best] : keep;
   L->part_blocks = pmg::residual_blocks(*L);
   if (status == PMG_OK && epw_out) *epw_out = L->epw;
