@@ -373,11 +373,14 @@ struct Vec16<double> {
 // column-major (a column's NR rows contiguous and 16-byte aligned); the caller sums over g < G.
 template <int NR, int NC, class T, int NT>
 struct ColMatvec {
-  static constexpr int RV = Vec16<T>::n, RT = NR / RV, G0 = NT / RT, G = G0 < NC ? G0 : NC;
+  // at most 8 column groups on small blocks, so that a workgroup holds several elements (EPB)
+  static constexpr int RV = Vec16<T>::n, RT = NR / RV, G0 = NT / RT, G1 = G0 < NC ? G0 : NC,
+                       G = (NR <= 64 && G1 > 8) ? 8 : G1, TPE = RT * G, EPB = NT / TPE;
   static_assert(NR % RV == 0, "rows come in whole vectors");
-  __device__ static void run(const T* __restrict__ X, const double* x, double* part) {
+  // lt: the thread's index among the TPE threads of its element
+  __device__ static void run(const T* __restrict__ X, const double* x, double* part, int lt) {
     using V = typename Vec16<T>::type;
-    const int rt = threadIdx.x % RT, g = threadIdx.x / RT;
+    const int rt = lt % RT, g = lt / RT;
     if (g >= G) return;
     double acc[RV];
 #pragma unroll
@@ -419,88 +422,103 @@ __device__ __forceinline__ int line_nbr(const LineArgs& a, int e, int side, int&
   return en;
 }
 
-// Substitution pass 1, one workgroup per element: z_k = W_k r_k, and u_k = E_{k+1} z_k, the trace of
-// z_k on the face shared with the next element of the line in that element's flux-point order.
+// The substitution passes run EPB elements per workgroup (several on the small coarse-level blocks),
+// TPE threads each; slot es of the workgroup holds element blockIdx.x * EPB + es.
+
+// Substitution pass 1: z_k = W_k r_k, and u_k = E_{k+1} z_k, the trace of z_k on the face shared with
+// the next element of the line in that element's flux-point order.
 template <int P, class T>
 __global__ void __launch_bounds__(256) k_line_zu(LineArgs a, const T* __restrict__ W, const double* __restrict__ r,
                                                  double* __restrict__ z, double* __restrict__ u) {
   using C = LineCfg<P>;
   constexpr int NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
   using MV = ColMatvec<N, N, T, NT>;
-  __shared__ double sx[N], sz[N];
-  __shared__ double part[MV::G * N];
-  const int ne = a.lv.ne, e = blockIdx.x, tid = threadIdx.x;
-  for (int t = tid; t < N; t += NT) sx[t] = r[((size_t)(t % NV) * NP + t / NV) * ne + e];
+  constexpr int EPB = MV::EPB, TPE = MV::TPE;
+  __shared__ double sx[EPB][N], sz[EPB][N];
+  __shared__ double part[EPB][MV::G * N];
+  const int ne = a.lv.ne, es = threadIdx.x / TPE, lt = threadIdx.x % TPE, e = blockIdx.x * EPB + es;
+  const bool live = es < EPB && e < ne;
+  if (live)
+    for (int t = lt; t < N; t += TPE) sx[es][t] = r[((size_t)(t % NV) * NP + t / NV) * ne + e];
   __syncthreads();
-  MV::run(W + (size_t)e * N * N, sx, part);
+  if (live) MV::run(W + (size_t)e * N * N, sx[es], part[es], lt);
   __syncthreads();
-  for (int t = tid; t < N; t += NT) {
-    double v = 0.0;
+  if (live)
+    for (int t = lt; t < N; t += TPE) {
+      double v = 0.0;
 #pragma unroll
-    for (int g = 0; g < MV::G; ++g) v += part[g * N + t];
-    sz[t] = v;
-    z[(size_t)e * N + t] = v;
-  }
-  int fe, on;
-  if (line_nbr(a, e, 1, fe, on) < 0) return;
+      for (int g = 0; g < MV::G; ++g) v += part[es][g * N + t];
+      sz[es][t] = v;
+      z[(size_t)e * N + t] = v;
+    }
   __syncthreads();
-  for (int t = tid; t < NJ; t += NT) u[(size_t)a.pos[e] * NJ + t] = face_trace<P>(a.ops, fe, on, sz, t / NV, t % NV);
+  int fe = -1, on = 0;
+  if (live && line_nbr(a, e, 1, fe, on) >= 0)
+    for (int t = lt; t < NJ; t += TPE)
+      u[(size_t)a.pos[e] * NJ + t] = face_trace<P>(a.ops, fe, on, sz[es], t / NV, t % NV);
 }
 
 // Substitution pass 3: y_k = z_k - C_k t_k (in place of z), and v_k = E_{k-1} y_k, the trace of y_k on
-// the face shared with the previous element in that element's order.
+// the face shared with the previous element in that element's order. A line's first element keeps
+// y = z and needs no trace.
 template <int P, class T>
 __global__ void __launch_bounds__(256) k_line_yv(LineArgs a, double* __restrict__ z, const double* __restrict__ tt,
                                                  double* __restrict__ v) {
   using C = LineCfg<P>;
   constexpr int NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
   using MV = ColMatvec<N, NJ, T, NT>;
-  __shared__ double sx[NJ], sy[N];
-  __shared__ double part[MV::G * N];
-  const int e = blockIdx.x, tid = threadIdx.x;
-  int fe, on;
-  if (line_nbr(a, e, 0, fe, on) < 0) return;            // a line's first element: y = z, no trace needed
-  const size_t pe = a.pos[e];
-  for (int t = tid; t < NJ; t += NT) sx[t] = tt[pe * NJ + t];
+  constexpr int EPB = MV::EPB, TPE = MV::TPE;
+  __shared__ double sx[EPB][NJ], sy[EPB][N];
+  __shared__ double part[EPB][MV::G * N];
+  const int es = threadIdx.x / TPE, lt = threadIdx.x % TPE, e = blockIdx.x * EPB + es;
+  int fe = -1, on = 0;
+  const bool live = es < EPB && e < a.lv.ne && line_nbr(a, e, 0, fe, on) >= 0;
+  const size_t pe = live ? (size_t)a.pos[e] : 0;
+  if (live)
+    for (int t = lt; t < NJ; t += TPE) sx[es][t] = tt[pe * NJ + t];
   __syncthreads();
-  MV::run(static_cast<const T*>(a.C) + (size_t)e * NJ * N, sx, part);
+  if (live) MV::run(static_cast<const T*>(a.C) + (size_t)e * NJ * N, sx[es], part[es], lt);
   __syncthreads();
-  for (int t = tid; t < N; t += NT) {
-    double y = z[(size_t)e * N + t];
+  if (live)
+    for (int t = lt; t < N; t += TPE) {
+      double y = z[(size_t)e * N + t];
 #pragma unroll
-    for (int g = 0; g < MV::G; ++g) y -= part[g * N + t];
-    sy[t] = y;
-    z[(size_t)e * N + t] = y;
-  }
+      for (int g = 0; g < MV::G; ++g) y -= part[es][g * N + t];
+      sy[es][t] = y;
+      z[(size_t)e * N + t] = y;
+    }
   __syncthreads();
-  for (int t = tid; t < NJ; t += NT) v[pe * NJ + t] = face_trace<P>(a.ops, fe, on, sy, t / NV, t % NV);
+  if (live)
+    for (int t = lt; t < NJ; t += TPE) v[pe * NJ + t] = face_trace<P>(a.ops, fe, on, sy[es], t / NV, t % NV);
 }
 
-// Substitution pass 5: x_k = y_k - B_k s_k, q += alpha x_k.
+// Substitution pass 5: x_k = y_k - B_k s_k (y_k alone at a line's last element), q += alpha x_k.
 template <int P, class T>
 __global__ void __launch_bounds__(256) k_line_x(LineArgs a, const double* __restrict__ y, const double* __restrict__ ss,
                                                 double* __restrict__ q, double alpha) {
   using C = LineCfg<P>;
   constexpr int NP = C::NP, NV = C::NV, N = C::N, NJ = C::NJ, NT = C::NT;
   using MV = ColMatvec<N, NJ, T, NT>;
-  __shared__ double sx[NJ];
-  __shared__ double part[MV::G * N];
-  const int ne = a.lv.ne, e = blockIdx.x, tid = threadIdx.x;
-  const bool last = a.fside[ne + e] < 0;
-  if (!last) {
-    for (int t = tid; t < NJ; t += NT) sx[t] = ss[(size_t)a.pos[e] * NJ + t];
-    __syncthreads();
-    MV::run(static_cast<const T*>(a.B) + (size_t)e * NJ * N, sx, part);
-    __syncthreads();
-  }
-  for (int t = tid; t < N; t += NT) {
-    double x = y[(size_t)e * N + t];
-    if (!last) {
+  constexpr int EPB = MV::EPB, TPE = MV::TPE;
+  __shared__ double sx[EPB][NJ];
+  __shared__ double part[EPB][MV::G * N];
+  const int ne = a.lv.ne, es = threadIdx.x / TPE, lt = threadIdx.x % TPE, e = blockIdx.x * EPB + es;
+  const bool live = es < EPB && e < ne;
+  const bool coupled = live && a.fside[ne + e] >= 0;
+  if (coupled)
+    for (int t = lt; t < NJ; t += TPE) sx[es][t] = ss[(size_t)a.pos[e] * NJ + t];
+  __syncthreads();
+  if (coupled) MV::run(static_cast<const T*>(a.B) + (size_t)e * NJ * N, sx[es], part[es], lt);
+  __syncthreads();
+  if (live)
+    for (int t = lt; t < N; t += TPE) {
+      double x = y[(size_t)e * N + t];
+      if (coupled) {
 #pragma unroll
-      for (int g = 0; g < MV::G; ++g) x -= part[g * N + t];
+        for (int g = 0; g < MV::G; ++g) x -= part[es][g * N + t];
+      }
+      q[((size_t)(t % NV) * NP + t / NV) * ne + e] += alpha * x;
     }
-    q[((size_t)(t % NV) * NP + t / NV) * ne + e] += alpha * x;
-  }
 }
 
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
@@ -604,11 +622,14 @@ template <int P, class T>
 hipError_t line_sweep_pt(const LineArgs& a, const LineFactors& lf, double* q, double alpha, hipStream_t st) {
   const int ne = a.lv.ne, NJ = LineCfg<P>::NJ, NT = LineCfg<P>::NT;
   double *u = lf.tr, *t = lf.tr + (size_t)ne * NJ, *v = lf.tr + (size_t)2 * ne * NJ, *s = lf.tr + (size_t)3 * ne * NJ;
-  hipLaunchKernelGGL((k_line_zu<P, T>), dim3(ne), dim3(NT), 0, st, a, (const T*)lf.Winv, (const double*)lf.r, lf.z, u);
+  constexpr int N = LineCfg<P>::N, NJc = LineCfg<P>::NJ;
+  constexpr int Ez = ColMatvec<N, N, T, 256>::EPB, Ec = ColMatvec<N, NJc, T, 256>::EPB;
+  const int gz = (ne + Ez - 1) / Ez, gc = (ne + Ec - 1) / Ec;
+  hipLaunchKernelGGL((k_line_zu<P, T>), dim3(gz), dim3(NT), 0, st, a, (const T*)lf.Winv, (const double*)lf.r, lf.z, u);
   hipLaunchKernelGGL(k_line_rec<P>, dim3(lf.n_lines), dim3(NT), 0, st, a, (const double*)lf.M, (const double*)u, t, 0);
-  hipLaunchKernelGGL((k_line_yv<P, T>), dim3(ne), dim3(NT), 0, st, a, lf.z, (const double*)t, v);
+  hipLaunchKernelGGL((k_line_yv<P, T>), dim3(gc), dim3(NT), 0, st, a, lf.z, (const double*)t, v);
   hipLaunchKernelGGL(k_line_rec<P>, dim3(lf.n_lines), dim3(NT), 0, st, a, (const double*)lf.N, (const double*)v, s, 1);
-  hipLaunchKernelGGL((k_line_x<P, T>), dim3(ne), dim3(NT), 0, st, a, (const double*)lf.z, (const double*)s, q, alpha);
+  hipLaunchKernelGGL((k_line_x<P, T>), dim3(gc), dim3(NT), 0, st, a, (const double*)lf.z, (const double*)s, q, alpha);
   return hipGetLastError();
 }
 
