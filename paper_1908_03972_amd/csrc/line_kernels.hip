@@ -33,6 +33,7 @@
 //                    a chain of K dependent n x n products per line.
 //   k_line_dense     The coupling blocks written out dense (for tests).
 #include "lines.hpp"
+#include "wave_ops.hpp"
 
 namespace pmg {
 namespace {
@@ -231,24 +232,15 @@ __global__ void __launch_bounds__(256) k_line_thomas(LineArgs a, const double* D
     // the columns at the end.
     for (int kk = 0; kk < N; ++kk) {
       if (tid < 64) {
-        double best = -1.0;
-        int bi = N;
-        for (int i = kk + tid; i < N; i += 64) {
-          const double av = fabs(sM[i * LD + kk]);
-          if (av > best) {
-            best = av;
-            bi = i;
-          }
-        }
-        for (int off = 32; off > 0; off >>= 1) {     // largest magnitude, ties to the lower row
-          const double ob = __shfl_xor(best, off, 64);
-          const int oi = __shfl_xor(bi, off, 64);
-          if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-          }
-        }
-        const int p = bi < N ? bi : kk;               // only non-finite columns leave no candidate
+        // pivot key: the upper word of |entry| (sign 0, exponent, 20 mantissa bits) with its low 7
+        // bits replaced by 127 - row; the largest key wins, so the pivot is within a factor
+        // 1 + 2^-13 of the largest candidate and ties go to the lowest row
+        static_assert(N <= 128, "row index in 7 bits");
+        unsigned key = 0u;
+        for (int i = kk + tid; i < N; i += 64)
+          key = max(key, (((unsigned)__double2hiint(fabs(sM[i * LD + kk]))) & ~0x7Fu) | (unsigned)(127 - i));
+        const unsigned wkey = wave_max_u32(key);
+        const int p = 127 - (int)(wkey & 0x7Fu);      // every row kk..N-1 is a candidate, so wkey != 0
         for (int i = tid; i < N; i += 64) sf[i] = (i == kk) ? 0.0 : (i == p ? sM[kk * LD + kk] : sM[i * LD + kk]);
         if (tid == 0) {
           sperm[kk] = p;
