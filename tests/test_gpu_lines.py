@@ -121,15 +121,19 @@ def test_line_blocks_parity(P):
 
 @pytest.mark.parametrize("P,prec,kind", [(1, 64, "radial"), (2, 64, "radial"), (3, 64, "radial"),
                                          (4, 64, "radial"), (4, 32, "radial"), (2, 64, "wrap"),
-                                         (3, 32, "wrap")])
+                                         (3, 32, "wrap"), (0, 32, "ragged"), (1, 32, "ragged"),
+                                         (1, 64, "ragged"), (2, 32, "ragged")])
 def test_line_sweep_parity(P, prec, kind):
     """Three steady line sweeps at pseudo-time step 1e3 dtau_min. The bound is ten times the
     oracle's own response to a one-ulp change of the state (FP64), or to W_k rounded to FP32 in a
-    block-Thomas solve with the oracle's blocks (FP32), and at least 1e-11."""
-    mesh = small_mesh()
+    block-Thomas solve with the oracle's blocks (FP32), and at least 1e-11. "ragged": radial lines
+    on a 13 x 7 O-mesh, whose 91 elements leave the last workgroup of the substitution kernels
+    partly empty at every grouping (64, 8, 4 or 3 elements per workgroup at P0-P2)."""
+    nw, nr = (13, 7) if kind == "ragged" else (NW, NR)
+    mesh = W.airfoil_o_mesh(nw, nr, ratio=1.3, r_far=10.0) if kind == "ragged" else small_mesh()
     olev = FRLevel(mesh, P, GAS, q_inf=QINF)
     glev = glevel(mesh, P)
-    lines = radial_lines(NW, NR) if kind == "radial" else wrap_lines(NW, NR)
+    lines = radial_lines(nw, nr) if kind in ("radial", "ragged") else wrap_lines(nw, nr)
     q = disturbed(olev, 3)
     dtau = 1e3 * OS.PMGSolver(mesh, GAS, OS.PMGOptions(p_levels=(P,), n_smooth=(1,)), q_inf=QINF).dtau_min(q)
     blocks = OL.line_blocks(olev, q, dtau, 0.0, lines)
