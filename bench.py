@@ -1,15 +1,18 @@
 """Benchmark: element-Jacobi DOF-updates/s and time to a 1e-8 residual drop on one MI355X.
 
-Workload (synthetic, seeded): isentropic vortex (Ma_inf = 0.005, strength 5, Sec. 4.1) on the
-periodic [-5,5]^2 square, 64 x 64 bilinear quads with vertices jittered by +-10% of the cell size,
-FR/CPR P = 3 with P-levels {3-2-1} and smoothing counts I{5-10-20}, ESDIRK3 (four stages),
-dt = 0.05, pseudo time dtau 0.01 -> 10 by the SER law, blocks rebuilt every 10 V-cycles, every
-implicit stage solved to a 1e-8 relative residual drop.
+Headline workload (synthetic): steady inviscid flow at Ma 0.001 past the unit sphere (Sec. 4.2
+setting) on the equiangular cubed sphere of 6 x 16 x 16 cells x 24 radial shells (36 864
+quadratic hexahedra, far field at 20 radii), FR/CPR P = 3 with P-levels {3-2-1-0} and smoothing
+counts I{5-10-20-20}, cut-off eps (kappa 1), CFL 30 -> 1e5 by the SER law, blocks rebuilt every 10
+V-cycles, started from the free stream and solved to a 1e-8 relative drop of the residual norm.
 
-A step is one physical ESDIRK3 time step (three implicit stage solves, every row of the hot path).
-The timed steps restart from the initial condition after the warm-up, so they are the first
-`steps` time steps of the workload. Both forms run: FP32 inverse blocks ("mixed", the headline
-`value`) and FP64 blocks ("fp64"); the residual, the update and the restriction stay FP64 in both.
+A step is one whole steady solve (every V-cycle until the 1e-8 drop, with every block rebuild the
+schedule asks for): every row of the hot path runs in it. `value` is the DOF-updates per second of
+the mixed form (FP32 inverse blocks on the smoother, FP64 residual, update and restriction, the
+V-cycles replayed from a HIP graph) over the K timed steps; `ms_per_step` is therefore its time to
+the 1e-8 drop. The plain FP64 form (FP64 blocks, eager launches) solves the same problem after it
+and both times to 1e-8 are reported. The final stdout line is the compact result; the optional
+blocks (`--extra`) go to a side JSON file and to stderr.
 """
 from __future__ import annotations
 
@@ -47,59 +50,51 @@ def dof_updates_per_vcycle(ne, p_levels, n_smooth, nv=4, dim=2):
     return tot
 
 
-def _cpu_sample(n_side, threads):
-    """Block rebuild on every level and one V-cycle of the first implicit ESDIRK3 stage by the CPU
-    oracle, with its BLAS/LAPACK limited to the given number of threads: (rebuild s, V-cycle s,
-    DOF-updates of the V-cycle, elements)."""
+def cpu_baseline(n_cells=2, n_shells=2, plev=(3, 2, 1, 0), nsm=(5, 10, 20, 20)):
+    """The CPU oracle on a bounded sample of the headline workload: one block rebuild on every level
+    and one V-cycle of the same steady sphere problem (same P-levels, smoothing counts, cut-off eps
+    and CFL start) on a cubed sphere of 6 x n_cells^2 x n_shells hexahedra, with the BLAS/LAPACK
+    pool limited to the host cores available to this process (at most 16). DOF-updates/s =
+    DOF-updates of one V-cycle / (V-cycle time + rebuild time / 10): the rebuild amortised as the
+    schedule does (one per 10 V-cycles)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import gas as OG
     from oracle import solver as OS
-    mesh = W.periodic_quad_mesh(n_side, 10.0, jitter=0.1, seed=W.JITTER_SEED)
-    vs = W.VortexSpec(length=10.0)
-    gas = OG.Gas(gamma=vs.gamma, rgas=vs.rgas, eps_mode="local")
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    mesh = W.cubed_sphere_mesh(n_cells, n_shells)
+    fs = W.FreeStream3Spec()
+    gas = OG.Gas(gamma=fs.gamma, rgas=fs.rgas, eps_mode="cutoff", ma_inf=fs.ma_inf, kappa=1.0)
     with threadpool_limits(threads):
-        opts = OS.PMGOptions(p_levels=P_LEVELS, n_smooth=N_SMOOTH)
-        sol = OS.PMGSolver(mesh, gas, opts, q_inf=vs.freestream())
+        opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, use_cfl=True, cfl_init=30.0, cfl_max=1e5,
+                             freeze_at_max=False)
+        sol = OS.PMGSolver(mesh, gas, opts, q_inf=fs.freestream())
         lev = sol.levels[0]
-        q = vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1])
-        A = OS.esdirk_tableau("esdirk3")
-        om = A[1, 1]
-        sol.c_mass = 1.0 / (om * DT)
-        sol.src = (OG.conservative(q, gas) + DT * A[1, 0] * lev.residual(q)) / (om * DT)
-        sol.dtau = opts.dtau_init
+        q = np.broadcast_to(fs.freestream(), (lev.ne, lev.npts, 5)).copy()
+        sol.c_mass, sol.src = 0.0, None
+        sol.dtau = opts.cfl_init * sol.dtau_min(q)
         t0 = time.perf_counter()
         sol.build_D(0, q)
         qb = q
-        for l in range(1, len(P_LEVELS)):
-            qb = OS.restrict(qb, P_LEVELS[l - 1], P_LEVELS[l])
+        for l in range(1, len(plev)):
+            qb = OS.restrict(qb, plev[l - 1], plev[l], 3)
             sol.build_D(l, qb)
         t_build = time.perf_counter() - t0
         sol.refresh_now = False
         t0 = time.perf_counter()
         sol.vcycle(0, q, None)
         t_vc = time.perf_counter() - t0
-    return t_build, t_vc, dof_updates_per_vcycle(mesh.n_elements, P_LEVELS, N_SMOOTH), mesh.n_elements
-
-
-def cpu_baseline(n_side=32):
-    """The CPU oracle on a bounded sample of the workload: one block rebuild on every level and
-    one V-cycle of the first implicit ESDIRK3 stage, on the same vortex with an n_side x n_side
-    jittered mesh, on one thread and on all the host cores available to this process (at most 16).
-    DOF-updates/s = DOF-updates of one V-cycle / (V-cycle time + rebuild/10), the rebuild amortised
-    as in the GPU metric; the faster run is the baseline."""
-    runs = {}
-    for threads in sorted({1, max(1, min(16, len(os.sched_getaffinity(0))))}):
-        t_build, t_vc, per_vc, ne = _cpu_sample(n_side, threads)
-        runs[threads] = (per_vc / (t_vc + t_build / 10.0), t_build, t_vc)
-    best = max(runs, key=lambda t: runs[t][0])
-    value, t_build, t_vc = runs[best]
-    return {"value": value, "unit": "DOF-updates/s", "cores": best, "kind": "oracle",
-            "sample": (f"block rebuild on all levels ({t_build:.1f} s) + one V-cycle ({t_vc:.1f} s) of the first "
-                       f"ESDIRK3 stage on the same vortex with a {n_side}x{n_side} jittered mesh "
-                       f"({ne} elements, {per_vc} DOF-updates per V-cycle); rebuild amortised 1/10"),
-            "value_per_thread_count": {str(t): v[0] for t, v in runs.items()},
-            "cpu": platform.processor() or platform.machine()}
+    per_vc = dof_updates_per_vcycle(mesh.n_elements, plev, nsm, nv=5, dim=3)
+    cpu = ""
+    try:
+        cpu = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        cpu = platform.processor() or platform.machine()
+    return {"value": per_vc / (t_vc + t_build / 10.0), "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, sphere P{{{'-'.join(map(str, plev))}}} on {mesh.n_elements} hexahedra "
+                       f"(6x{n_cells}x{n_cells}x{n_shells}): rebuild {t_build:.1f} s + one V-cycle {t_vc:.1f} s, "
+                       "rebuild amortised 1/10"),
+            "cpu": cpu}
 
 
 FORMS = {"mixed": (32, True), "fp64": (64, False)}   # (block precision, graph replay)
@@ -520,28 +515,173 @@ def progress(what):
     print(f"bench: {what} done at {time.perf_counter() - _T0:.1f} s", file=sys.stderr, flush=True)
 
 
+def vortex_block(api, torch, forms, steps, warmup, max_vcycles, kernel_reps, autotune=True):
+    """Config 2: isentropic vortex (Ma 0.005) on the periodic 64 x 64 jittered quad mesh, P{3-2-1},
+    I{5-10-20}, ESDIRK3 steps of dt 0.05 from the analytic vortex, every stage to 1e-8 or
+    max_vcycles, in both forms; the fine level's FP32 inverses (67 MB) fit the 256 MB Infinity
+    Cache, so its sweep fraction is not an HBM figure."""
+    mesh, vs = W.vortex_config2()
+    qinf = vs.freestream()
+    levels = [api.Level(mesh, P, gamma=vs.gamma, rgas=vs.rgas, eps_mode=0, ma_inf=vs.ma_inf, q_inf=qinf, q_ref=qinf)
+              for P in P_LEVELS]
+    xy = levels[0].points()
+    q0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(vs.state(xy[0], xy[1]) - qinf, -1, 0))).cuda()
+    L0 = levels[0]
+    work = torch.zeros((api.esdirk_stages(SCHEME),) + L0.shape, dtype=torch.float64, device="cuda")
+    per_vc = dof_updates_per_vcycle(L0.ne, P_LEVELS, N_SMOOTH)
+    out = {"workload": "isentropic vortex Ma 0.005, periodic 64x64 jittered quads, P{3-2-1} I{5-10-20}, "
+                       f"ESDIRK3 dt 0.05, {steps} steps, stages to 1e-8 or {max_vcycles} V-cycles"}
+    finals = {}
+    for form in forms:
+        if autotune:
+            for lv in levels:
+                lv.autotune(precision=FORMS[form][0], reps=20)
+        facs, solver, q, stage_stats, elapsed = run_form(api, torch, levels, q0, form, SCHEME, DT, steps, warmup,
+                                                         max_vcycles, work)
+        nvc = sum(st["n_vcycles"] for st in stage_stats)
+        ttt, floors = time_to_tolerances(stage_stats)
+        qk = q.clone()
+        c_mass = 1.0 / (DT * 1767732205903.0 / 4055673282236.0)
+        api.ejacobi_sweep(L0, facs[0], qk, 2, c_mass=c_mass, alpha_r=0.0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        api.ejacobi_sweep(L0, facs[0], qk, kernel_reps, c_mass=c_mass, alpha_r=0.0)
+        ev1.record()
+        torch.cuda.synchronize()
+        k_ms = ev0.elapsed_time(ev1) / kernel_reps
+        prec = FORMS[form][0]
+        launch_bytes = L0.ne * L0.n * ((4 if prec == 32 else 8) * L0.n + 24)
+        out[form] = {"dof_updates_per_s": nvc * per_vc / elapsed, "ms_per_vcycle": 1e3 * elapsed / max(nvc, 1),
+                     "vcycles_per_stage": [st["n_vcycles"] for st in stage_stats],
+                     "stages_converged_to_1e-8": sum(st["status"] == 0 for st in stage_stats),
+                     "time_to_tol_s_per_stage": ttt, "min_rel_residual_per_stage": floors,
+                     "fine_sweep_ms": k_ms, "fine_sweep_bytes": launch_bytes,
+                     "fine_sweep_frac_of_8TBs": launch_bytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "elements_per_workgroup": [lv.epw()[0] for lv in levels]}
+        finals[form] = q.detach().cpu().numpy()
+        del facs, solver
+    if "mixed" in finals and "fp64" in finals:
+        d = finals["fp64"]
+        out["mixed_vs_fp64_rel_err"] = (np.linalg.norm((finals["mixed"] - d).reshape(4, -1), axis=1)
+                                        / np.linalg.norm(d.reshape(4, -1), axis=1)).tolist()
+    return out, levels, q0
+
+
+def small_vortex_block(api, torch, forms):
+    """Config 1: the 8x8 P{2-1-0} ESDIRK2 vortex, five steps, stages to 1e-8 (at most 2000 V-cycles)."""
+    m1, v1 = W.vortex_config1()
+    qinf = v1.freestream()
+    lv1 = [api.Level(m1, P, gamma=v1.gamma, rgas=v1.rgas, eps_mode=0, ma_inf=v1.ma_inf, q_inf=qinf, q_ref=qinf)
+           for P in (2, 1, 0)]
+    xy = lv1[0].points()
+    q1 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(v1.state(xy[0], xy[1]) - qinf, -1, 0))).cuda()
+    w1 = torch.zeros((api.esdirk_stages(2),) + lv1[0].shape, dtype=torch.float64, device="cuda")
+    small = {}
+    for form in forms:
+        _, _, _, sst, el = run_form(api, torch, lv1, q1, form, 2, DT, 5, 1, 2000, w1)
+        small[form] = {"elapsed_s": el, "stages": len(sst),
+                       "stages_converged_to_1e-8": sum(s["status"] == 0 for s in sst),
+                       "vcycles_per_stage": [s["n_vcycles"] for s in sst],
+                       "time_to_1e-8_s_total": float(sum(s["seconds"] for s in sst))}
+    if "mixed" in small and "fp64" in small and small["mixed"]["time_to_1e-8_s_total"] > 0:
+        small["speedup_time_to_1e-8_mixed_over_fp64"] = (small["fp64"]["time_to_1e-8_s_total"]
+                                                         / small["mixed"]["time_to_1e-8_s_total"])
+    return small
+
+
+HEAD_PLEV = (3, 2, 1, 0)
+HEAD_NSM = (5, 10, 20, 20)
+HEAD_CFL = (30.0, 1e5)
+
+
+def sphere_headline(api, torch, steps, warmup, fp64_solves, max_vcycles, kernel_reps, autotune=True):
+    """The headline: K timed steady solves of the sphere at P{3-2-1-0} in the mixed form, then the
+    plain FP64 form on the same problem, the live duration of the fine-level fused sweep (the
+    dominant kernel) and of the fine-level block rebuild."""
+    mesh, fs = W.sphere_config5()
+    qinf = fs.freestream()
+    levels = [api.Level(mesh, P, gamma=fs.gamma, rgas=fs.rgas, eps_mode=1, ma_inf=fs.ma_inf, kappa=1.0,
+                        q_inf=qinf, q_ref=qinf) for P in HEAD_PLEV]
+    L0 = levels[0]
+    per_vc = dof_updates_per_vcycle(L0.ne, HEAD_PLEV, HEAD_NSM, nv=5, dim=3)
+    res = {"elements": L0.ne, "dof_fine": L0.ne * L0.n, "dof_updates_per_vcycle": per_vc}
+    finals = {}
+    for form, nsolve, nwarm in (("mixed", steps, warmup), ("fp64", fp64_solves, 1)):
+        if nsolve <= 0:
+            continue
+        prec, graph = FORMS[form]
+        if autotune:
+            for lv in levels:
+                lv.autotune(precision=prec, reps=5)             # setup, outside the timed region
+        facs = [api.Factors(lv, prec) for lv in levels]
+        solver = api.StageSolver(levels, facs, HEAD_NSM, tol_rel=1e-8, use_graph=graph, use_cfl=True,
+                                 cfl_init=HEAD_CFL[0], cfl_max=HEAD_CFL[1], freeze_at_max=False,
+                                 max_vcycles=max_vcycles)
+        q = L0.new_state()
+        for _ in range(nwarm):
+            q.zero_()                                            # the free stream (zero offset)
+            solver.solve(q, raise_on_error=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = []
+        for _ in range(nsolve):
+            q.zero_()
+            sts.append(solver.solve(q, raise_on_error=False))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        nvc = sum(st["n_vcycles"] for st in sts)
+        r = {"solves": nsolve, "elapsed_s": elapsed, "ms_per_solve": 1e3 * elapsed / nsolve,
+             "dof_updates_per_s": per_vc * nvc / elapsed, "vcycles": [st["n_vcycles"] for st in sts],
+             "rebuilds": [st["n_refresh"] for st in sts], "status": [st["status"] for st in sts],
+             "final_rel_residual": [st["history"][-1] / st["history"][0] for st in sts],
+             "ms_per_vcycle": 1e3 * elapsed / max(nvc, 1), "elements_per_workgroup": [lv.epw()[0] for lv in levels]}
+        # live per-launch duration of the dominant kernel, the fine-level fused residual + sweep,
+        # timed with HIP events on the stream the library launches on (torch's current stream);
+        # alpha_r = 0 keeps the converged state fixed, the kernel does the same work
+        qk = q.clone()
+        api.ejacobi_sweep(L0, facs[0], qk, 2, alpha_r=0.0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        api.ejacobi_sweep(L0, facs[0], qk, kernel_reps, alpha_r=0.0)
+        ev1.record()
+        torch.cuda.synchronize()
+        r["sweep_ms"] = ev0.elapsed_time(ev1) / kernel_reps
+        r["sweep_bytes"] = L0.ne * L0.n * ((4 if prec == 32 else 8) * L0.n + 24)
+        ev0.record()
+        api.fr_element_jacobian(L0, q, 1e2 * api.dtau_min(L0, q), 0.0, facs[0])
+        ev1.record()
+        torch.cuda.synchronize()
+        r["rebuild_ms"] = ev0.elapsed_time(ev1)
+        finals[form] = q.detach().cpu().numpy()
+        res[form] = r
+        del facs, solver
+        torch.cuda.empty_cache()
+        progress(f"sphere P{{3-2-1-0}} {form}: {nsolve} solves, {r['ms_per_solve']:.0f} ms each")
+    if "mixed" in finals and "fp64" in finals:
+        d = finals["fp64"]
+        res["mixed_vs_fp64_rel_err"] = (np.linalg.norm((finals["mixed"] - d).reshape(5, -1), axis=1)
+                                        / np.linalg.norm(d.reshape(5, -1), axis=1)).tolist()
+    return res
+
+
+EXTRAS = ("vortex", "small", "nk", "airfoil", "lines", "viscous", "sphere2")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3, help="timed steady solves of the headline (mixed form)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--max-vcycles", type=int, default=400)
-    ap.add_argument("--forms", default="mixed,fp64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-small", action="store_true", help="skip the 8x8 time-to-1e-8 measurement")
+    ap.add_argument("--fp64-solves", type=int, default=2, help="timed solves of the plain FP64 form")
+    ap.add_argument("--max-vcycles", type=int, default=200)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--no-airfoil", action="store_true", help="skip the 128x64 airfoil (P = 4) steady solves")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default elements per workgroup")
+    ap.add_argument("--extra", default="", help=f"comma list of further blocks: {','.join(EXTRAS)} or all")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="side file for the full results (the extra blocks, per-solve lists)")
+    ap.add_argument("--vortex-vcycles", type=int, default=400)
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default elements per workgroup on the vortex levels")
-    ap.add_argument("--no-lines", action="store_true",
-                    help="skip the airfoil comparison of element and radial element-line Jacobi")
-    ap.add_argument("--no-viscous", action="store_true", help="skip the eight-case viscous batch")
-    ap.add_argument("--no-sphere", action="store_true", help="skip the 3-D sphere steady solves")
-    ap.add_argument("--no-sphere-p3", action="store_true", help="skip the 3-D sphere P{3-2-1-0} steady solves")
-    ap.add_argument("--no-sphere-p2", action="store_true", help="skip the 3-D sphere P{2-1-0} steady solves")
-    ap.add_argument("--no-newton-krylov", action="store_true",
-                    help="skip the Newton-Krylov against FAS comparison on the 64x64 vortex stage")
     ap.add_argument("--sphere-vcycles", type=int, default=200)
     ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
     args = ap.parse_args()
@@ -549,172 +689,99 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU domain decomposition is described, not implemented)", file=sys.stderr)
         sys.exit(2)
+    extras = set(EXTRAS) if args.extra == "all" else {x for x in args.extra.split(",") if x}
+    unknown = extras - set(EXTRAS)
+    if unknown:
+        ap.error(f"unknown --extra blocks: {sorted(unknown)}")
 
     import torch
     from paper_1908_03972_amd import api
+    torch.cuda.set_device(0)
 
-    dev = torch.device("cuda", 0)
-
-    def setup(mesh, vs, plev):
-        qinf = vs.freestream()
-        levels = [api.Level(mesh, P, gamma=vs.gamma, rgas=vs.rgas, eps_mode=0, ma_inf=vs.ma_inf,
-                            q_inf=qinf, q_ref=qinf) for P in plev]
-        xy = levels[0].points()
-        # states are stored as offsets from the free stream (gauge pressure and temperature)
-        q0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(vs.state(xy[0], xy[1]) - qinf, -1, 0))).to(dev)
-        return levels, q0
-
-    mesh, vs = W.vortex_config2()
-    levels, q0 = setup(mesh, vs, P_LEVELS)
-    L0 = levels[0]
-    work = torch.zeros((api.esdirk_stages(SCHEME),) + L0.shape, dtype=torch.float64, device=dev)
-    per_vc = dof_updates_per_vcycle(L0.ne, P_LEVELS, N_SMOOTH)
-
-    results = {}
-    finals = {}
-    tuned = {}
-    for form in args.forms.split(","):
-        # elements per workgroup of the fused kernel, picked per level by the library's tuner for
-        # this form's block precision (setup, outside the timed region)
-        if args.no_autotune:
-            for lv in levels:
-                lv.set_epw(0)
-        else:
-            tuned[form] = [lv.autotune(precision=FORMS[form][0], reps=20) for lv in levels]
-        facs, solver, q, stage_stats, elapsed = run_form(api, torch, levels, q0, form, SCHEME, DT, args.steps,
-                                                         args.warmup, args.max_vcycles, work)
-        nvc = sum(st["n_vcycles"] for st in stage_stats)
-        ttt, floors = time_to_tolerances(stage_stats)
-        # live per-launch duration of the dominant kernel: the fused residual + sweep on the
-        # finest level, timed with HIP events on the stream the library launches on
-        # (alpha_r = 0 keeps the state fixed; the kernel does the same work)
-        qk = q.clone()
-        c_mass = 1.0 / (DT * 1767732205903.0 / 4055673282236.0)
-        api.ejacobi_sweep(L0, facs[0], qk, 2, c_mass=c_mass, alpha_r=0.0)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        api.ejacobi_sweep(L0, facs[0], qk, args.kernel_reps, c_mass=c_mass, alpha_r=0.0)
-        ev1.record()
-        torch.cuda.synchronize()
-        k_ms = ev0.elapsed_time(ev1) / args.kernel_reps
-        n = L0.n
-        prec = FORMS[form][0]
-        bytes_per_dof = (4 if prec == 32 else 8) * n + 24
-        launch_bytes = L0.ne * n * bytes_per_dof
-        results[form] = {
-            "block_precision": prec, "graph_replay": FORMS[form][1],
-            "dof_updates_per_s": nvc * per_vc / elapsed,
-            "elapsed_s": elapsed,
-            "ms_per_step": 1e3 * elapsed / args.steps,
-            "ms_per_vcycle": 1e3 * elapsed / max(nvc, 1),
-            "vcycles": nvc,
-            "vcycles_per_stage": [st["n_vcycles"] for st in stage_stats],
-            "stages_converged_to_1e-8": sum(st["status"] == 0 for st in stage_stats),
-            "stages": len(stage_stats),
-            "time_to_tol_s_per_stage": ttt,
-            "min_rel_residual_per_stage": floors,
-            "sweep_kernel_ms": k_ms,
-            "sweep_bytes_per_launch": launch_bytes,
-            "sweep_bytes_per_dof_update": bytes_per_dof,
-            "elements_per_workgroup": [lv.epw()[0] for lv in levels],
-            "autotune": [{"epw": t["epw"], "us_per_residual_and_sweep": {str(k): v for k, v in
-                                                                         t["us_per_residual_and_sweep"].items()}}
-                         for t in tuned.get(form, [])],
-        }
-        finals[form] = q.detach().cpu().numpy()
-        del facs, solver
-        progress(f"vortex 64x64 P{{3-2-1}} {form}")
-
-    head = "mixed" if "mixed" in results else next(iter(results))
-    r = results[head]
-    achieved = r["sweep_bytes_per_launch"] / (r["sweep_kernel_ms"] * 1e-3) / 1e9
-
-    def mean_time(res, tol):
-        v = [x for x in res["time_to_tol_s_per_stage"][tol] if x is not None]
-        return float(np.mean(v)) if len(v) == len(res["time_to_tol_s_per_stage"][tol]) else None
-
+    head = sphere_headline(api, torch, args.steps, args.warmup, args.fp64_solves, args.max_vcycles,
+                           args.kernel_reps, autotune=not args.no_autotune)
+    mx, f64 = head["mixed"], head.get("fp64")
+    achieved = mx["sweep_bytes"] / (mx["sweep_ms"] * 1e-3) / 1e9
+    n0 = 5 * (HEAD_PLEV[0] + 1) ** 3
+    traffic = measured_traffic(PROFILE_PMC_SPHERE3, KERNEL_SOURCES_3D)
+    if mx["elements_per_workgroup"][0] != 4:       # the counters were taken with 4 elements per workgroup
+        traffic = None
+    t_mx = mx["ms_per_solve"] * 1e-3
+    t_64 = f64["ms_per_solve"] * 1e-3 if f64 else None
     line = {
         "metric": METRIC,
-        "value": r["dof_updates_per_s"],
+        "value": mx["dof_updates_per_s"],
         "unit": "DOF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
+        "ms_per_step": mx["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if head == "mixed" else "f64",
+        "dtype": "f64 residual/update + f32 block solves",
         "data": "synthetic",
-        "config": {"workload": "isentropic vortex Ma 0.005, periodic 64x64 jittered quads, P{3-2-1} I{5-10-20}, "
-                               f"ESDIRK3 dt 0.05, stages to 1e-8 or {args.max_vcycles} V-cycles",
-                   "elements": L0.ne, "dof_fine": L0.ne * L0.n, "dof_updates_per_vcycle": per_vc,
-                   "form": head},
+        "config": {"workload": "steady Ma 0.001 flow past the unit sphere, cubed sphere 6x16x16x24 quadratic hexes "
+                               "(36864), P{3-2-1-0} I{5-10-20-20}, CFL 30->1e5, solve from free stream to 1e-8 drop",
+                   "elements": head["elements"], "dof_fine": head["dof_fine"],
+                   "dof_updates_per_vcycle": head["dof_updates_per_vcycle"], "form": "mixed, graph replay"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     # the counters were taken with the default grouping of the fine level
-                     "traffic": (measured_traffic() if FORMS[head][0] == 32
-                                 and r["elements_per_workgroup"][0] == L0.epw()[1][0] else None),
-                     "elements_per_workgroup": r["elements_per_workgroup"][0],
-                     "kernel": f"k_fr<3,{2 if FORMS[head][0] == 32 else 1}> (fused residual + element-Jacobi sweep, P=3)",
-                     "kernel_ms": r["sweep_kernel_ms"], "bytes_per_launch": r["sweep_bytes_per_launch"]},
-        "time_to_1e-4_s": mean_time(r, "1e-04"),
-        "time_to_1e-8_s": mean_time(r, "1e-08"),
-        "forms": results,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fr3<3,2> fine-level fused residual + element-Jacobi sweep (FP32 blocks)",
+                     "kernel_ms": mx["sweep_ms"], "bytes_per_launch": mx["sweep_bytes"],
+                     "bytes_per_dof_update": 4 * n0 + 24},
+        "time_to_1e-8_s": {"mixed": t_mx, "fp64": t_64},
+        "speedup_time_to_1e-8_mixed_over_fp64": (t_64 / t_mx) if t_64 else None,
+        "vcycles_per_solve": {"mixed": mx["vcycles"][0], "fp64": f64["vcycles"][0] if f64 else None},
+        "converged": all(s == 0 for s in mx["status"]) and (f64 is None or all(s == 0 for s in f64["status"])),
+        "fp64_form": ({"dof_updates_per_s": f64["dof_updates_per_s"], "sweep_ms": f64["sweep_ms"],
+                       "sweep_frac": f64["sweep_bytes"] / (f64["sweep_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "solves": f64["solves"]} if f64 else None),
+        "mixed_vs_fp64_rel_err_max": max(head["mixed_vs_fp64_rel_err"]) if "mixed_vs_fp64_rel_err" in head else None,
+        "fine_rebuild": {"ms_mixed": mx["rebuild_ms"], "ms_fp64": f64["rebuild_ms"] if f64 else None,
+                         "tflops_2n3_per_element_mixed": head["elements"] * 2.0 * n0 ** 3 / (mx["rebuild_ms"] * 1e-3) / 1e12},
     }
-    if "mixed" in finals and "fp64" in finals:
-        d = finals["fp64"]                     # offsets from the free stream
-        line["mixed_vs_fp64_rel_err"] = (np.linalg.norm((finals["mixed"] - finals["fp64"]).reshape(4, -1), axis=1)
-                                         / np.linalg.norm(d.reshape(4, -1), axis=1)).tolist()
-        t_m, t_f = mean_time(results["mixed"], "1e-04"), mean_time(results["fp64"], "1e-04")
-        line["speedup_time_to_1e-4_mixed_over_fp64"] = (t_f / t_m) if (t_m and t_f) else None
-    if not args.no_newton_krylov:
-        line["newton_krylov_vs_fas_64x64_P321_stage"] = newton_krylov_block(api, torch, levels, q0,
-                                                                            args.forms.split(","))
-        progress("Newton-Krylov against FAS")
-    if not args.no_small:
-        # time to the 1e-8 drop where it is reachable: the 8x8 P{2-1-0} ESDIRK2 vortex
-        m1, v1 = W.vortex_config1()
-        lv1, q1 = setup(m1, v1, (2, 1, 0))
-        w1 = torch.zeros((api.esdirk_stages(2),) + lv1[0].shape, dtype=torch.float64, device=dev)
-        small = {}
-        for form in args.forms.split(","):
-            _, _, _, sst, el = run_form(api, torch, lv1, q1, form, 2, DT, 5, 1, 2000, w1)
-            ttt, floors = time_to_tolerances(sst)
-            small[form] = {"elapsed_s": el, "stages": len(sst),
-                           "stages_converged_to_1e-8": sum(s["status"] == 0 for s in sst),
-                           "vcycles_per_stage": [s["n_vcycles"] for s in sst],
-                           "time_to_1e-8_s_mean": mean_time({"time_to_tol_s_per_stage": ttt}, "1e-08"),
-                           "time_to_1e-8_s_total": float(sum(s["seconds"] for s in sst))}
-        if "mixed" in small and "fp64" in small and small["mixed"]["time_to_1e-8_s_total"] > 0:
-            small["speedup_time_to_1e-8_mixed_over_fp64"] = (small["fp64"]["time_to_1e-8_s_total"]
-                                                             / small["mixed"]["time_to_1e-8_s_total"])
-        line["time_to_1e-8_8x8_P210_esdirk2"] = small
+    detail = {"headline": head}
+    if "vortex" in extras or "nk" in extras:
+        detail["vortex_64x64_P321_esdirk3"], vlevels, vq0 = vortex_block(
+            api, torch, ["mixed", "fp64"], 1, 1, args.vortex_vcycles, args.kernel_reps, not args.no_autotune)
+        progress("vortex 64x64")
+        if "nk" in extras:
+            detail["newton_krylov_vs_fas_64x64_P321_stage"] = newton_krylov_block(api, torch, vlevels, vq0,
+                                                                                  ["mixed", "fp64"])
+            progress("Newton-Krylov against FAS")
+        del vlevels, vq0
+    if "small" in extras:
+        detail["time_to_1e-8_8x8_P210_esdirk2"] = small_vortex_block(api, torch, ["mixed", "fp64"])
         progress("8x8 time to 1e-8")
-    if not args.no_airfoil:
-        line["airfoil_128x64_P4_steady"] = airfoil_block(api, torch, args.forms.split(","), args.airfoil_vcycles,
-                                                         args.kernel_reps)
+    if "airfoil" in extras:
+        detail["airfoil_128x64_P4_steady"] = airfoil_block(api, torch, ["mixed", "fp64"], args.airfoil_vcycles,
+                                                           args.kernel_reps)
         progress("airfoil steady solves")
-    if not args.no_lines:
-        line["airfoil_128x64_P421_element_vs_line_jacobi"] = airfoil_lines_block(api, torch, args.airfoil_vcycles,
-                                                                                args.kernel_reps)
+    if "lines" in extras:
+        detail["airfoil_128x64_P421_element_vs_line_jacobi"] = airfoil_lines_block(api, torch, args.airfoil_vcycles,
+                                                                                  args.kernel_reps)
         progress("airfoil element against line Jacobi")
-    if not args.no_viscous:
-        line["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
+    if "viscous" in extras:
+        detail["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
         progress("viscous batch")
-    if not args.no_sphere:
-        if not args.no_sphere_p2:
-            line["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, args.forms.split(","),
-                                                                    args.sphere_vcycles, args.kernel_reps)
-            progress("sphere P{2-1-0}")
-        if not args.no_sphere_p3:
-            line["sphere_cubed_16x16x24_P3_steady"] = sphere_block(
-                api, torch, args.forms.split(","), args.sphere_vcycles, args.kernel_reps, plev=(3, 2, 1, 0),
-                nsm=(5, 10, 20, 20), profile_pmc=PROFILE_PMC_SPHERE3, cfl_init=30.0)
-            progress("sphere P{3-2-1-0}")
+    if "sphere2" in extras:
+        detail["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, ["mixed", "fp64"], args.sphere_vcycles,
+                                                                 args.kernel_reps)
+        progress("sphere P{2-1-0}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
         progress("cpu baseline")
+    if args.detail:
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+            with open(args.detail, "w") as fh:
+                json.dump({"line": line, **detail}, fh, indent=1)
+        except OSError as e:
+            print(f"bench: could not write {args.detail}: {e}", file=sys.stderr)
+    for k, v in detail.items():
+        if k != "headline":
+            print(f"bench: {k}: {json.dumps(v)}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

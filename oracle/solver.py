@@ -265,8 +265,8 @@ class PMGSolver:
         sqrt(machine epsilon) times the absolute state (1e-3 for pressures near 6e4 at Ma 0.005). The right preconditioner is one FAS V-cycle of Sec. 3 started at q_m on
         F(q) - S_0 = 0 with S_0 = F(q_m) - e v, whose first sweep moves q_m by e D^{-1} v:
         M^{-1} v = (V(q_m) - q_m)/e with e = pc_rel sqrt(N) (||v|| = 1). Orthogonalisation: classical
-        Gram-Schmidt applied twice, the norm of the result from the second pass's dot products
-        (||w - V c||^2 = ||w||^2 - ||c||^2 for orthonormal V). dtau follows the SER law of eq. (31) and the blocks are rebuilt
+        Gram-Schmidt applied twice, then the norm of the orthogonalised vector itself.
+        dtau follows the SER law of eq. (31) and the blocks are rebuilt
         as in stage_solve (the coarse ones in the first preconditioner V-cycle of a refresh step).
         The history holds ||F|| per Newton step; st.krylov counts the directions taken."""
         o = self.opts
@@ -332,11 +332,10 @@ class PMGSolver:
                 c = np.array([float(np.sum(Vi * w)) for Vi in V])       # classical Gram-Schmidt
                 w = w - sum(ci * Vi for ci, Vi in zip(c, V))
                 H[:j + 1, j] += c
-                c = np.array([float(np.sum(Vi * w)) for Vi in V])       # applied again; its
-                ww = float(np.sum(w * w))                               # dots come with ||w||^2
+                c = np.array([float(np.sum(Vi * w)) for Vi in V])       # applied again
                 w = w - sum(ci * Vi for ci, Vi in zip(c, V))
                 H[:j + 1, j] += c
-                H[j + 1, j] = math.sqrt(max(ww - float(np.sum(c * c)), 0.0))
+                H[j + 1, j] = math.sqrt(float(np.sum(w * w)))
                 for i in range(j):                          # earlier rotations, then a new one
                     a, b = H[i, j], H[i + 1, j]
                     H[i, j], H[i + 1, j] = cs[i] * a + sn[i] * b, -sn[i] * a + cs[i] * b

@@ -128,3 +128,37 @@ def test_common_flux_is_upwind_for_supersonic_unpreconditioned_flow():
     assert errs[0] / errs[1] > 3.5      # second order in the jump
     b = a + 1e-3 * dirn                  # the downwind-weighted mean would be first order
     assert np.max(np.abs(G.common_flux(a, b, S, gas) - G.normal_flux(b, S, gas))) > 10 * errs[0]
+
+
+def _mach_state(ma, c=100.0, d=2, gas=GAS):
+    """Primitive states (p, u, T) of sound speed c (T = c^2 / (gamma R)) and speed |u| = ma c,
+    the velocity along a fixed oblique direction."""
+    T = c * c / (gas.gamma * gas.rgas)
+    ma = np.asarray(ma, float)
+    direction = np.array([0.6, 0.8]) if d == 2 else np.array([2.0, -3.0, 6.0]) / 7.0
+    u = (ma * c)[:, None] * direction[None, :]
+    return np.concatenate([np.full((ma.size, 1), 1.0e4), u, np.full((ma.size, 1), T)], axis=1)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_epsilon_closed_form(d):
+    """Eq. (11): eps = min(1, max(kappa Ma_inf, Ma)) with the cut-off, eps = min(1, Ma) without
+    (Sec. 4.1), and U_r = eps c in Theta of eq. (10). The states have Ma = |u|/c exactly; with
+    kappa = 2, Ma_inf = 0.01 the cut-off is 0.02, so a swapped min/max, kappa applied to the
+    local Mach number (max(Ma_inf, kappa Ma) = 0.03 at Ma = 0.015) or the cut-off applied in the
+    local mode all fail."""
+    ma = np.array([5e-4, 0.015, 0.02, 0.3, 0.999, 1.0, 2.0])
+    q = _mach_state(ma, d=d)
+    local = G.Gas(eps_mode="local")
+    cut = G.Gas(eps_mode="cutoff", ma_inf=0.01, kappa=2.0)
+    want_local = np.array([5e-4, 0.015, 0.02, 0.3, 0.999, 1.0, 1.0])
+    want_cut = np.array([0.02, 0.02, 0.02, 0.3, 0.999, 1.0, 1.0])
+    assert np.max(np.abs(G.epsilon(q, local) - want_local) / want_local) < 1e-14
+    assert np.max(np.abs(G.epsilon(q, cut) - want_cut) / want_cut) < 1e-14
+    # the reference velocity enters Gamma through Theta = 1/U_r^2 - rho_T/(rho C_p), U_r = eps c
+    for gas, want in ((local, want_local), (cut, want_cut)):
+        rho = q[:, 0] / (gas.rgas * q[:, -1])
+        rho_T = -q[:, 0] / (gas.rgas * q[:, -1] ** 2)
+        theta = 1.0 / (want * 100.0) ** 2 - rho_T / (rho * gas.cp)
+        gam = G.preconditioner(q, gas)
+        assert np.max(np.abs(gam[:, 0, 0] - theta) / theta) < 1e-13

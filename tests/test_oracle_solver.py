@@ -163,3 +163,51 @@ def test_esdirk_driver_temporal_order(name, order):
     # steps of T/4 .. T/16 are pre-asymptotic for the fourth-order scheme (measured 4.34); the band
     # still separates it from third and fifth order
     assert abs(rate - order) < (0.4 if order == 4 else 0.2), rate
+
+
+def _level_jacobian(level, x, c_mass):
+    """Dense dF/dq of a whole level (every element, the neighbours included) by complex step."""
+    n = x.size
+    A = np.zeros((n, n))
+    for k in range(n):
+        z = x.astype(complex).ravel()
+        z[k] += 1e-30j
+        A[:, k] = level.stage_residual(z.reshape(x.shape), c_mass).imag.ravel() / 1e-30
+    return A
+
+
+@pytest.mark.parametrize("Pf,Pc", [(2, 1), (3, 1)])
+def test_two_level_fas_correction_is_linear_coarse_solve(Pf, Pc):
+    """Sec. 3 with two levels, no fine sweeps and the coarse level solved to convergence: the FAS
+    correction added to the fine state, I(q^a_1 - q^b_1), must be I A_c^{-1} P d for a small
+    defect d = S_0 - F_0(q), with A_c the Jacobian of the coarse residual at the restricted state
+    P q (here a dense complex-step Jacobian of the whole coarse level). The defect is made small
+    by the source so that the problem is linear to ~1e-8; Ma 0.3 with a large mass term lets
+    element Jacobi converge on the coarse level in 60 sweeps. A sign error on P d, a missing or
+    wrong restriction of the state or the defect, or a wrong prolongation fails it; the test also
+    shows that A_c at a different coarse state moves the correction by far more than the bound."""
+    mesh = W.periodic_quad_mesh(3, 10.0, jitter=0.1, seed=5)
+    vs = W.VortexSpec(length=10.0, ma_inf=0.3)
+    cm = 10.0
+    sol = S.PMGSolver(mesh, GAS, S.PMGOptions(p_levels=(Pf, Pc), n_smooth=(0, 60), dtau_init=1e8))
+    lf, lc = sol.levels
+    q = vs.state(lf.geo.xy[..., 0], lf.geo.xy[..., 1])
+    rng = np.random.default_rng(11)
+    src = -lf.stage_residual(q, cm) + 1e-6 * rng.standard_normal(q.shape) * np.abs(lf.residual(q)).max(axis=(0, 1))
+    sol.c_mass, sol.src, sol.dtau = cm, src, 1e8
+    sol.refresh_now = True
+    q1 = sol.vcycle(0, q, None)
+    d = -lf.stage_residual(q, cm, src)
+    qb = S.restrict(q, Pf, Pc)
+    Pd = S.restrict(d, Pf, Pc)
+    C = np.linalg.solve(_level_jacobian(lc, qb, cm), Pd.ravel()).reshape(qb.shape)
+    want = S.prolong(C, Pc, Pf)
+    den = np.linalg.norm(want.reshape(-1, 4), axis=0)
+    err = np.linalg.norm((q1 - q - want).reshape(-1, 4), axis=0) / den
+    assert np.all(err < 1e-6), err
+    # power: the same correction with the coarse Jacobian taken at the element-mean velocity
+    qw = qb.copy()
+    qw[..., 1:3] = qb[..., 1:3].mean(axis=1, keepdims=True)
+    Cw = np.linalg.solve(_level_jacobian(lc, qw, cm), Pd.ravel()).reshape(qb.shape)
+    moved = np.linalg.norm((S.prolong(Cw, Pc, Pf) - want).reshape(-1, 4), axis=0) / den
+    assert np.all(moved > 100 * 1e-6), moved
