@@ -5,6 +5,8 @@
 //
 // Inverse blocks are stored as [n][Ne][npad]: W[c][e][r] = D_e^{-1}[r][c], rows padded to
 // npad = 4 ceil(n/4).
+#include <type_traits>
+
 #include "hex_points.hpp"
 #include "internal.hpp"
 #include "jac3.hpp"
@@ -364,42 +366,77 @@ __global__ void __launch_bounds__(256) k_point_jac3(JacArgs3 a, double* __restri
   element_point_jacobians3<P, 256>(a, e, sq, base, base + 3 * NP * NV * NV, base + 4 * NP * NV * NV);
 }
 
-// Large element blocks (n = 320 at P = 3): the FP64 block is larger than a compute unit's LDS and
-// registers together, so each workgroup owns a slot of a global work array (n x n column-major,
-// X[c n + r]) and takes elements in turn, one thread per row. The element's pointwise derivatives
-// come from k_point_jac3 (global memory, copied to LDS), the block is assembled row by row into
-// the slot and inverted by Gauss-Jordan elimination with partial pivoting on the row-scaled block,
-// in panels of B columns:
+// Large element blocks (n = 320 at P = 3): the block is larger than a compute unit's LDS, so each
+// workgroup owns a slot of a global work array (n x n row-major, X[r n + c], in the precision of
+// the stored inverse, T = float or double) and takes elements in turn, one thread per row. The
+// element's pointwise derivatives come from k_point_jac3 (global memory, copied to LDS), the block
+// is assembled row by row into the slot in FP64, row-scaled by powers of two, rounded to T and
+// inverted by Gauss-Jordan elimination with partial pivoting in T arithmetic, in panels of B
+// columns:
 //   * the panel's B steps run on each row's B panel entries held in registers; the pivot search and
-//     the broadcast of the pivot row go through LDS as in the register kernel. Eliminating in place
-//     (the pivot column's slot receives the transformed unit vector) leaves in the panel the columns
-//     e_p + u of T = I + U E^T, T the product of the panel's elementary transforms, E the unit
-//     vectors of the panel's pivot rows;
+//     the broadcast of the pivot row go through LDS as in the register kernel. Pivot rows stay
+//     unnormalised (every row keeps the scale of its pivot, divided out once at the end), so a
+//     step is one FMA per entry. Eliminating in place (the pivot column's slot receives the
+//     transformed unit vector) leaves in the panel the columns e_p + u of T = I + U E^T, T the
+//     product of the panel's elementary transforms, E the unit vectors of the panel's pivot rows;
 //   * every other column c then takes x_c += U x_c[pivot rows] (U = panel minus the pivot unit
-//     vectors), a rank-B update streamed through the slot in groups of 16 columns on the FP64
-//     matrix cores (16x16x4 tiles), every wave reading its old values before a barrier and
-//     writing after it.
+//     vectors), a rank-B update on the matrix cores (16x16x4 tiles, FP32 or FP64 with
+//     accumulation in the same precision): the pivot rows' old values (contiguous in the
+//     row-major slot) are gathered into LDS first, then every wave streams its own rows.
 // Barriers order the slot's accesses across the lanes of a wave. At the end, physical row p_i of
-// the slot is row i of the inverse with its columns in pivot order:
-// D_e^{-1}[i][p_m] = X[m n + p_i] s_{p_m}, s the row scales.
-template <int P>
+// the slot is row i of the inverse times its pivot f_i, with its columns in pivot order:
+// D_e^{-1}[i][p_m] = X[p_i n + m] s_{p_m} / f_i, s the row scales.
+template <int P, int B_>
 struct Big3 {
   static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
   static constexpr int NPAD = (N + 3) / 4 * 4;
-  static constexpr int B = 32, G = 16;   // panel width; columns per matrix-core tile
+  static constexpr int B = B_, G = 16;   // panel width; columns per matrix-core tile
   static constexpr int NT = N, NW = NT / 64;
   static constexpr int ASM = NV * NP + 4 * NP * NV * NV + 6 * NF * NV * NV;   // sq, sA, sDg, sB
   static constexpr int GJ = 2 * NW * B;                                       // pivot rows
   static constexpr int POOL = ASM > GJ ? ASM : GJ;
-  static_assert(N % 64 == 0 && N % B == 0 && B % G == 0 && B % 4 == 0 && G == 16,
-                "whole waves of four 16-row tiles, panels and 16-column groups");
+  // columns per gathered chunk of pivot rows in the update: 32 x 320 FP32 values at most, so
+  // that the B rows of a chunk (row stride padded by 64 bytes) fit in the pool
+  template <typename T>
+  static constexpr int chunk() { return N * 32 * 4 / (B * (int)sizeof(T)); }
+  static_assert(N % 64 == 0 && N % B == 0 && B % G == 0 && B % 4 == 0 && G == 16, "whole tiles and panels");
+  static_assert(N % chunk<float>() == 0 && N % chunk<double>() == 0 && chunk<float>() % G == 0 &&
+                chunk<double>() % G == 0, "whole 16-column groups per chunk");
+  static_assert(B * (chunk<float>() + 16) * 4 <= POOL * 8 && B * (chunk<double>() + 8) * 8 <= POOL * 8,
+                "gathered pivot rows fit the pool");
   static_assert(N <= 1023, "pivot keys carry the row in 10 bits");
 };
 
-template <int P>
-__global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __restrict__ ws,
-                                                         const double* __restrict__ pj) {
-  using C = Big3<P>;
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// 32-bit pivot key of |f|: its upper bits (the FP32 pattern, or the upper word of the FP64 one)
+// with the low 10 bits replaced by 1023 - row, so that the wave maximum also names the row
+__device__ __forceinline__ unsigned pivot_key(float f, int r) {
+  return (__float_as_uint(fabsf(f)) & ~0x3FFu) | (unsigned)(1023 - r);
+}
+__device__ __forceinline__ unsigned pivot_key(double f, int r) {
+  return (((unsigned)__double2hiint(fabs(f))) & ~0x3FFu) | (unsigned)(1023 - r);
+}
+
+// One 16x16x4 matrix-core step in T, and the row i of the 16 x 16 result held by accumulator
+// register v in lane group lk: D[i][j] sits in lane j + 16 (i / 4), register i % 4 for FP32 and
+// in lane j + 16 (i % 4), register i / 4 for FP64 (both checked on gfx950)
+__device__ __forceinline__ flt4 mfma16x16x4(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ int acc_row(int lk, int v) {
+  return sizeof(T) == 4 ? 4 * lk + v : lk + 4 * v;
+}
+
+template <int P, typename T, int BW>
+__global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* __restrict__ ws,
+                                                             const double* __restrict__ pj) {
+  using C = Big3<P, BW>;
+  using T4 = typename std::conditional<sizeof(T) == 4, flt4, dbl4>::type;
   constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, B = C::B, G = C::G, NW = C::NW,
                 NT = C::NT;
   __shared__ double pool[C::POOL];
@@ -410,61 +447,120 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
   double* sA = sq + NV * NP;
   double* sDg = sA + 3 * NP * NV * NV;
   double* sB = sDg + NP * NV * NV;
-  double* slot = pool;              // [2][NW][B], after the assembly
+  T* slot = reinterpret_cast<T*>(pool);   // [2][NW][B], after the assembly
 
   const int ne = a.lv.ne;
   const int r = threadIdx.x;
   const int lane = r & 63, wv = r >> 6;
   const size_t sstride = (size_t)NP * ne;
-  double* X = ws + (size_t)blockIdx.x * N * N;
+  T* X = ws + (size_t)blockIdx.x * N * N;
   const int pp = r / NV, v = r % NV;
   const int ii = pp % (P + 1), jj = (pp / (P + 1)) % (P + 1), kk = pp / ((P + 1) * (P + 1));
   bool bad = false;
+  // the 1-D operators in LDS: D (row-major), then g_L', g_R', l(-1), l(+1)
+  constexpr int kGL = (P + 1) * (P + 1), kGR = kGL + P + 1, kLM = kGR + P + 1, kLP = kLM + P + 1;
+  __shared__ double sop[kLP + P + 1];
+  if (r < (P + 1) * (P + 1)) sop[r] = a.ops.D[r];
+  if (r <= P) {
+    sop[kGL + r] = a.ops.gL[r];
+    sop[kGR + r] = a.ops.gR[r];
+    sop[kLM + r] = a.ops.lm[r];
+    sop[kLP + r] = a.ops.lp[r];
+  }
 
   for (int e = blockIdx.x; e < ne; e += gridDim.x) {
     __syncthreads();                        // the previous element is done with the pool and sperm
     {                                       // sA, sDg, sB are contiguous in the pool
-      const double* src = pj + (size_t)e * jac3_point_elems(P);
-      for (int t = r; t < (int)jac3_point_elems(P); t += NT) sA[t] = src[t];
+      constexpr int NPJ = (int)jac3_point_elems(P), U = 4;
+      const double* src = pj + (size_t)e * NPJ;
+      for (int t0 = r; t0 < NPJ; t0 += U * NT) {   // U loads in flight per thread
+        double vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = (t0 + u * NT < NPJ) ? src[t0 + u * NT] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (t0 + u * NT < NPJ) sA[t0 + u * NT] = vv[u];
+      }
     }
     __syncthreads();
 
-    // row r of D_e: the largest entry lies on the row point's three tensor lines
+    // row r of D_e: only the 10 points of the row point's three tensor lines couple to it, so
+    // the row is cleared and those 50 entries (the point itself gathering all three lines and
+    // the diagonal term, summed in the order x, y, z) are written over it; the largest entry sets
+    // the row's power-of-two scale
     const double ijac = a.lv.met[9 * sstride + (size_t)pp * ne + e];
+    const int ids[3] = {ii, jj, kk};
+    auto line_val = [&](int d, int m, int w) {       // the line-d term of column (point on d at m, w)
+      const int id = ids[d];
+      const int ss = d == 0 ? m + (P + 1) * (jj + (P + 1) * kk)
+                            : d == 1 ? ii + (P + 1) * (m + (P + 1) * kk) : ii + (P + 1) * (jj + (P + 1) * m);
+      const int kf = d == 0 ? jj + (P + 1) * kk : d == 1 ? ii + (P + 1) * kk : ii + (P + 1) * jj;
+      const double gl = sop[kGL + id] * sop[kLM + m], gr = sop[kGR + id] * sop[kLP + m];
+      const double cv = sop[id * (P + 1) + m] - gl - gr;
+      return cv * sA[d * NP * NV * NV + (ss * NV + v) * NV + w] +
+             gl * sB[(((2 * d) * NF + kf) * NV + v) * NV + w] + gr * sB[(((2 * d + 1) * NF + kf) * NV + v) * NV + w];
+    };
+    auto diag_val = [&](int w) {
+      double acc = 0.0;
+#pragma unroll 1
+      for (int d = 0; d < 3; ++d) acc += line_val(d, ids[d], w);
+      return acc * ijac + sDg[(pp * NV + v) * NV + w];
+    };
     double mx = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      for (int m = 0; m <= P; ++m) {
-        const int ss = d == 0 ? m + (P + 1) * (jj + (P + 1) * kk)
-                              : d == 1 ? ii + (P + 1) * (m + (P + 1) * kk) : ii + (P + 1) * (jj + (P + 1) * m);
-        for (int w = 0; w < NV; ++w) mx = fmax(mx, fabs(block_entry3<P>(a.ops, sA, sDg, sB, pp, v, ss, w, ijac)));
-      }
-    }
+#pragma unroll 1
+    for (int w = 0; w < NV; ++w) mx = fmax(mx, fabs(diag_val(w)));
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d)
+#pragma unroll 1
+      for (int m = 0; m <= P; ++m)
+        if (m != ids[d])
+          for (int w = 0; w < NV; ++w) mx = fmax(mx, fabs(line_val(d, m, w) * ijac));
     int ex = 0;
     frexp(mx, &ex);
     const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
     sscl[r] = scl;
-    for (int c = 0; c < N; ++c) {
-      const double dval = block_entry3<P>(a.ops, sA, sDg, sB, pp, v, c / NV, c % NV, ijac);
-      X[(size_t)c * N + r] = dval * scl;
-      if (a.D_out) a.D_out[((size_t)e * N + r) * N + c] = dval;
+    T* xr = X + (size_t)r * N;
+    double* dr = a.D_out ? a.D_out + ((size_t)e * N + r) * N : nullptr;
+#pragma unroll 8
+    for (int c = 0; c < N; ++c) xr[c] = (T)0;
+    if (dr)
+      for (int c = 0; c < N; ++c) dr[c] = 0.0;
+#pragma unroll 1
+    for (int w = 0; w < NV; ++w) {
+      const double dval = diag_val(w);
+      xr[pp * NV + w] = (T)(dval * scl);
+      if (dr) dr[pp * NV + w] = dval;
     }
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d)
+#pragma unroll 1
+      for (int m = 0; m <= P; ++m) {
+        if (m == ids[d]) continue;
+        const int ss = d == 0 ? m + (P + 1) * (jj + (P + 1) * kk)
+                              : d == 1 ? ii + (P + 1) * (m + (P + 1) * kk) : ii + (P + 1) * (jj + (P + 1) * m);
+        for (int w = 0; w < NV; ++w) {
+          const double dval = line_val(d, m, w) * ijac;
+          xr[ss * NV + w] = (T)(dval * scl);
+          if (dr) dr[ss * NV + w] = dval;
+        }
+      }
     __syncthreads();                        // the pool now holds pivot rows and staged values
 
     bool used = false;
     int my_step = 0;
+    T my_inv = (T)1;
     for (int k0 = 0; k0 < N; k0 += B) {
-      double row[B];
+      T row[B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) row[j] = X[(size_t)(k0 + j) * N + r];
+      for (int j = 0; j < B; ++j) row[j] = X[(size_t)r * N + k0 + j];
       // column cycling: before step j the row holds columns k0 + j .. k0 + B - 1, then the slots
       // of steps 0 .. j - 1; each step consumes entry 0 and appends its own slot, so after the
       // panel the row holds the B slots in step order
 #pragma unroll 1
       for (int j = 0; j < B; ++j) {
         const int par = j & 1;
-        const double fv = row[0];
-        const unsigned key =
-            used ? 0u : ((((unsigned)__double2hiint(fabs(fv))) & ~0x3FFu) | (unsigned)(1023 - r));
+        const T fv = row[0];
+        const unsigned key = used ? 0u : pivot_key(fv, r);
         const unsigned wkey = wave_max3(key);
         if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {
 #pragma unroll
@@ -485,80 +581,97 @@ __global__ void __launch_bounds__(Big3<P>::NT) k_jac3_big(JacArgs3 a, double* __
           bad = true;
           pr = 0;
         }
-        const double* prw = slot + (par * NW + win) * B;
-        double piv = prw[0];
-        if (piv == 0.0 || !isfinite(piv)) {
+        const T* prw = slot + (par * NW + win) * B;
+        T piv = prw[0];
+        if (piv == (T)0 || !isfinite(piv)) {
           bad = true;
-          piv = 1.0;
+          piv = (T)1;
         }
-        const double ip = 1.0 / piv;
+        const T ip = (T)1 / piv;
         const bool is_p = (r == pr);
         if (r == 0) sperm[k0 + j] = pr;
         if (is_p) {
           used = true;
           my_step = k0 + j;
+          my_inv = ip;
         }
-        const double g = is_p ? 0.0 : fv * ip;
-        const double mul = is_p ? ip : 1.0;
+        const T g = is_p ? (T)0 : fv * ip;
 #pragma unroll
-        for (int c = 0; c < B - 1; ++c) row[c] = fma(-g, prw[c + 1], row[c + 1] * mul);
-        row[B - 1] = is_p ? ip : -g;
+        for (int c = 0; c < B - 1; ++c) row[c] = fma(-g, prw[c + 1], row[c + 1]);
+        row[B - 1] = is_p ? (T)1 : -g;
       }
 #pragma unroll
-      for (int j = 0; j < B; ++j) X[(size_t)(k0 + j) * N + r] = row[j];
+      for (int j = 0; j < B; ++j) X[(size_t)r * N + k0 + j] = row[j];
       __syncthreads();                      // the panel is visible to the other lanes of each wave
-      // Rank-B update of every other column on the FP64 matrix cores, wave wv taking rows
-      // 64 wv .. 64 wv + 63 as four tiles of 16: per 16 columns cg.., D = X_p^T U^T + C with
-      //   A[i][k] = X_p[k][i]: lane i + 16 k holds the old value of column cg + i in the pivot row
-      //             of step k0 + 4 s + k,
-      //   B[k][j] = U[r0 + j][4 s + k]: lane j + 16 k (U = panel minus the pivot unit vectors),
-      //   C, D[i][j] = X[cg + i][r0 + j]: lane j + 16 (i mod 4), register i / 4,
-      // so that the 16 lanes of a register cover 16 consecutive rows of one column.
+      // Rank-B update of every other column on the matrix cores, wave wv taking rows
+      // 64 wv .. 64 wv + 63 as four tiles of 16: per 16 columns cg.., D = U X_p + C with
+      //   A[i][k] = U[r0 + i][4 s + k]: lane i + 16 k (U = panel minus the pivot unit vectors),
+      //   B[k][j] = X_p[4 s + k][cg + j]: lane j + 16 k, the old value of column cg + j in the
+      //             pivot row of step k0 + 4 s + k, from LDS,
+      //   C, D[i][j] = X[r0 + i][cg + j]: lane j + 16 lk, register v with i = acc_row(lk, v),
+      // so that the 16 lanes of a register cover 64 (FP32) or 128 (FP64) contiguous bytes of one
+      // row. The pivot rows' old values of a chunk of CW columns are first gathered into LDS
+      // (xp, row stride CWP), so that after one barrier every wave streams its own rows.
       const int lr = lane & 15, lk = lane >> 4;
-      double uop[4][B / 4];
+      T uop[4][B / 4];
 #pragma unroll
-      for (int T = 0; T < 4; ++T) {
+      for (int TT = 0; TT < 4; ++TT) {
 #pragma unroll
         for (int s4 = 0; s4 < B / 4; ++s4) {
-          const int row_ = 64 * wv + 16 * T + lr, m = 4 * s4 + lk;
-          const double u = X[(k0 + m) * N + row_];
-          uop[T][s4] = (sperm[k0 + m] == row_) ? u - 1.0 : u;
+          const int row_ = 64 * wv + 16 * TT + lr, m = 4 * s4 + lk;
+          const T u = X[(size_t)row_ * N + k0 + m];
+          uop[TT][s4] = (sperm[k0 + m] == row_) ? u - (T)1 : u;
         }
       }
-      for (int cg = 0; cg < N; cg += G) {
-        if (cg >= k0 && cg < k0 + B) continue;
-        double xop[B / 4];
-#pragma unroll
-        for (int s4 = 0; s4 < B / 4; ++s4) xop[s4] = X[(cg + lr) * N + sperm[k0 + 4 * s4 + lk]];
-        dbl4 acc[4];
-#pragma unroll
-        for (int T = 0; T < 4; ++T) {
-#pragma unroll
-          for (int v2 = 0; v2 < 4; ++v2) acc[T][v2] = X[(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr];
+      constexpr int CW = C::template chunk<T>(), CWP = CW + 64 / (int)sizeof(T);
+      T* xp = reinterpret_cast<T*>(pool);   // [B][CWP]; the panel's pivot rows are done with
+      for (int c0 = 0; c0 < N; c0 += CW) {
+        __syncthreads();                    // LDS free (pivot slots, or the previous chunk)
+        for (int t = r; t < B * CW; t += NT) {
+          const int k = t / CW, c = t % CW;
+          xp[k * CWP + c] = X[(size_t)sperm[k0 + k] * N + c0 + c];
         }
-        __syncthreads();                    // every wave holds its old values before any wave stores
+        __syncthreads();                    // every old pivot-row value is in LDS before any store
+        for (int cg = c0; cg < c0 + CW; cg += G) {
+          if (cg >= k0 && cg < k0 + B) continue;
+          T4 acc[4];
 #pragma unroll
-        for (int s4 = 0; s4 < B / 4; ++s4) {
+          for (int TT = 0; TT < 4; ++TT) {
 #pragma unroll
-          for (int T = 0; T < 4; ++T) acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(xop[s4], uop[T][s4], acc[T], 0, 0, 0);
-        }
+            for (int v2 = 0; v2 < 4; ++v2)
+              acc[TT][v2] = X[(size_t)(64 * wv + 16 * TT + acc_row<T>(lk, v2)) * N + cg + lr];
+          }
 #pragma unroll
-        for (int T = 0; T < 4; ++T) {
+          for (int s4 = 0; s4 < B / 4; ++s4) {
+            const T xb = xp[(4 * s4 + lk) * CWP + (cg - c0) + lr];
 #pragma unroll
-          for (int v2 = 0; v2 < 4; ++v2) X[(cg + lk + 4 * v2) * N + 64 * wv + 16 * T + lr] = acc[T][v2];
+            for (int TT = 0; TT < 4; ++TT) acc[TT] = mfma16x16x4(uop[TT][s4], xb, acc[TT]);
+          }
+#pragma unroll
+          for (int TT = 0; TT < 4; ++TT) {
+#pragma unroll
+            for (int v2 = 0; v2 < 4; ++v2)
+              X[(size_t)(64 * wv + 16 * TT + acc_row<T>(lk, v2)) * N + cg + lr] = acc[TT][v2];
+          }
         }
       }
       __syncthreads();                      // the updated columns are visible before the next panel
     }
     __syncthreads();                        // sperm and sscl complete
-    for (int m = 0; m < N; ++m) {
-      const int col = sperm[m];
-      const double val = X[(size_t)m * N + r] * sscl[col];
-      const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
-      if (a.precision == 32)
-        static_cast<float*>(a.W)[o_] = (float)val;
-      else
-        static_cast<double*>(a.W)[o_] = val;
+    for (int m0 = 0; m0 < N; m0 += 16) {    // sixteen loads in flight per thread, then the stores
+      T xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xv[u] = X[(size_t)r * N + m0 + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int col = sperm[m0 + u];
+        const double val = (double)(xv[u] * my_inv) * sscl[col];
+        const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
+        if (a.precision == 32)
+          static_cast<float*>(a.W)[o_] = (float)val;
+        else
+          static_cast<double*>(a.W)[o_] = val;
+      }
     }
   }
   if (bad) *a.flag = 1;
@@ -594,7 +707,14 @@ hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, 
       const int grid = fac.ws_slots < L.ne ? fac.ws_slots : L.ne;
       double* pj = fac.ws + (size_t)fac.ws_slots * L.n * L.n;   // after the work slots
       hipLaunchKernelGGL(k_point_jac3<3>, dim3(L.ne), dim3(256), 0, st, a, pj);
-      hipLaunchKernelGGL(k_jac3_big<3>, dim3(grid), dim3(Big3<3>::NT), 0, st, a, fac.ws, (const double*)pj);
+      // the mixed form (FP32 inverses) eliminates in FP32 on the FP32 matrix cores, the plain form in FP64
+      // (panels of 32 columns)
+      if (fac.precision == 32)
+        hipLaunchKernelGGL((k_jac3_big<3, float, 32>), dim3(grid), dim3(Big3<3, 32>::NT), 0, st, a,
+                           reinterpret_cast<float*>(fac.ws), (const double*)pj);
+      else
+        hipLaunchKernelGGL((k_jac3_big<3, double, 32>), dim3(grid), dim3(Big3<3, 32>::NT), 0, st, a, fac.ws,
+                           (const double*)pj);
       return hipGetLastError();
     }
     default: return hipErrorInvalidValue;

@@ -63,17 +63,34 @@ def tolerance(floor):
     return np.maximum(PARITY_REL, 10.0 * floor)
 
 
-def fp32_solver_class():
-    """The oracle's PMG solver with the smoother's block inverses rounded to FP32 and the
-    block-vector products taken in FP32: the rounding the mixed-precision smoother introduces,
-    reproduced on the CPU so that its effect sizes the FP32 parity tolerance (at Ma <= 1e-3 the
-    temperature update amplifies it far beyond u_32)."""
+def fp32_inverse(D):
+    """Inverse of the block(s) D [..., n, n] computed in FP32: rows scaled by powers of two to a
+    largest entry in [1/2, 1) (exact), the scaled block rounded to FP32 and inverted by LAPACK in
+    FP32 with partial pivoting, the scales folded back. This reproduces the size of the error of an
+    FP32 elimination (the GPU's mixed form) on the CPU; returned in FP64."""
+    D = np.asarray(D, dtype=np.float64)
+    mx = np.max(np.abs(D), axis=-1)
+    s = np.ldexp(1.0, -np.frexp(np.where(mx > 0, mx, 1.0))[1])
+    inv32 = np.linalg.inv((D * s[..., :, None]).astype(np.float32)).astype(np.float64)
+    return inv32 * s[..., None, :]
+
+
+def fp32_solver_class(fp32_elimination=False):
+    """The oracle's PMG solver with the smoother's block inverses in FP32 and the block-vector
+    products taken in FP32: the rounding the mixed-precision smoother introduces, reproduced on
+    the CPU so that its effect sizes the FP32 parity tolerance (at Ma <= 1e-3 the temperature
+    update amplifies it far beyond u_32). With fp32_elimination the inverse itself is computed
+    in FP32 (``fp32_inverse``, as the large hexahedral blocks are on the GPU); otherwise the FP64
+    inverse is rounded to FP32."""
     from oracle import solver as OS
 
     class PMGSolverFP32(OS.PMGSolver):
         def smooth(self, l, q, S, nsweep):
             lev = self.levels[l]
-            winv = np.linalg.inv(self.D[l]).astype(np.float32)
+            if fp32_elimination:
+                winv = fp32_inverse(self.D[l]).astype(np.float32)
+            else:
+                winv = np.linalg.inv(self.D[l]).astype(np.float32)
             for _ in range(nsweep):
                 Fq = self.F(l, q, S).reshape(lev.ne, lev.n, 1).astype(np.float32)
                 dq = np.matmul(winv, Fq).astype(np.float64)
