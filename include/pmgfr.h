@@ -301,6 +301,16 @@ typedef struct {
                                      at the initial guess (pmg_dtau_min); dtau_init/dtau_max unused */
   double cfl_init;                /* 1e2 in Sec. 4.2                                             */
   double cfl_max;                 /* 1e5 in Sec. 4.2                                             */
+  int32_t stage_guess;            /* initial guess of an implicit stage in esdirk_step (the paper
+                                     states none): 0 the previous stage value, 1 the explicit
+                                     predictor q_c^n + dt (sum_j a_ij R_j + omega R_{i-1}) in
+                                     primitive variables. Use 1 once q^n is a solved time level
+                                     (R(q^n) is then the discrete time derivative): from such a
+                                     state the previous stage value starts too close to the
+                                     solution for the relative tolerance and the SER law. From an
+                                     unsolved initial condition R(q^n) carries the scheme's
+                                     truncation error and the predictor is far off: use 0.
+                                     esdirk_stage_solve starts from the q it is given         */
 } pmg_solve_opts;
 
 typedef struct {

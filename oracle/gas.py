@@ -76,6 +76,15 @@ def conservative(q, gas: Gas):
                            (rho * specific_energy(q, gas))[..., None]], axis=-1)
 
 
+def primitive(qc, gas: Gas):
+    """Inverse of ``conservative``: (rho, rho u_i, rho E) -> (p, u_i, T) with p from the total
+    energy, p = (gamma - 1)(rho E - rho |u|^2 / 2), and T = p / (rho R) (ideal gas, Sec. 2.1)."""
+    rho = qc[..., 0]
+    u = qc[..., 1:-1] / rho[..., None]
+    p = (gas.gamma - 1.0) * (qc[..., -1] - 0.5 * rho * np.sum(u * u, axis=-1))
+    return np.concatenate([p[..., None], u, (p / (rho * gas.rgas))[..., None]], axis=-1)
+
+
 def sound_speed(q, gas: Gas):
     _, _, T = _split(q)
     return np.sqrt(gas.gamma * gas.rgas * T)

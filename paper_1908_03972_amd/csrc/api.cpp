@@ -1114,6 +1114,7 @@ pmg_status check_opts(const pmg_solve_opts* o) {
     return fail(PMG_E_ARG, "bad dtau range");
   }
   if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
+  if (o->stage_guess != 0 && o->stage_guess != 1) return fail(PMG_E_ARG, "stage_guess must be 0 or 1");
   return PMG_OK;
 }
 
@@ -1537,6 +1538,7 @@ extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, doubl
   const int s = esdirk_tableau(scheme, A);
   if (s == 0) return fail(PMG_E_ARG, "unknown ESDIRK scheme");
   if (!o || !q || !work || o->n_levels < 1 || !o->levels || !o->levels[0]) return fail(PMG_E_ARG, "null argument");
+  if (o->stage_guess != 0 && o->stage_guess != 1) return fail(PMG_E_ARG, "stage_guess must be 0 or 1");
   if (!(dt > 0.0)) return fail(PMG_E_ARG, "dt must be positive");
   pmg_level L0 = o->levels[0];
   const size_t ns = L0->state_elems();
@@ -1556,6 +1558,10 @@ extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, doubl
     for (int j = 0; j < i; ++j) a_row[j] = A[i * s + j];
     pmg_solve_stats* sti = (stats && i - 1 < n_stats) ? &stats[i - 1] : nullptr;
     double* R_out = (i < s - 1) ? const_cast<double*>(R[i]) : nullptr;
+    if (o->stage_guess == 1) {   // the explicit predictor; otherwise q holds the previous stage value
+      DeviceGuard guard(L0->device);
+      PMG_HIP(pmg::launch_stage_predict(*L0, qc_n, R.data(), a_row, i, dt, omega, q, as_stream(stream)));
+    }
     const pmg_status r = esdirk_stage_solve(o, omega, dt, qc_n, R.data(), a_row, i, q, R_out, sti, stream);
     if (r == PMG_E_NOT_CONVERGED) {
       // the last iterate stands in for the stage value; later stages still run
@@ -1785,6 +1791,9 @@ extern "C" pmg_status esdirk_step_batched(pmg_batch B, int32_t scheme, const dou
       Rout[c] = (i < s - 1) ? const_cast<double*>(R[c][i]) : nullptr;
       st_i[c] = stats ? stats[c * (s - 1) + (i - 1)] : pmg_solve_stats{};
       if (!stats) st_i[c].history = nullptr;
+      if (run[c] && B->opts[c].stage_guess == 1)   // the explicit predictor as the stage's guess
+        PMG_HIP(pmg::launch_stage_predict(*B->opts[c].levels[0], qc[c], R[c].data(), a_row, i, dt[c], omega, q[c],
+                                          caller));
     }
     if (pmg_status e = stage_solve_cases(B, run, om.data(), dt, qc.data(), Rp.data(), ar.data(), np.data(), q,
                                          Rout.data(), st_i.data(), status, caller))

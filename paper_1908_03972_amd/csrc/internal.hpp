@@ -136,6 +136,10 @@ hipError_t launch_copy(size_t n, const double* src, double* dst, hipStream_t st)
 hipError_t launch_prolong(const pmg_level_s& Lc, const pmg_level_s& Lf, const double* I1, const double* xa,
                           const double* xb, double* xf, int nvar, hipStream_t st);
 hipError_t launch_conservative(const pmg_level_s& L, const double* q, double* qc, hipStream_t st);
+// q = the explicit predictor of a stage, q_c^n + dt (sum_j a_j R_j + omega R_{n_prev - 1}), in
+// primitive offsets
+hipError_t launch_stage_predict(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
+                                int n_prev, double dt, double omega, double* q, hipStream_t st);
 hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
                                int n_prev, double dt, double c_mass, double* src, hipStream_t st);
 int residual_blocks(const pmg_level_s& L);

@@ -104,6 +104,9 @@ __global__ void __launch_bounds__(256) k_prolong(int ne, int nvar, int nc1, int 
 struct Ref4 {
   double v[4];
 };
+struct Ref5 {
+  double v[5];
+};
 
 __global__ void __launch_bounds__(256) k_conservative(int n_points, GasParams g, Ref4 ref,
                                                       const double* __restrict__ q, double* __restrict__ qc) {
@@ -132,6 +135,34 @@ __global__ void __launch_bounds__(256) k_stage_source(size_t n, StageSrc s, doub
   double acc = 0.0;
   for (int k = 0; k < s.n; ++k) acc += s.a[k] * s.R[k][idx];
   src[idx] = c_mass * (qc_n[idx] + dt * acc);
+}
+
+// Explicit predictor of an ESDIRK stage: q_c = q_c^n + dt sum_j a_j R_j (the coefficient of the
+// previous stage's residual carries the extra omega), converted to primitive variables
+// (p, u_i, T) with p = (gamma - 1)(rho E - rho |u|^2 / 2), T = p / (rho R), stored as offsets from
+// q_ref. One thread per solution point; nv = 4 (2-D) or 5 (3-D), layout [nv][npts].
+__global__ void __launch_bounds__(256) k_stage_predict(int npts, int nv, StageSrc s, double dt, GasParams gas,
+                                                       Ref5 ref, const double* __restrict__ qc_n,
+                                                       double* __restrict__ q) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npts) return;
+  double c[5];
+  for (int v = 0; v < nv; ++v) {
+    const size_t o = (size_t)v * npts + idx;
+    double acc = 0.0;
+    for (int k = 0; k < s.n; ++k) acc += s.a[k] * s.R[k][o];
+    c[v] = qc_n[o] + dt * acc;
+  }
+  const double rho = c[0];
+  double ke = 0.0;
+  for (int v = 1; v < nv - 1; ++v) {
+    const double u = c[v] / rho;
+    ke += u * c[v];
+    q[(size_t)v * npts + idx] = u - ref.v[v];
+  }
+  const double p = (gas.gamma - 1.0) * (c[nv - 1] - 0.5 * ke);
+  q[idx] = p - ref.v[0];
+  q[(size_t)(nv - 1) * npts + idx] = p / (rho * gas.rgas) - ref.v[nv - 1];
 }
 
 // norms[v] = sqrt(sum_b part[b][v]); norms[Nv] = sqrt(sum_v sum_b part[b][v]). One workgroup,
@@ -269,6 +300,24 @@ hipError_t launch_stage_source(const pmg_level_s& L, const double* qc_n, const d
   }
   const size_t n = L.state_elems();
   hipLaunchKernelGGL(k_stage_source, dim3(blocks_for(n)), dim3(256), 0, st, n, s, dt, c_mass, qc_n, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_predict(const pmg_level_s& L, const double* qc_n, const double* const* R, const double* a,
+                                int n_prev, double dt, double omega, double* q, hipStream_t st) {
+  if (n_prev < 1 || n_prev > kMaxStages) return hipErrorInvalidValue;
+  StageSrc s{};
+  s.n = n_prev;
+  for (int k = 0; k < n_prev; ++k) {
+    s.R[k] = R[k];
+    s.a[k] = a[k] + (k == n_prev - 1 ? omega : 0.0);
+  }
+  Ref5 ref{};
+  for (int k = 0; k < 5; ++k) ref.v[k] = L.q_ref[k];
+  const int npts = L.np * L.ne;
+  if (npts == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stage_predict, dim3(blocks_for((size_t)npts)), dim3(256), 0, st, npts, L.nv, s, dt, L.gas,
+                     ref, qc_n, q);
   return hipGetLastError();
 }
 
