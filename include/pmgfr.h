@@ -234,6 +234,21 @@ pmg_status pmg_line_blocks(pmg_factors F, const double* q, double dtau, double c
 pmg_status fr_residual(pmg_level L, const double* q, const double* src, const double* S, double c_mass,
                        double* F, double* norms, void* stream);
 
+/*
+ * fr_residual_noalloc — fr_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same arguments, kernels
+ * and results (F and norms bit for bit), but the per-workgroup partial sums of the norms are kept
+ * in a file-scope device array of the library (65536 doubles = 512 KiB per device, held until the
+ * process ends) instead of the level's workspace. Nothing is allocated or freed in the call.
+ * Limit: with norms, the level's workgroups times Nv must not exceed 65536 (every level of the
+ * configurations here fits, the 36 864-hexahedron P3 level uses 46 080); larger levels get
+ * PMG_E_ARG before any launch. Calls that overlap on one device (several host threads, or
+ * streams not ordered with each other) share that array and race: order them on one stream.
+ * Every call writes all the partials it reads, so nothing needs clearing between calls.
+ */
+pmg_status fr_residual_noalloc(pmg_level L, const double* q, const double* src, const double* S, double c_mass,
+                               double* F, double* norms, void* stream);
+
 /* q_c = (rho, rho u, rho v, rho E) of a stored primitive state (Sec. 2.1); q_c is absolute (not
  * offset). q, qc: device state layout. */
 pmg_status fr_conservative(pmg_level L, const double* q, double* qc, void* stream);

@@ -88,6 +88,7 @@ SIGNATURES = {
                                              C.POINTER(pmg_factors)]),
     "pmg_line_blocks": (pmg_status, [pmg_factors, DP, C.c_double, C.c_double, DP, DP, DP, C.c_void_p]),
     "fr_residual": (pmg_status, [pmg_level, DP, DP, DP, C.c_double, DP, DP, C.c_void_p]),
+    "fr_residual_noalloc": (pmg_status, [pmg_level, DP, DP, DP, C.c_double, DP, DP, C.c_void_p]),
     "fr_conservative": (pmg_status, [pmg_level, DP, DP, C.c_void_p]),
     "fr_element_jacobian": (pmg_status, [pmg_level, DP, C.c_double, C.c_double, DP, pmg_factors, C.c_void_p]),
     "ejacobi_sweep": (pmg_status, [pmg_level, pmg_factors, DP, DP, DP, C.c_double, C.c_int32, C.c_double, DP, DP,

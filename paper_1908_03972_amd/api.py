@@ -187,6 +187,15 @@ def fr_residual(level: Level, q, F, src=None, S=None, c_mass: float = 0.0, norms
                                 _norms_ptr(level, norms), _stream(stream)), "fr_residual")
 
 
+def fr_residual_noalloc(level: Level, q, F, src=None, S=None, c_mass: float = 0.0, norms=None, stream=None):
+    """fr_residual whose norm partials live in the library's static device scratch (the C entry
+    point allocates nothing)."""
+    A.check(A.lib().fr_residual_noalloc(level.handle, level.check_state(q, "q", False),
+                                        level.check_state(src, "src"), level.check_state(S, "S"), c_mass,
+                                        level.check_state(F, "F", False), _norms_ptr(level, norms),
+                                        _stream(stream)), "fr_residual_noalloc")
+
+
 def fr_conservative(level: Level, q, qc, stream=None):
     A.check(A.lib().fr_conservative(level.handle, level.check_state(q, "q", False),
                                     level.check_state(qc, "qc", False), _stream(stream)), "fr_conservative")

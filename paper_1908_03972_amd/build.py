@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PMGFR_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "hex_geometry.cpp", "fr_kernels.hip", "fr3_kernels.hip", "jac3_kernels.hip", "jac_kernels.hip",
-           "transfer_kernels.hip", "krylov_kernels.hip", "line_kernels.hip"]
+           "transfer_kernels.hip", "krylov_kernels.hip", "line_kernels.hip", "noalloc.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -321,6 +321,8 @@ pmg_status check_level(pmg_level L) {
 
 }  // namespace
 
+pmg_status pmg::set_error(pmg_status code, const char* msg) { return fail(code, msg); }
+
 // =============================================================================================
 extern "C" {
 

@@ -532,14 +532,14 @@ static ResArgs3 base_args3(const pmg_level_s& L) {
 }
 
 hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double* src, const double* S,
-                            double c_mass, double* F, bool want_norms, hipStream_t st) {
+                            double c_mass, double* F, bool want_norms, hipStream_t st, double* part) {
   ResArgs3 a = base_args3(L);
   a.q = q;
   a.src = src;
   a.S = S;
   a.c_mass = c_mass;
   a.F = F;
-  a.part = want_norms ? L.part : nullptr;
+  a.part = want_norms ? (part ? part : L.part) : nullptr;
   return launch_fr3<0>(L.P, a, L.ne, L.epw, st);
 }
 

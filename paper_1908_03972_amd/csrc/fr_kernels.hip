@@ -725,15 +725,15 @@ static ResArgs base_args(const pmg_level_s& L) {
 }
 
 hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* src, const double* S,
-                           double c_mass, double* F, bool want_norms, hipStream_t st) {
-  if (L.dim == 3) return launch_residual3(L, q, src, S, c_mass, F, want_norms, st);
+                           double c_mass, double* F, bool want_norms, hipStream_t st, double* part) {
+  if (L.dim == 3) return launch_residual3(L, q, src, S, c_mass, F, want_norms, st, part);
   ResArgs a = base_args(L);
   a.q = q;
   a.src = src;
   a.S = S;
   a.c_mass = c_mass;
   a.F = F;
-  a.part = want_norms ? L.part : nullptr;
+  a.part = want_norms ? (part ? part : L.part) : nullptr;
   if (L.visc) {
     const hipError_t e = launch_gradient_traces(L, q, st);
     if (e != hipSuccess) return e;

@@ -122,12 +122,18 @@ struct pmg_factors_s {
 namespace pmg {
 
 // kernel launchers (fr_kernels.hip, jac_kernels.hip, transfer_kernels.hip)
+// with want_norms, the per-workgroup partial sums of F^2 go to `part` (residual_blocks(L) x Nv
+// doubles) when given, else to the level's workspace
 hipError_t launch_residual(const pmg_level_s& L, const double* q, const double* src, const double* S,
-                           double c_mass, double* F, bool want_norms, hipStream_t st);
+                           double c_mass, double* F, bool want_norms, hipStream_t st, double* part = nullptr);
 hipError_t launch_sweep(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
                         const double* src, const double* S, double c_mass, double alpha, bool want_norms,
                         hipStream_t st);
 hipError_t launch_norm_finalize(const pmg_level_s& L, hipStream_t st);
+// norms[v] and the composite norm from nblk x nv partial sums into a caller's device array
+hipError_t launch_norm_finalize_to(const double* part, int nblk, int nv, double* norms, hipStream_t st);
+// records the message pmg_last_error returns (for entry points outside api.cpp)
+int32_t set_error(int32_t code, const char* msg);   // a pmg_status
 hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, double c_mass, double* D_out,
                            pmg_factors_s& fac, hipStream_t st);
 hipError_t launch_restrict(const pmg_level_s& Lf, const pmg_level_s& Lc, const double* R1, const double* xf,
@@ -157,7 +163,7 @@ int residual_blocks3(const pmg_level_s& L);
 int default_epw3(int P);
 int epw3_candidates(int P, int* out);
 hipError_t launch_residual3(const pmg_level_s& L, const double* q, const double* src, const double* S,
-                            double c_mass, double* F, bool want_norms, hipStream_t st);
+                            double c_mass, double* F, bool want_norms, hipStream_t st, double* part = nullptr);
 hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const double* q_in, double* q_out,
                          const double* src, const double* S, double c_mass, double alpha, bool want_norms,
                          hipStream_t st);

@@ -322,7 +322,11 @@ hipError_t launch_stage_predict(const pmg_level_s& L, const double* qc_n, const 
 }
 
 hipError_t launch_norm_finalize(const pmg_level_s& L, hipStream_t st) {
-  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, L.part, residual_blocks(L), L.nv, L.norms);
+  return launch_norm_finalize_to(L.part, residual_blocks(L), L.nv, L.norms, st);
+}
+
+hipError_t launch_norm_finalize_to(const double* part, int nblk, int nv, double* norms, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, part, nblk, nv, norms);
   return hipGetLastError();
 }
 
