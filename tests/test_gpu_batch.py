@@ -140,3 +140,50 @@ def test_batch_rejects_shared_levels():
     opts = (A.SolveOpts * 2)(s1.opts, s2.opts)
     h = A.pmg_batch()
     assert A.lib().pmg_batch_create(opts, 2, h) == A.PMG_E_ARG
+
+
+def test_batched_cases_against_the_oracle():
+    """Two cases in one batch, each checked against the CPU oracle (not only against its own
+    single-case run): the 8x8 vortex at P{2-1-0} with FP64 blocks on an ESDIRK2 second stage, and
+    the ragged 13x11 jittered vortex at P{3-1} with FP32 blocks, steady; three V-cycles each,
+    within ten times the oracle's own one-ulp floor (FP64) or FP32-rounding floor (FP32)."""
+    from oracle import solver as OS
+    from gpu_helpers import fp32_solver_class, from_dev, rel_err_per_var
+    g = OG.Gas(gamma=VS.gamma, rgas=VS.rgas, eps_mode="local", ma_inf=VS.ma_inf)
+    qinf = VS.freestream()
+    mesh_a, mesh_b = W.periodic_quad_mesh(8, 10.0), W.periodic_rect_mesh(13, 11, 10.0, 10.0, jitter=0.1, seed=3)
+    (la, qa0, _), (lb, qb0, _) = (vortex_case(mesh_a, (2, 1, 0), (5, 10, 20), 64, True),
+                                  vortex_case(mesh_b, (3, 1), (3, 6), 32, False))
+    gam, dt, nvc = 1 - 2 ** -0.5, 0.05, 3
+    olev = FRLevel(mesh_a, 2, g, q_inf=qinf)
+    qa = VS.state(olev.geo.xy[..., 0], olev.geo.xy[..., 1])
+    src = (OG.conservative(qa, g) + dt * gam * olev.residual(qa)) / (gam * dt)
+    qb = from_dev(qb0) + qinf
+
+    def oracle(mesh, plev, nsm, q0, cls=OS.PMGSolver, unsteady=False):
+        sol = cls(mesh, g, OS.PMGOptions(p_levels=plev, n_smooth=nsm, max_vcycles=nvc, tol=1e-30), q_inf=qinf)
+        if unsteady:
+            return sol.stage_solve(q0, 1.0 / (gam * dt), src)
+        return sol.stage_solve(q0)
+
+    rng = np.random.default_rng(5)
+    ra, _ = oracle(mesh_a, (2, 1, 0), (5, 10, 20), qa, unsteady=True)
+    ra_p, _ = oracle(mesh_a, (2, 1, 0), (5, 10, 20), qa * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=qa.shape)),
+                     unsteady=True)
+    rb, _ = oracle(mesh_b, (3, 1), (3, 6), qb)
+    rb_p, _ = oracle(mesh_b, (3, 1), (3, 6), qb, cls=fp32_solver_class())
+    mk = lambda lv, prec, graph: api.StageSolver(lv, [api.Factors(x, prec) for x in lv],  # noqa
+                                                  (5, 10, 20) if len(lv) == 3 else (3, 6), tol_rel=1e-30,
+                                                  max_vcycles=nvc, use_graph=graph)
+    batch = api.Batch([mk(la, 64, True), mk(lb, 32, False)])
+    qs = [qa0.clone(), qb0.clone()]
+    out = batch.solve(qs, omega=[gam, 0.0], dt=[dt, None], qc_n=[to_dev(OG.conservative(qa, g)), None],
+                      R_prev=[[to_dev(olev.residual(qa))], None], a_row=[[gam], None], raise_on_error=False)
+    torch.cuda.synchronize()
+    assert [o["n_vcycles"] for o in out] == [nvc, nvc]
+    for q, ref, pert in ((qs[0], ra, ra_p), (qs[1], rb, rb_p)):
+        err = rel_err_per_var(from_dev(q), ref - qinf)
+        floor = rel_err_per_var(pert - qinf, ref - qinf)
+        print("batched case err", err, "floor", floor)
+        assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
+    batch.close()

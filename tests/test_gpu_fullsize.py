@@ -151,6 +151,46 @@ def test_vortex_fullsize_blocks_and_sweep(vortex, prec, dtau):
         assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (e, err, floor)
 
 
+def test_vortex_fullsize_stage_vcycles(vortex):
+    """Two V-cycles of the first implicit ESDIRK3 stage on the whole 64x64 vortex mesh, P{3-2-1},
+    I{5-10-20}, dtau 0.01 -> 10, FP64 blocks, the V-cycles replayed from a HIP graph as the
+    benchmark runs them: the state after each V-cycle and the residual history against the
+    oracle, within ten times the oracle's own response to a one-ulp change of the start."""
+    mesh, vs, gas = vortex
+    plev, nsm, nvc = (3, 2, 1), (5, 10, 20), 2
+    qinf = vs.freestream()
+    A = OS.esdirk_tableau("esdirk3")
+    om, dt = A[1, 1], 0.05
+    olev = FRLevel(mesh, 3, gas, q_inf=qinf)
+    q0 = vs.state(olev.geo.xy[..., 0], olev.geo.xy[..., 1])
+    R0 = olev.residual(q0)
+    src = (OG.conservative(q0, gas) + dt * A[1, 0] * R0) / (om * dt)
+
+    def run(qs):
+        sol = OS.PMGSolver(mesh, gas, OS.PMGOptions(p_levels=plev, n_smooth=nsm, max_vcycles=nvc, tol=1e-30),
+                           q_inf=qinf)
+        return sol.stage_solve(qs, 1.0 / (om * dt), src)
+
+    q_ref, st = run(q0)
+    q_pert, st_pert = run(ulp_moved(q0, 4))
+    floor = rel_err_per_var(q_pert - qinf, q_ref - qinf)
+    h_ref = np.array(st.history)
+    h_floor = np.max(np.abs(np.array(st_pert.history) - h_ref) / h_ref)
+    levels = [vortex_level(mesh, vs, P) for P in plev]
+    solver = api.StageSolver(levels, [api.Factors(lv, 64) for lv in levels], nsm, max_vcycles=nvc, tol_rel=1e-30,
+                             use_graph=True)
+    q = to_dev(q0 - qinf)
+    out = solver.solve(q, omega=om, dt=dt, qc_n=to_dev(OG.conservative(q0, gas)), R_prev=[to_dev(R0)],
+                       a_row=[A[1, 0]], raise_on_error=False)
+    torch.cuda.synchronize()
+    assert out["n_vcycles"] == nvc
+    err = rel_err_per_var(from_dev(q), q_ref - qinf)
+    h_err = np.abs(np.array(out["history"]) - h_ref) / h_ref
+    print("vortex 64x64 V-cycles err", err, "floor", floor, "history err", h_err, "floor", h_floor)
+    assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
+    assert np.all(h_err <= max(1e-11, 10.0 * h_floor))
+
+
 # ---------------------------------------------------------------------------------------------
 # the 128x64 airfoil O-mesh, P4, steady
 

@@ -170,3 +170,43 @@ def test_viscous_stage_solve_parity(name, plev, nsm):
     print(plev, "state err", err, "floor", floor, "history err", h_err)
     assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
     assert np.all(h_err <= max(1e-11, 10.0 * floor.max()))
+
+
+@pytest.mark.parametrize("plev,nsm", [((4, 3, 2, 1), (3, 6, 10, 10)), ((2, 1, 0), (3, 6, 10))])
+def test_viscous_fp32_vcycles_as_benchmarked(plev, nsm):
+    """The viscous batch's form: FP32 element blocks, the hierarchies used for P4 and P2 cases
+    ({4-3-2-1}, {2-1-0}) on a no-slip O-mesh, CFL 1 -> 1e2; three V-cycles of an ESDIRK3
+    second-stage solve against the oracle, within ten times the deviation that FP32 block
+    inverses and products cause in the oracle itself."""
+    mesh = mesh_of("airfoil")
+    nvc = 3
+    A = OS.esdirk_tableau("esdirk3")
+    dt, om = 0.05, A[1, 1]
+    kw = dict(use_cfl=True, cfl_init=1.0, cfl_max=1e2)
+
+    def run(q0, cls=OS.PMGSolver):
+        sol = cls(mesh, GAS, OS.PMGOptions(p_levels=plev, n_smooth=nsm, max_vcycles=nvc, tol=1e-30, **kw), q_inf=QINF)
+        lev = sol.levels[0]
+        src = (OG.conservative(q0, GAS) + dt * A[1, 0] * lev.residual(q0)) / (om * dt)
+        return sol.stage_solve(q0, 1.0 / (om * dt), src)
+
+    olev = FRLevel(mesh, plev[0], GAS, q_inf=QINF)
+    q0 = disturbed(olev, 5)
+    q_ref, st = run(q0)
+    q_pert, st_pert = run(q0, fp32_solver_class())
+    floor = rel_err_per_var(q_pert - QINF, q_ref - QINF)
+    h_ref = np.array(st.history)
+    h_floor = np.max(np.abs(np.array(st_pert.history) - h_ref) / h_ref)
+    glevels = [glevel(mesh, P) for P in plev]
+    facs = [api.Factors(lv, 32) for lv in glevels]
+    solver = api.StageSolver(glevels, facs, nsm, max_vcycles=nvc, tol_rel=1e-30, use_graph=True, **kw)
+    q = to_dev(q0 - QINF)
+    out = solver.solve(q, omega=om, dt=dt, qc_n=to_dev(OG.conservative(q0, GAS)),
+                       R_prev=[to_dev(olev.residual(q0))], a_row=[A[1, 0]], raise_on_error=False)
+    torch.cuda.synchronize()
+    assert out["status"] == -6 and out["n_vcycles"] == nvc
+    err = rel_err_per_var(from_dev(q), q_ref - QINF)
+    h_err = np.abs(np.array(out["history"]) - h_ref) / h_ref
+    print(plev, "FP32 state err", err, "floor", floor, "history err", h_err, "floor", h_floor)
+    assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
+    assert np.all(h_err <= max(1e-11, 10.0 * h_floor))
