@@ -593,6 +593,82 @@ def small_vortex_block(api, torch, forms):
     return small
 
 
+TIMEREF_STEPS = {2: (100, 200, 400), 3: (100, 200, 400), 4: (40, 80, 120)}
+
+
+def time_refinement_block(api, torch, schemes=(2, 3, 4), n=50, prec=32, first_guess="previous", steps=None):
+    """Sec. 4.1's time-refinement study (Table 1's setting): the isentropic vortex at Ma 0.005 on
+    the periodic [-10, 10]^2 square with n x n elements, P5 with P{5-3-1} and I{20-20-40}, dtau
+    0.01 -> 10, blocks rebuilt every 10 V-cycles, every implicit stage solved to a 1e-4 relative
+    drop (at most 200 V-cycles), advanced over one period t = 20 with the step counts of Table 1,
+    the first step's stages from the previous stage value and later ones from the explicit
+    predictor. Errors are RMS over the solution points (uniform mesh) against the exact vortex,
+    which is back at its start after one period; orders from successive step sizes, both
+    against the exact solution and from the differences of successive solutions."""
+    vs = W.VortexSpec(length=20.0, ma_inf=0.005)
+    mesh = W.periodic_quad_mesh(n, 20.0)
+    qinf = vs.freestream()
+    plev, nsm = (5, 3, 1), (20, 20, 40)
+    levels = [api.Level(mesh, P, gamma=vs.gamma, rgas=vs.rgas, eps_mode=0, ma_inf=vs.ma_inf, q_inf=qinf, q_ref=qinf)
+              for P in plev]
+    xy = levels[0].points()
+    exact = vs.state(xy[0], xy[1])                                     # [Np][Ne][4]
+    q0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(exact - qinf, -1, 0))).cuda()
+    facs = [api.Factors(lv, prec) for lv in levels]
+    solvers = [api.StageSolver(levels, facs, nsm, dtau_init=0.01, dtau_max=10.0, refresh_every=10, freeze_at_max=True,
+                               tol_rel=1e-4, max_vcycles=200, use_graph=True, stage_guess=g)
+               for g in (first_guess, "predictor")]
+
+    def rho_u_p(x):
+        p, u, T = x[..., 0], x[..., 1], x[..., 3]
+        return np.stack([p / (vs.rgas * T), u, p], axis=-1)
+
+    ref = rho_u_p(exact)
+    out = {"workload": f"vortex Ma 0.005, periodic [-10,10]^2, {n}x{n} quads, P5, P{{5-3-1}} I{{20-20-40}}, "
+                       f"dtau 0.01->10, stage tol 1e-4, one period t=20, FP{prec} blocks",
+           "error": "RMS over solution points against the exact vortex (rho, u, p)"}
+    for scheme in schemes:
+        res = {"dt": [], "err": [], "stages": 0, "stages_converged": 0, "vcycles": 0, "seconds": 0.0}
+        sols = []
+        for nsteps in (steps or TIMEREF_STEPS)[scheme]:
+            dt = 20.0 / nsteps
+            q = q0.clone()
+            work = torch.zeros((api.esdirk_stages(scheme),) + levels[0].shape, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(nsteps):
+                st = api.esdirk_step(solvers[min(k, 1)], scheme, dt, q, work, raise_on_error=False)
+                res["stages"] += len(st)
+                res["stages_converged"] += sum(x["status"] == 0 for x in st)
+                res["vcycles"] += sum(x["n_vcycles"] for x in st)
+                bad = [x["status"] for x in st if x["status"] not in (0, -6)]
+                if k % 25 == 0 or bad:
+                    print(f"bench: ESDIRK{scheme} t/{nsteps} step {k}: statuses {[x['status'] for x in st]} "
+                          f"V-cycles {[x['n_vcycles'] for x in st]} "
+                          f"r/r0 {[x['history'][-1] / x['history'][0] for x in st if x['history'] and x['history'][0]]}",
+                          file=sys.stderr, flush=True)
+                if bad:
+                    res["failed_at_step"] = k
+                    break
+            torch.cuda.synchronize()
+            res["seconds"] += time.perf_counter() - t0
+            qh = np.moveaxis(q.cpu().numpy(), 0, -1) + qinf
+            sols.append(rho_u_p(qh))
+            res["dt"].append(dt)
+            res["err"].append(np.sqrt(np.mean((sols[-1] - ref).reshape(-1, 3) ** 2, axis=0)).tolist())
+            progress(f"time refinement ESDIRK{scheme} dt = t/{nsteps}")
+        e = np.array(res["err"])
+        r = np.array((steps or TIMEREF_STEPS)[scheme], float)
+        res["order_vs_exact"] = (np.log(e[:-1] / e[1:]) / np.log(r[1:, None] / r[:-1, None])).tolist()
+        if len(sols) == 3:
+            d1 = np.sqrt(np.mean((sols[1] - sols[0]).reshape(-1, 3) ** 2, axis=0))
+            d2 = np.sqrt(np.mean((sols[2] - sols[1]).reshape(-1, 3) ** 2, axis=0))
+            if r[1] / r[0] == r[2] / r[1]:                        # equal ratios: the classic estimate
+                res["order_self"] = (np.log(d1 / d2) / np.log(r[1] / r[0])).tolist()
+        out[f"esdirk{scheme}"] = res
+    return out
+
+
 HEAD_PLEV = (3, 2, 1, 0)
 HEAD_NSM = (5, 10, 20, 20)
 HEAD_CFL = (30.0, 1e5)
@@ -668,7 +744,7 @@ def sphere_headline(api, torch, steps, warmup, fp64_solves, max_vcycles, kernel_
     return res
 
 
-EXTRAS = ("vortex", "small", "nk", "airfoil", "lines", "viscous", "sphere2")
+EXTRAS = ("vortex", "small", "nk", "airfoil", "lines", "viscous", "sphere2", "timeref")
 
 
 def main():
@@ -769,6 +845,8 @@ def main():
     if "viscous" in extras:
         detail["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
         progress("viscous batch")
+    if "timeref" in extras:
+        detail["time_refinement_vortex50_P5"] = time_refinement_block(api, torch)
     if "sphere2" in extras:
         detail["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, ["mixed", "fp64"], args.sphere_vcycles,
                                                                  args.kernel_reps)

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__((Cfg3<P, EPW_>::NT)) k_fr3(ResArgs3 a) {
   const int el = tid % EPW;
   const int p = act ? tid / EPW : 0;
   const bool pt = act && p < NP;
-  const int e = blockIdx.x * EPW + el;
+  const int e = xcd_group(blockIdx.x, gridDim.x) * EPW + el;
   const bool valid = pt && e < ne;
   const int i = p % N1, j = (p / N1) % N1, k = p / (N1 * N1);
   const size_t sstride = (size_t)NP * ne;
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__((Cfg3<P, EPW_>::NT)) k_fr3(ResArgs3 a) {
     sync3<C::NT>();
     if (tid < EPW * C::MVL) {
       const int el2 = tid / C::MVL, l = tid % C::MVL;
-      const int e2 = blockIdx.x * EPW + el2;
+      const int e2 = xcd_group(blockIdx.x, gridDim.x) * EPW + el2;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       if (e2 < ne) {
         const double* fe = s_fe + el2 * NPAD;

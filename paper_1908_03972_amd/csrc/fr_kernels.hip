@@ -138,7 +138,7 @@ __global__ void __launch_bounds__((Cfg<P, EPW_>::NT)) k_fr(ResArgs a) {
   const int el = tid % EPW;
   const int p = act ? tid / EPW : 0;
   const bool pt = act && p < NP;            // this lane owns solution point p
-  const int e = blockIdx.x * EPW + el;
+  const int e = xcd_group(blockIdx.x, gridDim.x) * EPW + el;
   const bool valid = pt && e < ne;
   const int i = p % N1, j = p / N1;
   static_assert(N1 * N1 + 4 * N1 <= C::NT, "one lane per operator entry");
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__((Cfg<P, EPW_>::NT)) k_fr(ResArgs a) {
     // of elements past the end re-read a valid chunk into the padding or an unused slot. Issued
     // once the neighbour gathers are consumed: the compiler's wait for any load issued before a
     // direct-to-LDS load also waits for the latter.
-    const int e0 = blockIdx.x * EPW;
+    const int e0 = xcd_group(blockIdx.x, gridDim.x) * EPW;
     const float* wb = static_cast<const float*>(a.W);
 #pragma unroll
     for (int it = 0; it < SW_INSTR; ++it) {
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__((Cfg<P, EPW_>::NT)) k_fr(ResArgs a) {
     block_sync<C::NT>();
     if (tid < C::NPT) {
       const int el2 = tid / NP, p2 = tid % NP;
-      const int e2 = blockIdx.x * EPW + el2;
+      const int e2 = xcd_group(blockIdx.x, gridDim.x) * EPW + el2;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       if (e2 < ne) {
         const double* fe = s_fe + el2 * N;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(Cfg<P>::NT) k_grad(LevelView lv, Ops1D o, cons
   const int el = tid % EPW;
   const int p = act ? tid / EPW : 0;
   const bool pt = act && p < NP;
-  const int e = blockIdx.x * EPW + el;
+  const int e = xcd_group(blockIdx.x, gridDim.x) * EPW + el;
   const bool valid = pt && e < ne;
   const int i = p % N1, j = p / N1;
   const size_t sstride = (size_t)NP * ne, gp = (size_t)p * ne + e;

@@ -12,6 +12,18 @@
 
 namespace pmg {
 
+// Workgroups are dispatched to the device's eight XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has its own L2. A kernel whose workgroup b covers element group g reads the
+// element-fastest arrays ([variable][point][element]) in runs of (elements per group) x 8 bytes;
+// groups that share a 128-byte line must run on one XCD or every XCD fetches the whole line. The
+// element group of workgroup b among nb: XCD x takes a contiguous range of groups (the first
+// nb mod 8 XCDs one group more), in the order its workgroups are dispatched.
+__device__ __forceinline__ int xcd_group(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, r = nb % kXcd, x = b % kXcd, k = b / kXcd;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 constexpr int kMaxN1 = 7;   // P <= 6
 constexpr int kNv2 = 4;     // 2-D primitive variables (p, u, v, T)
 
