@@ -17,6 +17,7 @@ namespace pmg {
 // ---- element blocks (eqs. (28)-(30)) and their inverses ----------------------------------
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 struct JacArgs3 {
   LevelView lv;
@@ -369,8 +370,9 @@ __global__ void __launch_bounds__(256) k_point_jac3(JacArgs3 a, double* __restri
 // Large element blocks (n = 320 at P = 3): the block is larger than a compute unit's LDS, so each
 // workgroup owns a slot of a global work array (n x n row-major, X[r n + c], in the precision of
 // the stored inverse, T = float or double) and takes elements in turn, one thread per row. The
-// element's pointwise derivatives come from k_point_jac3 (global memory, copied to LDS), the block
-// is assembled row by row into the slot in FP64, row-scaled by powers of two, rounded to T and
+// element's pointwise derivatives come from k_point_jac3 (global memory, read in place); the slot
+// is cleared with whole-line stores, each thread assembles its row's non-zero entries in FP64,
+// scales the row by a power of two, rounds it to T and writes it into the slot, and the block is
 // inverted by Gauss-Jordan elimination with partial pivoting in T arithmetic, in panels of B
 // columns:
 //   * the panel's B steps run on each row's B panel entries held in registers; the pivot search and
@@ -392,13 +394,15 @@ struct Big3 {
   static constexpr int NPAD = (N + 3) / 4 * 4;
   static constexpr int B = B_, G = 16;   // panel width; columns per matrix-core tile
   static constexpr int NT = N, NW = NT / 64;
-  static constexpr int ASM = NV * NP + 4 * NP * NV * NV + 6 * NF * NV * NV;   // sq, sA, sDg, sB
-  static constexpr int GJ = 2 * NW * B;                                       // pivot rows
-  static constexpr int POOL = ASM > GJ ? ASM : GJ;
-  // columns per gathered chunk of pivot rows in the update: 32 x 320 FP32 values at most, so
-  // that the B rows of a chunk (row stride padded by 64 bytes) fit in the pool
+  // columns per gathered chunk of pivot rows in the update: 32 x 320 FP32 values at most
   template <typename T>
   static constexpr int chunk() { return N * 32 * 4 / (B * (int)sizeof(T)); }
+  // LDS pool in doubles: the pivot rows of the panel steps ([2][NW][B]), then the gathered pivot
+  // rows of a chunk (B rows, stride padded by 64 bytes)
+  static constexpr int GJ = 2 * NW * B;
+  static constexpr int XPF = B * (chunk<float>() + 16) * 4 / 8, XPD = B * (chunk<double>() + 8);
+  static constexpr int XP = XPF > XPD ? XPF : XPD;
+  static constexpr int POOL = XP > GJ ? XP : GJ;
   static_assert(N % 64 == 0 && N % B == 0 && B % G == 0 && B % 4 == 0 && G == 16, "whole tiles and panels");
   static_assert(N % chunk<float>() == 0 && N % chunk<double>() == 0 && chunk<float>() % G == 0 &&
                 chunk<double>() % G == 0, "whole 16-column groups per chunk");
@@ -432,8 +436,13 @@ __device__ __forceinline__ int acc_row(int lk, int v) {
   return sizeof(T) == 4 ? 4 * lk + v : lk + 4 * v;
 }
 
+// The FP32 instance is held to four waves per SIMD (at most 128 registers): two workgroups of five
+// waves are then resident on each CU, and one's panel steps overlap the other's memory-bound
+// phases (without the bound the compiler took 126 registers and only one workgroup per CU ran at a
+// time, 1.3x slower). The FP64 instance needs more registers and runs one workgroup per CU.
 template <int P, typename T, int BW>
-__global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* __restrict__ ws,
+__global__ void __launch_bounds__((Big3<P, BW>::NT)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_jac3_big(JacArgs3 a, T* __restrict__ ws,
                                                              const double* __restrict__ pj) {
   using C = Big3<P, BW>;
   using T4 = typename std::conditional<sizeof(T) == 4, flt4, dbl4>::type;
@@ -443,11 +452,7 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
   __shared__ double sscl[N];
   __shared__ int sperm[N];
   __shared__ unsigned skey[2][NW];
-  double* sq = pool;
-  double* sA = sq + NV * NP;
-  double* sDg = sA + 3 * NP * NV * NV;
-  double* sB = sDg + NP * NV * NV;
-  T* slot = reinterpret_cast<T*>(pool);   // [2][NW][B], after the assembly
+  T* slot = reinterpret_cast<T*>(pool);   // [2][NW][B] pivot rows of the panel steps
 
   const int ne = a.lv.ne;
   const int r = threadIdx.x;
@@ -470,19 +475,18 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
 
   for (int e = blockIdx.x; e < ne; e += gridDim.x) {
     __syncthreads();                        // the previous element is done with the pool and sperm
-    {                                       // sA, sDg, sB are contiguous in the pool
-      constexpr int NPJ = (int)jac3_point_elems(P), U = 4;
-      const double* src = pj + (size_t)e * NPJ;
-      for (int t0 = r; t0 < NPJ; t0 += U * NT) {   // U loads in flight per thread
-        double vv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) vv[u] = (t0 + u * NT < NPJ) ? src[t0 + u * NT] : 0.0;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (t0 + u * NT < NPJ) sA[t0 + u * NT] = vv[u];
-      }
+    // the element's pointwise derivatives, read in place (L2-resident once touched): the flux
+    // Jacobians sA, the diagonal term sDg and the common-flux derivatives sB, one after the other
+    const double* sA = pj + (size_t)e * jac3_point_elems(P);
+    const double* sDg = sA + 3 * NP * NV * NV;
+    const double* sB = sDg + NP * NV * NV;
+    {   // clear the slot with 16-byte stores along its rows (whole lines per wave); the rows'
+        // non-zero entries are written after the barrier that follows the row scales
+      using V16 = typename std::conditional<sizeof(T) == 4, flt4, dbl2>::type;
+      V16* xz = reinterpret_cast<V16*>(X);
+      constexpr int NZ = N * N * (int)sizeof(T) / 16;
+      for (int t = r; t < NZ; t += NT) xz[t] = V16{};
     }
-    __syncthreads();
 
     // row r of D_e: only the 10 points of the row point's three tensor lines couple to it, so
     // the row is cleared and those 50 entries (the point itself gathering all three lines and
@@ -521,10 +525,9 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
     sscl[r] = scl;
     T* xr = X + (size_t)r * N;
     double* dr = a.D_out ? a.D_out + ((size_t)e * N + r) * N : nullptr;
-#pragma unroll 8
-    for (int c = 0; c < N; ++c) xr[c] = (T)0;
     if (dr)
       for (int c = 0; c < N; ++c) dr[c] = 0.0;
+    __syncthreads();                        // the slot is clear
 #pragma unroll 1
     for (int w = 0; w < NV; ++w) {
       const double dval = diag_val(w);
@@ -544,7 +547,7 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
           if (dr) dr[ss * NV + w] = dval;
         }
       }
-    __syncthreads();                        // the pool now holds pivot rows and staged values
+    __syncthreads();                        // every row of the slot is written
 
     bool used = false;
     int my_step = 0;
@@ -562,9 +565,10 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
         const T fv = row[0];
         const unsigned key = used ? 0u : pivot_key(fv, r);
         const unsigned wkey = wave_max3(key);
-        if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {
-#pragma unroll
-          for (int c = 0; c < B; ++c) slot[(par * NW + wv) * B + c] = row[c];
+        if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {   // the row shifted by one, pivot last,
+#pragma unroll                                                    // so that the reads below are aligned
+          for (int c = 0; c < B - 1; ++c) slot[(par * NW + wv) * B + c] = row[c + 1];
+          slot[(par * NW + wv) * B + B - 1] = row[0];
         }
         if (lane == 0) skey[par][wv] = wkey;
         __syncthreads();
@@ -582,7 +586,7 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
           pr = 0;
         }
         const T* prw = slot + (par * NW + win) * B;
-        T piv = prw[0];
+        T piv = prw[B - 1];
         if (piv == (T)0 || !isfinite(piv)) {
           bad = true;
           piv = (T)1;
@@ -597,7 +601,7 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
         }
         const T g = is_p ? (T)0 : fv * ip;
 #pragma unroll
-        for (int c = 0; c < B - 1; ++c) row[c] = fma(-g, prw[c + 1], row[c + 1]);
+        for (int c = 0; c < B - 1; ++c) row[c] = fma(-g, prw[c], row[c + 1]);
         row[B - 1] = is_p ? (T)1 : -g;
       }
 #pragma unroll
@@ -613,13 +617,18 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
       // row. The pivot rows' old values of a chunk of CW columns are first gathered into LDS
       // (xp, row stride CWP), so that after one barrier every wave streams its own rows.
       const int lr = lane & 15, lk = lane >> 4;
+      // slot offsets split into a per-lane part (one 32-bit register) and a uniform part, so that
+      // every load and store addresses the slot as a scalar base plus that register
+      const unsigned uoff = (unsigned)((64 * wv + lr) * N + lk);
+      const unsigned aoff = (unsigned)((64 * wv + acc_row<T>(lk, 0)) * N + lr);
+      constexpr int VS = sizeof(T) == 4 ? 1 : 4;   // row step of accumulator register v
       T uop[4][B / 4];
 #pragma unroll
       for (int TT = 0; TT < 4; ++TT) {
 #pragma unroll
         for (int s4 = 0; s4 < B / 4; ++s4) {
           const int row_ = 64 * wv + 16 * TT + lr, m = 4 * s4 + lk;
-          const T u = X[(size_t)row_ * N + k0 + m];
+          const T u = (X + 16 * TT * N + k0 + 4 * s4)[uoff];
           uop[TT][s4] = (sperm[k0 + m] == row_) ? u - (T)1 : u;
         }
       }
@@ -632,15 +641,21 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
           xp[k * CWP + c] = X[(size_t)sperm[k0 + k] * N + c0 + c];
         }
         __syncthreads();                    // every old pivot-row value is in LDS before any store
-        for (int cg = c0; cg < c0 + CW; cg += G) {
-          if (cg >= k0 && cg < k0 + B) continue;
-          T4 acc[4];
+        // the chunk's 16-column groups outside the panel, in order
+        const int ps = k0 > c0 ? k0 : c0, pe = (k0 + B < c0 + CW) ? k0 + B : c0 + CW;
+        const int skip = pe > ps ? pe - ps : 0, ng = (CW - skip) / G;
+        auto group = [&](int g) {
+          const int cg = c0 + G * g;
+          return (skip && cg >= ps) ? cg + skip : cg;
+        };
+        auto load_acc = [&](T4(&acc)[4], int cg) {
 #pragma unroll
           for (int TT = 0; TT < 4; ++TT) {
 #pragma unroll
-            for (int v2 = 0; v2 < 4; ++v2)
-              acc[TT][v2] = X[(size_t)(64 * wv + 16 * TT + acc_row<T>(lk, v2)) * N + cg + lr];
+            for (int v2 = 0; v2 < 4; ++v2) acc[TT][v2] = (X + (16 * TT + VS * v2) * N + cg)[aoff];
           }
+        };
+        auto update_store = [&](T4(&acc)[4], int cg) {
 #pragma unroll
           for (int s4 = 0; s4 < B / 4; ++s4) {
             const T xb = xp[(4 * s4 + lk) * CWP + (cg - c0) + lr];
@@ -650,9 +665,13 @@ __global__ void __launch_bounds__((Big3<P, BW>::NT)) k_jac3_big(JacArgs3 a, T* _
 #pragma unroll
           for (int TT = 0; TT < 4; ++TT) {
 #pragma unroll
-            for (int v2 = 0; v2 < 4; ++v2)
-              X[(size_t)(64 * wv + 16 * TT + acc_row<T>(lk, v2)) * N + cg + lr] = acc[TT][v2];
+            for (int v2 = 0; v2 < 4; ++v2) (X + (16 * TT + VS * v2) * N + cg)[aoff] = acc[TT][v2];
           }
+        };
+        for (int g = 0; g < ng; ++g) {
+          T4 acc_a[4];
+          load_acc(acc_a, group(g));
+          update_store(acc_a, group(g));
         }
       }
       __syncthreads();                      // the updated columns are visible before the next panel
