@@ -773,11 +773,13 @@ pmg_status pmg_factors_create(pmg_level L, int32_t precision, pmg_factors* out) 
     delete F;
     return fail(PMG_E_HIP, "hipMemset element blocks");
   }
-  if (L->dim == 3 && L->P == 3) {   // large blocks: one FP64 work slot per resident workgroup
+  if (L->dim == 3 && (L->P == 3 || (L->P == 2 && precision == 32))) {
+    // every element's pointwise derivatives (P = 3, and P = 2 with FP32 inverses), after one FP64
+    // work slot per resident workgroup of the large-block elimination (P = 3)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, L->device) != hipSuccess || cus <= 0)
       cus = 256;
-    F->ws_slots = 2 * cus < L->ne ? 2 * cus : L->ne;
+    F->ws_slots = L->P == 3 ? (2 * cus < L->ne ? 2 * cus : L->ne) : 0;
     // the slots, then every element's pointwise derivatives
     const size_t elems = (size_t)F->ws_slots * L->n * L->n + (size_t)L->ne * pmg::jac3_point_elems(L->P);
     if (hipMalloc(&F->ws, elems * sizeof(double)) != hipSuccess) {

@@ -126,7 +126,7 @@ struct pmg_factors_s {
   int precision = 64;     // 64: FP64 inverse blocks; 32: FP32 inverse blocks
   void* W = nullptr;      // [n][Ne][npad] element inverse blocks, column-major per element
   size_t bytes = 0;
-  double* ws = nullptr;   // work array of the large-block elimination: ws_slots x n x n FP64 (3-D P = 3)
+  double* ws = nullptr;   // 3-D P = 3 (and P = 2 with FP32 inverses): ws_slots x n x n FP64 work slots (P = 3), then every element's pointwise derivatives
   int ws_slots = 0;
   pmg::LineFactors* lines = nullptr;   // element-line Jacobi instead of element Jacobi (lines.hpp)
 };

@@ -67,6 +67,19 @@ __device__ __forceinline__ double quad_dpp(double x) {
 }
 constexpr int kQuadFirst = 0x00;   // quad_perm [0,0,0,0]
 constexpr int kQuadNext = 0xF9;    // quad_perm [1,2,3,3]: the next lane of the quad
+template <int CTRL>
+__device__ __forceinline__ float quad_dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+// 32-bit pivot key of |f|: its upper bits (the FP32 pattern, or the upper word of the FP64 one)
+// with the low 10 bits replaced by 1023 - r, so that the wave maximum also names the row or thread
+__device__ __forceinline__ unsigned pivot_key(float f, int r) {
+  return (__float_as_uint(fabsf(f)) & ~0x3FFu) | (unsigned)(1023 - r);
+}
+__device__ __forceinline__ unsigned pivot_key(double f, int r) {
+  return (((unsigned)__double2hiint(fabs(f))) & ~0x3FFu) | (unsigned)(1023 - r);
+}
 
 // The element's state (sq, [Nv][Np]) and its pointwise derivatives into LDS, all threads of the
 // workgroup taking part: sA[d] = dF~_d/dq at each solution point ([(pp Nv + v) Nv + w], three
@@ -215,18 +228,22 @@ __device__ __forceinline__ double block_entry3(const Ops1D& o, const double* sA,
   return dval;
 }
 
-template <int P, int S>
-__global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
+// Element blocks held in registers (n <= 135): S threads per row, Gauss-Jordan in T arithmetic
+// (T = float for FP32 inverses at P = 2, double otherwise). The pointwise derivatives are computed
+// here with dual numbers, or, with FROM_PJ, copied from the global array k_point_jac3 wrote (the
+// kernel then carries no dual-number code and needs far fewer registers).
+template <int P, int S, typename T, bool FROM_PJ>
+__global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, const double* __restrict__ pj) {
   using C = Rows3<P, S>;
   constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NJ = C::NJ, H = C::H, NW = C::NW, NT = C::NT,
                 NPAD = C::NPAD;
-  __shared__ double sq[NV * NP];
+  __shared__ double sq[FROM_PJ ? 1 : NV * NP];
   __shared__ double sA[3 * NP * NV * NV];
   __shared__ double sDg[NP * NV * NV];
   __shared__ double sB[6 * NF * NV * NV];
   __shared__ double sscl[NJ];
   __shared__ int sperm[NJ];
-  __shared__ double slot[2][NW][NJ];
+  __shared__ T slot[2][NW][NJ];
   __shared__ unsigned skey[2][NW];
 
   const int ne = a.lv.ne;
@@ -235,7 +252,24 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
   const int lane = tid & 63, wv = tid >> 6;
   const size_t sstride = (size_t)NP * ne;
 
-  element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
+  if constexpr (FROM_PJ) {   // sA, sDg, sB one after the other in the element's record
+    const double* src = pj + (size_t)e * jac3_point_elems(P);
+    constexpr int NA = 3 * NP * NV * NV, ND = NP * NV * NV, NB = 6 * NF * NV * NV, NALL = NA + ND + NB, U = 4;
+    for (int t0 = tid; t0 < NALL; t0 += U * NT) {   // U loads in flight per thread
+      double vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) vv[u] = (t0 + u * NT < NALL) ? src[t0 + u * NT] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * NT;
+        if (t < NA) sA[t] = vv[u];
+        else if (t < NA + ND) sDg[t - NA] = vv[u];
+        else if (t < NALL) sB[t - NA - ND] = vv[u];
+      }
+    }
+  } else {
+    element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
+  }
   __syncthreads();
 
   const bool has_row = tid < S * NJ;
@@ -244,26 +278,14 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
   const bool real_row = has_row && r < N;
   const int pp = real_row ? r / NV : 0, v = r % NV;
   const double ijac = a.lv.met[9 * sstride + (size_t)pp * ne + e];
-  double row[H];
-#pragma unroll
-  for (int jc = 0; jc < H; ++jc) {
-    const int c = h * H + jc;
-    double dval = 0.0;
-    if (real_row && c < N) {
-      dval = block_entry3<P>(a.ops, sA, sDg, sB, pp, v, c / NV, c % NV, ijac);
-    } else if (has_row && !real_row) {
-      dval = (c == r) ? 1.0 : 0.0;                // padding: identity row
-    }
-    row[jc] = dval;
-  }
-  if (a.D_out && real_row) {
-#pragma unroll
-    for (int jc = 0; jc < H; ++jc)
-      if (h * H + jc < N) a.D_out[((size_t)e * N + r) * N + h * H + jc] = row[jc];
-  }
+  auto entry = [&](int c) {
+    if (real_row && c < N) return block_entry3<P>(a.ops, sA, sDg, sB, pp, v, c / NV, c % NV, ijac);
+    return (has_row && !real_row && c == r) ? 1.0 : 0.0;   // padding: identity row
+  };
+  // the row's power-of-two scale from its largest entry (in FP64), then the scaled row in T
   double mx = 0.0;
-#pragma unroll
-  for (int jc = 0; jc < H; ++jc) mx = fmax(mx, fabs(row[jc]));
+#pragma unroll 1
+  for (int jc = 0; jc < H; ++jc) mx = fmax(mx, fabs(entry(h * H + jc)));
   if (S == 4) {
     mx = fmax(mx, __shfl_xor(mx, 1, 64));
     mx = fmax(mx, __shfl_xor(mx, 2, 64));
@@ -271,19 +293,24 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
   int ex = 0;
   frexp(mx, &ex);
   const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
+  T row[H];
 #pragma unroll
-  for (int jc = 0; jc < H; ++jc) row[jc] *= scl;
+  for (int jc = 0; jc < H; ++jc) {
+    const double dval = entry(h * H + jc);
+    if (a.D_out && real_row && h * H + jc < N) a.D_out[((size_t)e * N + r) * N + h * H + jc] = dval;
+    row[jc] = (T)(dval * scl);
+    __builtin_amdgcn_sched_barrier(0);   // one entry at a time: keeps the assembly's registers few
+  }
   if (has_row && h == 0) sscl[r] = scl;
 
   bool used = !has_row;
   int my_step = 0;
-  double my_inv = 1.0;
+  T my_inv = (T)1;
   bool bad = false;
   for (int kstep = 0; kstep < NJ; ++kstep) {
     const int par = kstep & 1;
-    const double fval = (S == 4) ? quad_dpp<kQuadFirst>(row[0]) : row[0];
-    const unsigned key = (used || h != 0) ? 0u
-                         : ((((unsigned)__double2hiint(fabs(fval))) & ~0x3FFu) | (unsigned)(1023 - tid));
+    const T fval = (S == 4) ? quad_dpp<kQuadFirst>(row[0]) : row[0];
+    const unsigned key = (used || h != 0) ? 0u : pivot_key(fval, tid);
     const unsigned wkey = wave_max3(key);
     const int wtid = 1023 - (int)(wkey & 0x3FFu);
     if (wkey != 0u && tid >= wtid && tid < wtid + S) {
@@ -305,27 +332,27 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
       bad = true;
       pr_row = (pr_row < NJ && pr_row >= 0) ? pr_row : NJ - 1;
     }
-    const double* prw = slot[par][win];
-    double piv = prw[0];
-    if (piv == 0.0 || !isfinite(piv)) {
+    const T* prw = slot[par][win];
+    T piv = prw[0];
+    if (piv == (T)0 || !isfinite(piv)) {
       bad = true;
-      piv = 1.0;
+      piv = (T)1;
     }
-    const double ip = 1.0 / piv;
+    const T ip = (T)1 / piv;
     const bool is_p = has_row && (r == pr_row);
     if (tid == 0) sperm[kstep] = pr_row;
-    const double g = is_p ? 0.0 : fval * ip;
+    const T g = is_p ? (T)0 : fval * ip;
     if (is_p) {
       used = true;
       my_step = kstep;
       my_inv = ip;
     }
-    const double nxt = (S == 4) ? quad_dpp<kQuadNext>(row[0]) : 0.0;
-    const double* prh = prw + h * H;
+    const T nxt = (S == 4) ? quad_dpp<kQuadNext>(row[0]) : (T)0;
+    const T* prh = prw + h * H;
     constexpr int B = 16;
 #pragma unroll
     for (int j0 = 0; j0 < H - 1; j0 += B) {
-      double buf[B];
+      T buf[B];
 #pragma unroll
       for (int jb = 0; jb < B; ++jb)
         if (j0 + jb < H - 1) buf[jb] = prh[j0 + jb + 1];
@@ -336,7 +363,7 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
     if (S == 4 && h < S - 1)
       row[H - 1] = fma(-g, prw[(h + 1) * H], nxt);
     else
-      row[H - 1] = is_p ? 1.0 : -g;
+      row[H - 1] = is_p ? (T)1 : -g;
   }
   if (bad) *a.flag = 1;
   __syncthreads();
@@ -345,7 +372,7 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
     for (int jc = 0; jc < H; ++jc) {
       const int col = sperm[h * H + jc];
       if (col >= N) continue;
-      const double val = row[jc] * my_inv * sscl[col];
+      const double val = (double)(row[jc] * my_inv) * sscl[col];
       const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
       if (a.precision == 32)
         static_cast<float*>(a.W)[o_] = (float)val;
@@ -413,14 +440,6 @@ struct Big3 {
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-// 32-bit pivot key of |f|: its upper bits (the FP32 pattern, or the upper word of the FP64 one)
-// with the low 10 bits replaced by 1023 - row, so that the wave maximum also names the row
-__device__ __forceinline__ unsigned pivot_key(float f, int r) {
-  return (__float_as_uint(fabsf(f)) & ~0x3FFu) | (unsigned)(1023 - r);
-}
-__device__ __forceinline__ unsigned pivot_key(double f, int r) {
-  return (((unsigned)__double2hiint(fabs(f))) & ~0x3FFu) | (unsigned)(1023 - r);
-}
 
 // One 16x16x4 matrix-core step in T, and the row i of the 16 x 16 result held by accumulator
 // register v in lane group lk: D[i][j] sits in lane j + 16 (i / 4), register i % 4 for FP32 and
@@ -700,7 +719,8 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
 
 template <int P, int S>
 static hipError_t launch_jac3_p(const JacArgs3& a, int ne, hipStream_t st) {
-  hipLaunchKernelGGL((k_jac3_rows<P, S>), dim3(ne), dim3(Rows3<P, S>::NT), 0, st, a);
+  hipLaunchKernelGGL((k_jac3_rows<P, S, double, false>), dim3(ne), dim3(Rows3<P, S>::NT), 0, st, a,
+                     (const double*)nullptr);
   return hipGetLastError();
 }
 
@@ -720,7 +740,16 @@ hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, 
   switch (L.P) {
     case 0: return launch_jac3_p<0, 1>(a, L.ne, st);
     case 1: return launch_jac3_p<1, 1>(a, L.ne, st);
-    case 2: return launch_jac3_p<2, 4>(a, L.ne, st);
+    case 2: {
+      // FP64 inverses: one kernel, the pointwise derivatives computed in place; FP32 inverses: the
+      // pointwise derivatives first, then an FP32 elimination without dual numbers (32 against
+      // 39 ms on the 36 864-element sphere; the FP64 elimination split the same way took 43.5 ms)
+      if (fac.precision != 32 || !fac.ws) return launch_jac3_p<2, 4>(a, L.ne, st);
+      hipLaunchKernelGGL(k_point_jac3<2>, dim3(L.ne), dim3(256), 0, st, a, fac.ws);
+      hipLaunchKernelGGL((k_jac3_rows<2, 4, float, true>), dim3(L.ne), dim3(Rows3<2, 4>::NT), 0, st, a,
+                         (const double*)fac.ws);
+      return hipGetLastError();
+    }
     case 3: {
       if (!fac.ws || fac.ws_slots <= 0) return hipErrorInvalidValue;
       const int grid = fac.ws_slots < L.ne ? fac.ws_slots : L.ne;

@@ -79,15 +79,16 @@ def fp32_solver_class(fp32_elimination=False):
     """The oracle's PMG solver with the smoother's block inverses in FP32 and the block-vector
     products taken in FP32: the rounding the mixed-precision smoother introduces, reproduced on
     the CPU so that its effect sizes the FP32 parity tolerance (at Ma <= 1e-3 the temperature
-    update amplifies it far beyond u_32). With fp32_elimination the inverse itself is computed
-    in FP32 (``fp32_inverse``, as the large hexahedral blocks are on the GPU); otherwise the FP64
-    inverse is rounded to FP32."""
+    update amplifies it far beyond u_32). Where fp32_elimination holds (a bool, or a predicate on
+    the level's P) the inverse itself is computed in FP32 (``fp32_inverse``, as the hexahedral
+    blocks of P >= 2 are on the GPU); otherwise the FP64 inverse is rounded to FP32."""
     from oracle import solver as OS
 
     class PMGSolverFP32(OS.PMGSolver):
         def smooth(self, l, q, S, nsweep):
             lev = self.levels[l]
-            if fp32_elimination:
+            elim = fp32_elimination(lev.P) if callable(fp32_elimination) else fp32_elimination
+            if elim:
                 winv = fp32_inverse(self.D[l]).astype(np.float32)
             else:
                 winv = np.linalg.inv(self.D[l]).astype(np.float32)

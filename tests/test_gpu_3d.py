@@ -164,8 +164,8 @@ def test_sweep_parity_3d(request, P, prec):
     if prec == 64:
         rng = np.random.default_rng(11)
         ref_pert, _ = oracle_sweeps(q * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q.shape)))
-    else:                                   # n = 320 blocks are eliminated in FP32
-        ref_pert, _ = oracle_sweeps(q, fp32_solver_class(fp32_elimination=P == 3))
+    else:                                   # FP32 inverses of P >= 2 are eliminated in FP32
+        ref_pert, _ = oracle_sweeps(q, fp32_solver_class(fp32_elimination=P >= 2))
     floor = rel_err_per_var(ref_pert - QINF, ref - QINF)
     glev = glevel(sphere, P)
     fac = api.Factors(glev, prec)
@@ -196,7 +196,7 @@ def test_steady_solve_parity_3d(request, plev, prec):
         rng = np.random.default_rng(7)
         q_pert, st_pert = run_oracle(q0 * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q0.shape)))
     else:
-        q_pert, st_pert = run_oracle(q0, fp32_solver_class(fp32_elimination=plev[0] == 3))
+        q_pert, st_pert = run_oracle(q0, fp32_solver_class(fp32_elimination=lambda p: p >= 2))
     floor = rel_err_per_var(q_pert - QINF, q_ref - QINF)
     h_floor = np.max(np.abs(np.array(st_pert.history) - np.array(st.history)) / np.array(st.history))
     levels = [glevel(sphere, P) for P in plev]
@@ -250,7 +250,7 @@ def test_sphere_fullsize_residual_blocks_and_sweep():
         Dref = patch_block(mesh, gas, P, q, e, dtau, 0.0, qinf)
         berr = scaled_block_error(Dg[e].cpu().numpy()[None], Dref[None], q[e:e + 1])
         ref = np.linalg.solve(Dref, F[e].ravel())
-        alt = (np.linalg.inv(Dref).astype(np.float32) @ F[e].ravel().astype(np.float32)).astype(np.float64)
+        alt = (fp32_inverse(Dref).astype(np.float32) @ F[e].ravel().astype(np.float32)).astype(np.float64)
         e_err = rel_err_per_var(dq[e], ref.reshape(-1, 5))
         floor = rel_err_per_var(alt.reshape(-1, 5), ref.reshape(-1, 5))
         print("sphere e", e, "block err", berr, "update err", e_err, "floor", floor)
