@@ -80,6 +80,21 @@ __device__ __forceinline__ unsigned pivot_key(float f, int r) {
 __device__ __forceinline__ unsigned pivot_key(double f, int r) {
   return (((unsigned)__double2hiint(fabs(f))) & ~0x3FFu) | (unsigned)(1023 - r);
 }
+// the key of |f| 2^e2 without forming the product: e2 added to the exponent field; values whose
+// scaled exponent leaves the normal range count as zero (below) or infinity (above), and the
+// unscaled subnormals as zero
+__device__ __forceinline__ unsigned pivot_key(float f, int r, int e2) {
+  const unsigned b = __float_as_uint(fabsf(f));
+  const int eb = (int)(b >> 23) + e2;
+  const unsigned sb = ((b >> 23) == 0u || eb <= 0) ? 0u : (eb >= 255 ? 0x7F800000u : b + ((unsigned)e2 << 23));
+  return (sb & ~0x3FFu) | (unsigned)(1023 - r);
+}
+__device__ __forceinline__ unsigned pivot_key(double f, int r, int e2) {
+  const unsigned b = (unsigned)__double2hiint(fabs(f));
+  const int eb = (int)(b >> 20) + e2;
+  const unsigned sb = ((b >> 20) == 0u || eb <= 0) ? 0u : (eb >= 2047 ? 0x7FF00000u : b + ((unsigned)e2 << 20));
+  return (sb & ~0x3FFu) | (unsigned)(1023 - r);
+}
 
 // The element's state (sq, [Nv][Np]) and its pointwise derivatives into LDS, all threads of the
 // workgroup taking part: sA[d] = dF~_d/dq at each solution point ([(pp Nv + v) Nv + w], three
@@ -398,10 +413,10 @@ __global__ void __launch_bounds__(256) k_point_jac3(JacArgs3 a, double* __restri
 // workgroup owns a slot of a global work array (n x n row-major, X[r n + c], in the precision of
 // the stored inverse, T = float or double) and takes elements in turn, one thread per row. The
 // element's pointwise derivatives come from k_point_jac3 (global memory, read in place); the slot
-// is cleared with whole-line stores, each thread assembles its row's non-zero entries in FP64,
-// scales the row by a power of two, rounds it to T and writes it into the slot, and the block is
-// inverted by Gauss-Jordan elimination with partial pivoting in T arithmetic, in panels of B
-// columns:
+// is cleared with whole-line stores, each thread assembles its row's non-zero entries in FP64 and
+// writes them rounded to T, and the block is inverted by Gauss-Jordan elimination with partial
+// pivoting in T arithmetic (pivots chosen on the rows equilibrated by powers of two), in panels of
+// B columns:
 //   * the panel's B steps run on each row's B panel entries held in registers; the pivot search and
 //     the broadcast of the pivot row go through LDS as in the register kernel. Pivot rows stay
 //     unnormalised (every row keeps the scale of its pivot, divided out once at the end), so a
@@ -414,7 +429,7 @@ __global__ void __launch_bounds__(256) k_point_jac3(JacArgs3 a, double* __restri
 //     row-major slot) are gathered into LDS first, then every wave streams its own rows.
 // Barriers order the slot's accesses across the lanes of a wave. At the end, physical row p_i of
 // the slot is row i of the inverse times its pivot f_i, with its columns in pivot order:
-// D_e^{-1}[i][p_m] = X[p_i n + m] s_{p_m} / f_i, s the row scales.
+// D_e^{-1}[i][p_m] = X[p_i n + m] / f_i.
 template <int P, int B_>
 struct Big3 {
   static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
@@ -468,9 +483,9 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
   constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NPAD = C::NPAD, B = C::B, G = C::G, NW = C::NW,
                 NT = C::NT;
   __shared__ double pool[C::POOL];
-  __shared__ double sscl[N];
   __shared__ int sperm[N];
   __shared__ unsigned skey[2][NW];
+  __shared__ T sinv[N];                   // 1 / pivot of every step
   T* slot = reinterpret_cast<T*>(pool);   // [2][NW][B] pivot rows of the panel steps
 
   const int ne = a.lv.ne;
@@ -529,28 +544,22 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
       for (int d = 0; d < 3; ++d) acc += line_val(d, ids[d], w);
       return acc * ijac + sDg[(pp * NV + v) * NV + w];
     };
-    double mx = 0.0;
-#pragma unroll 1
-    for (int w = 0; w < NV; ++w) mx = fmax(mx, fabs(diag_val(w)));
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d)
-#pragma unroll 1
-      for (int m = 0; m <= P; ++m)
-        if (m != ids[d])
-          for (int w = 0; w < NV; ++w) mx = fmax(mx, fabs(line_val(d, m, w) * ijac));
-    int ex = 0;
-    frexp(mx, &ex);
-    const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
-    sscl[r] = scl;
+    // one pass: the entries are written unscaled (rounded to T) while the row's largest entry is
+    // found; the row's power-of-two scale 2^e2 then enters only the pivot keys. Scaling a row by a
+    // power of two commutes exactly with every operation of the elimination, so this is the
+    // elimination of the row-equilibrated block, pivot for pivot, without the scaled copy, and
+    // the result is the inverse of the block itself
     T* xr = X + (size_t)r * N;
     double* dr = a.D_out ? a.D_out + ((size_t)e * N + r) * N : nullptr;
     if (dr)
       for (int c = 0; c < N; ++c) dr[c] = 0.0;
     __syncthreads();                        // the slot is clear
+    double mx = 0.0;
 #pragma unroll 1
     for (int w = 0; w < NV; ++w) {
       const double dval = diag_val(w);
-      xr[pp * NV + w] = (T)(dval * scl);
+      mx = fmax(mx, fabs(dval));
+      xr[pp * NV + w] = (T)dval;
       if (dr) dr[pp * NV + w] = dval;
     }
 #pragma unroll 1
@@ -562,15 +571,17 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
                               : d == 1 ? ii + (P + 1) * (m + (P + 1) * kk) : ii + (P + 1) * (jj + (P + 1) * m);
         for (int w = 0; w < NV; ++w) {
           const double dval = line_val(d, m, w) * ijac;
-          xr[ss * NV + w] = (T)(dval * scl);
+          mx = fmax(mx, fabs(dval));
+          xr[ss * NV + w] = (T)dval;
           if (dr) dr[ss * NV + w] = dval;
         }
       }
+    int ex = 0;
+    frexp(mx, &ex);
+    const int e2 = (mx > 0.0 && isfinite(mx)) ? -ex : 0;
     __syncthreads();                        // every row of the slot is written
 
     bool used = false;
-    int my_step = 0;
-    T my_inv = (T)1;
     for (int k0 = 0; k0 < N; k0 += B) {
       T row[B];
 #pragma unroll
@@ -582,7 +593,7 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
       for (int j = 0; j < B; ++j) {
         const int par = j & 1;
         const T fv = row[0];
-        const unsigned key = used ? 0u : pivot_key(fv, r);
+        const unsigned key = used ? 0u : pivot_key(fv, r, e2);
         const unsigned wkey = wave_max3(key);
         if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {   // the row shifted by one, pivot last,
 #pragma unroll                                                    // so that the reads below are aligned
@@ -615,8 +626,7 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
         if (r == 0) sperm[k0 + j] = pr;
         if (is_p) {
           used = true;
-          my_step = k0 + j;
-          my_inv = ip;
+          sinv[k0 + j] = ip;
         }
         const T g = is_p ? (T)0 : fv * ip;
 #pragma unroll
@@ -695,16 +705,20 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
       }
       __syncthreads();                      // the updated columns are visible before the next panel
     }
-    __syncthreads();                        // sperm and sscl complete
+    __syncthreads();                        // sperm and sinv complete
+    // thread r writes row r of the inverse (slot row p_r), so that for each column the lanes of
+    // a wave store consecutive entries of W
+    const int prow = sperm[r];
+    const T pinv = sinv[r];
     for (int m0 = 0; m0 < N; m0 += 16) {    // sixteen loads in flight per thread, then the stores
       T xv[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) xv[u] = X[(size_t)r * N + m0 + u];
+      for (int u = 0; u < 16; ++u) xv[u] = X[(size_t)prow * N + m0 + u];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int col = sperm[m0 + u];
-        const double val = (double)(xv[u] * my_inv) * sscl[col];
-        const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
+        const double val = (double)(xv[u] * pinv);
+        const size_t o_ = ((size_t)col * ne + e) * NPAD + r;
         if (a.precision == 32)
           static_cast<float*>(a.W)[o_] = (float)val;
         else
