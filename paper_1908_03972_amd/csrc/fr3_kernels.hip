@@ -397,6 +397,104 @@ __global__ void __launch_bounds__(256) k_restrict3(int ne, int nvar, int nf1, in
   if (xc2) xc2[idx] = acc;
 }
 
+// The same restriction sum-factorised for fixed sizes: one thread per (element, variable, coarse
+// plane cc) contracts the element's fine values along k first (each fine value read once per
+// plane), then along i and j in registers
+template <int NF, int NC>
+__global__ void __launch_bounds__(256) k_restrict3t(int ne, int nvar, Mat1D3 R, const double* __restrict__ xf,
+                                                    double* __restrict__ xc, double* __restrict__ xc2) {
+  const size_t total = (size_t)nvar * NC * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int cc = (int)(rest % NC), v = (int)(rest / NC);
+  const double* base = xf + (size_t)v * NF * NF * NF * ne + e;
+  double t[NF][NF];                 // t[j][i] = sum_k R[cc][k] x[i][j][k]
+#pragma unroll
+  for (int j = 0; j < NF; ++j)
+#pragma unroll
+    for (int i = 0; i < NF; ++i) t[j][i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const double rk = R.m[cc * NF + k];
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int i = 0; i < NF; ++i) t[j][i] += rk * base[(size_t)(i + NF * (j + NF * k)) * ne];
+  }
+  double* out = xc + ((size_t)v * NC * NC * NC + (size_t)NC * NC * cc) * ne + e;
+  double* out2 = xc2 ? xc2 + ((size_t)v * NC * NC * NC + (size_t)NC * NC * cc) * ne + e : nullptr;
+#pragma unroll
+  for (int ca = 0; ca < NC; ++ca) {
+    double u[NF];                   // u[j] = sum_i R[ca][i] t[j][i]
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) a += R.m[ca * NF + i] * t[j][i];
+      u[j] = a;
+    }
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) a += R.m[cb * NF + j] * u[j];
+      out[(size_t)(ca + NC * cb) * ne] = a;
+      if (out2) out2[(size_t)(ca + NC * cb) * ne] = a;
+    }
+  }
+}
+
+// The same prolongation sum-factorised: one thread per (element, variable, fine plane fk)
+template <int NC, int NF>
+__global__ void __launch_bounds__(256) k_prolong3t(int ne, int nvar, Mat1D3 I, const double* __restrict__ xa,
+                                                   const double* __restrict__ xb, double* __restrict__ xf) {
+  const size_t total = (size_t)nvar * NF * ne;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int e = (int)(idx % ne);
+  const size_t rest = idx / ne;
+  const int fk = (int)(rest % NF), v = (int)(rest / NF);
+  const size_t off = (size_t)v * NC * NC * NC * ne + e;
+  double t[NC][NC];                 // t[b][a] = sum_c I[fk][c] d[a][b][c]
+#pragma unroll
+  for (int b = 0; b < NC; ++b)
+#pragma unroll
+    for (int a2 = 0; a2 < NC; ++a2) t[b][a2] = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double ic = I.m[fk * NC + c];
+#pragma unroll
+    for (int b = 0; b < NC; ++b)
+#pragma unroll
+      for (int a2 = 0; a2 < NC; ++a2) {
+        const size_t o = off + (size_t)(a2 + NC * (b + NC * c)) * ne;
+        const double d = xb ? (xa[o] - xb[o]) : xa[o];
+        t[b][a2] += ic * d;
+      }
+  }
+  double* out = xf + ((size_t)v * NF * NF * NF + (size_t)NF * NF * fk) * ne + e;
+#pragma unroll
+  for (int fi = 0; fi < NF; ++fi) {
+    double u[NC];                   // u[b] = sum_a I[fi][a] t[b][a]
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+      double a = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 < NC; ++a2) a += I.m[fi * NC + a2] * t[b][a2];
+      u[b] = a;
+    }
+#pragma unroll
+    for (int fj = 0; fj < NF; ++fj) {
+      double a = 0.0;
+#pragma unroll
+      for (int b = 0; b < NC; ++b) a += I.m[fj * NC + b] * u[b];
+      out[(size_t)(fi + NF * fj) * ne] += a;
+    }
+  }
+}
+
 // x_f[v][pf][e] += sum I[k][c] I[j][b] I[i][a] (xa - xb)[v][a + nc b + nc^2 c][e]
 __global__ void __launch_bounds__(256) k_prolong3(int ne, int nvar, int nc1, int nf1, Mat1D3 I,
                                                   const double* __restrict__ xa, const double* __restrict__ xb,
@@ -565,6 +663,15 @@ hipError_t launch_restrict3(const pmg_level_s& Lf, const pmg_level_s& Lc, const 
   for (int k = 0; k < Lc.n1 * Lf.n1; ++k) R.m[k] = R1[k];
   const size_t total = (size_t)nvar * Lc.np * Lc.ne;
   if (total == 0) return hipSuccess;
+  const size_t tt = (size_t)nvar * Lc.n1 * Lc.ne;   // threads of the sum-factorised kernels
+#define PMG_RESTRICT3(NF, NC)                                                                            \
+  if (Lf.n1 == NF && Lc.n1 == NC) {                                                                      \
+    hipLaunchKernelGGL((k_restrict3t<NF, NC>), dim3(blocks3(tt)), dim3(256), 0, st, Lf.ne, nvar, R, xf, xc, xc2); \
+    return hipGetLastError();                                                                            \
+  }
+  PMG_RESTRICT3(4, 3) PMG_RESTRICT3(3, 2) PMG_RESTRICT3(2, 1) PMG_RESTRICT3(4, 2) PMG_RESTRICT3(4, 1)
+  PMG_RESTRICT3(3, 1)
+#undef PMG_RESTRICT3
   hipLaunchKernelGGL(k_restrict3, dim3(blocks3(total)), dim3(256), 0, st, Lf.ne, nvar, Lf.n1, Lc.n1, R, xf, xc,
                      xc2);
   return hipGetLastError();
@@ -576,6 +683,15 @@ hipError_t launch_prolong3(const pmg_level_s& Lc, const pmg_level_s& Lf, const d
   for (int k = 0; k < Lc.n1 * Lf.n1; ++k) I.m[k] = I1[k];
   const size_t total = (size_t)nvar * Lf.np * Lf.ne;
   if (total == 0) return hipSuccess;
+  const size_t tt = (size_t)nvar * Lf.n1 * Lf.ne;   // threads of the sum-factorised kernels
+#define PMG_PROLONG3(NC, NF)                                                                             \
+  if (Lc.n1 == NC && Lf.n1 == NF) {                                                                      \
+    hipLaunchKernelGGL((k_prolong3t<NC, NF>), dim3(blocks3(tt)), dim3(256), 0, st, Lf.ne, nvar, I, xa, xb, xf); \
+    return hipGetLastError();                                                                            \
+  }
+  PMG_PROLONG3(3, 4) PMG_PROLONG3(2, 3) PMG_PROLONG3(1, 2) PMG_PROLONG3(2, 4) PMG_PROLONG3(1, 4)
+  PMG_PROLONG3(1, 3)
+#undef PMG_PROLONG3
   hipLaunchKernelGGL(k_prolong3, dim3(blocks3(total)), dim3(256), 0, st, Lf.ne, nvar, Lc.n1, Lf.n1, I, xa, xb,
                      xf);
   return hipGetLastError();
