@@ -72,17 +72,11 @@ __device__ __forceinline__ float quad_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-// 32-bit pivot key of |f|: its upper bits (the FP32 pattern, or the upper word of the FP64 one)
-// with the low 10 bits replaced by 1023 - r, so that the wave maximum also names the row or thread
-__device__ __forceinline__ unsigned pivot_key(float f, int r) {
-  return (__float_as_uint(fabsf(f)) & ~0x3FFu) | (unsigned)(1023 - r);
-}
-__device__ __forceinline__ unsigned pivot_key(double f, int r) {
-  return (((unsigned)__double2hiint(fabs(f))) & ~0x3FFu) | (unsigned)(1023 - r);
-}
-// the key of |f| 2^e2 without forming the product: e2 added to the exponent field; values whose
-// scaled exponent leaves the normal range count as zero (below) or infinity (above), and the
-// unscaled subnormals as zero
+// 32-bit pivot key of |f| 2^e2 (the row's value after equilibration by the power of two 2^e2):
+// the upper bits of that value (the FP32 pattern, or the upper word of the FP64 one), formed by
+// adding e2 to the exponent field, with the low 10 bits replaced by 1023 - r, so that the wave
+// maximum also names the row or thread; values whose scaled exponent leaves the normal range
+// count as zero (below) or infinity (above), and unscaled subnormals as zero
 __device__ __forceinline__ unsigned pivot_key(float f, int r, int e2) {
   const unsigned b = __float_as_uint(fabsf(f));
   const int eb = (int)(b >> 23) + e2;
@@ -256,7 +250,6 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, con
   __shared__ double sA[3 * NP * NV * NV];
   __shared__ double sDg[NP * NV * NV];
   __shared__ double sB[6 * NF * NV * NV];
-  __shared__ double sscl[NJ];
   __shared__ int sperm[NJ];
   __shared__ T slot[2][NW][NJ];
   __shared__ unsigned skey[2][NW];
@@ -297,26 +290,26 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, con
     if (real_row && c < N) return block_entry3<P>(a.ops, sA, sDg, sB, pp, v, c / NV, c % NV, ijac);
     return (has_row && !real_row && c == r) ? 1.0 : 0.0;   // padding: identity row
   };
-  // the row's power-of-two scale from its largest entry (in FP64), then the scaled row in T
+  // one pass: the row's entries rounded to T, unscaled, and its largest entry (in FP64), whose
+  // power-of-two scale 2^e2 enters only the pivot keys (as in the large-block kernel: the
+  // elimination of the row-equilibrated block, pivot for pivot, without the scaled copy)
   double mx = 0.0;
-#pragma unroll 1
-  for (int jc = 0; jc < H; ++jc) mx = fmax(mx, fabs(entry(h * H + jc)));
+  T row[H];
+#pragma unroll
+  for (int jc = 0; jc < H; ++jc) {
+    const double dval = entry(h * H + jc);
+    if (a.D_out && real_row && h * H + jc < N) a.D_out[((size_t)e * N + r) * N + h * H + jc] = dval;
+    mx = fmax(mx, fabs(dval));
+    row[jc] = (T)dval;
+    __builtin_amdgcn_sched_barrier(0);   // one entry at a time: keeps the assembly's registers few
+  }
   if (S == 4) {
     mx = fmax(mx, __shfl_xor(mx, 1, 64));
     mx = fmax(mx, __shfl_xor(mx, 2, 64));
   }
   int ex = 0;
   frexp(mx, &ex);
-  const double scl = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
-  T row[H];
-#pragma unroll
-  for (int jc = 0; jc < H; ++jc) {
-    const double dval = entry(h * H + jc);
-    if (a.D_out && real_row && h * H + jc < N) a.D_out[((size_t)e * N + r) * N + h * H + jc] = dval;
-    row[jc] = (T)(dval * scl);
-    __builtin_amdgcn_sched_barrier(0);   // one entry at a time: keeps the assembly's registers few
-  }
-  if (has_row && h == 0) sscl[r] = scl;
+  const int e2 = (mx > 0.0 && isfinite(mx)) ? -ex : 0;
 
   bool used = !has_row;
   int my_step = 0;
@@ -325,7 +318,7 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, con
   for (int kstep = 0; kstep < NJ; ++kstep) {
     const int par = kstep & 1;
     const T fval = (S == 4) ? quad_dpp<kQuadFirst>(row[0]) : row[0];
-    const unsigned key = (used || h != 0) ? 0u : pivot_key(fval, tid);
+    const unsigned key = (used || h != 0) ? 0u : pivot_key(fval, tid, e2);
     const unsigned wkey = wave_max3(key);
     const int wtid = 1023 - (int)(wkey & 0x3FFu);
     if (wkey != 0u && tid >= wtid && tid < wtid + S) {
@@ -387,7 +380,7 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, con
     for (int jc = 0; jc < H; ++jc) {
       const int col = sperm[h * H + jc];
       if (col >= N) continue;
-      const double val = (double)(row[jc] * my_inv) * sscl[col];
+      const double val = (double)(row[jc] * my_inv);
       const size_t o_ = ((size_t)col * ne + e) * NPAD + my_step;
       if (a.precision == 32)
         static_cast<float*>(a.W)[o_] = (float)val;
