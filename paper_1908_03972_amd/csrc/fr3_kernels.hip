@@ -324,7 +324,9 @@ __global__ void __launch_bounds__((Cfg3<P, EPW_>::NT)) k_fr3(ResArgs3 a) {
         if constexpr (MODE == 2) {
           const float* w0 = static_cast<const float*>(a.W) + (size_t)e2 * NPAD + 4 * l;
           float accf[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
+          // block columns requested before the first is waited for: all 40 at P1 and 16 at P2 (9-10%
+          // faster than 8 on the sphere levels: more bytes in flight per CU), 8 at P3 (no gain)
+#pragma unroll (N <= 40 ? 40 : N <= 135 ? 16 : 8)
           for (int c = 0; c < N; ++c) {
             const float4 w = *reinterpret_cast<const float4*>(w0 + c * cs);
             const float fc = (float)fe[c];
