@@ -237,16 +237,15 @@ __device__ __forceinline__ double block_entry3(const Ops1D& o, const double* sA,
   return dval;
 }
 
-// Element blocks held in registers (n <= 135): S threads per row, Gauss-Jordan in T arithmetic
-// (T = float for FP32 inverses at P = 2, double otherwise). The pointwise derivatives are computed
-// here with dual numbers, or, with FROM_PJ, copied from the global array k_point_jac3 wrote (the
-// kernel then carries no dual-number code and needs far fewer registers).
-template <int P, int S, typename T, bool FROM_PJ>
-__global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, const double* __restrict__ pj) {
+// Element blocks held in registers (n <= 135): S threads per row, Gauss-Jordan in FP64 (T); the
+// pointwise derivatives are computed here with dual numbers.
+template <int P, int S>
+__global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
   using C = Rows3<P, S>;
+  using T = double;
   constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NJ = C::NJ, H = C::H, NW = C::NW, NT = C::NT,
                 NPAD = C::NPAD;
-  __shared__ double sq[FROM_PJ ? 1 : NV * NP];
+  __shared__ double sq[NV * NP];
   __shared__ double sA[3 * NP * NV * NV];
   __shared__ double sDg[NP * NV * NV];
   __shared__ double sB[6 * NF * NV * NV];
@@ -260,24 +259,7 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a, con
   const int lane = tid & 63, wv = tid >> 6;
   const size_t sstride = (size_t)NP * ne;
 
-  if constexpr (FROM_PJ) {   // sA, sDg, sB one after the other in the element's record
-    const double* src = pj + (size_t)e * jac3_point_elems(P);
-    constexpr int NA = 3 * NP * NV * NV, ND = NP * NV * NV, NB = 6 * NF * NV * NV, NALL = NA + ND + NB, U = 4;
-    for (int t0 = tid; t0 < NALL; t0 += U * NT) {   // U loads in flight per thread
-      double vv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) vv[u] = (t0 + u * NT < NALL) ? src[t0 + u * NT] : 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * NT;
-        if (t < NA) sA[t] = vv[u];
-        else if (t < NA + ND) sDg[t - NA] = vv[u];
-        else if (t < NALL) sB[t - NA - ND] = vv[u];
-      }
-    }
-  } else {
-    element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
-  }
+  element_point_jacobians3<P, NT>(a, e, sq, sA, sDg, sB);
   __syncthreads();
 
   const bool has_row = tid < S * NJ;
@@ -722,12 +704,214 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
   if (bad) *a.flag = 1;
 }
 
+// Mid-size element blocks held in LDS (P = 2: n = 135 padded to NR = 144 with identity rows and
+// columns), inverted in FP32 by the panel Gauss-Jordan of the large-block kernel, but with the whole
+// block in LDS: one workgroup of three waves per element, the panels' B = 16 steps on the rows'
+// panel entries in registers, every other column's rank-16 update on the FP32 matrix cores with
+// its operands and accumulators read from and written back to LDS. The pointwise derivatives come
+// from k_point_jac3; the row's power-of-two equilibration enters only the pivot keys.
+template <int P>
+struct Lds3 {
+  static constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1, NV = 5, N = NV * NP;
+  static constexpr int NR = (N + 15) / 16 * 16;     // rows and columns with the identity padding
+  static constexpr int NPAD = (N + 3) / 4 * 4;      // row stride of the stored inverse
+  static constexpr int XS = NR + 4;                 // LDS row stride (words)
+  static constexpr int B = 16, NT = 192, NW = 3;
+  static constexpr int TPW = NR / 16 / NW;          // 16-row tiles per wave in the update
+  static constexpr int NPJ = (4 * NP + 6 * NF) * NV * NV;
+  static_assert(NR % (16 * NW) == 0 && NR % B == 0 && NR <= NT, "whole tiles per wave, one thread per row");
+  static_assert(NT <= 1023, "pivot keys carry the row in 10 bits");
+};
+
+template <int P>
+__global__ void __launch_bounds__(Lds3<P>::NT) k_jac3_lds(JacArgs3 a, const double* __restrict__ pj) {
+  using C = Lds3<P>;
+  constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NR = C::NR, NPAD = C::NPAD, XS = C::XS, B = C::B,
+                NT = C::NT, NW = C::NW, TPW = C::TPW, NPJ = C::NPJ;
+  __shared__ float X[NR * XS];
+  __shared__ double sj[NPJ];                 // sA, sDg, sB one after the other
+  __shared__ float xp[B * XS];               // old pivot-row values of a panel
+  __shared__ float slot[2][NW][B];
+  __shared__ int sperm[NR];
+  __shared__ float sinv[NR];
+  __shared__ unsigned skey[2][NW];
+
+  const int ne = a.lv.ne;
+  const int e = blockIdx.x;
+  const int r = threadIdx.x;
+  const int lane = r & 63, wv = r >> 6;
+  const size_t sstride = (size_t)NP * ne;
+  {
+    const double* src = pj + (size_t)e * NPJ;
+    constexpr int U = 4;
+    for (int t0 = r; t0 < NPJ; t0 += U * NT) {   // U loads in flight per thread
+      double vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) vv[u] = (t0 + u * NT < NPJ) ? src[t0 + u * NT] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (t0 + u * NT < NPJ) sj[t0 + u * NT] = vv[u];
+    }
+    for (int t = r; t < NR * XS; t += NT) X[t] = 0.f;
+  }
+  __syncthreads();
+  const double* sA = sj;
+  const double* sDg = sj + 3 * NP * NV * NV;
+  const double* sB = sDg + NP * NV * NV;
+
+  // row r: the 1 + 3P points of the row point's three tensor lines (the point itself once);
+  // padding rows are identity rows
+  int e2 = 0;
+  if (r < N) {
+    const int pp = r / NV, v = r % NV;
+    const int ii = pp % (P + 1), jj = (pp / (P + 1)) % (P + 1), kk = pp / ((P + 1) * (P + 1));
+    const double ijac = a.lv.met[9 * sstride + (size_t)pp * ne + e];
+    double* dr = a.D_out ? a.D_out + ((size_t)e * N + r) * N : nullptr;
+    if (dr)
+      for (int c = 0; c < N; ++c) dr[c] = 0.0;
+    double mx = 0.0;
+#pragma unroll 1
+    for (int t = 0; t < 1 + 3 * P; ++t) {
+      int ss = pp;
+      if (t > 0) {
+        const int d = (t - 1) / P, mo = (t - 1) % P;
+        const int own = d == 0 ? ii : d == 1 ? jj : kk;
+        const int m = mo < own ? mo : mo + 1;   // the other points of line d
+        ss = d == 0 ? m + (P + 1) * (jj + (P + 1) * kk)
+                    : d == 1 ? ii + (P + 1) * (m + (P + 1) * kk) : ii + (P + 1) * (jj + (P + 1) * m);
+      }
+#pragma unroll 1
+      for (int w = 0; w < NV; ++w) {
+        const double dval = block_entry3<P>(a.ops, sA, sDg, sB, pp, v, ss, w, ijac);
+        mx = fmax(mx, fabs(dval));
+        X[r * XS + ss * NV + w] = (float)dval;
+        if (dr) dr[ss * NV + w] = dval;
+      }
+    }
+    int ex = 0;
+    frexp(mx, &ex);
+    e2 = (mx > 0.0 && isfinite(mx)) ? -ex : 0;
+  } else if (r < NR) {
+    X[r * XS + r] = 1.f;
+  }
+  __syncthreads();
+
+  bool used = r >= NR;
+  bool bad = false;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int k0 = 0; k0 < NR; k0 += B) {
+    float row[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) row[j] = (r < NR) ? X[r * XS + k0 + j] : 0.f;
+    // column cycling as in the large-block kernel
+#pragma unroll 1
+    for (int j = 0; j < B; ++j) {
+      const int par = j & 1;
+      const float fv = row[0];
+      const unsigned key = used ? 0u : pivot_key(fv, r, e2);
+      const unsigned wkey = wave_max3(key);
+      if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {   // the row shifted by one, pivot last
+#pragma unroll
+        for (int c = 0; c < B - 1; ++c) slot[par][wv][c] = row[c + 1];
+        slot[par][wv][B - 1] = row[0];
+      }
+      if (lane == 0) skey[par][wv] = wkey;
+      __syncthreads();
+      int win = 0;
+      unsigned bk = skey[par][0];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) {
+        const unsigned k2 = skey[par][w2];
+        win = (k2 > bk) ? w2 : win;
+        bk = (k2 > bk) ? k2 : bk;
+      }
+      int pr = 1023 - (int)(bk & 0x3FFu);
+      if (bk == 0u || pr >= NR) {
+        bad = true;
+        pr = 0;
+      }
+      const float* prw = slot[par][win];
+      float piv = prw[B - 1];
+      if (piv == 0.f || !isfinite(piv)) {
+        bad = true;
+        piv = 1.f;
+      }
+      const float ip = 1.f / piv;
+      const bool is_p = (r == pr);
+      if (r == 0) sperm[k0 + j] = pr;
+      if (is_p) {
+        used = true;
+        sinv[k0 + j] = ip;
+      }
+      const float g = is_p ? 0.f : fv * ip;
+#pragma unroll
+      for (int c = 0; c < B - 1; ++c) row[c] = fmaf(-g, prw[c], row[c + 1]);
+      row[B - 1] = is_p ? 1.f : -g;
+    }
+    if (r < NR) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) X[r * XS + k0 + j] = row[j];
+    }
+    __syncthreads();                      // the panel and sperm are complete
+    // the old values of the panel's pivot rows, then the rank-16 update of every other column
+    for (int t = r; t < B * NR; t += NT) {
+      const int k = t / NR, c = t % NR;
+      xp[k * XS + c] = X[sperm[k0 + k] * XS + c];
+    }
+    float uop[TPW][B / 4];
+#pragma unroll
+    for (int TT = 0; TT < TPW; ++TT) {
+#pragma unroll
+      for (int s4 = 0; s4 < B / 4; ++s4) {
+        const int row_ = 16 * (TPW * wv + TT) + lr, m = k0 + 4 * s4 + lk;
+        const float u = X[row_ * XS + m];
+        uop[TT][s4] = (sperm[m] == row_) ? u - 1.f : u;
+      }
+    }
+    __syncthreads();                      // xp complete, every panel value read
+#pragma unroll 1
+    for (int cg = 0; cg < NR; cg += 16) {
+      if (cg == k0) continue;             // B == 16: the panel is one column group
+      flt4 acc[TPW];
+#pragma unroll
+      for (int TT = 0; TT < TPW; ++TT) {
+#pragma unroll
+        for (int v2 = 0; v2 < 4; ++v2) acc[TT][v2] = X[(16 * (TPW * wv + TT) + 4 * lk + v2) * XS + cg + lr];
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < B / 4; ++s4) {
+        const float xb = xp[(4 * s4 + lk) * XS + cg + lr];
+#pragma unroll
+        for (int TT = 0; TT < TPW; ++TT) acc[TT] = mfma16x16x4(uop[TT][s4], xb, acc[TT]);
+      }
+#pragma unroll
+      for (int TT = 0; TT < TPW; ++TT) {
+#pragma unroll
+        for (int v2 = 0; v2 < 4; ++v2) X[(16 * (TPW * wv + TT) + 4 * lk + v2) * XS + cg + lr] = acc[TT][v2];
+      }
+    }
+    __syncthreads();                      // the updated columns are visible before the next panel
+  }
+  if (bad) *a.flag = 1;
+  // row i of the inverse is slot row p_i = sperm[i] over 1/f_i, columns in pivot order
+  if (r < N) {
+    const int prow = sperm[r];
+    const float pinv = sinv[r];
+#pragma unroll 4
+    for (int m = 0; m < N; ++m) {
+      const int col = sperm[m];
+      if (col >= N) continue;             // only a singular block (flagged) pivots on a padding row
+      const double val = (double)(X[prow * XS + m] * pinv);
+      static_cast<float*>(a.W)[((size_t)col * ne + e) * NPAD + r] = (float)val;
+    }
+  }
+}
+
 // ---- launchers -------------------------------------------------------------------------------
 
 template <int P, int S>
 static hipError_t launch_jac3_p(const JacArgs3& a, int ne, hipStream_t st) {
-  hipLaunchKernelGGL((k_jac3_rows<P, S, double, false>), dim3(ne), dim3(Rows3<P, S>::NT), 0, st, a,
-                     (const double*)nullptr);
+  hipLaunchKernelGGL((k_jac3_rows<P, S>), dim3(ne), dim3(Rows3<P, S>::NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -748,13 +932,13 @@ hipError_t launch_jacobian3(const pmg_level_s& L, const double* q, double dtau, 
     case 0: return launch_jac3_p<0, 1>(a, L.ne, st);
     case 1: return launch_jac3_p<1, 1>(a, L.ne, st);
     case 2: {
-      // FP64 inverses: one kernel, the pointwise derivatives computed in place; FP32 inverses: the
-      // pointwise derivatives first, then an FP32 elimination without dual numbers (32 against
-      // 39 ms on the 36 864-element sphere; the FP64 elimination split the same way took 43.5 ms)
+      // FP64 inverses: the register-row kernel, pointwise derivatives computed in place (40 ms on
+      // the 36 864-element sphere); FP32 inverses: the pointwise derivatives first, then the block
+      // in LDS eliminated in FP32 with matrix-core updates (21 ms; the register-row elimination in
+      // FP32 took 28 ms, split the same way in FP64 43.5 ms)
       if (fac.precision != 32 || !fac.ws) return launch_jac3_p<2, 4>(a, L.ne, st);
       hipLaunchKernelGGL(k_point_jac3<2>, dim3(L.ne), dim3(256), 0, st, a, fac.ws);
-      hipLaunchKernelGGL((k_jac3_rows<2, 4, float, true>), dim3(L.ne), dim3(Rows3<2, 4>::NT), 0, st, a,
-                         (const double*)fac.ws);
+      hipLaunchKernelGGL(k_jac3_lds<2>, dim3(L.ne), dim3(Lds3<2>::NT), 0, st, a, (const double*)fac.ws);
       return hipGetLastError();
     }
     case 3: {
