@@ -11,12 +11,12 @@
 #include "internal.hpp"
 #include "jac3.hpp"
 #include "physics3.hpp"
+#include "wave_ops.hpp"
 
 namespace pmg {
 
 // ---- element blocks (eqs. (28)-(30)) and their inverses ----------------------------------
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 struct JacArgs3 {
@@ -48,15 +48,6 @@ struct Rows3 {
   static_assert(S * NJ <= 1023, "pivot keys carry the thread index in 10 bits");
 };
 
-__device__ __forceinline__ unsigned wave_max3(unsigned v) {
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xf, 0xf, false));   // row_ror:1
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xf, 0xf, false));   // row_ror:2
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));   // row_ror:4
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));   // row_ror:8
-  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
-  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
-  return max(max(a, b), max(c, d));
-}
 
 // a double from a lane of the same quad selected by the DPP quad permutation CTRL
 template <int CTRL>
@@ -72,23 +63,6 @@ __device__ __forceinline__ float quad_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-// 32-bit pivot key of |f| 2^e2 (the row's value after equilibration by the power of two 2^e2):
-// the upper bits of that value (the FP32 pattern, or the upper word of the FP64 one), formed by
-// adding e2 to the exponent field, with the low 10 bits replaced by 1023 - r, so that the wave
-// maximum also names the row or thread; values whose scaled exponent leaves the normal range
-// count as zero (below) or infinity (above), and unscaled subnormals as zero
-__device__ __forceinline__ unsigned pivot_key(float f, int r, int e2) {
-  const unsigned b = __float_as_uint(fabsf(f));
-  const int eb = (int)(b >> 23) + e2;
-  const unsigned sb = ((b >> 23) == 0u || eb <= 0) ? 0u : (eb >= 255 ? 0x7F800000u : b + ((unsigned)e2 << 23));
-  return (sb & ~0x3FFu) | (unsigned)(1023 - r);
-}
-__device__ __forceinline__ unsigned pivot_key(double f, int r, int e2) {
-  const unsigned b = (unsigned)__double2hiint(fabs(f));
-  const int eb = (int)(b >> 20) + e2;
-  const unsigned sb = ((b >> 20) == 0u || eb <= 0) ? 0u : (eb >= 2047 ? 0x7FF00000u : b + ((unsigned)e2 << 20));
-  return (sb & ~0x3FFu) | (unsigned)(1023 - r);
-}
 
 // The element's state (sq, [Nv][Np]) and its pointwise derivatives into LDS, all threads of the
 // workgroup taking part: sA[d] = dF~_d/dq at each solution point ([(pp Nv + v) Nv + w], three
@@ -301,7 +275,7 @@ __global__ void __launch_bounds__((Rows3<P, S>::NT)) k_jac3_rows(JacArgs3 a) {
     const int par = kstep & 1;
     const T fval = (S == 4) ? quad_dpp<kQuadFirst>(row[0]) : row[0];
     const unsigned key = (used || h != 0) ? 0u : pivot_key(fval, tid, e2);
-    const unsigned wkey = wave_max3(key);
+    const unsigned wkey = wave_max_u32(key);
     const int wtid = 1023 - (int)(wkey & 0x3FFu);
     if (wkey != 0u && tid >= wtid && tid < wtid + S) {
 #pragma unroll
@@ -428,22 +402,6 @@ struct Big3 {
   static_assert(N <= 1023, "pivot keys carry the row in 10 bits");
 };
 
-typedef float flt4 __attribute__((ext_vector_type(4)));
-
-
-// One 16x16x4 matrix-core step in T, and the row i of the 16 x 16 result held by accumulator
-// register v in lane group lk: D[i][j] sits in lane j + 16 (i / 4), register i % 4 for FP32 and
-// in lane j + 16 (i % 4), register i / 4 for FP64 (both checked on gfx950)
-__device__ __forceinline__ flt4 mfma16x16x4(float a, float b, flt4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-template <typename T>
-__device__ __forceinline__ int acc_row(int lk, int v) {
-  return sizeof(T) == 4 ? 4 * lk + v : lk + 4 * v;
-}
 
 // The FP32 instance is held to four waves per SIMD (at most 128 registers): two workgroups of five
 // waves are then resident on each CU, and one's panel steps overlap the other's memory-bound
@@ -569,7 +527,7 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
         const int par = j & 1;
         const T fv = row[0];
         const unsigned key = used ? 0u : pivot_key(fv, r, e2);
-        const unsigned wkey = wave_max3(key);
+        const unsigned wkey = wave_max_u32(key);
         if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {   // the row shifted by one, pivot last,
 #pragma unroll                                                    // so that the reads below are aligned
           for (int c = 0; c < B - 1; ++c) slot[(par * NW + wv) * B + c] = row[c + 1];
@@ -809,7 +767,7 @@ __global__ void __launch_bounds__(Lds3<P>::NT) k_jac3_lds(JacArgs3 a, const doub
       const int par = j & 1;
       const float fv = row[0];
       const unsigned key = used ? 0u : pivot_key(fv, r, e2);
-      const unsigned wkey = wave_max3(key);
+      const unsigned wkey = wave_max_u32(key);
       if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {   // the row shifted by one, pivot last
 #pragma unroll
         for (int c = 0; c < B - 1; ++c) slot[par][wv][c] = row[c + 1];

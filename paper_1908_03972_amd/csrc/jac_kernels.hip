@@ -336,6 +336,202 @@ static hipError_t launch_jac_rows(const JacArgs& a, int ne, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Blocks with FP32 inverses at P = 4 (n = 100 padded to NR = 112 with identity rows and columns)
+// held in LDS and inverted in FP32 by the panel Gauss-Jordan of the hexahedral kernels: panels of
+// 16 columns whose steps run on the rows' panel entries in registers (one thread per row, column
+// cycling, unnormalised pivot rows, the row's power-of-two equilibration in the pivot keys), then
+// the rank-16 update of every other column on the FP32 matrix cores, accumulators and operands in
+// LDS. The pointwise derivatives are computed as in k_jac_rows; viscous blocks subtract Dv.
+template <int P>
+struct LdsCfg {
+  static constexpr int N1 = P + 1, NP = N1 * N1, NV = 4, N = NV * NP;
+  static constexpr int NR = (N + 15) / 16 * 16, XS = NR + 4, B = 16, NW = 2, NT = 64 * NW;
+  static constexpr int TILES = NR / 16, TPW = (TILES + NW - 1) / NW;
+  static_assert(NR <= NT, "one thread per row");
+};
+
+template <int P>
+__global__ void __launch_bounds__(LdsCfg<P>::NT) k_jac_lds(JacArgs a) {
+  using C = LdsCfg<P>;
+  constexpr int N1 = C::N1, NP = C::NP, NV = C::NV, N = C::N, NR = C::NR, XS = C::XS, B = C::B, NW = C::NW,
+                NT = C::NT, TILES = C::TILES, TPW = C::TPW;
+  __shared__ float X[NR * XS];
+  __shared__ float xp[B * XS];
+  __shared__ double sq[NV * NP];
+  __shared__ double sAF[NP * 16], sAG[NP * 16], sDg[NP * 16];
+  __shared__ double sB[4 * N1 * 16];
+  __shared__ float slot[2][NW][B];
+  __shared__ int sperm[NR];
+  __shared__ float sinv[NR];
+  __shared__ unsigned skey[2][NW];
+
+  const int ne = a.lv.ne;
+  const int e = blockIdx.x;
+  const int r = threadIdx.x;
+  const int lane = r & 63, wv = r >> 6;
+  const size_t sstride = (size_t)NP * ne;
+  const Ops1D& o = a.ops;
+
+  for (int t = r; t < NV * NP; t += NT) {
+    const int v = t / NP, pp = t % NP;
+    sq[t] = a.q[v * sstride + (size_t)pp * ne + e];
+  }
+  for (int t = r; t < NR * XS; t += NT) X[t] = 0.f;
+  __syncthreads();
+  for (int t = r; t < NP * NV; t += NT) point_jacobian(a, e, sq, t, NP, ne, sstride, sAF, sAG, sDg);
+  for (int t = r; t < 4 * N1 * NV; t += NT) face_jacobian(a, e, sq, t, N1, NP, ne, sstride, sB);
+  __syncthreads();
+
+  // row r of D_e (every column: viscous blocks couple beyond the two tensor lines), rounded to
+  // FP32; its largest entry sets the power-of-two scale of the pivot keys. Padding rows: identity
+  int e2 = 0;
+  if (r < N) {
+    const int pp = r / NV, v = r % NV, i = pp % N1, jj = pp / N1;
+    const double ijac = a.lv.met[4 * sstride + (size_t)pp * ne + e];
+    double mx = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < N; ++c) {
+      const int ss = c / NV, w = c % NV, k = ss % N1, l = ss / N1;
+      double acc = 0.0;
+      if (l == jj) {
+        const double cx = o.D[i * N1 + k] - o.gL[i] * o.lm[k] - o.gR[i] * o.lp[k];
+        acc += cx * sAF[(ss * NV + v) * NV + w] + o.gL[i] * o.lm[k] * sB[((0 * N1 + jj) * NV + v) * NV + w] +
+               o.gR[i] * o.lp[k] * sB[((1 * N1 + jj) * NV + v) * NV + w];
+      }
+      if (k == i) {
+        const double cy = o.D[jj * N1 + l] - o.gL[jj] * o.lm[l] - o.gR[jj] * o.lp[l];
+        acc += cy * sAG[(ss * NV + v) * NV + w] + o.gL[jj] * o.lm[l] * sB[((2 * N1 + i) * NV + v) * NV + w] +
+               o.gR[jj] * o.lp[l] * sB[((3 * N1 + i) * NV + v) * NV + w];
+      }
+      double dval = acc * ijac;
+      if (pp == ss) dval += sDg[(pp * NV + v) * NV + w];
+      if (a.Dv) dval -= a.Dv[((size_t)e * N + r) * N + c];
+      if (a.D_out) a.D_out[((size_t)e * N + r) * N + c] = dval;
+      mx = fmax(mx, fabs(dval));
+      X[r * XS + c] = (float)dval;
+    }
+    int ex = 0;
+    frexp(mx, &ex);
+    e2 = (mx > 0.0 && isfinite(mx)) ? -ex : 0;
+  } else if (r < NR) {
+    X[r * XS + r] = 1.f;
+  }
+  __syncthreads();
+
+  bool used = r >= NR;
+  bool bad = false;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int k0 = 0; k0 < NR; k0 += B) {
+    float row[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) row[j] = (r < NR) ? X[r * XS + k0 + j] : 0.f;
+#pragma unroll 1
+    for (int j = 0; j < B; ++j) {
+      const int par = j & 1;
+      const float fv = row[0];
+      const unsigned key = used ? 0u : pivot_key(fv, r, e2);
+      const unsigned wkey = wave_max_u32(key);
+      if (wkey != 0u && r == 1023 - (int)(wkey & 0x3FFu)) {   // the row shifted by one, pivot last
+#pragma unroll
+        for (int c = 0; c < B - 1; ++c) slot[par][wv][c] = row[c + 1];
+        slot[par][wv][B - 1] = row[0];
+      }
+      if (lane == 0) skey[par][wv] = wkey;
+      __syncthreads();
+      int win = 0;
+      unsigned bk = skey[par][0];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) {
+        const unsigned k2 = skey[par][w2];
+        win = (k2 > bk) ? w2 : win;
+        bk = (k2 > bk) ? k2 : bk;
+      }
+      int pr = 1023 - (int)(bk & 0x3FFu);
+      if (bk == 0u || pr >= NR) {
+        bad = true;
+        pr = 0;
+      }
+      const float* prw = slot[par][win];
+      float piv = prw[B - 1];
+      if (piv == 0.f || !isfinite(piv)) {
+        bad = true;
+        piv = 1.f;
+      }
+      const float ip = 1.f / piv;
+      const bool is_p = (r == pr);
+      if (r == 0) sperm[k0 + j] = pr;
+      if (is_p) {
+        used = true;
+        sinv[k0 + j] = ip;
+      }
+      const float g = is_p ? 0.f : fv * ip;
+#pragma unroll
+      for (int c = 0; c < B - 1; ++c) row[c] = fmaf(-g, prw[c], row[c + 1]);
+      row[B - 1] = is_p ? 1.f : -g;
+    }
+    if (r < NR) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) X[r * XS + k0 + j] = row[j];
+    }
+    __syncthreads();                      // the panel and sperm are complete
+    for (int t = r; t < B * NR; t += NT) {
+      const int k = t / NR, c = t % NR;
+      xp[k * XS + c] = X[sperm[k0 + k] * XS + c];
+    }
+    float uop[TPW][B / 4];
+#pragma unroll
+    for (int TT = 0; TT < TPW; ++TT) {
+      const int tile = TPW * wv + TT;
+#pragma unroll
+      for (int s4 = 0; s4 < B / 4; ++s4) {
+        const int row_ = 16 * tile + lr, m = k0 + 4 * s4 + lk;
+        const float u = tile < TILES ? X[row_ * XS + m] : 0.f;
+        uop[TT][s4] = (tile < TILES && sperm[m] == row_) ? u - 1.f : u;
+      }
+    }
+    __syncthreads();                      // xp complete, every panel value read
+#pragma unroll 1
+    for (int cg = 0; cg < NR; cg += 16) {
+      if (cg == k0) continue;             // B == 16: the panel is one column group
+      flt4 acc[TPW];
+#pragma unroll
+      for (int TT = 0; TT < TPW; ++TT) {
+        const int tile = TPW * wv + TT;
+#pragma unroll
+        for (int v2 = 0; v2 < 4; ++v2)
+          acc[TT][v2] = tile < TILES ? X[(16 * tile + 4 * lk + v2) * XS + cg + lr] : 0.f;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < B / 4; ++s4) {
+        const float xb = xp[(4 * s4 + lk) * XS + cg + lr];
+#pragma unroll
+        for (int TT = 0; TT < TPW; ++TT) acc[TT] = mfma16x16x4(uop[TT][s4], xb, acc[TT]);
+      }
+#pragma unroll
+      for (int TT = 0; TT < TPW; ++TT) {
+        const int tile = TPW * wv + TT;
+        if (tile < TILES) {
+#pragma unroll
+          for (int v2 = 0; v2 < 4; ++v2) X[(16 * tile + 4 * lk + v2) * XS + cg + lr] = acc[TT][v2];
+        }
+      }
+    }
+    __syncthreads();                      // the updated columns are visible before the next panel
+  }
+  if (bad) *a.flag = 1;
+  // row r of the inverse: slot row sperm[r] over its pivot, columns in pivot order
+  if (r < N) {
+    const int prow = sperm[r];
+    const float pinv = sinv[r];
+#pragma unroll 4
+    for (int m = 0; m < N; ++m) {
+      const int col = sperm[m];
+      if (col >= N) continue;             // only a singular block (flagged) pivots on a padding row
+      static_cast<float*>(a.W)[((size_t)col * ne + e) * N + r] = X[prow * XS + m] * pinv;
+    }
+  }
+}
+
 // Viscous part of the element blocks, dR_vis,e/dq_e (BR2, Sec. 2.3), by forward-mode duals: one
 // workgroup per element, K columns of the block per pass. Each pass seeds K unknowns of the
 // element, evaluates the element's viscous residual with the neighbours' states and gradient
@@ -570,7 +766,12 @@ hipError_t launch_jacobian(const pmg_level_s& L, const double* q, double dtau, d
     case 1: return launch_jac_rows<1, 1>(a, L.ne, st);
     case 2: return launch_jac_rows<2, 1>(a, L.ne, st);
     case 3: return launch_jac_rows<3, 1>(a, L.ne, st);
-    case 4: return launch_jac_rows<4, 2>(a, L.ne, st);
+    case 4:
+      if (fac.precision == 32 && fac.W) {   // FP32 inverses: the block in LDS, matrix-core updates
+        hipLaunchKernelGGL(k_jac_lds<4>, dim3(L.ne), dim3(LdsCfg<4>::NT), 0, st, a);
+        return hipGetLastError();
+      }
+      return launch_jac_rows<4, 2>(a, L.ne, st);
     case 5: return launch_jac_rows<5, 4>(a, L.ne, st);
     default: return hipErrorInvalidValue;
   }

@@ -17,7 +17,7 @@ from oracle import gas as OG
 from oracle import solver as OS
 from oracle.fr import FRLevel
 
-from gpu_helpers import from_dev, rel_err_per_var, rounding_floor, to_dev, tolerance
+from gpu_helpers import fp32_inverse, from_dev, rel_err_per_var, rounding_floor, to_dev, tolerance
 from patches import patch_block
 
 pytestmark = pytest.mark.gpu
@@ -39,17 +39,19 @@ def scaled_block_error(got, ref, qe, qinf):
     return float(np.max(np.abs(got - ref) * scale[None, :] / rowmax))
 
 
-def sampled_update_check(D, F, F_ulp, dq_gpu, prec, seed=3):
+def sampled_update_check(D, F, F_ulp, dq_gpu, prec, seed=3, fp32_elimination=False):
     """Sweep update of one element against the oracle's solve D dq = F. The bound is ten times
     what the same rounding does to the oracle: the stage residual from a state moved by one ulp
     (F_ulp; at low Mach number the residual amplifies rounding), and a one-ulp perturbation of D
-    (FP64 blocks) or the inverse rounded to FP32 and applied in FP32 (FP32 blocks)."""
+    (FP64 blocks) or the inverse rounded to FP32, or computed in FP32 where the GPU eliminates in
+    FP32 (P4), and applied in FP32 (FP32 blocks)."""
     ref = np.linalg.solve(D, F)
     if prec == 64:
         rng = np.random.default_rng(seed)
         alt = np.linalg.solve(D * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=D.shape)), F)
     else:
-        alt = (np.linalg.inv(D).astype(np.float32) @ F.astype(np.float32)).astype(np.float64)
+        inv32 = fp32_inverse(D) if fp32_elimination else np.linalg.inv(D)
+        alt = (inv32.astype(np.float32) @ F.astype(np.float32)).astype(np.float64)
     nv = 4
     err = rel_err_per_var(dq_gpu.reshape(-1, nv), ref.reshape(-1, nv))
     floor = np.maximum(rel_err_per_var(alt.reshape(-1, nv), ref.reshape(-1, nv)),
@@ -267,7 +269,8 @@ def test_airfoil_fullsize_blocks_and_sweep(airfoil, prec):
     for e in airfoil_sample(128, 64, 4):
         Dref = patch_block(mesh, gas, P, q, e, dtau, 0.0, qinf)
         berr = scaled_block_error(Dg[e].cpu().numpy(), Dref, q[e], qinf)
-        err, floor = sampled_update_check(Dref, F[e].ravel(), F_ulp[e].ravel(), dq[e], prec)
+        err, floor = sampled_update_check(Dref, F[e].ravel(), F_ulp[e].ravel(), dq[e], prec,
+                                          fp32_elimination=True)
         print("airfoil e", e, "block err", berr, "update err", err, "floor", floor)
         assert berr < 1e-12
         assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (e, err, floor)
@@ -334,7 +337,8 @@ def test_viscous_fullsize_blocks_and_sweep(viscous):
     for e in airfoil_sample(256, 96, 5):
         Dref = patch_block(mesh, gas, P, q, e, dtau, c_mass, qinf)
         berr = scaled_block_error(Dg[e].cpu().numpy(), Dref, q[e], qinf)
-        err, floor = sampled_update_check(Dref, F[e].ravel(), F_ulp[e].ravel(), dq[e], prec)
+        err, floor = sampled_update_check(Dref, F[e].ravel(), F_ulp[e].ravel(), dq[e], prec,
+                                          fp32_elimination=True)
         print("viscous e", e, "block err", berr, "update err", err, "floor", floor)
         assert berr < 1e-11
         assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (e, err, floor)
