@@ -602,13 +602,15 @@ def small_vortex_block(api, torch, forms):
 TIMEREF_STEPS = {2: (100, 200, 400), 3: (100, 200, 400), 4: (40, 80, 120)}
 
 
-def time_refinement_block(api, torch, schemes=(2, 3, 4), n=50, prec=32, first_guess="previous", steps=None):
+def time_refinement_block(api, torch, schemes=(2, 3, 4), n=50, prec=32, first_guess="previous", steps=None,
+                          later_guess="predictor", ser_floor=False):
     """Sec. 4.1's time-refinement study (Table 1's setting): the isentropic vortex at Ma 0.005 on
     the periodic [-10, 10]^2 square with n x n elements, P5 with P{5-3-1} and I{20-20-40}, dtau
     0.01 -> 10, blocks rebuilt every 10 V-cycles, every implicit stage solved to a 1e-4 relative
     drop (at most 200 V-cycles), advanced over one period t = 20 with the step counts of Table 1,
     the first step's stages from the previous stage value and later ones from the explicit
-    predictor. Errors are RMS over the solution points (uniform mesh) against the exact vortex,
+    predictor (or, with later_guess="previous", from the previous stage value throughout; with
+    ser_floor the SER law never takes dtau below 0.01). Errors are RMS over the solution points (uniform mesh) against the exact vortex,
     which is back at its start after one period; orders from successive step sizes, both
     against the exact solution and from the differences of successive solutions."""
     vs = W.VortexSpec(length=20.0, ma_inf=0.005)
@@ -622,8 +624,8 @@ def time_refinement_block(api, torch, schemes=(2, 3, 4), n=50, prec=32, first_gu
     q0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(exact - qinf, -1, 0))).cuda()
     facs = [api.Factors(lv, prec) for lv in levels]
     solvers = [api.StageSolver(levels, facs, nsm, dtau_init=0.01, dtau_max=10.0, refresh_every=10, freeze_at_max=True,
-                               tol_rel=1e-4, max_vcycles=200, use_graph=True, stage_guess=g)
-               for g in (first_guess, "predictor")]
+                               tol_rel=1e-4, max_vcycles=200, use_graph=True, stage_guess=g, ser_floor=ser_floor)
+               for g in (first_guess, later_guess)]
 
     def rho_u_p(x):
         p, u, T = x[..., 0], x[..., 1], x[..., 3]
@@ -632,7 +634,8 @@ def time_refinement_block(api, torch, schemes=(2, 3, 4), n=50, prec=32, first_gu
     ref = rho_u_p(exact)
     out = {"workload": f"vortex Ma 0.005, periodic [-10,10]^2, {n}x{n} quads, P5, P{{5-3-1}} I{{20-20-40}}, "
                        f"dtau 0.01->10, stage tol 1e-4, one period t=20, FP{prec} blocks",
-           "error": "RMS over solution points against the exact vortex (rho, u, p)"}
+           "error": "RMS over solution points against the exact vortex (rho, u, p)",
+           "stage_guess": [first_guess, later_guess], "ser_floor": bool(ser_floor)}
     for scheme in schemes:
         res = {"dt": [], "err": [], "stages": 0, "stages_converged": 0, "vcycles": 0, "seconds": 0.0}
         sols = []
@@ -772,6 +775,12 @@ def main():
     ap.add_argument("--airfoil-vcycles", type=int, default=600)
     ap.add_argument("--sphere-vcycles", type=int, default=200)
     ap.add_argument("--viscous-vcycles", type=int, default=10, help="V-cycles per stage in the viscous batch")
+    ap.add_argument("--timeref-mode", choices=("predictor", "floor"), default="predictor",
+                    help="time refinement: later stages from the explicit predictor, or from the previous stage "
+                         "value with the SER floor")
+    ap.add_argument("--timeref-schemes", default="2,3,4")
+    ap.add_argument("--timeref-steps", default="", help="comma list of step counts for every scheme (default: "
+                                                      "the per-scheme counts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -814,7 +823,13 @@ def main():
         detail["viscous_batch_256x96"] = viscous_batch_block(api, torch, args.viscous_vcycles)
         progress("viscous batch")
     if "timeref" in extras:
-        detail["time_refinement_vortex50_P5"] = time_refinement_block(api, torch)
+        floor = args.timeref_mode == "floor"
+        schemes = tuple(int(x) for x in args.timeref_schemes.split(",") if x)
+        steps = ({sc: tuple(int(x) for x in args.timeref_steps.split(",")) for sc in schemes}
+                 if args.timeref_steps else None)
+        detail["time_refinement_vortex50_P5"] = time_refinement_block(
+            api, torch, schemes=schemes, steps=steps, later_guess="previous" if floor else "predictor",
+            ser_floor=floor)
     if "sphere2" in extras:
         detail["sphere_cubed_16x16x24_P2_steady"] = sphere_block(api, torch, ["mixed", "fp64"], args.sphere_vcycles,
                                                                  args.kernel_reps)

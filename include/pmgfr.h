@@ -326,6 +326,9 @@ typedef struct {
                                      unsolved initial condition R(q^n) carries the scheme's
                                      truncation error and the predictor is far off: use 0.
                                      esdirk_stage_solve starts from the q it is given         */
+  int32_t ser_floor;              /* 1: the SER law of eq. (31) never takes dtau below its value at
+                                     V-cycle 0 (dtau_init, or cfl_init dtau_min); the paper
+                                     states no lower bound. 0: none (the default)               */
 } pmg_solve_opts;
 
 typedef struct {

@@ -4,7 +4,8 @@ continuation and the ESDIRK driver (Secs. 2.4 and 3).
 Readings, where the paper is silent:
 * ||F|| is the Euclidean norm over every solution point and variable of the fine level.
 * Pseudo time: dtau_0 = dtau_init at the start of every stage solve; afterwards the SER
-  law of eq. (31), dtau_m = min(dtau_{m-1} (r_{m-1}/r_m)^1.5, dtau_max), with one global
+  law of eq. (31), dtau_m = min(dtau_{m-1} (r_{m-1}/r_m)^1.5, dtau_max) (optionally never
+  below dtau_init: ser_floor, a reading, as eq. (31) states no lower bound), with one global
   dtau shared by all levels. (The CFL form of eqs. (31)-(33) scales the same law by the
   mesh's dtau_min.)
 * The smoother D is rebuilt on every level at V-cycles m = 0, k, 2k, ... (k = 10, Sec. 4.1);
@@ -101,6 +102,8 @@ class PMGOptions:
     dtau_init: float = 0.01
     dtau_max: float = 10.0
     ser_exp: float = 1.5
+    # a lower bound of the SER law at its V-cycle-0 value (the paper states none; a reading)
+    ser_floor: bool = False
     refresh_every: int = 10
     freeze_at_max: bool = True
     tol: float = 1e-8
@@ -231,6 +234,8 @@ class PMGSolver:
                 self.dtau = dtau_init
             else:
                 self.dtau = min(self.dtau * (r_prev / r) ** o.ser_exp, dtau_max)
+                if o.ser_floor:
+                    self.dtau = max(self.dtau, dtau_init)
             st.r_final = r
             if r == 0.0 or r / st.r0 <= o.tol:
                 st.converged = True
@@ -292,6 +297,8 @@ class PMGSolver:
                 self.dtau = dtau_init
             else:
                 self.dtau = min(self.dtau * (r_prev / r) ** o.ser_exp, dtau_max)
+                if o.ser_floor:
+                    self.dtau = max(self.dtau, dtau_init)
             st.r_final = r
             if r == 0.0 or r / st.r0 <= o.tol:
                 st.converged = True

@@ -48,6 +48,7 @@ class SolveOpts(C.Structure):
         ("tol_rel", C.c_double), ("max_vcycles", C.c_int32), ("alpha_r", C.c_double),
         ("use_graph", C.c_int32), ("use_cfl", C.c_int32), ("cfl_init", C.c_double), ("cfl_max", C.c_double),
         ("stage_guess", C.c_int32),
+        ("ser_floor", C.c_int32),
     ]
 
 

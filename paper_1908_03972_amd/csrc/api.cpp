@@ -1090,6 +1090,7 @@ struct StageRun {
   double* q = nullptr;
   double* R_out = nullptr;
   double dtau_max = 0.0;
+  double dtau_floor = 0.0;      // lower bound of the SER law (dtau_init with ser_floor, else 0)
   double r0 = 0.0, r = 0.0, r_prev = 0.0, dtau_last_refresh = -1.0;
   int m = 0;                    // V-cycles done
   bool active = false;          // a norm is in flight and more V-cycles may follow
@@ -1119,6 +1120,7 @@ pmg_status check_opts(const pmg_solve_opts* o) {
   }
   if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
   if (o->stage_guess != 0 && o->stage_guess != 1) return fail(PMG_E_ARG, "stage_guess must be 0 or 1");
+  if (o->ser_floor != 0 && o->ser_floor != 1) return fail(PMG_E_ARG, "ser_floor must be 0 or 1");
   return PMG_OK;
 }
 
@@ -1174,6 +1176,7 @@ pmg_status stage_begin(StageRun& R, const pmg_solve_opts* o, double omega, doubl
     stats->n_refresh = 0;
   }
   s.dtau = dtau_init;
+  R.dtau_floor = o->ser_floor ? dtau_init : 0.0;
   R.m = 0;
   R.dtau_last_refresh = -1.0;
   R.result = PMG_E_NOT_CONVERGED;
@@ -1201,7 +1204,8 @@ pmg_status stage_advance(StageRun& R) {
   if (m == 0) {
     R.r0 = R.r;
   } else {
-    s.dtau = std::min(s.dtau * std::pow(R.r_prev / R.r, o->ser_exponent), R.dtau_max);   // eq. (31)
+    s.dtau = std::max(std::min(s.dtau * std::pow(R.r_prev / R.r, o->ser_exponent), R.dtau_max),   // eq. (31)
+                      R.dtau_floor);
   }
   if (R.r == 0.0 || R.r / R.r0 <= o->tol_rel) {
     R.result = PMG_OK;
@@ -1364,7 +1368,8 @@ extern "C" pmg_status nk_stage_solve(const pmg_solve_opts* o, const pmg_nk_opts*
     if (m == 0)
       r0 = r;
     else
-      s.dtau = std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), R.dtau_max);   // eq. (31)
+      s.dtau = std::max(std::min(s.dtau * std::pow(r_prev / r, o->ser_exponent), R.dtau_max),   // eq. (31)
+                        R.dtau_floor);
     if (r == 0.0 || r / r0 <= o->tol_rel) {
       result = PMG_OK;
       break;
@@ -1543,6 +1548,7 @@ extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, doubl
   if (s == 0) return fail(PMG_E_ARG, "unknown ESDIRK scheme");
   if (!o || !q || !work || o->n_levels < 1 || !o->levels || !o->levels[0]) return fail(PMG_E_ARG, "null argument");
   if (o->stage_guess != 0 && o->stage_guess != 1) return fail(PMG_E_ARG, "stage_guess must be 0 or 1");
+  if (o->ser_floor != 0 && o->ser_floor != 1) return fail(PMG_E_ARG, "ser_floor must be 0 or 1");
   if (!(dt > 0.0)) return fail(PMG_E_ARG, "dt must be positive");
   pmg_level L0 = o->levels[0];
   const size_t ns = L0->state_elems();

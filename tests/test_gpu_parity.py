@@ -252,19 +252,24 @@ def test_stage_solve_parity(case):
         assert np.all(h_err <= max(1e-11, 10.0 * h_floor32))
 
 
-@pytest.mark.parametrize("scheme,name,guess,steps", [(2, "esdirk2", "predictor", 2), (2, "esdirk2", "previous", 1),
-                                                      (3, "esdirk3", "predictor", 2), (4, "esdirk4", "predictor", 2)])
-def test_esdirk_step_parity(scheme, name, guess, steps):
+@pytest.mark.parametrize("scheme,name,guess,steps,floor", [(2, "esdirk2", "predictor", 2, False),
+                                                            (2, "esdirk2", "previous", 1, False),
+                                                            (2, "esdirk2", "previous", 2, True),
+                                                            (3, "esdirk3", "predictor", 2, False),
+                                                            (4, "esdirk4", "predictor", 2, False)])
+def test_esdirk_step_parity(scheme, name, guess, steps, floor):
     """ESDIRK2, ESDIRK3 or ESDIRK4 time steps (eq. (24)) through the C ABI against the oracle's
     driver, stages converged to a 1e-4 relative drop, each implicit stage started from the explicit
     predictor or from the previous stage value; with the predictor the first step starts from
     the previous stage values (the analytic vortex is not a solved time level) and the second
-    step from the predictor."""
+    step from the predictor. With floor, the SER law is bounded below by its V-cycle-0 value on
+    both sides (the second step's stages from the previous stage value jump and would otherwise
+    shrink dtau)."""
     from gpu_helpers import gas_for
     mesh = MESHES["cfg1_8x8"]()
     plev, nsm = (2, 1, 0), (5, 10, 20)
     gas = gas_for(VS)
-    opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, tol=1e-4, max_vcycles=60)
+    opts = OS.PMGOptions(p_levels=plev, n_smooth=nsm, tol=1e-4, max_vcycles=60, ser_floor=floor)
     osol = OS.PMGSolver(mesh, gas, opts, q_inf=VS.freestream())
     q0 = vortex_on(osol.levels[0], VS)
     tab = OS.esdirk_tableau(name)
@@ -285,7 +290,7 @@ def test_esdirk_step_parity(scheme, name, guess, steps):
     glevels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf,
                          q_ref=REF) for P in plev]
     facs = [api.Factors(lv, 64) for lv in glevels]
-    solvers = [api.StageSolver(glevels, facs, nsm, tol_rel=1e-4, max_vcycles=60, stage_guess=g)
+    solvers = [api.StageSolver(glevels, facs, nsm, tol_rel=1e-4, max_vcycles=60, stage_guess=g, ser_floor=floor)
                for g in ("previous", guess)]
     q = to_dev(q0 - REF)
     assert api.esdirk_stages(scheme) == tab.shape[0]

@@ -214,6 +214,31 @@ def test_two_level_fas_correction_is_linear_coarse_solve(Pf, Pc):
 
 
 @pytest.mark.slow
+def test_ser_floor_keeps_dtau_at_or_above_its_start():
+    """The SER floor (ser_floor, a reading: eq. (31) states no lower bound) on the stage of the
+    stage-guess test below that jumps: without it dtau falls below dtau_init after the jump, with
+    it every dtau of the history stays at or above dtau_init, and the first V-cycles, before any
+    reduction, are the same."""
+    vs = W.VortexSpec(length=20.0, ma_inf=0.005)
+    mesh = W.periodic_quad_mesh(8, 20.0)
+    tab = S.esdirk_tableau("esdirk2")
+
+    def solver(nvc, floor):
+        return S.PMGSolver(mesh, GAS, S.PMGOptions(p_levels=(2, 1, 0), n_smooth=(5, 10, 20), tol=1e-4,
+                                                   max_vcycles=nvc, ser_floor=floor), q_inf=vs.freestream())
+
+    sol = solver(60, False)
+    lev = sol.levels[0]
+    q1, _ = sol.esdirk_step(vs.state(lev.geo.xy[..., 0], lev.geo.xy[..., 1]), 0.2, tab, stage_guess="previous")
+    _, st_free = solver(8, False).esdirk_step(q1, 0.2, tab, stage_guess="previous")
+    _, st_floor = solver(8, True).esdirk_step(q1, 0.2, tab, stage_guess="previous")
+    d0 = st_free[0].dtau_history[0]
+    assert min(st_free[0].dtau_history) < 0.5 * d0
+    assert min(st_floor[0].dtau_history) >= d0
+    assert st_floor[0].history[:2] == st_free[0].history[:2]
+
+
+@pytest.mark.slow
 def test_stage_guess_predictor_converges_after_first_step():
     """The reading of the stage's initial guess (Sec. 2.4 states none), in the Sec. 4.1 setting
     (vortex on the periodic [-10, 10]^2 square at Ma 0.005, dtau 0.01 -> 10 by eq. (31), blocks
