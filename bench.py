@@ -116,7 +116,8 @@ def time_to_tolerances(stage_stats):
     return out, floors
 
 
-def run_form(api, torch, levels, q0, form, scheme, dt, steps, warmup, max_vcycles, work, later_guess="predictor"):
+def run_form(api, torch, levels, q0, form, scheme, dt, steps, warmup, max_vcycles, work, later_guess="predictor",
+             lookahead=1):
     """`steps` ESDIRK steps from q0 (after `warmup` untimed ones): the first step's stages start
     from the previous stage value (q0 is not a solved time level), the later ones from
     `later_guess` (the explicit predictor by default)."""
@@ -125,7 +126,7 @@ def run_form(api, torch, levels, q0, form, scheme, dt, steps, warmup, max_vcycle
     solvers = [api.StageSolver(levels, facs, N_SMOOTH if len(levels) == 3 else (5, 10, 20)[:len(levels)],
                                dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5, refresh_every=10,
                                freeze_at_max=True, tol_rel=1e-8, max_vcycles=max_vcycles, use_graph=graph,
-                               stage_guess=g) for g in ("previous", later_guess)]
+                               stage_guess=g, lookahead=lookahead) for g in ("previous", later_guess)]
     q = q0.clone()
     for k in range(warmup):
         api.esdirk_step(solvers[min(k, 1)], scheme, dt, q, work, raise_on_error=False)
@@ -568,6 +569,15 @@ def vortex_block(api, torch, forms, steps, warmup, max_vcycles, kernel_reps, aut
                      "elements_per_workgroup": [lv.epw()[0] for lv in levels]}
         finals[form] = q.detach().cpu().numpy()
         del facs, solver
+        if form == "mixed":   # the same steps with one V-cycle per host stopping test
+            facs, solver, q, st_off, el_off = run_form(api, torch, levels, q0, form, SCHEME, DT, steps, warmup,
+                                                       max_vcycles, work, lookahead=0)
+            out[form]["lookahead_off"] = {
+                "ms_per_vcycle": 1e3 * el_off / max(sum(st["n_vcycles"] for st in st_off), 1),
+                "speedup_of_lookahead": el_off / elapsed,
+                "identical_result": bool(np.array_equal(q.detach().cpu().numpy(), finals[form])) and
+                [st["history"] for st in st_off] == [st["history"] for st in stage_stats]}
+            del facs, solver
     if "mixed" in finals and "fp64" in finals:
         d = finals["fp64"]
         out["mixed_vs_fp64_rel_err"] = (np.linalg.norm((finals["mixed"] - d).reshape(4, -1), axis=1)

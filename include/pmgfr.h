@@ -329,6 +329,18 @@ typedef struct {
   int32_t ser_floor;              /* 1: the SER law of eq. (31) never takes dtau below its value at
                                      V-cycle 0 (dtau_init, or cfl_init dtau_min); the paper
                                      states no lower bound. 0: none (the default)               */
+  int32_t lookahead;              /* single-case stage solves (esdirk_stage_solve, esdirk_step):
+                                     1: between block rebuilds, enqueue the next V-cycle before the
+                                     host has read the norm of the one in flight, so that the device
+                                     does not wait for the host's stopping test; the state before
+                                     it is kept in the finest level's workspace and restored when
+                                     the test says stop, so results, norm history and V-cycle
+                                     counts are those of 0. Skipped where the last rate of decrease
+                                     predicts the tolerance within a factor 8 (a discarded V-cycle
+                                     costs its whole time). 2: the same without the prediction
+                                     (every eligible V-cycle; for tests). 0: one V-cycle per host
+                                     test (the default). Ignored by the batched and Newton-Krylov
+                                     solves                                                     */
 } pmg_solve_opts;
 
 typedef struct {

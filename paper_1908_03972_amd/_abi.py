@@ -49,6 +49,7 @@ class SolveOpts(C.Structure):
         ("use_graph", C.c_int32), ("use_cfl", C.c_int32), ("cfl_init", C.c_double), ("cfl_max", C.c_double),
         ("stage_guess", C.c_int32),
         ("ser_floor", C.c_int32),
+        ("lookahead", C.c_int32),
     ]
 
 

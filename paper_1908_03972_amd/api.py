@@ -239,7 +239,7 @@ class StageSolver:
     def __init__(self, levels, factors, n_smooth, *, dtau_init=0.01, dtau_max=10.0, ser_exponent=1.5,
                  refresh_every=10, freeze_at_max=True, tol_rel=1e-8, max_vcycles=200, alpha_r=1.0,
                  use_graph=False, use_cfl=False, cfl_init=1e2, cfl_max=1e5, stage_guess="previous",
-                 ser_floor=False):
+                 ser_floor=False, lookahead=1):
         self.levels = list(levels)
         self.factors = list(factors)
         nl = len(self.levels)
@@ -255,6 +255,9 @@ class StageSolver:
         o.use_cfl, o.cfl_init, o.cfl_max = int(use_cfl), cfl_init, cfl_max
         o.stage_guess = {"previous": 0, "predictor": 1}[stage_guess]   # used by esdirk_step
         o.ser_floor = int(ser_floor)
+        if lookahead not in (0, 1, 2):
+            raise ValueError("lookahead must be 0 (off), 1 (on) or 2 (always, for tests)")
+        o.lookahead = int(lookahead)
         self.opts = o
 
     def solve(self, q, *, omega=0.0, dt=0.0, qc_n=None, R_prev=(), a_row=(), R_out=None, stream=None,

@@ -248,10 +248,27 @@ pmg_status alloc_zero(double** dst, size_t n) {
   return PMG_OK;
 }
 
+// Pinned norm copies and their events for the stage solve's lookahead.
+pmg_status alloc_lookahead(pmg_level_s* L) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&L->hnorm), 16 * sizeof(double)) != hipSuccess) {
+    L->hnorm = nullptr;
+    return fail(PMG_E_NOMEM, "hipHostMalloc failed for the norm copies");
+  }
+  for (hipEvent_t& ev : L->ev_norm)
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ev = nullptr;
+      return fail(PMG_E_HIP, "hipEventCreateWithFlags");
+    }
+  return PMG_OK;
+}
+
 void free_level(pmg_level_s* L) {
   if (!L) return;
   if (L->vc_exec) (void)hipGraphExecDestroy(L->vc_exec);
   if (L->capture_stream) (void)hipStreamDestroy(L->capture_stream);
+  for (hipEvent_t ev : L->ev_norm)
+    if (ev) (void)hipEventDestroy(ev);
+  if (L->hnorm) (void)hipHostFree(L->hnorm);
   void* ptrs[] = {L->met,  L->fvec,   L->nbr,   L->nbf, L->ori, L->wq,    L->wF,     L->wS,  L->wqb, L->wql,
                   L->wsrc, L->part,   L->norms, L->flag, L->hdx, L->dtpart, L->dtmin, L->lam, L->gface, L->Dv};
   for (void* p : ptrs)
@@ -418,6 +435,10 @@ static pmg_status create_hex_level(const pmg_level_desc* d, pmg_level* out) {
   if (hipMemset(L->flag, 0, sizeof(int)) != hipSuccess) {
     free_level(L);
     return fail(PMG_E_HIP, "hipMemset fault flag");
+  }
+  if ((s = alloc_lookahead(L))) {
+    free_level(L);
+    return s;
   }
   *out = L;
   return PMG_OK;
@@ -590,6 +611,10 @@ pmg_status pmg_level_create(const pmg_level_desc* d, pmg_level* out) {
   if (hipMemset(L->flag, 0, sizeof(int)) != hipSuccess) {
     free_level(L);
     return fail(PMG_E_HIP, "hipMemset fault flag");
+  }
+  if ((s = alloc_lookahead(L))) {
+    free_level(L);
+    return s;
   }
   *out = L;
   return PMG_OK;
@@ -1084,6 +1109,16 @@ pmg_status vcycle_graph(Solve& s, double* q) {
 // The single and the batched entry points share it: stage_begin enqueues the set-up and the norm of
 // q^0, stage_advance consumes the latest norm (host copy), applies the SER law of eq. (31) and
 // enqueues the next V-cycle with its norm, stage_finish checks the fault flags and fills the stats.
+//
+// Lookahead (single-case solves): between block rebuilds a V-cycle depends on the host only through
+// the decision to run it (Delta tau enters through the blocks alone), so the V-cycle after the one
+// in flight is enqueued before the host has read the in-flight one's norm, and the device does not
+// wait for the host between V-cycles. The state before that speculative V-cycle is copied to the
+// finest level's restriction buffer (unused on the finest level); when the norm then says stop,
+// the copy is restored, so the result, the norm history and the V-cycle count are those of the
+// plain loop. No speculation where the next V-cycle rebuilds blocks or would pass max_vcycles, or
+// where the last rate of decrease predicts the tolerance within a factor of 8 (a stop there would
+// cost a whole V-cycle, more than the host wait it saves).
 struct StageRun {
   Solve s;
   pmg_solve_stats* stats = nullptr;
@@ -1097,6 +1132,12 @@ struct StageRun {
   pmg_status result = PMG_E_NOT_CONVERGED;
   std::chrono::steady_clock::time_point t_start;
   double* host_norms = nullptr; // [Nv + 1] host copy of the finest-level norms
+  // lookahead (null spec_norms: off)
+  double* spec_norms = nullptr; // [Nv + 1] norm copy of the speculative V-cycle
+  hipEvent_t ev_cur = nullptr;  // recorded after the copy into host_norms
+  hipEvent_t ev_spec = nullptr; // recorded after the copy into spec_norms
+  bool spec = false;            // a speculative V-cycle and its norm copy are in flight
+  double rate = 1.0;            // r_m / r_{m-1} of the last two norms read
 };
 
 pmg_status check_opts(const pmg_solve_opts* o) {
@@ -1121,12 +1162,56 @@ pmg_status check_opts(const pmg_solve_opts* o) {
   if (o->refresh_every < 1 || o->max_vcycles < 0) return fail(PMG_E_ARG, "bad refresh/max_vcycles");
   if (o->stage_guess != 0 && o->stage_guess != 1) return fail(PMG_E_ARG, "stage_guess must be 0 or 1");
   if (o->ser_floor != 0 && o->ser_floor != 1) return fail(PMG_E_ARG, "ser_floor must be 0 or 1");
+  if (o->lookahead < 0 || o->lookahead > 2) return fail(PMG_E_ARG, "lookahead must be 0, 1 or 2");
   return PMG_OK;
 }
 
-pmg_status enqueue_norm_copy(StageRun& R) {
+pmg_status enqueue_norm_copy(StageRun& R, double* dst, hipEvent_t ev) {
   pmg_level L0 = R.s.o->levels[0];
-  PMG_HIP(hipMemcpyAsync(R.host_norms, L0->norms, (L0->nv + 1) * sizeof(double), hipMemcpyDeviceToHost, R.s.st));
+  PMG_HIP(hipMemcpyAsync(dst, L0->norms, (L0->nv + 1) * sizeof(double), hipMemcpyDeviceToHost, R.s.st));
+  if (ev) PMG_HIP(hipEventRecord(ev, R.s.st));
+  return PMG_OK;
+}
+
+pmg_status enqueue_norm_copy(StageRun& R) { return enqueue_norm_copy(R, R.host_norms, R.ev_cur); }
+
+// Whether the V-cycle that the stage_advance reading the norm of V-cycle m (after the one in flight)
+// would enqueue rebuilds the finest blocks.
+bool refresh_at(const StageRun& R, int m) {
+  const pmg_solve_opts* o = R.s.o;
+  const bool frozen = o->freeze_at_max && R.dtau_last_refresh >= R.dtau_max;
+  return (m == 0) || (m % o->refresh_every == 0 && !frozen);
+}
+
+// Enqueue the V-cycle after the one in flight (R.m V-cycles done once it ends) if that is safe
+// and likely to be kept.
+pmg_status maybe_speculate(StageRun& R) {
+  const pmg_solve_opts* o = R.s.o;
+  if (!R.spec_norms || R.spec || !R.active) return PMG_OK;
+  const int m = R.m;
+  if (m >= o->max_vcycles || refresh_at(R, m)) return PMG_OK;
+  if (o->lookahead == 1 && R.r0 > 0.0 && R.r * std::min(R.rate, 1.0) <= 8.0 * o->tol_rel * R.r0)
+    return PMG_OK;   // r_m predicted within 8x of the tolerance
+  pmg_level L0 = o->levels[0];
+  Solve& s = R.s;
+  PMG_HIP(hipMemcpyAsync(L0->wqb, R.q, L0->state_elems() * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+  s.refresh = false;
+  if (o->use_graph) {
+    if (pmg_status e = vcycle_graph(s, R.q)) return e;
+  } else {
+    if (pmg_status e = vcycle_and_norm(s, R.q)) return e;
+  }
+  if (pmg_status e = enqueue_norm_copy(R, R.spec_norms, R.ev_spec)) return e;
+  R.spec = true;
+  return PMG_OK;
+}
+
+// A stop while a speculative V-cycle is in flight: put back the state from before it.
+pmg_status drop_speculation(StageRun& R) {
+  if (!R.spec) return PMG_OK;
+  pmg_level L0 = R.s.o->levels[0];
+  PMG_HIP(hipMemcpyAsync(R.q, L0->wqb, L0->state_elems() * sizeof(double), hipMemcpyDeviceToDevice, R.s.st));
+  R.spec = false;
   return PMG_OK;
 }
 
@@ -1199,24 +1284,33 @@ pmg_status stage_advance(StageRun& R) {
   R.active = false;
   if (!std::isfinite(R.r)) {
     R.result = fail(PMG_E_NONFINITE, "non-finite residual norm");
-    return PMG_OK;
+    return drop_speculation(R);
   }
   if (m == 0) {
     R.r0 = R.r;
   } else {
     s.dtau = std::max(std::min(s.dtau * std::pow(R.r_prev / R.r, o->ser_exponent), R.dtau_max),   // eq. (31)
                       R.dtau_floor);
+    R.rate = R.r_prev > 0.0 ? R.r / R.r_prev : 1.0;
   }
   if (R.r == 0.0 || R.r / R.r0 <= o->tol_rel) {
     R.result = PMG_OK;
-    return PMG_OK;
+    return drop_speculation(R);
   }
   if (m >= o->max_vcycles) {
     R.result = fail(PMG_E_NOT_CONVERGED, "stage solve reached max_vcycles");
-    return PMG_OK;
+    return drop_speculation(R);
   }
-  const bool frozen = o->freeze_at_max && R.dtau_last_refresh >= R.dtau_max;
-  s.refresh = (m == 0) || (m % o->refresh_every == 0 && !frozen);
+  if (R.spec) {   // the V-cycle this step would enqueue (no rebuild) is in flight: keep it
+    R.spec = false;
+    std::swap(R.host_norms, R.spec_norms);
+    std::swap(R.ev_cur, R.ev_spec);
+    R.r_prev = R.r;
+    R.m = m + 1;
+    R.active = true;
+    return maybe_speculate(R);
+  }
+  s.refresh = refresh_at(R, m);
   if (s.refresh) {
     PMG_HIP(build_blocks(*L0, R.q, s.dtau, s.c_mass, nullptr, *o->factors[0], s.st));
     ++s.n_refresh;
@@ -1231,7 +1325,7 @@ pmg_status stage_advance(StageRun& R) {
   R.m = m + 1;
   if (pmg_status e = enqueue_norm_copy(R)) return e;
   R.active = true;
-  return PMG_OK;
+  return maybe_speculate(R);
 }
 
 pmg_status stage_finish(StageRun& R) {
@@ -1269,14 +1363,25 @@ extern "C" pmg_status esdirk_stage_solve(const pmg_solve_opts* o, double omega, 
                                          double* q, double* R_out, pmg_solve_stats* stats, void* stream) {
   if (pmg_status e = check_opts(o)) return e;
   DeviceGuard guard(o->levels[0]->device);
+  pmg_level L0 = o->levels[0];
   StageRun R;
-  double hn[8];
-  R.host_norms = hn;
+  R.host_norms = L0->hnorm;
+  R.spec_norms = o->lookahead ? L0->hnorm + 8 : nullptr;
+  R.ev_cur = L0->ev_norm[0];
+  R.ev_spec = L0->ev_norm[1];
   const hipStream_t st = as_stream(stream);
-  if (pmg_status e = stage_begin(R, o, omega, dt, qc_n, R_prev, a_row, n_prev, q, R_out, stats, st)) return e;
-  while (R.active) {
-    PMG_HIP(hipStreamSynchronize(st));
-    if (pmg_status e = stage_advance(R)) return e;
+  pmg_status e = stage_begin(R, o, omega, dt, qc_n, R_prev, a_row, n_prev, q, R_out, stats, st);
+  while (e == PMG_OK && R.active) {
+    const hipError_t w = hipEventSynchronize(R.ev_cur);   // the latest kept norm (a speculative
+    if (w != hipSuccess) {                                  // V-cycle may still run behind it)
+      e = hip_fail(w, "hipEventSynchronize");
+      break;
+    }
+    e = stage_advance(R);
+  }
+  if (e != PMG_OK) {   // leave nothing of this solve in flight
+    (void)hipStreamSynchronize(st);
+    return e;
   }
   return stage_finish(R);
 }
@@ -1549,6 +1654,7 @@ extern "C" pmg_status esdirk_step(const pmg_solve_opts* o, int32_t scheme, doubl
   if (!o || !q || !work || o->n_levels < 1 || !o->levels || !o->levels[0]) return fail(PMG_E_ARG, "null argument");
   if (o->stage_guess != 0 && o->stage_guess != 1) return fail(PMG_E_ARG, "stage_guess must be 0 or 1");
   if (o->ser_floor != 0 && o->ser_floor != 1) return fail(PMG_E_ARG, "ser_floor must be 0 or 1");
+  if (o->lookahead < 0 || o->lookahead > 2) return fail(PMG_E_ARG, "lookahead must be 0, 1 or 2");
   if (!(dt > 0.0)) return fail(PMG_E_ARG, "dt must be positive");
   pmg_level L0 = o->levels[0];
   const size_t ns = L0->state_elems();

@@ -98,6 +98,10 @@ struct pmg_level_s {
   hipGraphExec_t vc_exec = nullptr;
   hipStream_t capture_stream = nullptr;
   std::vector<uintptr_t> vc_key;
+  // host side of the stage solve's lookahead (finest level only): two pinned copies of the norms
+  // ([2][8]) and the events that mark their arrival
+  double* hnorm = nullptr;
+  hipEvent_t ev_norm[2] = {nullptr, nullptr};
   size_t state_elems() const { return (size_t)nv * np * ne; }
   pmg::LevelView view() const {
     pmg::LevelView v;
