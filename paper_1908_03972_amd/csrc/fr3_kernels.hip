@@ -17,6 +17,7 @@
 #include "internal.hpp"
 #include "hex_points.hpp"
 #include "physics3.hpp"
+#include "block_loads.hpp"
 
 namespace pmg {
 
@@ -59,6 +60,7 @@ struct ResArgs3 {
   const void* W;
   double alpha;
   double* q_out;
+  int w_stream;   // FP32 blocks larger than the Infinity Cache: non-temporal loads
 };
 
 template <int NT>
@@ -324,17 +326,23 @@ __global__ void __launch_bounds__((Cfg3<P, EPW_>::NT)) k_fr3(ResArgs3 a) {
         if constexpr (MODE == 2) {
           const float* w0 = static_cast<const float*>(a.W) + (size_t)e2 * NPAD + 4 * l;
           float accf[4] = {0.f, 0.f, 0.f, 0.f};
-          // block columns requested before the first is waited for: all 40 at P1 and 16 at P2 (9-10%
-          // faster than 8 on the sphere levels: more bytes in flight per CU), 8 at P3 (no gain)
+          auto matvec = [&](auto nt) {
+            // block columns requested before the first is waited for: all 40 at P1 and 16 at P2
+            // (9-10% faster than 8 on the sphere levels: more bytes in flight per CU), 8 at P3 (no gain)
 #pragma unroll (N <= 40 ? 40 : N <= 135 ? 16 : 8)
-          for (int c = 0; c < N; ++c) {
-            const float4 w = *reinterpret_cast<const float4*>(w0 + c * cs);
-            const float fc = (float)fe[c];
-            accf[0] = fmaf(w.x, fc, accf[0]);
-            accf[1] = fmaf(w.y, fc, accf[1]);
-            accf[2] = fmaf(w.z, fc, accf[2]);
-            accf[3] = fmaf(w.w, fc, accf[3]);
-          }
+            for (int c = 0; c < N; ++c) {
+              const blk_f4 w = load_block4<decltype(nt)::value>(w0 + c * cs);
+              const float fc = (float)fe[c];
+              accf[0] = fmaf(w.x, fc, accf[0]);
+              accf[1] = fmaf(w.y, fc, accf[1]);
+              accf[2] = fmaf(w.z, fc, accf[2]);
+              accf[3] = fmaf(w.w, fc, accf[3]);
+            }
+          };
+          if (a.w_stream)
+            matvec(std::true_type{});
+          else
+            matvec(std::false_type{});
 #pragma unroll
           for (int t = 0; t < 4; ++t) acc[t] = (double)accf[t];
         } else {
@@ -655,6 +663,8 @@ hipError_t launch_sweep3(const pmg_level_s& L, const pmg_factors_s& fac, const d
   a.W = fac.W;
   a.alpha = alpha;
   a.q_out = q_out;
+  const size_t npad = (size_t)(L.n + 3) / 4 * 4;
+  a.w_stream = fac.precision == 32 && (size_t)L.ne * L.n * npad * 4 > kStreamBlocksBytes;
   if (fac.precision == 32) return launch_fr3<2>(L.P, a, L.ne, L.epw, st);
   return launch_fr3<1>(L.P, a, L.ne, L.epw, st);
 }

@@ -18,6 +18,7 @@
 // input buffer only).
 #include "internal.hpp"
 #include "vcycle.hpp"
+#include "block_loads.hpp"
 
 namespace pmg {
 
@@ -96,6 +97,7 @@ struct ResArgs {
   double alpha;
   double* q_out;
   double* S_out;   // non-null: S held P w, the defect is P w and S_out receives F(q) - P w
+  int w_stream;    // FP32 blocks larger than the Infinity Cache: non-temporal loads
 };
 
 // MODE 0: residual only; 1: sweep with FP64 inverse blocks; 2: sweep with FP32 inverse blocks
@@ -529,15 +531,21 @@ __global__ void __launch_bounds__((Cfg<P, EPW_>::NT)) k_fr(ResArgs a) {
             accf[2] = fmaf(w.z, fc, accf[2]);
             accf[3] = fmaf(w.w, fc, accf[3]);
           }
+          auto matvec = [&](auto nt) {
 #pragma unroll MV_UNROLL
-          for (int c = CPF; c < N; ++c) {
-            const float4 w = *reinterpret_cast<const float4*>(w0 + c * cs);
-            const float fc = (float)fe[c];
-            accf[0] = fmaf(w.x, fc, accf[0]);
-            accf[1] = fmaf(w.y, fc, accf[1]);
-            accf[2] = fmaf(w.z, fc, accf[2]);
-            accf[3] = fmaf(w.w, fc, accf[3]);
-          }
+            for (int c = CPF; c < N; ++c) {
+              const blk_f4 w = load_block4<decltype(nt)::value>(w0 + c * cs);
+              const float fc = (float)fe[c];
+              accf[0] = fmaf(w.x, fc, accf[0]);
+              accf[1] = fmaf(w.y, fc, accf[1]);
+              accf[2] = fmaf(w.z, fc, accf[2]);
+              accf[3] = fmaf(w.w, fc, accf[3]);
+            }
+          };
+          if (a.w_stream)
+            matvec(std::true_type{});
+          else
+            matvec(std::false_type{});
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[v] = (double)accf[v];
         } else {
@@ -754,6 +762,7 @@ static hipError_t launch_sweep2(const pmg_level_s& L, const pmg_factors_s& fac, 
   a.W = fac.W;
   a.alpha = alpha;
   a.q_out = q_out;
+  a.w_stream = fac.precision == 32 && (size_t)L.ne * L.n * L.n * 4 > kStreamBlocksBytes;
   if (L.visc) {
     const hipError_t e = launch_gradient_traces(L, q_in, st);
     if (e != hipSuccess) return e;

@@ -640,7 +640,10 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
     }
     __syncthreads();                        // sperm and sinv complete
     // thread r writes row r of the inverse (slot row p_r), so that for each column the lanes of
-    // a wave store consecutive entries of W
+    // a wave store consecutive entries of W. The stores are non-temporal: the inverses (15 GB at
+    // P3 on the 36864-element sphere) are not read again in this kernel, and cached they would
+    // push the other workgroups' work slots out of the Infinity Cache (86 -> 76 ms per FP32
+    // rebuild of that level)
     const int prow = sperm[r];
     const T pinv = sinv[r];
     for (int m0 = 0; m0 < N; m0 += 16) {    // sixteen loads in flight per thread, then the stores
@@ -653,9 +656,9 @@ k_jac3_big(JacArgs3 a, T* __restrict__ ws,
         const double val = (double)(xv[u] * pinv);
         const size_t o_ = ((size_t)col * ne + e) * NPAD + r;
         if (a.precision == 32)
-          static_cast<float*>(a.W)[o_] = (float)val;
+          __builtin_nontemporal_store((float)val, static_cast<float*>(a.W) + o_);
         else
-          static_cast<double*>(a.W)[o_] = val;
+          __builtin_nontemporal_store(val, static_cast<double*>(a.W) + o_);
       }
     }
   }
