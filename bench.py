@@ -490,8 +490,8 @@ PROFILE_PMC_SPHERE = os.path.join(ROOT, "profiles", "k_fr3_sweep_sphere16x16x24_
 PROFILE_PMC_SPHERE3 = os.path.join(ROOT, "profiles", "k_fr3_sweep_sphere16x16x24_P3_pmc.txt")
 
 
-KERNEL_SOURCES_2D = ("fr_kernels.hip", "physics.hpp", "internal.hpp")
-KERNEL_SOURCES_3D = ("fr3_kernels.hip", "hex_points.hpp", "physics3.hpp", "physics.hpp", "internal.hpp")
+KERNEL_SOURCES_2D = ("fr_kernels.hip", "physics.hpp", "internal.hpp", "block_loads.hpp", "vcycle.hpp")
+KERNEL_SOURCES_3D = ("fr3_kernels.hip", "hex_points.hpp", "physics3.hpp", "physics.hpp", "internal.hpp", "block_loads.hpp")
 
 
 def kernel_source_hash(files=KERNEL_SOURCES_2D):
