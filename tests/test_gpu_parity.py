@@ -169,7 +169,8 @@ def test_sweep_parity(mesh_name, P, prec):
                                     q_inf=VS.freestream())
         sol32.c_mass, sol32.src, sol32.dtau = c_mass, src, dtau
         sol32.build_D(0, q)
-        floor32 = rel_err_per_var(sol32.smooth(0, q, None, 3) - VS.freestream(), ref - VS.freestream())
+        ref32 = sol32.smooth(0, q, None, 3)
+        floor32 = rel_err_per_var(ref32 - VS.freestream(), ref - VS.freestream())
         print("fp32 floor", floor32)
         assert np.all(err <= np.maximum(1e-11, 10.0 * floor32)), (err, floor32)
     Fref = olev.stage_residual(ref, c_mass, src)
@@ -179,7 +180,11 @@ def test_sweep_parity(mesh_name, P, prec):
     if prec == 64:
         assert np.all(ferr <= np.maximum(1e-11, 10.0 * ffloor)), (ferr, ffloor)
     else:
-        assert np.all(ferr < 1e-2), ferr
+        # the residual after FP32 sweeps: ten times the deviation the oracle's own FP32 sweeps leave
+        # in it (the FP64 residual of the FP32-swept state against that of the FP64-swept one)
+        ffloor32 = rel_err_per_var(olev.stage_residual(ref32, c_mass, src), Fref)
+        print("F_after fp32 floor", ffloor32)
+        assert np.all(ferr <= np.maximum(1e-11, 10.0 * ffloor32)), (ferr, ffloor32)
 
 
 def _stage_case(case):
