@@ -187,3 +187,54 @@ def test_batched_cases_against_the_oracle():
         print("batched case err", err, "floor", floor)
         assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (err, floor)
     batch.close()
+
+
+def test_batched_cases_against_the_oracle():
+    """Two FP64 cases of different mesh size and hierarchy solved together as one batch (the 8 x 8
+    P{2-1-0} and the ragged 13 x 11 P{3-1} vortex, ESDIRK2 second stage, three V-cycles each):
+    every case's state and residual history against the oracle's stage solve, within ten times the
+    oracle's own one-ulp floor, as the single-case solves are tested."""
+    from gpu_helpers import from_dev, rel_err_per_var
+    from oracle import solver as OS
+    g = OG.Gas(gamma=VS.gamma, rgas=VS.rgas, eps_mode="local", ma_inf=VS.ma_inf)
+    qinf = VS.freestream()
+    A2 = OS.esdirk_tableau("esdirk2")
+    dt, om = 0.05, A2[1, 1]
+    specs = [(W.periodic_quad_mesh(8, 10.0), (2, 1, 0), (5, 10, 20)),
+             (W.periodic_rect_mesh(13, 11, 10.0, 10.0, jitter=0.1, seed=3), (3, 1), (3, 6))]
+    nvc = 3
+    solvers, qs, qcs, R1s, refs = [], [], [], [], []
+    for mesh, plev, nsm in specs:
+        olev = FRLevel(mesh, plev[0], g, q_inf=qinf)
+        q0 = VS.state(olev.geo.xy[..., 0], olev.geo.xy[..., 1])
+
+        def run_oracle(x, mesh=mesh, plev=plev, nsm=nsm):
+            osol = OS.PMGSolver(mesh, g, OS.PMGOptions(p_levels=plev, n_smooth=nsm, max_vcycles=nvc, tol=1e-30),
+                                q_inf=qinf)
+            src = (OG.conservative(x, g) + dt * A2[1, 0] * osol.levels[0].residual(x)) / (om * dt)
+            return osol.stage_solve(x, 1.0 / (om * dt), src, max_vcycles=nvc)
+
+        q_ref, st = run_oracle(q0)
+        rng = np.random.default_rng(7)
+        q_pert, _ = run_oracle(q0 * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=q0.shape)))
+        refs.append((q_ref, st, rel_err_per_var(q_pert - qinf, q_ref - qinf)))
+        levels = [api.Level(mesh, P, gamma=VS.gamma, rgas=VS.rgas, eps_mode=0, ma_inf=VS.ma_inf, q_inf=qinf,
+                            q_ref=qinf) for P in plev]
+        solvers.append(api.StageSolver(levels, [api.Factors(lv, 64) for lv in levels], nsm, max_vcycles=nvc,
+                                       tol_rel=1e-30))
+        qs.append(to_dev(q0 - qinf))
+        qcs.append(to_dev(OG.conservative(q0, g)))
+        R1s.append(to_dev(olev.residual(q0)))
+    batch = api.Batch(solvers)
+    out = batch.solve(qs, omega=[om, om], dt=[dt, dt], qc_n=qcs, R_prev=[[R1s[0]], [R1s[1]]],
+                      a_row=[[A2[1, 0]], [A2[1, 0]]], raise_on_error=False)
+    torch.cuda.synchronize()
+    for c, (q_ref, st, floor) in enumerate(refs):
+        assert out[c]["n_vcycles"] == nvc
+        err = rel_err_per_var(from_dev(qs[c]), q_ref - qinf)
+        h_ref = np.array(st.history)
+        h_err = np.abs(np.array(out[c]["history"]) - h_ref) / h_ref
+        print("batched case", c, "state err", err, "floor", floor, "history err", h_err)
+        assert np.all(err <= np.maximum(1e-11, 10.0 * floor)), (c, err, floor)
+        assert np.all(h_err <= max(1e-11, 10.0 * floor.max())), (c, h_err)
+    batch.close()
