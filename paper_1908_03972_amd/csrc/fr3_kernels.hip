@@ -327,9 +327,10 @@ __global__ void __launch_bounds__((Cfg3<P, EPW_>::NT)) k_fr3(ResArgs3 a) {
           const float* w0 = static_cast<const float*>(a.W) + (size_t)e2 * NPAD + 4 * l;
           float accf[4] = {0.f, 0.f, 0.f, 0.f};
           auto matvec = [&](auto nt) {
-            // block columns requested before the first is waited for: all 40 at P1 and 16 at P2
-            // (9-10% faster than 8 on the sphere levels: more bytes in flight per CU), 8 at P3 (no gain)
-#pragma unroll (N <= 40 ? 40 : N <= 135 ? 16 : 8)
+            // block columns requested before the first is waited for: all 40 at P1 and 24 at P2
+            // (8 -> 16 made the sphere levels 9-10% faster, 16 -> 24 with non-temporal loads 3%:
+            // more bytes in flight per CU), 8 at P3 (more gains nothing there)
+#pragma unroll (N <= 40 ? 40 : N <= 135 ? 24 : 8)
             for (int c = 0; c < N; ++c) {
               const blk_f4 w = load_block4<decltype(nt)::value>(w0 + c * cs);
               const float fc = (float)fe[c];
