@@ -687,8 +687,8 @@ struct Lds3 {
 template <int P>
 __global__ void __launch_bounds__(Lds3<P>::NT) k_jac3_lds(JacArgs3 a, const double* __restrict__ pj) {
   using C = Lds3<P>;
-  constexpr int NP = C::NP, NF = C::NF, NV = C::NV, N = C::N, NR = C::NR, NPAD = C::NPAD, XS = C::XS, B = C::B,
-                NT = C::NT, NW = C::NW, TPW = C::TPW, NPJ = C::NPJ;
+  constexpr int NP = C::NP, NV = C::NV, N = C::N, NR = C::NR, NPAD = C::NPAD, XS = C::XS, B = C::B, NT = C::NT,
+                NW = C::NW, TPW = C::TPW, NPJ = C::NPJ;
   __shared__ float X[NR * XS];
   __shared__ double sj[NPJ];                 // sA, sDg, sB one after the other
   __shared__ float xp[B * XS];               // old pivot-row values of a panel
