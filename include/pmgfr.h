@@ -61,7 +61,7 @@ typedef struct pmg_batch_s* pmg_batch;
 const char* pmg_last_error(void);
 
 /* Version of this ABI (major * 100 + minor); the library returns PMG_ABI_VERSION. */
-#define PMG_ABI_VERSION 107
+#define PMG_ABI_VERSION 108
 int32_t pmg_abi_version(void);
 
 /*

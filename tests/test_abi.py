@@ -71,3 +71,34 @@ def test_esdirk_tableaux_match_the_oracle():
         assert A.lib().esdirk_butcher(scheme, buf) == s
         assert np.max(np.abs(np.array(buf[:]).reshape(s, s) - ref)) < 1e-15
     assert A.lib().esdirk_butcher(5, None) == 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every field of the ctypes mirrors in the binding sits at the offset a C compiler gives it
+    from include/pmgfr.h, and every struct has the header's size (a field added on one side only
+    would shift the rest)."""
+    import shutil
+    import subprocess
+    from paper_1908_03972_amd import _abi as A
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pmg_level_desc": A.LevelDesc, "pmg_solve_opts": A.SolveOpts, "pmg_solve_stats": A.SolveStats,
+               "pmg_nk_opts": A.NkOpts}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "pmgfr.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, "-o", str(exe), str(src)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
