@@ -102,3 +102,41 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def _c_class(decl):
+    """'ptr', 'i32', 'i64' or 'f64' for one C parameter or return type of the header."""
+    d = decl.strip()
+    if "*" in d or re.match(r"(const\s+)?(pmg_level|pmg_factors|pmg_batch)\b", d):
+        return "ptr"
+    t = re.sub(r"\b(const|struct)\b", "", d).split()[0]
+    return {"int32_t": "i32", "pmg_status": "i32", "int64_t": "i64", "double": "f64"}[t]
+
+
+def _py_class(t):
+    if t in (ctypes.c_int32,):
+        return "i32"
+    if t in (ctypes.c_int64,):
+        return "i64"
+    if t in (ctypes.c_double,):
+        return "f64"
+    if t in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(t, "_type_") and issubclass(t, ctypes._Pointer):
+        return "ptr"
+    raise AssertionError(f"unclassified ctypes type {t}")
+
+
+def test_binding_signatures_match_the_header():
+    """Each function the binding declares has the header's arity, and each argument and return value
+    the header's kind (pointer or handle, 32- or 64-bit integer, double)."""
+    from paper_1908_03972_amd import _abi as A
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    for name, (res, args) in A.SIGNATURES.items():
+        m = re.search(r"([\w\s\*]+?)\b" + name + r"\s*\(([^;{}]*)\)\s*;", text)
+        assert m, name
+        ret = m.group(1).split("\n")[-1]
+        params = [p for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        assert len(params) == len(args), (name, len(params), len(args))
+        assert _c_class(ret) == _py_class(res), (name, ret, res)
+        for i, (p, a) in enumerate(zip(params, args)):
+            assert _c_class(p) == _py_class(a), (name, i, p, a)
