@@ -266,3 +266,27 @@ def test_stage_guess_predictor_converges_after_first_step():
     for s in st_pred:
         assert s.converged, s.history
         assert max(s.history) <= 1.0 * s.history[0]
+
+
+def test_vcycle_without_rebuild_does_not_depend_on_dtau():
+    """Delta tau enters the V-cycle only through the element blocks (eqs. (28)-(30)): between block
+    rebuilds the same blocks and state give the same V-cycle for any Delta tau. The stage solve's
+    lookahead on the GPU (the V-cycle after the one in flight enqueued before the SER law has set
+    Delta tau from the in-flight norm) is exact because of this."""
+    mesh, vs = _vortex(n=3, P=2)
+    sol = S.PMGSolver(mesh, GAS, S.PMGOptions(p_levels=(2, 1, 0), n_smooth=(2, 3, 4)), q_inf=vs.freestream())
+    q = vs.state(sol.levels[0].geo.xy[..., 0], sol.levels[0].geo.xy[..., 1])
+    sol.dtau = 0.05
+    sol.refresh_now = True                   # blocks of every level, as at a rebuild
+    sol.build_D(0, q)
+    q1 = sol.vcycle(0, q, None)
+    sol.refresh_now = False
+    outs = []
+    for dtau in (1e-3, 0.05, 7.0):
+        sol.dtau = dtau
+        outs.append(sol.vcycle(0, q1, None))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    sol.dtau = 7.0                           # a rebuild at another Delta tau does change the cycle
+    sol.refresh_now = True
+    sol.build_D(0, q1)
+    assert not np.array_equal(sol.vcycle(0, q1, None), outs[1])
